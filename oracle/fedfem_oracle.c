@@ -1,0 +1,389 @@
+/*
+ * FP64 CPU oracle for the fast explicit dynamics FEM (FED-FEM) of
+ * Zhang & Chauhan, "Fast explicit dynamics finite element algorithm for
+ * transient heat transfer" (arXiv 1909.03355).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU library is checked against.  Nothing in the product path links it; it
+ * shares no code, header or table with the GPU library.
+ *
+ * It follows the paper's three stages (Sec. 3.5) literally:
+ *   pre-computation  - per element det J and B, G = 8 det(J) B^T (hexahedra,
+ *                      one centre Gauss point, Eq. 17, 19) or G = V B^T
+ *                      (tetrahedra, Eq. 18, 19); lumped thermal mass (Sec. 3.1)
+ *   time stepping    - element loads F_e = G D(T) B T_e (Eq. 20), summed at
+ *                      the nodes without a global K (Eq. 10-11), surface loads
+ *                      Q (Eqs. 4, 5, 7), explicit update (Eq. 15-16), then the
+ *                      essential condition (Eq. 3) for the next step.
+ * Readings of the paper used here (where it is garbled or silent):
+ *   - F in Eq. 9-16 is read as the conductive heat INTO the nodes, -K T, so
+ *     the update is T += dt (Q - K T) / C  (K = sum of B^T D B dV is PSD).
+ *   - convection adds -h A (T - Ta) into a node (the physical sign, Eq. 7's).
+ *   - surface loads are lumped to the face nodes with area |f| / n_f.
+ *   - c(T) is evaluated at the node, D(T) at the element mean temperature.
+ *   - the lumped mass uses the exact element volume (2x2x2 Gauss for a
+ *     trilinear hexahedron, which is exact), stiffness uses 8 det J(0).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const int HEX_S[8][3] = {
+    {-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+    {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+
+static double det3(double J[3][3]) {
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+/* Inverse of a 3x3 matrix by the adjugate. */
+static void inv3(double J[3][3], double d, double R[3][3]) {
+  R[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / d;
+  R[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / d;
+  R[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / d;
+  R[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / d;
+  R[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / d;
+  R[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / d;
+  R[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / d;
+  R[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / d;
+  R[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / d;
+}
+
+/* Derivatives of the trilinear shape functions N_a = (1+s_a.xi)(1+s_a.eta)(1+s_a.zeta)/8
+ * with respect to the natural coordinates, at natural point p. */
+static void hex_dN(const double p[3], double dN[8][3]) {
+  for (int a = 0; a < 8; a++) {
+    double sx = HEX_S[a][0], sy = HEX_S[a][1], sz = HEX_S[a][2];
+    dN[a][0] = sx * (1 + sy * p[1]) * (1 + sz * p[2]) / 8.0;
+    dN[a][1] = sy * (1 + sx * p[0]) * (1 + sz * p[2]) / 8.0;
+    dN[a][2] = sz * (1 + sx * p[0]) * (1 + sy * p[1]) / 8.0;
+  }
+}
+
+/* J[i][j] = d x_i / d xi_j = sum_a X_a,i dN_a/dxi_j */
+static void hex_jac(double X[8][3], double dN[8][3], double J[3][3]) {
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0;
+      for (int a = 0; a < 8; a++) s += X[a][i] * dN[a][j];
+      J[i][j] = s;
+    }
+}
+
+/* Solve A X = I for a 4x4 matrix by Gauss-Jordan elimination with partial
+ * pivoting; returns det(A). */
+static double inv4(double A[4][4], double X[4][4]) {
+  double M[4][8];
+  for (int i = 0; i < 4; i++)
+    for (int j = 0; j < 4; j++) {
+      M[i][j] = A[i][j];
+      M[i][4 + j] = (i == j) ? 1.0 : 0.0;
+    }
+  double det = 1.0;
+  for (int c = 0; c < 4; c++) {
+    int piv = c;
+    for (int r = c + 1; r < 4; r++)
+      if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+    if (M[piv][c] == 0.0) return 0.0;
+    if (piv != c) {
+      for (int j = 0; j < 8; j++) {
+        double t = M[c][j];
+        M[c][j] = M[piv][j];
+        M[piv][j] = t;
+      }
+      det = -det;
+    }
+    double p = M[c][c];
+    det *= p;
+    for (int j = 0; j < 8; j++) M[c][j] /= p;
+    for (int r = 0; r < 4; r++) {
+      if (r == c) continue;
+      double f = M[r][c];
+      for (int j = 0; j < 8; j++) M[r][j] -= f * M[c][j];
+    }
+  }
+  for (int i = 0; i < 4; i++)
+    for (int j = 0; j < 4; j++) X[i][j] = M[i][4 + j];
+  return det;
+}
+
+/*
+ * Pre-computation (Sec. 3.5 (i).2): per element B (3 x ne, row-major at
+ * B[(e*3+i)*ne + a]), the stiffness weight W (8 det J(0) for hexahedra, V
+ * for tetrahedra), the exact volume V and the orientation determinant.
+ * Returns the number of inverted or degenerate elements.
+ */
+int64_t orc_geometry(int ne, int64_t E, const double *x, const double *y,
+                     const double *z, const int32_t *conn, double *B, double *W,
+                     double *V, double *detJ0) {
+  int64_t bad = 0;
+  for (int64_t e = 0; e < E; e++) {
+    if (ne == 8) {
+      double X[8][3], dN[8][3], J[3][3], Ji[3][3];
+      for (int a = 0; a < 8; a++) {
+        int32_t k = conn[(int64_t)a * E + e];
+        X[a][0] = x[k];
+        X[a][1] = y[k];
+        X[a][2] = z[k];
+      }
+      const double zero[3] = {0, 0, 0};
+      hex_dN(zero, dN);
+      hex_jac(X, dN, J);
+      double d = det3(J);
+      detJ0[e] = d;
+      if (!(d > 0)) {
+        bad++;
+        d = (d == 0) ? 1.0 : d;
+      }
+      inv3(J, d, Ji);
+      /* B = J^{-T} dN^T:  B[i][a] = sum_j Ji[j][i] dN[a][j] */
+      for (int i = 0; i < 3; i++)
+        for (int a = 0; a < 8; a++) {
+          double s = 0;
+          for (int j = 0; j < 3; j++) s += Ji[j][i] * dN[a][j];
+          B[(e * 3 + i) * 8 + a] = s;
+        }
+      W[e] = 8.0 * detJ0[e];
+      /* exact volume of the trilinear map: 2x2x2 Gauss, unit weights */
+      double vol = 0;
+      const double g = 1.0 / sqrt(3.0);
+      for (int q = 0; q < 8; q++) {
+        double p[3] = {HEX_S[q][0] * g, HEX_S[q][1] * g, HEX_S[q][2] * g};
+        double dNq[8][3], Jq[3][3];
+        hex_dN(p, dNq);
+        hex_jac(X, dNq, Jq);
+        vol += det3(Jq);
+      }
+      V[e] = vol;
+    } else {
+      /* linear tetrahedron: N_a(x) = C[0][a] + C[1][a] x + C[2][a] y + C[3][a] z
+       * with C = P^{-1}, P rows [1 x_a y_a z_a]; B[i][a] = C[1+i][a]. */
+      double P[4][4], C[4][4];
+      for (int a = 0; a < 4; a++) {
+        int32_t k = conn[(int64_t)a * E + e];
+        P[a][0] = 1.0;
+        P[a][1] = x[k];
+        P[a][2] = y[k];
+        P[a][3] = z[k];
+      }
+      double d = inv4(P, C);
+      detJ0[e] = d;
+      if (d == 0.0) bad++;
+      for (int i = 0; i < 3; i++)
+        for (int a = 0; a < 4; a++) B[(e * 3 + i) * 4 + a] = C[1 + i][a];
+      V[e] = fabs(d) / 6.0;
+      W[e] = V[e];
+    }
+  }
+  return bad;
+}
+
+/* Area of every boundary face: planar triangles by the cross product,
+ * bilinear quadrilaterals by 2x2 Gauss quadrature of |x_u x x_v|. */
+void orc_face_areas(int nfn, int64_t nf, const double *x, const double *y,
+                    const double *z, const int32_t *faces, double *area) {
+  for (int64_t f = 0; f < nf; f++) {
+    double X[4][3];
+    for (int b = 0; b < nfn; b++) {
+      int32_t k = faces[f * nfn + b];
+      X[b][0] = x[k];
+      X[b][1] = y[k];
+      X[b][2] = z[k];
+    }
+    if (nfn == 3) {
+      double u[3], v[3];
+      for (int i = 0; i < 3; i++) {
+        u[i] = X[1][i] - X[0][i];
+        v[i] = X[2][i] - X[0][i];
+      }
+      double c0 = u[1] * v[2] - u[2] * v[1];
+      double c1 = u[2] * v[0] - u[0] * v[2];
+      double c2 = u[0] * v[1] - u[1] * v[0];
+      area[f] = 0.5 * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    } else {
+      static const double su[4] = {-1, 1, 1, -1}, sv[4] = {-1, -1, 1, 1};
+      const double g = 1.0 / sqrt(3.0);
+      double A = 0;
+      for (int q = 0; q < 4; q++) {
+        double pu = su[q] * g, pv = sv[q] * g;
+        double xu[3] = {0, 0, 0}, xv[3] = {0, 0, 0};
+        for (int b = 0; b < 4; b++) {
+          double dnu = su[b] * (1 + sv[b] * pv) / 4.0;
+          double dnv = sv[b] * (1 + su[b] * pu) / 4.0;
+          for (int i = 0; i < 3; i++) {
+            xu[i] += X[b][i] * dnu;
+            xv[i] += X[b][i] * dnv;
+          }
+        }
+        double c0 = xu[1] * xv[2] - xu[2] * xv[1];
+        double c1 = xu[2] * xv[0] - xu[0] * xv[2];
+        double c2 = xu[0] * xv[1] - xu[1] * xv[0];
+        A += sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+      }
+      area[f] = A;
+    }
+  }
+}
+
+/* Everything one explicit run needs; arrays are per element (E), per node
+ * (N), per face (nf) as named.  Dk is the element conductivity tensor, 6 rows
+ * (xx, yy, zz, xy, yz, xz) of length E, with any per-element factor folded in;
+ * D(T) = Dk * (s0 + s1 * Tbar).  c(T) = c0 + c1 * T. */
+typedef struct {
+  int32_t ne, nfn;
+  int64_t N, E, nf, npt, ndir;
+  const int32_t *conn;
+  const double *B, *W, *V;
+  const double *rho, *c0, *c1, *s0, *s1, *Dk;
+  const int32_t *faces;
+  const double *farea, *fh, *fTa, *feps, *fq;
+  const int32_t *pt_nodes;
+  const double *pt_W;
+  const int32_t *dir_nodes;
+  const double *dir_T;
+  const double *dt; /* per node */
+  double Tz, sigma;
+} orc_problem;
+
+/* Element load F_e = G D(Tbar) B T_e with G = W B^T (Eq. 19-20). */
+static void element_load(const orc_problem *P, int64_t e, const double *T, double *Fe) {
+  int ne = P->ne;
+  int64_t E = P->E;
+  double Te[8], Tbar = 0;
+  for (int a = 0; a < ne; a++) {
+    Te[a] = T[P->conn[(int64_t)a * E + e]];
+    Tbar += Te[a];
+  }
+  Tbar /= ne;
+  double s = P->s0[e] + P->s1[e] * Tbar;
+  const double *Dk = P->Dk;
+  double D[3][3];
+  D[0][0] = Dk[0 * E + e] * s;
+  D[1][1] = Dk[1 * E + e] * s;
+  D[2][2] = Dk[2 * E + e] * s;
+  D[0][1] = D[1][0] = Dk[3 * E + e] * s;
+  D[1][2] = D[2][1] = Dk[4 * E + e] * s;
+  D[0][2] = D[2][0] = Dk[5 * E + e] * s;
+  const double *Be = P->B + e * 3 * ne;
+  double g[3], q[3];
+  for (int i = 0; i < 3; i++) {
+    g[i] = 0;
+    for (int a = 0; a < ne; a++) g[i] += Be[i * ne + a] * Te[a];
+  }
+  for (int i = 0; i < 3; i++) q[i] = D[i][0] * g[0] + D[i][1] * g[1] + D[i][2] * g[2];
+  for (int a = 0; a < ne; a++) {
+    double s2 = 0;
+    for (int i = 0; i < 3; i++) s2 += P->W[e] * Be[i * ne + a] * q[i];
+    Fe[a] = s2;
+  }
+}
+
+/* Net nodal conductive load F = sum_e F_e (summed in element order) and the
+ * lumped heat capacity C_k = sum_{e owns k} rho_e V_e / n_e * c_e(T_k). */
+void orc_loads(const orc_problem *P, const double *T, double *Fe, double *F, double *C) {
+  int ne = P->ne;
+  int64_t E = P->E;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < E; e++) element_load(P, e, T, Fe + e * ne);
+  memset(F, 0, sizeof(double) * P->N);
+  memset(C, 0, sizeof(double) * P->N);
+  for (int64_t e = 0; e < E; e++)
+    for (int a = 0; a < ne; a++) {
+      int32_t k = P->conn[(int64_t)a * E + e];
+      F[k] += Fe[e * ne + a];
+      C[k] += P->rho[e] * P->V[e] / ne * (P->c0[e] + P->c1[e] * T[k]);
+    }
+}
+
+/* Net nodal surface heat input Q (Eqs. 4, 5, 7 with the readings above), plus
+ * concentrated nodal loads. */
+void orc_surface(const orc_problem *P, const double *T, double *Q) {
+  memset(Q, 0, sizeof(double) * P->N);
+  for (int64_t i = 0; i < P->npt; i++) Q[P->pt_nodes[i]] += P->pt_W[i];
+  for (int64_t f = 0; f < P->nf; f++) {
+    double share = P->farea[f] / P->nfn;
+    for (int b = 0; b < P->nfn; b++) {
+      int32_t k = P->faces[f * P->nfn + b];
+      double conv = -P->fh[f] * (T[k] - P->fTa[f]);
+      double rad = -P->sigma * P->feps[f] *
+                   (pow(T[k] - P->Tz, 4) - pow(P->fTa[f] - P->Tz, 4));
+      Q[k] += share * (conv + rad + P->fq[f]);
+    }
+  }
+}
+
+/* nsteps explicit steps in place on T (Eq. 16, then Eq. 3).  Work arrays:
+ * Fe[E*ne], F, C, Q, Tn [N].  If hist is non-null, hist[(n)*N + k] receives
+ * T after n steps for n = 0..nsteps. */
+void orc_run(const orc_problem *P, double *T, int64_t nsteps, double *Fe, double *F,
+             double *C, double *Q, double *Tn, double *hist) {
+  int64_t N = P->N;
+  if (hist) memcpy(hist, T, sizeof(double) * N);
+  for (int64_t n = 0; n < nsteps; n++) {
+    orc_loads(P, T, Fe, F, C);
+    orc_surface(P, T, Q);
+    for (int64_t k = 0; k < N; k++) Tn[k] = T[k] + P->dt[k] * (Q[k] - F[k]) / C[k];
+    for (int64_t i = 0; i < P->ndir; i++) Tn[P->dir_nodes[i]] = P->dir_T[i];
+    memcpy(T, Tn, sizeof(double) * N);
+    if (hist) memcpy(hist + (n + 1) * N, T, sizeof(double) * N);
+  }
+}
+
+/*
+ * Discrete adjoint of orc_run for problems that are linear in T (s1 = 0,
+ * c1 = 0, no radiation).  Given hist (T^0..T^nsteps) and lam = dL/dT^nsteps,
+ * runs the steps in reverse:
+ *   mu      = dt * lam / C            (zero on Dirichlet nodes)
+ *   g_logk += -mu_e . K_e T^n_e        (K_e = W B^T D B, d K_e / d log k_e = K_e)
+ *   g_c    += -lam_k (T^{n+1}_k - T^n_k) / C_k * rho V_e / ne
+ *   g_h    += -mu_k |f| / n_f (T^n_k - Ta_f)
+ *   lam    <- lam - (K + H) mu,  then zero on Dirichlet nodes
+ * On return lam holds dL/dT^0.  Requires is_dir[N] (1 on Dirichlet nodes).
+ */
+void orc_adjoint_linear(const orc_problem *P, const double *hist, int64_t nsteps,
+                        const int8_t *is_dir, double *lam, double *g_logk,
+                        double *g_c, double *g_h, double *Fe, double *F, double *C,
+                        double *mu) {
+  int ne = P->ne;
+  int64_t N = P->N, E = P->E;
+  for (int64_t n = nsteps - 1; n >= 0; n--) {
+    const double *Tn = hist + n * N, *Tn1 = hist + (n + 1) * N;
+    orc_loads(P, Tn, Fe, F, C); /* C at T^n (constant here); Fe unused */
+    for (int64_t k = 0; k < N; k++) mu[k] = is_dir[k] ? 0.0 : P->dt[k] * lam[k] / C[k];
+    /* element terms */
+    for (int64_t e = 0; e < E; e++) {
+      double KT[8];
+      element_load(P, e, Tn, KT); /* K_e T^n_e */
+      double dot = 0;
+      for (int a = 0; a < ne; a++) {
+        int32_t k = P->conn[(int64_t)a * E + e];
+        dot += mu[k] * KT[a];
+        if (!is_dir[k])
+          g_c[e] += -lam[k] * (Tn1[k] - Tn[k]) / C[k] * P->rho[e] * P->V[e] / ne;
+      }
+      g_logk[e] += -dot;
+    }
+    for (int64_t f = 0; f < P->nf; f++) {
+      double share = P->farea[f] / P->nfn;
+      for (int b = 0; b < P->nfn; b++) {
+        int32_t k = P->faces[f * P->nfn + b];
+        g_h[f] += -mu[k] * share * (Tn[k] - P->fTa[f]);
+      }
+    }
+    /* lam <- lam - K mu - H mu (K symmetric) */
+    orc_loads(P, mu, Fe, F, C); /* F = K mu; C discarded */
+    for (int64_t k = 0; k < N; k++) lam[k] -= F[k];
+    for (int64_t f = 0; f < P->nf; f++) {
+      double share = P->farea[f] / P->nfn;
+      for (int b = 0; b < P->nfn; b++) {
+        int32_t k = P->faces[f * P->nfn + b];
+        lam[k] -= share * P->fh[f] * mu[k];
+      }
+    }
+    for (int64_t k = 0; k < N; k++)
+      if (is_dir[k]) lam[k] = 0.0;
+  }
+}

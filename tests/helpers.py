@@ -1,0 +1,50 @@
+"""Small problem builders shared by the tests (inputs only, no method math)."""
+from __future__ import annotations
+
+import numpy as np
+
+from workloads import mesh as M, problems as P
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def single_element(elem, X, mat=None):
+    """One element with node coordinates X (ne x 3)."""
+    ne = X.shape[0]
+    conn = np.arange(ne, dtype=np.int32)[:, None].copy()
+    m = dict(elem=elem, x=X[:, 0].copy(), y=X[:, 1].copy(), z=X[:, 2].copy(), conn=conn)
+    p = P._base(m, "single")
+    p["materials"] = [mat or P.material(rho=1.0, c0=1.0, k=[1.0])]
+    p["dt"] = 1e-9
+    return p
+
+
+def distorted_hex(seed=0, amp=0.15):
+    """A non-affine hexahedron: unit cube corners jittered."""
+    g = np.random.default_rng(seed)
+    X = (M.HEX_SIGNS.astype(float) + 1.0) / 2.0
+    return X + amp * g.uniform(-1, 1, size=X.shape)
+
+
+def random_tet(seed=0):
+    g = np.random.default_rng(seed)
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    return X + 0.2 * g.uniform(-1, 1, size=X.shape)
+
+
+def aniso_material(rho=1.0, c0=1.0):
+    return P.material(rho=rho, c0=c0, k=[3.0, 2.0, 1.5, 0.4, -0.3, 0.2])
+
+
+def D_of(mat, s=1.0):
+    k = mat["k"]
+    return s * np.array([[k[0], k[3], k[5]], [k[3], k[1], k[4]], [k[5], k[4], k[2]]])
+
+
+def box_problem(elem, n, side=1.0, mat=None, nsteps=1):
+    m = M.box_hex(n, n, n, side, side, side) if elem == "hex8" else \
+        M.box_tet_kuhn(n, n, n, side, side, side)
+    p = P._base(m, f"box_{elem}_{n}")
+    p["materials"] = [mat or P.material(rho=1000.0, c0=1000.0, k=[1.0])]
+    p["nsteps"] = nsteps
+    return p, m

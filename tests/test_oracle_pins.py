@@ -1,0 +1,467 @@
+"""Pins of the FP64 oracle against things other than itself: brute force on
+tiny inputs (finite differences of the interpolant, dense assembly), closed
+forms (1-D FTCS reduction, Fourier series, 7-point Laplacian, critical step),
+invariants (energy balance, constants, hourglass modes) and the paper's patch
+tests (Sec. 4.1, geometry of Fig. 2(c)).  CPU only."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from tests import helpers as H
+from workloads import mesh as M, problems as P
+
+SIG = 5.67e-8
+
+
+# ----------------------------------------------------------------------------
+# brute force: the element load from finite differences of the interpolant
+def _trilinear(V, xi):
+    N = np.prod(1.0 + M.HEX_SIGNS * np.asarray(xi), axis=1) / 8.0
+    return N @ V
+
+
+def hex_energy(X, T, D):
+    """8 det J(0) gradT(0)^T D gradT(0), with J and the natural gradient of T
+    at the centre taken by central differences of the trilinear interpolant
+    (exact for a trilinear map)."""
+    h = 0.25
+    J = np.zeros((3, 3))
+    gxi = np.zeros(3)
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        J[:, j] = (_trilinear(X, e) - _trilinear(X, -e)) / (2 * h)
+        gxi[j] = (_trilinear(T[:, None], e) - _trilinear(T[:, None], -e))[0] / (2 * h)
+    g = np.linalg.solve(J.T, gxi)
+    return 8.0 * np.linalg.det(J) * g @ D @ g
+
+
+def tet_energy(X, T, D):
+    """V gradT^T D gradT with the plane through the four values solved
+    directly and V from the determinant of the edge vectors."""
+    A = np.hstack([X, np.ones((4, 1))])
+    coef = np.linalg.solve(A, T)
+    g = coef[:3]
+    V = abs(np.linalg.det(X[1:] - X[0])) / 6.0
+    return V * g @ D @ g
+
+
+def fd_load(energy, X, T, D):
+    """F = d/dT (1/2 T^T K T): central differences of an exact quadratic."""
+    F = np.zeros(T.size)
+    for a in range(T.size):
+        d = np.zeros(T.size)
+        d[a] = 0.5
+        F[a] = (energy(X, T + d, D) - energy(X, T - d, D)) / (4 * 0.5)
+    return F
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("elem", ["hex8", "tet4"])
+def test_element_load_bruteforce(elem, seed):
+    mat = H.aniso_material()
+    X = H.distorted_hex(seed) if elem == "hex8" else H.random_tet(seed)
+    p = H.single_element(elem, X, mat)
+    o = Oracle(p)
+    T = np.random.default_rng(seed + 10).uniform(-5, 5, X.shape[0])
+    F, _ = o.loads(T)
+    energy = hex_energy if elem == "hex8" else tet_energy
+    D = H.D_of(mat)
+    Fb = fd_load(energy, X, T, D)
+    assert np.max(np.abs(F - Fb)) <= 1e-11 * np.max(np.abs(Fb))
+    # the quadratic form itself, and symmetry / constants in the null space
+    assert abs(T @ F - energy(X, T, D)) <= 1e-11 * abs(energy(X, T, D))
+    F1, _ = o.loads(np.full(X.shape[0], 3.7))
+    assert np.max(np.abs(F1)) < 1e-12
+
+
+def _dense_step(p, T, cfun, sfun, dt):
+    """One explicit step assembled densely from brute-force element matrices:
+    K_e from the polarised quadratic form, lumped capacity from independent
+    volumes, convection from face areas of the axis-aligned box."""
+    X = np.stack([p["x"], p["y"], p["z"]], axis=1)
+    N = X.shape[0]
+    conn = p["conn"]
+    ne = conn.shape[0]
+    energy = hex_energy if ne == 8 else tet_energy
+    mat = p["materials"][0]
+    K = np.zeros((N, N))
+    Cap = np.zeros(N)
+    for e in range(conn.shape[1]):
+        idx = conn[:, e]
+        Xe = X[idx]
+        D = H.D_of(mat, sfun(T[idx].mean()))
+        Ke = np.zeros((ne, ne))
+        for a in range(ne):
+            for b in range(ne):
+                ea, eb = np.eye(ne)[a], np.eye(ne)[b]
+                Ke[a, b] = (energy(Xe, ea + eb, D) - energy(Xe, ea - eb, D)) / 4.0
+        K[np.ix_(idx, idx)] += Ke
+        if ne == 8:
+            vol = np.prod(Xe.max(0) - Xe.min(0))
+        else:
+            vol = abs(np.linalg.det(Xe[1:] - Xe[0])) / 6.0
+        Cap[idx] += mat["rho"] * vol / ne * cfun(T[idx])
+    Q = np.zeros(N)
+    for f, fa in enumerate(p["faces"]):
+        Xf = X[fa]
+        if fa.size == 4:
+            area = np.linalg.norm(np.cross(Xf[1] - Xf[0], Xf[3] - Xf[0]))
+        else:
+            area = 0.5 * np.linalg.norm(np.cross(Xf[1] - Xf[0], Xf[2] - Xf[0]))
+        for k in fa:
+            Q[k] += area / fa.size * (-p["face_h"][f] * (T[k] - p["face_Ta"][f])
+                                      - SIG * p["face_eps"][f] * ((T[k] - p["Tz"]) ** 4
+                                                                   - (p["face_Ta"][f] - p["Tz"]) ** 4)
+                                      + p["face_q"][f])
+    return T + dt * (Q - K @ T) / Cap
+
+
+@pytest.mark.parametrize("elem", ["hex8", "tet4"])
+def test_one_step_dense(elem):
+    mat = P.material(rho=900.0, c0=800.0, c1=1.5, k=[3.0, 2.0, 1.5, 0.4, -0.3, 0.2],
+                     s0=1.0, s1=0.004)
+    p, m = H.box_problem(elem, 2, side=0.1, mat=mat)
+    faces, sides = M.box_side_faces(m)
+    P.set_faces(p, faces, h=np.where(sides % 2 == 0, 12.0, 7.0), Ta=15.0,
+                eps=np.where(sides == 5, 0.7, 0.0), q=np.where(sides == 4, 500.0, 0.0))
+    p["T0"] = np.random.default_rng(3).uniform(20, 60, m["x"].size)
+    p["T_lo"], p["T_hi"] = 0.0, 100.0
+    o = Oracle(p)
+    T1 = o.run(1)
+    ref = _dense_step(p, o.initial(), lambda T: 800.0 + 1.5 * T,
+                      lambda Tb: 1.0 + 0.004 * Tb, o.dt[0])
+    assert np.max(np.abs(T1 - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+# ----------------------------------------------------------------------------
+# geometry closed forms
+def test_areas_and_mass_totals():
+    for elem in ("hex8", "tet4"):
+        p, m = H.box_problem(elem, 3, side=0.2)
+        faces, _ = M.box_side_faces(m)
+        P.set_faces(p, faces)
+        o = Oracle(p)
+        assert abs(o.farea.sum() - 6 * 0.04) < 1e-15
+        assert abs(o.V.sum() - 0.008) < 1e-16
+        _, Cap = o.loads(np.zeros(o.N))
+        assert abs(Cap.sum() - 1000.0 * 1000.0 * 0.008) < 1e-8
+
+
+def test_patch_volumes():
+    """The 16-node patch of Fig. 2(c) tiles the unit cube: exact element
+    volumes add to 1 for both meshes.  For the distorted hexahedra the one-point
+    weight 8 det J(0) does not (the reason the mass uses the exact volume)."""
+    x, y, z = M.patch_nodes(os.path.join(H.GOLDEN, "patch_nodes.txt"))
+    for mesh in (M.patch_hex(x, y, z), M.patch_tet(x, y, z)):
+        p = P._base(mesh, "patch")
+        p["materials"] = [P.material(1.0, 1.0, [1.0])]
+        o = Oracle(p)
+        assert o.n_bad == 0
+        assert abs(o.V.sum() - 1.0) < 1e-13
+    oh = Oracle(dict(P._base(M.patch_hex(x, y, z), "ph"), materials=[P.material(1, 1, [1])]))
+    assert abs(oh.W.sum() - 1.0) > 1e-3
+    # mass conservation (Sec. 3.1): the lumped capacity of the distorted
+    # patch adds up to rho c times the cube's volume
+    ph = dict(P._base(M.patch_hex(x, y, z), "ph"), materials=[P.material(700.0, 900.0, [1])])
+    _, Cap = Oracle(ph).loads(np.zeros(16))
+    assert abs(Cap.sum() - 700.0 * 900.0) < 1e-9
+
+
+# ----------------------------------------------------------------------------
+# patch tests (Sec. 4.1): a linear field imposed on the boundary is reproduced
+def _relax(o, T, tol=1e-12, chunk=2000, maxit=200):
+    for _ in range(maxit):
+        Tn = o.run(chunk, T0=T, apply_initial=False)
+        if np.max(np.abs(Tn - T)) < tol:
+            return Tn
+        T = Tn
+    return T
+
+
+def _linear_patch(p, bnodes, lin):
+    p["dir_nodes"] = bnodes.astype(np.int32)
+    p["dir_T"] = lin[bnodes]
+    p["T0"] = np.zeros(lin.size)
+    o = Oracle(p)
+    return o, _relax(o, o.initial())
+
+
+def test_patch_tet_paper_geometry():
+    x, y, z = M.patch_nodes(os.path.join(H.GOLDEN, "patch_nodes.txt"))
+    mesh = M.patch_tet(x, y, z)
+    p = P._base(mesh, "patch_tet")
+    p["materials"] = [P.material(1.0, 1.0, [1.0])]
+    lin = 200 * x + 100 * y + 200 * z          # the field of Sec. 4.1
+    o, T = _linear_patch(p, np.arange(8), lin)
+    assert np.max(np.abs(T - lin)) < 1e-9
+
+
+@pytest.mark.parametrize("elem", ["hex8", "tet4"])
+def test_patch_anisotropic_affine_grid(elem):
+    """Linear fields solve div(D grad T) = 0 for any constant D, so both
+    element types must reproduce them on an affinely mapped grid."""
+    n = 3
+    m = M.box_hex(n, n, n) if elem == "hex8" else M.box_tet_kuhn(n, n, n)
+    A = np.array([[1.0, 0.3, 0.1], [0.0, 0.9, 0.2], [0.1, 0.0, 1.1]])
+    X = np.stack([m["x"], m["y"], m["z"]], 1) @ A.T
+    m = dict(m, x=X[:, 0].copy(), y=X[:, 1].copy(), z=X[:, 2].copy())
+    p = P._base(m, "affine")
+    p["materials"] = [H.aniso_material()]
+    lin = 200 * m["x"] + 100 * m["y"] + 200 * m["z"] + 7.0
+    o, T = _linear_patch(p, M.boundary_nodes(m), lin)
+    assert np.max(np.abs(T - lin)) < 1e-8
+
+
+def test_patch_distorted_hex_known_result():
+    """Recorded known result: with the literal one-point centre-B hexahedron
+    (Eq. 17) the distorted 7-element patch does NOT reproduce the linear field
+    exactly: the interior rows of K T_lin are not zero."""
+    x, y, z = M.patch_nodes(os.path.join(H.GOLDEN, "patch_nodes.txt"))
+    p = P._base(M.patch_hex(x, y, z), "patch_hex")
+    p["materials"] = [P.material(1.0, 1.0, [1.0])]
+    o = Oracle(p)
+    lin = 200 * x + 100 * y + 200 * z
+    F, _ = o.loads(lin)
+    assert np.max(np.abs(F[8:])) > 1.0
+
+
+# ----------------------------------------------------------------------------
+# workload 1 reduces to 1-D FTCS at every step (exact identity)
+def test_cube_plain_equals_ftcs():
+    p = P.cube_plain(10, 1000)
+    o = Oracle(p)
+    assert abs(o.dt_crit - 5000.0) < 1e-9          # rho c h^2 / (2 k)
+    hist = o.run(1000, history=True)
+    r = o.dt[0] * 1.0 / (1000.0 * 1000.0) / 0.01
+    u = np.zeros(11)
+    u[10] = 100.0
+    lev = np.rint(p["z"] * 10).astype(int)
+    worst = 0.0
+    for n in range(1, 1001):
+        un = u.copy()
+        un[0] = u[0] + r * 2 * (u[1] - u[0])      # insulated: mirror node
+        un[1:10] = u[1:10] + r * (u[:9] - 2 * u[1:10] + u[2:11])
+        u = un
+        if n in (1, 10, 100, 1000):
+            worst = max(worst, np.max(np.abs(hist[n] - u[lev])))
+    assert worst < 1e-11
+
+
+def fourier(z, at, terms=400):
+    m = np.arange(terms)[:, None]
+    lam = (2 * m + 1) * np.pi / 2
+    s = ((-1.0) ** m / (2 * m + 1)) * np.cos(lam * z[None, :]) * np.exp(-lam ** 2 * at)
+    return 100.0 - (400.0 / np.pi) * s.sum(0)
+
+
+def test_fourier_convergence():
+    """Continuum check: T = 100 - (400/pi) sum (-1)^m/(2m+1) cos(..) exp(..)
+    at alpha t = 0.45 with r = 0.45 fixed; the error falls ~4x per halving."""
+    errs = []
+    for n in (10, 20, 40):
+        m = M.box_hex(1, 1, n, 1.0 / n, 1.0 / n, 1.0)
+        p = P._base(m, "col")
+        p["materials"] = [P.material(1000.0, 1000.0, [1.0])]
+        top = np.nonzero(np.isclose(m["z"], 1.0))[0].astype(np.int32)
+        p["dir_nodes"], p["dir_T"] = top, np.full(top.size, 100.0)
+        o = Oracle(p)
+        steps = n * n                               # alpha t = steps r h^2 = 0.45
+        T = o.run(steps)
+        alpha_t = steps * o.dt[0] * 1e-6
+        assert abs(alpha_t - 0.45) < 1e-12
+        errs.append(np.max(np.abs(T - fourier(m["z"], alpha_t))))
+    assert errs[0] < 0.3
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+# ----------------------------------------------------------------------------
+# invariants
+def test_energy_balance_nonlinear():
+    """Insulated, nonlinear c(T) and D(T), point sources: the heat stored in a
+    step, sum_k C_k(T^n) (T^{n+1}_k - T^n_k), equals dt * sum of the inputs."""
+    mat = P.material(rho=1000.0, c0=1000.0, c1=2.0, k=[1.0, 2.0, 0.5], s0=1.0, s1=0.005)
+    for elem in ("hex8", "tet4"):
+        p, m = H.box_problem(elem, 4, side=0.1, mat=mat)
+        g = np.random.default_rng(5)
+        p["T0"] = g.uniform(20, 80, m["x"].size)
+        p["pt_nodes"] = np.array([3, 17, 40], np.int32)
+        p["pt_W"] = np.array([2.0, 1.0, 0.5])
+        p["T_lo"], p["T_hi"] = 0.0, 200.0
+        o = Oracle(p)
+        T0 = o.initial()
+        T1 = o.run(1)
+        n_inc = np.bincount(m["conn"].ravel(), minlength=m["x"].size)
+        vol = 0.1 ** 3 / m["conn"].shape[1]
+        Cap = 1000.0 * vol / m["conn"].shape[0] * n_inc * (1000.0 + 2.0 * T0)
+        stored = np.sum(Cap * (T1 - T0))
+        assert abs(stored - o.dt[0] * 3.5) < 1e-10 * abs(stored)
+
+
+def test_constant_field_is_fixed_point():
+    mat = P.material(rho=1000.0, c0=1000.0, c1=2.0, k=[1.0, 2.0, 0.5], s0=1.0, s1=0.005)
+    for elem in ("hex8", "tet4"):
+        p, m = H.box_problem(elem, 3, side=0.1, mat=mat)
+        p["T0"] = np.full(m["x"].size, 42.0)
+        p["T_lo"], p["T_hi"] = 0.0, 100.0
+        T1 = Oracle(p).run(3)
+        assert np.max(np.abs(T1 - 42.0)) < 1e-11
+
+
+def test_hourglass_mode_is_fixed_point():
+    """(-1)^(i+j+k) has zero centre gradient in every hexahedron (Eq. 17
+    integrates at the centre only), so it is not damped at all."""
+    p, m = H.box_problem("hex8", 4, side=1.0)
+    n = 4
+    k, j, i = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    p["T0"] = ((-1.0) ** (i + j + k)).ravel() * 5.0
+    T1 = Oracle(p).run(5)
+    assert np.max(np.abs(T1 - p["T0"])) < 1e-12
+
+
+def test_kuhn_tets_give_seven_point_laplacian():
+    """Isotropic Kuhn tetrahedra on a regular grid: every interior row of K is
+    k h (6, -1 x 6) and the lumped mass is rho c h^3, i.e. one explicit step
+    is the 7-point finite-difference Laplacian update."""
+    n, side = 4, 0.4
+    h = side / n
+    p, m = H.box_problem("tet4", n, side=side, mat=P.material(1000.0, 1000.0, [2.0]))
+    g = np.random.default_rng(9)
+    T = g.uniform(0, 10, m["x"].size)
+    p["T0"] = T
+    o = Oracle(p)
+    T1 = o.run(1)
+    Tg = T.reshape(n + 1, n + 1, n + 1)
+    lap = (Tg[2:, 1:-1, 1:-1] + Tg[:-2, 1:-1, 1:-1] + Tg[1:-1, 2:, 1:-1] + Tg[1:-1, :-2, 1:-1]
+           + Tg[1:-1, 1:-1, 2:] + Tg[1:-1, 1:-1, :-2] - 6 * Tg[1:-1, 1:-1, 1:-1])
+    expect = Tg[1:-1, 1:-1, 1:-1] + o.dt[0] * 2.0 * h * lap / (1000.0 * 1000.0 * h ** 3)
+    got = T1.reshape(n + 1, n + 1, n + 1)[1:-1, 1:-1, 1:-1]
+    assert np.max(np.abs(got - expect)) < 1e-12
+
+
+def test_critical_step_is_sharp():
+    """Eq. 29: the x-checkerboard is the fastest mode of the one-point
+    hexahedral grid; 1.01 dt_crit amplifies it, 0.99 dt_crit damps it."""
+    n = 8
+    amps = []
+    for f in (0.99, 1.01):
+        p, m = H.box_problem("hex8", n, side=1.0)
+        p["T0"] = ((-1.0) ** np.rint(m["x"] * n)) * 1.0
+        o = Oracle(p)
+        p["dt"] = f * o.dt_crit
+        o = Oracle(p)
+        amps.append(np.max(np.abs(o.run(400))))
+    assert amps[0] < 0.5 and amps[1] > 2.0
+
+
+def test_single_hex_boundary_recursion():
+    """One hexahedron with convection and radiation on all faces and a uniform
+    temperature: F = 0, every node carries area 3 a^2 / 4 and capacity
+    rho c a^3 / 8, so all nodes follow the scalar explicit-Euler recursion."""
+    a, h, eps, Ta, rho, c = 0.05, 25.0, 0.6, 10.0, 2000.0, 500.0
+    m = M.box_hex(1, 1, 1, a, a, a)
+    p = P._base(m, "one")
+    p["materials"] = [P.material(rho, c, [5.0])]
+    faces, _ = M.box_side_faces(m)
+    P.set_faces(p, faces, h=h, Ta=Ta, eps=eps)
+    p["T0"] = np.full(8, 300.0)
+    p["T_lo"], p["T_hi"] = 0.0, 300.0
+    o = Oracle(p)
+    T = 300.0
+    A, Cap = 3 * a * a / 4, rho * c * a ** 3 / 8
+    for _ in range(50):
+        T = T + o.dt[0] / Cap * A * (-h * (T - Ta) - SIG * eps * ((T + 273.15) ** 4 - (Ta + 273.15) ** 4))
+    assert np.max(np.abs(o.run(50) - T)) < 1e-11 * T
+
+
+# ----------------------------------------------------------------------------
+# adjoint
+def _adjoint_problem():
+    n = 4
+    p, m = H.box_problem("hex8", n, side=0.1, mat=P.material(1000.0, 1000.0, [1.0]))
+    g = np.random.default_rng(11)
+    p["elem_kscale"] = np.exp(0.5 * g.standard_normal(n ** 3))
+    faces, sides = M.box_side_faces(m)
+    P.set_faces(p, faces[sides != 0], h=15.0, Ta=20.0)
+    bottom = np.nonzero(np.isclose(m["x"], 0.0))[0].astype(np.int32)
+    p["dir_nodes"], p["dir_T"] = bottom, np.full(bottom.size, 50.0)
+    p["T0"] = g.uniform(80, 100, m["x"].size)
+    p["dt"] = 2.0
+    return p, m
+
+
+def _loss(p, sens, target, nsteps):
+    T = Oracle(p).run(nsteps)
+    return 0.5 * np.sum((T[sens] - target) ** 2), T
+
+
+def test_adjoint_matches_finite_differences():
+    p, m = _adjoint_problem()
+    nsteps = 30
+    sens = np.array([5, 40, 77, 100, 120])
+    target = np.full(sens.size, 60.0)
+    o = Oracle(p)
+    hist = o.run(nsteps, history=True)
+    lam = np.zeros(o.N)
+    lam[sens] = hist[-1][sens] - target
+    g = o.adjoint_linear(hist, lam)
+    eps = 1e-4
+    theta = np.log(p["elem_kscale"])
+    for e in (0, 13, 37, 63):
+        th = theta.copy()
+        th[e] += eps
+        Lp, _ = _loss(dict(p, elem_kscale=np.exp(th)), sens, target, nsteps)
+        th[e] -= 2 * eps
+        Lm, _ = _loss(dict(p, elem_kscale=np.exp(th)), sens, target, nsteps)
+        fd = (Lp - Lm) / (2 * eps)
+        assert abs(fd - g["g_logk"][e]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g["g_logk"]).max())
+    # heat capacity (per element, via per-element materials) and h (per face),
+    # each at the entry with the largest gradient so the differences are not
+    # lost in the rounding of the loss
+    eps = 1e-3
+    e = int(np.argmax(np.abs(g["g_c"])))
+    mats = [P.material(1000.0, 1000.0, [1.0]) for _ in range(o.E)]
+    base = dict(p, materials=mats, elem_material=np.arange(o.E, dtype=np.int32))
+    Ls = []
+    for d in (eps, -eps):
+        mm = [dict(x) for x in mats]
+        mm[e]["c0"] = 1000.0 * (1 + d)
+        Ls.append(_loss(dict(base, materials=mm), sens, target, nsteps)[0])
+    fd_c = (Ls[0] - Ls[1]) / (2 * eps * 1000.0)
+    assert abs(fd_c - g["g_c"][e]) <= 1e-6 * abs(fd_c)
+    f = int(np.argmax(np.abs(g["g_h"])))
+    Ls = []
+    for d in (eps, -eps):
+        hh = p["face_h"].copy()
+        hh[f] *= (1 + d)
+        Ls.append(_loss(dict(p, face_h=hh), sens, target, nsteps)[0])
+    fd_h = (Ls[0] - Ls[1]) / (2 * eps * 15.0)
+    assert abs(fd_h - g["g_h"][f]) <= 1e-6 * abs(fd_h)
+
+
+def test_adjoint_transpose_identity():
+    """<w, J v> = <J^T w, v> for the one-step Jacobian J (the step is affine
+    in T for a T-independent problem, so J v is a difference of two steps)."""
+    p, m = _adjoint_problem()
+    o = Oracle(p)
+    g = np.random.default_rng(4)
+    T = o.initial()
+    v = g.standard_normal(o.N)
+    v[o.dir_nodes] = 0.0
+    w = g.standard_normal(o.N)
+    Jv = o.run(1, T0=T + v, apply_initial=False) - o.run(1, T0=T, apply_initial=False)
+    hist = o.run(1, T0=T, apply_initial=False, history=True)
+    JTw = o.adjoint_linear(hist, w)["lam0"]
+    assert abs(w @ Jv - JTw @ v) < 1e-12 * abs(w @ Jv)
+
+
+def test_error_norms():
+    a = np.array([1.0, 2.0, -4.0])
+    b = np.array([1.0, 2.5, -4.0])
+    assert oracle.err_max(b, a) == 0.5 / 4.0
+    assert abs(oracle.err_rms(b, a) - np.sqrt(0.25 / 21.0)) < 1e-16
