@@ -1,0 +1,192 @@
+/*
+ * fedfem.h - C ABI of the MI355X (gfx950) library for the fast explicit
+ * dynamics finite element algorithm (FED-FEM) for transient heat transfer of
+ * Zhang & Chauhan (arXiv 1909.03355).
+ *
+ * The library runs the paper's per-time-step hot path on one GPU:
+ *   element thermal loads from precomputed geometry and a temperature-
+ *   dependent (isotropic, orthotropic or anisotropic) conductivity (Sec. 3.2,
+ *   Eq. 17-20), summed at the nodes without a global stiffness matrix
+ *   (Sec. 3.1, Eq. 10-12), convection / radiation / flux surface loads
+ *   (Sec. 2, Eq. 4, 5, 7) and the explicit update with a lumped capacity
+ *   (Sec. 3.1, Eq. 13-16), plus the pre-computation stage of Sec. 3.5 (i) and
+ *   the stability bound of Sec. 3.4.
+ *
+ * Conventions for every function:
+ *   - Return value: FED_OK (0) or a negative fed_status.  The message of the
+ *     last error on the calling thread is returned by fed_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Host arrays passed in are copied before the call returns; the caller
+ *     keeps ownership.  Device arrays are hipMalloc'ed device pointers owned
+ *     by the caller unless stated otherwise.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued asynchronously on it; only functions documented as
+ *     synchronising wait for it.
+ *   - Node and element numbering is the caller's (0-based) everywhere; the
+ *     library's internal (tiled) order never leaks out.
+ *   - Temperatures are in degrees Celsius, lengths in metres, SI otherwise.
+ */
+#ifndef FEDFEM_H
+#define FEDFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FED_OK = 0,
+  FED_E_ARG = -1,      /* invalid argument (sizes, indices, null pointers, values) */
+  FED_E_MESH = -2,     /* inverted or degenerate element, or unusable topology */
+  FED_E_UNSTABLE = -3, /* dt above the stability bound, or the health check fired */
+  FED_E_HIP = -4,      /* a HIP runtime call failed */
+  FED_E_STATE = -5,    /* call made in the wrong state (e.g. step before set_temperature) */
+  FED_E_NOMEM = -6     /* device or host allocation failed */
+} fed_status;
+
+enum { FED_TET4 = 4, FED_HEX8 = 8 };
+
+/* Arithmetic of the time stepping.  Pre-computation is always FP64. */
+enum {
+  FED_FP32C = 0, /* FP32 loads and updates, nodal temperatures kept as a compensated
+                    (hi, lo) FP32 pair so that thousands of small increments do not
+                    round away */
+  FED_FP64 = 1,  /* FP64 throughout */
+  FED_FP32 = 2   /* plain FP32 (no compensation), for error comparisons */
+};
+
+/* Mesh (Sec. 3.5 (i).1).  conn is structure-of-arrays: conn[a*n_elems + e] is the
+ * node of local node a of element e.  Hexahedron local order in natural
+ * coordinates (xi, eta, zeta): (---)(+--)(++-)(-+-)(--+)(+-+)(+++)(-++), and it
+ * must give a positive Jacobian determinant at the centre.  Tetrahedra may have
+ * either orientation. */
+typedef struct {
+  int32_t elem; /* FED_HEX8 or FED_TET4 */
+  int64_t n_nodes, n_elems;
+  const double *x, *y, *z; /* host, n_nodes each */
+  const int32_t *conn;     /* host, elem * n_elems */
+} fed_mesh;
+
+/* Material (Sec. 2, Eq. 1): density rho, heat capacity c(T) = c0 + c1 T and
+ * conductivity D(T) = k * (s0 + s1 T) with k the symmetric tensor
+ * [xx, yy, zz, xy, yz, xz].  Orthotropic: zero off-diagonals; isotropic: equal
+ * diagonals.  D is evaluated at the element's mean nodal temperature and c at the
+ * node (Sec. 4.2.2).  s0 and s1 must be the same for every material. */
+typedef struct {
+  double rho, c0, c1;
+  double k[6];
+  double s0, s1;
+} fed_material;
+
+typedef struct {
+  int32_t n_materials;
+  const fed_material *materials;   /* host, n_materials */
+  const int32_t *elem_material;    /* host, n_elems material ids, or NULL (all 0) */
+  const double *elem_k;            /* host, 6 * n_elems per-element k tensor (rows of
+                                      length n_elems) replacing the material's, or NULL */
+  const double *elem_kscale;       /* host, n_elems positive factors on D, or NULL */
+} fed_materials;
+
+/* Boundary conditions (Sec. 2, Eq. 3-7).  Faces are lumped to their nodes with
+ * area |f| / face_nodes each.  Heat into a node from face f is
+ *   |f|/n_f * ( -h (T - Ta) - sigma eps ((T - Tz)^4 - (Ta - Tz)^4) + q ),
+ * sigma = 5.67e-8.  Faces with eps > 0 that share a node must share Ta.
+ * Dirichlet nodes hold dir_T from fed_set_temperature on. */
+typedef struct {
+  int64_t n_dir;
+  const int32_t *dir_nodes; /* host */
+  const double *dir_T;      /* host */
+  int64_t n_faces;
+  int32_t face_nodes;       /* 3 (triangle) or 4 (bilinear quad) */
+  const int32_t *faces;     /* host, faces[f*face_nodes + b] */
+  const double *face_h, *face_Ta, *face_eps, *face_q; /* host, n_faces each; NULL = 0 */
+  int64_t n_pt;
+  const int32_t *pt_nodes;  /* host, concentrated heat inputs (W) */
+  const double *pt_W;
+  double Tz;                /* absolute zero in Celsius, normally -273.15 */
+} fed_bcs;
+
+typedef struct {
+  int32_t prec;              /* FED_FP32C, FED_FP64 or FED_FP32 */
+  double dt;                 /* > 0: fixed time step; 0: safety * dt_crit */
+  double safety;             /* used when dt == 0 (e.g. 0.9) */
+  double T_lo, T_hi;         /* temperature range over which dt_crit is bounded and
+                                which the health check watches */
+  int32_t allow_unstable;    /* 1: accept dt > dt_crit */
+  const int32_t *node_instance; /* host, n_nodes instance ids of a batched mesh of
+                                   independent instances (one dt per instance), or NULL */
+  int32_t tile_nodes;        /* owned nodes per tile; 0 = default */
+  int32_t block_threads;     /* threads per tile workgroup (64..1024); 0 = default */
+} fed_options;
+
+typedef struct fed_ctx fed_ctx;
+
+/* Sizes and per-step traffic of a context (for reporting). */
+typedef struct {
+  int64_t n_nodes, n_elems, n_instances;
+  int64_t n_tiles, n_elems_expanded, n_halo, n_bnd_nodes;
+  int32_t elem, prec, block_threads, lds_bytes;
+  double algorithmic_bytes_per_step; /* unique bytes one step must move (see DESIGN) */
+  double moved_bytes_per_step;       /* bytes requested including tile halo redundancy */
+} fed_info;
+
+/*
+ * Pre-computation stage (Sec. 3.5 (i)): validates the inputs on the host, builds
+ * the tiles, then on the GPU in FP64 computes per element det J, B, G (Eq. 17-19)
+ * folded into one symmetric 3x3 operator, the lumped capacity (Eq. 14, 21), the
+ * per-node surface coefficients and the stability bound dt_crit (Sec. 3.4, Eq. 29;
+ * element-eigenvalue bound).  Synchronises `stream`.  On success *out owns all
+ * device memory of the context until fed_destroy.
+ * Errors: FED_E_ARG (bad sizes/indices/values), FED_E_MESH (det J <= 0 at a hex
+ * centre, zero-volume tet, node incidence too high), FED_E_UNSTABLE (dt > dt_crit
+ * without allow_unstable), FED_E_HIP, FED_E_NOMEM.
+ */
+int fed_create(const fed_mesh *mesh, const fed_materials *mats, const fed_bcs *bcs,
+               const fed_options *opt, void *stream, fed_ctx **out);
+
+/* Stability bound and the time step in use, per instance (n = number of entries
+ * the arrays can hold; the count is fed_info.n_instances). */
+int fed_dt(const fed_ctx *ctx, double *dt_crit, double *dt_used, int64_t n);
+
+int fed_info_get(const fed_ctx *ctx, fed_info *out);
+
+/* Initialisation stage (Sec. 3.5 (ii)): sets T (n_nodes FP64, caller order) and
+ * applies the essential condition (Eq. 3).  T is a host pointer if on_device == 0,
+ * else a device pointer.  Resets the step counter. */
+int fed_set_temperature(fed_ctx *ctx, const double *T, int32_t on_device, void *stream);
+
+/* Time-stepping stage (Sec. 3.5 (iii)): enqueues nsteps explicit steps, each one
+ * kernel launch that computes every element load, sums them per node in a fixed
+ * order, adds the surface loads and updates T (Eq. 16), keeping Dirichlet nodes
+ * fixed.  Asynchronous.  FED_E_STATE before fed_set_temperature. */
+int fed_step(fed_ctx *ctx, int64_t nsteps, void *stream);
+
+/* Same as fed_step, but replays a captured HIP graph of `graph_steps` launches
+ * (0 = default) for the bulk of the steps. */
+int fed_step_graph(fed_ctx *ctx, int64_t nsteps, int32_t graph_steps, void *stream);
+
+/* Copies the current temperatures (FP64, caller order; FP32C returns hi + lo) to
+ * T (host if on_device == 0).  Synchronises `stream`, then runs the health check
+ * (all temperatures finite and within [T_lo - w, T_hi + w], w = T_hi - T_lo);
+ * returns FED_E_UNSTABLE if it fired. */
+int fed_get_temperature(fed_ctx *ctx, double *T, int32_t on_device, void *stream);
+
+/* Number of steps taken since fed_set_temperature. */
+int fed_steps_taken(const fed_ctx *ctx, int64_t *steps);
+
+/* Exact state save/restore (hi and lo arrays of n_nodes values of the working
+ * precision: float for FP32C/FP32, double for FP64; lo is ignored except for
+ * FP32C), caller order, host memory.  Synchronises `stream`. */
+int fed_get_state(fed_ctx *ctx, void *hi, void *lo, int64_t *step, void *stream);
+int fed_set_state(fed_ctx *ctx, const void *hi, const void *lo, int64_t step, void *stream);
+
+/* Destroys the context and frees its device memory (synchronises the device). */
+void fed_destroy(fed_ctx *ctx);
+
+const char *fed_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEDFEM_H */

@@ -1,0 +1,702 @@
+// C ABI of the FED-FEM library (see include/fedfem.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fedfem.h"
+#include "fed_internal.h"
+#include "fed_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(FED_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),  \
+                  __FILE__, __LINE__);                                                \
+  } while (0)
+
+// device allocations of a context, freed together
+struct DevPool {
+  std::vector<void *> ptrs;
+  hipError_t alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+  void release(void *p) {
+    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    if (it != ptrs.end()) {
+      (void)hipFree(p);
+      ptrs.erase(it);
+    }
+  }
+  void free_all() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+}  // namespace
+
+struct fed_ctx {
+  int prec = 0, ne = 8, rb = 4;
+  int64_t N = 0, E = 0, Eexp = 0, nrec = 0, ninst = 1, ndir = 0;
+  fed::Tiling til;
+  DevPool pool;
+  // step working set
+  fed::TileHdr *d_tiles = nullptr;
+  uint16_t *d_ent = nullptr;
+  int32_t *d_halo = nullptr, *d_perm = nullptr, *d_eorig = nullptr;
+  void *d_H = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
+  void *d_rA = nullptr, *d_rAT = nullptr, *d_reA = nullptr, *d_rTa = nullptr, *d_rP = nullptr;
+  void *d_T[2] = {nullptr, nullptr};
+  float *d_lo[2] = {nullptr, nullptr};
+  int32_t *d_dir_node = nullptr;
+  double *d_dir_T = nullptr;
+  int *d_flag = nullptr;
+  double *d_Tuser = nullptr;  // FP64 staging in caller order
+  // kept FP64 pre-computation
+  double *d_H0 = nullptr, *d_kscale = nullptr, *d_V = nullptr;
+  double *d_M0 = nullptr, *d_M1 = nullptr;
+  // scalars
+  double s0 = 1, s1 = 0, Tz = -273.15, T_lo = 0, T_hi = 0;
+  int tdk = 0, tdc = 0, block = 256, nper = 1;
+  std::vector<double> dt_crit, dt_used;
+  int cur = 0;
+  int64_t steps = 0;
+  bool have_T = false;
+  // graph of captured steps
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
+  int gsteps = 0, gparity = -1;
+  fed_info info{};
+
+  fed::StepArgs step_args(int parity) const {
+    fed::StepArgs a{};
+    a.prec = prec;
+    a.ne = ne;
+    a.tdk = tdk;
+    a.tdc = tdc;
+    a.nt = til.nt;
+    a.nper = nper;
+    a.block = block;
+    a.lds = til.lds_bytes;
+    a.pb = til.pb;
+    a.maxinc = til.maxinc;
+    a.Eexp = Eexp;
+    a.tiles = d_tiles;
+    a.ent = d_ent;
+    a.halo = d_halo;
+    a.H = d_H;
+    a.Tin = d_T[parity];
+    a.Tout = d_T[1 - parity];
+    a.loin = d_lo[parity];
+    a.loout = d_lo[1 - parity];
+    a.alpha = d_alpha;
+    a.beta = d_beta;
+    a.rA = d_rA;
+    a.rAT = d_rAT;
+    a.reA = d_reA;
+    a.rTa = d_rTa;
+    a.rP = d_rP;
+    a.s0 = s0;
+    a.s1 = s1;
+    a.Tz = Tz;
+    return a;
+  }
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    gsteps = 0;
+    gparity = -1;
+  }
+
+  ~fed_ctx() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    pool.free_all();
+  }
+};
+
+namespace {
+
+template <typename T>
+hipError_t upload(DevPool &pool, T **d, const T *h, size_t n) {
+  hipError_t e = pool.alloc((void **)d, n * sizeof(T));
+  if (e != hipSuccess || n == 0) return e;
+  return hipMemcpy(*d, h, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, const fed_options *o) {
+  if (!m || !mt || !bc || !o) return fail(FED_E_ARG, "null argument");
+  if (m->elem != FED_HEX8 && m->elem != FED_TET4) return fail(FED_E_ARG, "elem must be 4 or 8");
+  if (m->n_nodes <= 0 || m->n_elems <= 0) return fail(FED_E_ARG, "empty mesh");
+  if (m->n_nodes >= (1LL << 31) || m->n_elems >= (1LL << 31))
+    return fail(FED_E_ARG, "mesh too large for 32-bit ids");
+  if (!m->x || !m->y || !m->z || !m->conn) return fail(FED_E_ARG, "null mesh array");
+  for (int64_t k = 0; k < m->n_nodes; k++)
+    if (!finite(m->x[k]) || !finite(m->y[k]) || !finite(m->z[k]))
+      return fail(FED_E_ARG, "non-finite coordinate at node %lld", (long long)k);
+  const int64_t nc = (int64_t)m->elem * m->n_elems;
+  for (int64_t i = 0; i < nc; i++)
+    if (m->conn[i] < 0 || m->conn[i] >= m->n_nodes)
+      return fail(FED_E_ARG, "connectivity entry %lld out of range", (long long)i);
+  if (mt->n_materials < 1 || !mt->materials) return fail(FED_E_ARG, "no materials");
+  for (int i = 0; i < mt->n_materials; i++) {
+    const fed_material &q = mt->materials[i];
+    if (!(q.rho > 0) || !finite(q.c0) || !finite(q.c1) || !finite(q.s0) || !finite(q.s1))
+      return fail(FED_E_ARG, "material %d: rho must be positive and values finite", i);
+    for (int r = 0; r < 6; r++)
+      if (!finite(q.k[r])) return fail(FED_E_ARG, "material %d: non-finite k", i);
+    if (q.s0 != mt->materials[0].s0 || q.s1 != mt->materials[0].s1)
+      return fail(FED_E_ARG, "all materials must share s0 and s1");
+    double clo = q.c0 + q.c1 * o->T_lo, chi = q.c0 + q.c1 * o->T_hi;
+    double slo = q.s0 + q.s1 * o->T_lo, shi = q.s0 + q.s1 * o->T_hi;
+    if (!(clo > 0 && chi > 0)) return fail(FED_E_ARG, "material %d: c(T) not positive on [T_lo, T_hi]", i);
+    if (!(slo > 0 && shi > 0)) return fail(FED_E_ARG, "material %d: D(T) not positive on [T_lo, T_hi]", i);
+  }
+  if (mt->elem_material)
+    for (int64_t e = 0; e < m->n_elems; e++)
+      if (mt->elem_material[e] < 0 || mt->elem_material[e] >= mt->n_materials)
+        return fail(FED_E_ARG, "elem_material[%lld] out of range", (long long)e);
+  if (mt->elem_kscale)
+    for (int64_t e = 0; e < m->n_elems; e++)
+      if (!(mt->elem_kscale[e] > 0) || !finite(mt->elem_kscale[e]))
+        return fail(FED_E_ARG, "elem_kscale[%lld] must be positive and finite", (long long)e);
+  if (mt->elem_k)
+    for (int64_t i = 0; i < 6 * m->n_elems; i++)
+      if (!finite(mt->elem_k[i])) return fail(FED_E_ARG, "non-finite elem_k");
+  if (bc->n_dir < 0 || (bc->n_dir > 0 && (!bc->dir_nodes || !bc->dir_T)))
+    return fail(FED_E_ARG, "bad Dirichlet arrays");
+  for (int64_t i = 0; i < bc->n_dir; i++)
+    if (bc->dir_nodes[i] < 0 || bc->dir_nodes[i] >= m->n_nodes || !finite(bc->dir_T[i]))
+      return fail(FED_E_ARG, "Dirichlet entry %lld invalid", (long long)i);
+  if (bc->n_faces < 0) return fail(FED_E_ARG, "n_faces < 0");
+  if (bc->n_faces > 0) {
+    if (bc->face_nodes != 3 && bc->face_nodes != 4) return fail(FED_E_ARG, "face_nodes must be 3 or 4");
+    if (!bc->faces) return fail(FED_E_ARG, "null faces");
+    for (int64_t i = 0; i < bc->n_faces * bc->face_nodes; i++)
+      if (bc->faces[i] < 0 || bc->faces[i] >= m->n_nodes)
+        return fail(FED_E_ARG, "face entry %lld out of range", (long long)i);
+    for (int64_t f = 0; f < bc->n_faces; f++) {
+      if (bc->face_h && !(bc->face_h[f] >= 0 && finite(bc->face_h[f])))
+        return fail(FED_E_ARG, "face_h[%lld] must be >= 0", (long long)f);
+      if (bc->face_eps && !(bc->face_eps[f] >= 0 && bc->face_eps[f] <= 1))
+        return fail(FED_E_ARG, "face_eps[%lld] must be in [0, 1]", (long long)f);
+      if (bc->face_Ta && !finite(bc->face_Ta[f])) return fail(FED_E_ARG, "non-finite face_Ta");
+      if (bc->face_q && !finite(bc->face_q[f])) return fail(FED_E_ARG, "non-finite face_q");
+    }
+  }
+  if (bc->n_pt < 0 || (bc->n_pt > 0 && (!bc->pt_nodes || !bc->pt_W)))
+    return fail(FED_E_ARG, "bad point-load arrays");
+  for (int64_t i = 0; i < bc->n_pt; i++)
+    if (bc->pt_nodes[i] < 0 || bc->pt_nodes[i] >= m->n_nodes || !finite(bc->pt_W[i]))
+      return fail(FED_E_ARG, "point load %lld invalid", (long long)i);
+  if (!finite(bc->Tz)) return fail(FED_E_ARG, "non-finite Tz");
+  if (o->prec != FED_FP32C && o->prec != FED_FP64 && o->prec != FED_FP32)
+    return fail(FED_E_ARG, "unknown precision %d", o->prec);
+  if (!(o->dt >= 0) || !finite(o->dt)) return fail(FED_E_ARG, "dt must be >= 0");
+  if (o->dt == 0 && !(o->safety > 0)) return fail(FED_E_ARG, "safety must be > 0 when dt == 0");
+  if (!(o->T_hi > o->T_lo)) return fail(FED_E_ARG, "need T_lo < T_hi");
+  if (o->node_instance)
+    for (int64_t k = 0; k < m->n_nodes; k++)
+      if (o->node_instance[k] < 0 || o->node_instance[k] >= m->n_nodes)
+        return fail(FED_E_ARG, "node_instance[%lld] out of range", (long long)k);
+  if (o->tile_nodes < 0) return fail(FED_E_ARG, "tile_nodes < 0");
+  if (o->block_threads != 0 &&
+      (o->block_threads < 64 || o->block_threads > 1024 || o->block_threads % 64))
+    return fail(FED_E_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
+  return FED_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fed_last_error(void) { return g_err.c_str(); }
+
+int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
+               const fed_options *o, void *stream, fed_ctx **out) {
+  if (!out) return fail(FED_E_ARG, "null out");
+  *out = nullptr;
+  int rc = validate(m, mt, bc, o);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = m->n_nodes, E = m->n_elems;
+  const int ne = m->elem;
+  std::unique_ptr<fed_ctx> c(new (std::nothrow) fed_ctx());
+  if (!c) return fail(FED_E_NOMEM, "host allocation failed");
+  c->prec = o->prec;
+  c->ne = ne;
+  c->rb = o->prec == FED_FP64 ? 8 : 4;
+  c->N = N;
+  c->E = E;
+  c->Tz = bc->Tz;
+  c->T_lo = o->T_lo;
+  c->T_hi = o->T_hi;
+  c->s0 = mt->materials[0].s0;
+  c->s1 = mt->materials[0].s1;
+  c->tdk = c->s1 != 0.0;
+  for (int i = 0; i < mt->n_materials; i++) c->tdc |= mt->materials[i].c1 != 0.0;
+  c->block = o->block_threads ? o->block_threads : 256;
+
+  // ---- host index work: boundary records, instances, tiling ---------------
+  std::vector<uint8_t> has_bnd(N, 0);
+  for (int64_t i = 0; i < bc->n_faces * bc->face_nodes; i++) has_bnd[bc->faces[i]] = 1;
+  for (int64_t i = 0; i < bc->n_pt; i++) has_bnd[bc->pt_nodes[i]] = 1;
+  // radiation ambient must be single-valued per node
+  std::vector<double> taR(N, 0.0);
+  std::vector<uint8_t> taSet(N, 0);
+  for (int64_t f = 0; f < bc->n_faces; f++) {
+    double eps = bc->face_eps ? bc->face_eps[f] : 0.0;
+    if (eps <= 0) continue;
+    double ta = bc->face_Ta ? bc->face_Ta[f] : 0.0;
+    for (int b = 0; b < bc->face_nodes; b++) {
+      int32_t k = bc->faces[f * bc->face_nodes + b];
+      if (taSet[k] && taR[k] != ta)
+        return fail(FED_E_ARG, "radiating faces at node %d have different Ta", k);
+      taSet[k] = 1;
+      taR[k] = ta;
+    }
+  }
+  c->ninst = 1;
+  if (o->node_instance) {
+    int32_t mx = 0;
+    for (int64_t k = 0; k < N; k++) mx = std::max(mx, o->node_instance[k]);
+    c->ninst = (int64_t)mx + 1;
+    for (int64_t e = 0; e < E; e++)
+      for (int a = 1; a < ne; a++)
+        if (o->node_instance[m->conn[(int64_t)a * E + e]] != o->node_instance[m->conn[e]])
+          return fail(FED_E_ARG, "element %lld spans two instances", (long long)e);
+  }
+  fed::TilingInput ti;
+  ti.N = N;
+  ti.E = E;
+  ti.ne = ne;
+  ti.x = m->x;
+  ti.y = m->y;
+  ti.z = m->z;
+  ti.conn = m->conn;
+  ti.node_instance = o->node_instance;
+  ti.has_bnd = has_bnd.data();
+  ti.target_nodes = o->tile_nodes ? o->tile_nodes : 512;
+  ti.lds_budget = 64 * 1024;
+  ti.real_bytes = c->rb;
+  std::string terr = fed::build_tiling(ti, c->til);
+  if (!terr.empty()) return fail(FED_E_MESH, "tiling: %s", terr.c_str());
+  fed::Tiling &T = c->til;
+  c->Eexp = (int64_t)T.eorig.size();
+  c->nper = (T.nt + 7) / 8;
+  // boundary records in internal order + their (face | point) items
+  std::vector<int32_t> rec_node;
+  std::vector<std::vector<int32_t>> items_of(N);
+  for (int64_t f = 0; f < bc->n_faces; f++)
+    for (int b = 0; b < bc->face_nodes; b++) items_of[bc->faces[f * bc->face_nodes + b]].push_back((int32_t)f);
+  for (int64_t i = 0; i < bc->n_pt; i++) items_of[bc->pt_nodes[i]].push_back(-(int32_t)(i + 1));
+  std::vector<int64_t> rec_ptr{0};
+  std::vector<int32_t> rec_item;
+  std::vector<double> rec_ta;
+  for (int32_t t = 0; t < T.nt; t++) {
+    const fed::TileHdr &th = T.tiles[t];
+    for (int32_t j = 0; j < th.nbnd; j++) {
+      int32_t ki = th.nstart + j, k = T.iperm[ki];
+      rec_node.push_back(ki);
+      for (int32_t it : items_of[k]) rec_item.push_back(it);
+      rec_ptr.push_back((int64_t)rec_item.size());
+      rec_ta.push_back(taR[k]);
+    }
+  }
+  items_of.clear();
+  items_of.shrink_to_fit();
+  c->nrec = (int64_t)rec_node.size();
+  std::vector<int32_t> node_inst_int, elem_inst;
+  if (o->node_instance) {
+    node_inst_int.resize(N);
+    for (int64_t k = 0; k < N; k++) node_inst_int[T.perm[k]] = o->node_instance[k];
+    elem_inst.resize(E);
+    for (int64_t e = 0; e < E; e++) elem_inst[e] = o->node_instance[m->conn[e]];
+  }
+  std::vector<uint8_t> is_dir(N, 0);
+  std::vector<int32_t> dir_node(bc->n_dir);
+  for (int64_t i = 0; i < bc->n_dir; i++) {
+    dir_node[i] = T.perm[bc->dir_nodes[i]];
+    is_dir[dir_node[i]] = 1;
+  }
+  c->ndir = bc->n_dir;
+
+  // ---- device pre-computation in FP64 (Sec. 3.5 (i)) ------------------------
+  DevPool tmp;
+  struct TmpGuard {
+    DevPool &p;
+    ~TmpGuard() { p.free_all(); }
+  } guard{tmp};
+  DevPool &P = c->pool;
+  double *d_x, *d_y, *d_z;
+  int32_t *d_conn;
+  fed::MatDev *d_mats;
+  int32_t *d_emat = nullptr;
+  double *d_ek = nullptr;
+  HIPCHK(upload(tmp, &d_x, m->x, N));
+  HIPCHK(upload(tmp, &d_y, m->y, N));
+  HIPCHK(upload(tmp, &d_z, m->z, N));
+  HIPCHK(upload(tmp, &d_conn, m->conn, (size_t)ne * E));
+  static_assert(sizeof(fed::MatDev) == sizeof(fed_material), "material layout");
+  HIPCHK(upload(tmp, &d_mats, reinterpret_cast<const fed::MatDev *>(mt->materials),
+                (size_t)mt->n_materials));
+  if (mt->elem_material) HIPCHK(upload(tmp, &d_emat, mt->elem_material, (size_t)E));
+  if (mt->elem_k) HIPCHK(upload(tmp, &d_ek, mt->elem_k, (size_t)6 * E));
+  {
+    std::vector<double> ks(E, 1.0);
+    if (mt->elem_kscale) std::copy(mt->elem_kscale, mt->elem_kscale + E, ks.begin());
+    HIPCHK(upload(P, &c->d_kscale, ks.data(), (size_t)E));
+  }
+  int *d_cnt;
+  HIPCHK(tmp.alloc((void **)&d_cnt, 2 * sizeof(int)));
+  HIPCHK(hipMemsetAsync(d_cnt, 0, 2 * sizeof(int), s));
+  double *d_lamgeo;
+  HIPCHK(P.alloc((void **)&c->d_H0, sizeof(double) * 6 * E));
+  HIPCHK(P.alloc((void **)&c->d_V, sizeof(double) * E));
+  HIPCHK(tmp.alloc((void **)&d_lamgeo, sizeof(double) * E));
+  fed::GeomArgs ga{ne, E, d_x, d_y, d_z, d_conn, d_mats, d_emat, d_ek,
+                   c->d_H0, c->d_V, d_lamgeo, d_cnt, d_cnt + 1};
+  HIPCHK(fed::launch_geom(ga, s));
+  int cnt[2];
+  HIPCHK(hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (cnt[0]) return fail(FED_E_MESH, "%d inverted or degenerate elements", cnt[0]);
+  if (cnt[1]) return fail(FED_E_ARG, "%d conductivity tensors are not positive definite", cnt[1]);
+  // lumped capacity per internal node
+  int64_t *d_incp;
+  int32_t *d_ince;
+  HIPCHK(upload(tmp, &d_incp, T.inc_ptr.data(), T.inc_ptr.size()));
+  HIPCHK(upload(tmp, &d_ince, T.inc_elem.data(), T.inc_elem.size()));
+  double *d_Cmin;
+  HIPCHK(P.alloc((void **)&c->d_M0, sizeof(double) * N));
+  HIPCHK(P.alloc((void **)&c->d_M1, sizeof(double) * N));
+  HIPCHK(tmp.alloc((void **)&d_Cmin, sizeof(double) * N));
+  fed::MassArgs ma{N, ne, d_incp, d_ince, d_mats, d_emat, c->d_V, o->T_lo, o->T_hi,
+                   c->d_M0, c->d_M1, d_Cmin};
+  HIPCHK(fed::launch_mass(ma, s));
+  // boundary lumping
+  int32_t *d_faces = nullptr, *d_recitem = nullptr, *d_recnode = nullptr;
+  int64_t *d_recptr = nullptr;
+  double *d_fh = nullptr, *d_fTa = nullptr, *d_feps = nullptr, *d_fq = nullptr, *d_farea = nullptr;
+  double *d_ptW = nullptr, *b64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const int64_t nf = bc->n_faces;
+  if (nf > 0) {
+    HIPCHK(upload(tmp, &d_faces, bc->faces, (size_t)nf * bc->face_nodes));
+    if (bc->face_h) HIPCHK(upload(tmp, &d_fh, bc->face_h, (size_t)nf));
+    if (bc->face_Ta) HIPCHK(upload(tmp, &d_fTa, bc->face_Ta, (size_t)nf));
+    if (bc->face_eps) HIPCHK(upload(tmp, &d_feps, bc->face_eps, (size_t)nf));
+    if (bc->face_q) HIPCHK(upload(tmp, &d_fq, bc->face_q, (size_t)nf));
+    HIPCHK(tmp.alloc((void **)&d_farea, sizeof(double) * nf));
+  }
+  if (bc->n_pt > 0) HIPCHK(upload(tmp, &d_ptW, bc->pt_W, (size_t)bc->n_pt));
+  const int64_t nrec = c->nrec;
+  if (nrec > 0) {
+    HIPCHK(upload(tmp, &d_recptr, rec_ptr.data(), rec_ptr.size()));
+    HIPCHK(upload(tmp, &d_recitem, rec_item.data(), rec_item.size()));
+    HIPCHK(upload(tmp, &d_recnode, rec_node.data(), rec_node.size()));
+    for (int i = 0; i < 4; i++) HIPCHK(tmp.alloc((void **)&b64[i], sizeof(double) * nrec));
+    HIPCHK(upload(tmp, &b64[4], rec_ta.data(), rec_ta.size()));
+  }
+  fed::BndArgs ba{nf, bc->face_nodes, d_faces, d_x, d_y, d_z, d_fh, d_fTa, d_feps, d_fq,
+                  d_farea, nrec, d_recptr, d_recitem, d_ptW, b64[0], b64[1], b64[2], b64[3]};
+  HIPCHK(fed::launch_bnd(ba, s));
+  // stability bound per instance (Sec. 3.4)
+  int32_t *d_einst = nullptr, *d_ninst = nullptr;
+  if (o->node_instance) {
+    HIPCHK(upload(tmp, &d_einst, elem_inst.data(), elem_inst.size()));
+    HIPCHK(upload(P, &d_ninst, node_inst_int.data(), node_inst_int.size()));
+  }
+  unsigned long long *d_lam;
+  HIPCHK(tmp.alloc((void **)&d_lam, sizeof(unsigned long long) * 2 * c->ninst));
+  HIPCHK(hipMemsetAsync(d_lam, 0, sizeof(unsigned long long) * 2 * c->ninst, s));
+  fed::DtArgs da{ne, E, nrec, d_lamgeo, c->d_kscale, d_mats, d_emat, d_einst, d_recnode, d_ninst,
+                 b64[0], b64[2], d_Cmin, o->T_lo, o->T_hi, bc->Tz, d_lam, d_lam + c->ninst};
+  HIPCHK(fed::launch_dt(da, s));
+  std::vector<unsigned long long> lam(2 * c->ninst);
+  HIPCHK(hipMemcpyAsync(lam.data(), d_lam, lam.size() * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->dt_crit.resize(c->ninst);
+  c->dt_used.resize(c->ninst);
+  for (int64_t i = 0; i < c->ninst; i++) {
+    double le, lb;
+    std::memcpy(&le, &lam[i], 8);
+    std::memcpy(&lb, &lam[c->ninst + i], 8);
+    double l = le + lb;
+    c->dt_crit[i] = l > 0 ? 2.0 / l : INFINITY;
+    if (o->dt > 0) {
+      c->dt_used[i] = o->dt;
+      if (o->dt > c->dt_crit[i] && !o->allow_unstable)
+        return fail(FED_E_UNSTABLE, "dt %.6g exceeds dt_crit %.6g (instance %lld)", o->dt,
+                    c->dt_crit[i], (long long)i);
+    } else {
+      if (!std::isfinite(c->dt_crit[i]))
+        return fail(FED_E_ARG, "dt_crit is unbounded (no conduction or boundary exchange); give dt");
+      c->dt_used[i] = o->safety * c->dt_crit[i];
+    }
+  }
+  // ---- working arrays in the step precision ---------------------------------
+  const int rb = c->rb;
+  double *d_dtinst;
+  uint8_t *d_isdir;
+  HIPCHK(upload(tmp, &d_dtinst, c->dt_used.data(), c->dt_used.size()));
+  HIPCHK(upload(tmp, &d_isdir, is_dir.data(), is_dir.size()));
+  HIPCHK(P.alloc(&c->d_alpha, (size_t)rb * N));
+  if (c->tdc) HIPCHK(P.alloc(&c->d_beta, (size_t)rb * N));
+  else {
+    HIPCHK(P.alloc(&c->d_beta, (size_t)rb * N));
+  }
+  void **recs[5] = {&c->d_rA, &c->d_rAT, &c->d_reA, &c->d_rTa, &c->d_rP};
+  for (int i = 0; i < 5; i++) HIPCHK(P.alloc(recs[i], (size_t)rb * std::max<int64_t>(nrec, 1)));
+  fed::NodeArrArgs na{c->prec, N, nrec, c->d_M0, c->d_M1, d_dtinst, d_ninst, d_isdir,
+                      b64[0], b64[1], b64[2], b64[4], b64[3],
+                      c->d_alpha, c->d_beta, c->d_rA, c->d_rAT, c->d_reA, c->d_rTa, c->d_rP};
+  HIPCHK(fed::launch_node_arrays(na, s));
+  HIPCHK(upload(P, &c->d_eorig, T.eorig.data(), T.eorig.size()));
+  HIPCHK(P.alloc(&c->d_H, (size_t)rb * 6 * c->Eexp));
+  HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->Eexp, E, c->d_eorig, c->d_H0,
+                              c->d_kscale, c->d_H, s));
+  HIPCHK(upload(P, &c->d_tiles, T.tiles.data(), T.tiles.size()));
+  HIPCHK(upload(P, &c->d_ent, T.ent.data(), T.ent.size()));
+  if (T.halo.empty()) T.halo.push_back(0);  // keep a valid (unused) device array
+  HIPCHK(upload(P, &c->d_halo, T.halo.data(), T.halo.size()));
+  HIPCHK(upload(P, &c->d_perm, T.perm.data(), T.perm.size()));
+  HIPCHK(P.alloc(&c->d_T[0], (size_t)rb * N));
+  HIPCHK(P.alloc(&c->d_T[1], (size_t)rb * N));
+  if (c->prec == FED_FP32C) {
+    HIPCHK(P.alloc((void **)&c->d_lo[0], sizeof(float) * N));
+    HIPCHK(P.alloc((void **)&c->d_lo[1], sizeof(float) * N));
+  }
+  if (c->ndir) {
+    HIPCHK(upload(P, &c->d_dir_node, dir_node.data(), dir_node.size()));
+    HIPCHK(upload(P, &c->d_dir_T, bc->dir_T, (size_t)c->ndir));
+  }
+  HIPCHK(P.alloc((void **)&c->d_flag, sizeof(int)));
+  HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  HIPCHK(P.alloc((void **)&c->d_Tuser, sizeof(double) * N));
+  if (T.lds_bytes > 64 * 1024)
+    return fail(FED_E_MESH, "tile needs %d bytes of LDS", T.lds_bytes);
+  HIPCHK(fed::step_set_lds_limit(c->prec == FED_FP64 ? 1 : (c->prec == FED_FP32C ? 0 : 2), ne,
+                                 c->tdk, c->tdc, std::max(T.lds_bytes, 1)));
+  HIPCHK(hipStreamSynchronize(s));
+  // ---- info -------------------------------------------------------------------
+  fed_info &I = c->info;
+  I.n_nodes = N;
+  I.n_elems = E;
+  I.n_instances = c->ninst;
+  I.n_tiles = T.nt;
+  I.n_elems_expanded = c->Eexp;
+  int64_t nhalo = 0;
+  for (const fed::TileHdr &th : T.tiles) nhalo += th.nhalo;
+  I.n_halo = nhalo;
+  I.n_bnd_nodes = nrec;
+  I.elem = ne;
+  I.prec = c->prec;
+  I.block_threads = c->block;
+  I.lds_bytes = T.lds_bytes;
+  // unique bytes of one step: per element its packed entries (2 B / node) and the
+  // 6-entry operator; per node T read + write (and lo read + write for FP32C),
+  // alpha (and beta when c depends on T); per boundary node its 5 coefficients.
+  double elem_b = 2.0 * ne + 6.0 * rb;
+  double node_b = 2.0 * rb + (c->prec == FED_FP32C ? 8.0 : 0.0) + rb + (c->tdc ? rb : 0.0);
+  I.algorithmic_bytes_per_step = elem_b * E + node_b * N + 5.0 * rb * nrec;
+  I.moved_bytes_per_step = elem_b * c->Eexp + node_b * N + 5.0 * rb * nrec +
+                           (4.0 + rb) * (double)nhalo + sizeof(fed::TileHdr) * T.nt;
+  *out = c.release();
+  return FED_OK;
+}
+
+int fed_dt(const fed_ctx *c, double *dt_crit, double *dt_used, int64_t n) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  if (n < c->ninst) return fail(FED_E_ARG, "arrays hold %lld entries, need %lld", (long long)n,
+                                (long long)c->ninst);
+  for (int64_t i = 0; i < c->ninst; i++) {
+    if (dt_crit) dt_crit[i] = c->dt_crit[i];
+    if (dt_used) dt_used[i] = c->dt_used[i];
+  }
+  return FED_OK;
+}
+
+int fed_info_get(const fed_ctx *c, fed_info *out) {
+  if (!c || !out) return fail(FED_E_ARG, "null argument");
+  *out = c->info;
+  return FED_OK;
+}
+
+int fed_set_temperature(fed_ctx *c, const double *T, int32_t on_device, void *stream) {
+  if (!c || !T) return fail(FED_E_ARG, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  const double *src = T;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(c->d_Tuser, T, sizeof(double) * c->N, hipMemcpyHostToDevice, s));
+    src = c->d_Tuser;
+  }
+  c->cur = 0;
+  HIPCHK(fed::launch_set_T(c->prec, c->N, src, c->d_perm, c->d_T[0], c->d_lo[0], c->ndir,
+                           c->d_dir_node, c->d_dir_T, s));
+  if (!on_device) HIPCHK(hipStreamSynchronize(s));  // the host buffer may be reused
+  c->steps = 0;
+  c->have_T = true;
+  HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  return FED_OK;
+}
+
+int fed_step(fed_ctx *c, int64_t nsteps, void *stream) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  if (!c->have_T) return fail(FED_E_STATE, "fed_set_temperature must come first");
+  if (nsteps < 0) return fail(FED_E_ARG, "nsteps < 0");
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t n = 0; n < nsteps; n++) {
+    fed::StepArgs a = c->step_args(c->cur);
+    HIPCHK(fed::launch_step(a, s));
+    c->cur ^= 1;
+  }
+  c->steps += nsteps;
+  return FED_OK;
+}
+
+int fed_step_graph(fed_ctx *c, int64_t nsteps, int32_t graph_steps, void *stream) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  if (!c->have_T) return fail(FED_E_STATE, "fed_set_temperature must come first");
+  if (nsteps < 0 || graph_steps < 0) return fail(FED_E_ARG, "negative count");
+  hipStream_t s = (hipStream_t)stream;
+  int gs = graph_steps ? graph_steps : 100;
+  gs += gs & 1;  // even, so every replay starts on the same buffer
+  if (nsteps < gs) return fed_step(c, nsteps, stream);
+  if (c->gexec && (c->gsteps != gs || c->gparity != c->cur)) c->drop_graph();
+  if (!c->gexec) {
+    // capture on a private stream (the caller's may be the legacy null stream,
+    // which cannot be captured); the graph is then launched on the caller's stream
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = c->cap_stream;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int par = c->cur;
+    for (int i = 0; i < gs; i++) {
+      fed::StepArgs a = c->step_args(par);
+      hipError_t e = fed::launch_step(a, cs);
+      if (e != hipSuccess) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        return fail(FED_E_HIP, "capture launch failed: %s", hipGetErrorString(e));
+      }
+      par ^= 1;
+    }
+    HIPCHK(hipStreamEndCapture(cs, &c->graph));
+    HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    c->gsteps = gs;
+    c->gparity = c->cur;
+  }
+  int64_t reps = nsteps / gs;
+  for (int64_t r = 0; r < reps; r++) HIPCHK(hipGraphLaunch(c->gexec, s));
+  c->steps += reps * gs;
+  return fed_step(c, nsteps - reps * gs, stream);
+}
+
+int fed_get_temperature(fed_ctx *c, double *T, int32_t on_device, void *stream) {
+  if (!c || !T) return fail(FED_E_ARG, "null argument");
+  if (!c->have_T) return fail(FED_E_STATE, "no temperature set");
+  hipStream_t s = (hipStream_t)stream;
+  double w = c->T_hi - c->T_lo;
+  HIPCHK(fed::launch_check(c->prec, c->N, c->d_T[c->cur], c->d_lo[c->cur], c->T_lo - w,
+                           c->T_hi + w, c->d_flag, s));
+  double *dst = on_device ? T : c->d_Tuser;
+  HIPCHK(fed::launch_get_T(c->prec, c->N, c->d_perm, c->d_T[c->cur], c->d_lo[c->cur], dst, s));
+  int flag = 0;
+  if (!on_device)
+    HIPCHK(hipMemcpyAsync(T, c->d_Tuser, sizeof(double) * c->N, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (flag)
+    return fail(FED_E_UNSTABLE,
+                "health check: a temperature is non-finite or outside [%g, %g] after %lld steps",
+                c->T_lo - w, c->T_hi + w, (long long)c->steps);
+  return FED_OK;
+}
+
+int fed_steps_taken(const fed_ctx *c, int64_t *steps) {
+  if (!c || !steps) return fail(FED_E_ARG, "null argument");
+  *steps = c->steps;
+  return FED_OK;
+}
+
+int fed_get_state(fed_ctx *c, void *hi, void *lo, int64_t *step, void *stream) {
+  if (!c || !hi) return fail(FED_E_ARG, "null argument");
+  if (!c->have_T) return fail(FED_E_STATE, "no temperature set");
+  hipStream_t s = (hipStream_t)stream;
+  const int rb = c->rb;
+  void *tmp;
+  HIPCHK(hipMallocAsync(&tmp, (size_t)rb * c->N, s));
+  HIPCHK(fed::launch_permute(rb, c->N, c->d_perm, c->d_T[c->cur], tmp, 0, s));
+  HIPCHK(hipMemcpyAsync(hi, tmp, (size_t)rb * c->N, hipMemcpyDeviceToHost, s));
+  if (lo && c->prec == FED_FP32C) {
+    HIPCHK(fed::launch_permute(4, c->N, c->d_perm, c->d_lo[c->cur], tmp, 0, s));
+    HIPCHK(hipMemcpyAsync(lo, tmp, sizeof(float) * c->N, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipFreeAsync(tmp, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (step) *step = c->steps;
+  return FED_OK;
+}
+
+int fed_set_state(fed_ctx *c, const void *hi, const void *lo, int64_t step, void *stream) {
+  if (!c || !hi) return fail(FED_E_ARG, "null argument");
+  if (c->prec == FED_FP32C && !lo) return fail(FED_E_ARG, "FP32C state needs lo");
+  hipStream_t s = (hipStream_t)stream;
+  const int rb = c->rb;
+  void *tmp;
+  HIPCHK(hipMallocAsync(&tmp, (size_t)rb * c->N, s));
+  c->cur = 0;
+  HIPCHK(hipMemcpyAsync(tmp, hi, (size_t)rb * c->N, hipMemcpyHostToDevice, s));
+  HIPCHK(fed::launch_permute(rb, c->N, c->d_perm, tmp, c->d_T[0], 1, s));
+  if (c->prec == FED_FP32C) {
+    HIPCHK(hipMemcpyAsync(tmp, lo, sizeof(float) * c->N, hipMemcpyHostToDevice, s));
+    HIPCHK(fed::launch_permute(4, c->N, c->d_perm, tmp, c->d_lo[0], 1, s));
+  }
+  HIPCHK(hipFreeAsync(tmp, s));
+  HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->steps = step;
+  c->have_T = true;
+  return FED_OK;
+}
+
+void fed_destroy(fed_ctx *c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  delete c;
+}
+
+}  // extern "C"

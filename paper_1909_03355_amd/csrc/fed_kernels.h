@@ -1,0 +1,126 @@
+// Launchers of the FED-FEM HIP kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fed_internal.h"
+
+namespace fed {
+
+// Material record, same layout as the public fed_material.
+struct MatDev {
+  double rho, c0, c1;
+  double k[6];
+  double s0, s1;
+};
+
+struct GeomArgs {
+  int ne;
+  int64_t E;
+  const double *x, *y, *z;
+  const int32_t *conn;     // caller ids, [ne * E]
+  const MatDev *mats;
+  const int32_t *emat;     // nullable
+  const double *ek;        // nullable, [6 * E]
+  double *H0;              // [6 * E] symmetric operator without per-element factor
+  double *V;               // [E] exact volume
+  double *lamgeo;          // [E] W / V * lambda_max(L^T B B^T L), k = L L^T
+  int *nbad;               // inverted / degenerate element count
+  int *nnotspd;            // conductivity tensors that are not SPD
+};
+
+struct MassArgs {
+  int64_t N;
+  int ne;
+  const int64_t *inc_ptr;
+  const int32_t *inc_elem;
+  const MatDev *mats;
+  const int32_t *emat;
+  const double *V;
+  double T_lo, T_hi;
+  double *M0, *M1, *Cmin;  // internal node order
+};
+
+struct BndArgs {
+  int64_t nf;
+  int nfn;
+  const int32_t *faces;    // caller ids
+  const double *x, *y, *z;
+  const double *fh, *fTa, *feps, *fq;  // nullable
+  double *farea;
+  // per boundary record (internal order of the record nodes)
+  int64_t nrec;
+  const int64_t *rec_ptr;  // CSR over (face id >= 0 | point load -(i+1))
+  const int32_t *rec_item;
+  const double *pt_W;
+  double *bhA, *bhAT, *beA, *bP;
+};
+
+struct DtArgs {
+  int ne;
+  int64_t E, nrec;
+  const double *lamgeo, *kscale;
+  const MatDev *mats;
+  const int32_t *emat;
+  const int32_t *elem_inst;   // nullable
+  const int32_t *rec_node;    // internal node of every record
+  const int32_t *node_inst;   // nullable, internal order
+  const double *bhA, *beA, *Cmin;
+  double T_lo, T_hi, Tz;
+  unsigned long long *lamE, *lamB;  // per instance, bit patterns of positive doubles
+};
+
+struct NodeArrArgs {
+  int prec;
+  int64_t N, nrec;
+  const double *M0, *M1, *dt_inst;
+  const int32_t *node_inst;   // nullable
+  const uint8_t *is_dir;
+  const double *bhA, *bhAT, *beA, *bTa, *bP;
+  void *alpha, *beta;         // R[N]
+  void *rA, *rAT, *reA, *rTa, *rP;  // R[nrec]
+};
+
+struct StepArgs {
+  int prec, ne;
+  int tdk, tdc;               // temperature-dependent conductivity / capacity
+  int nt, nper, block, lds;
+  int pb, maxinc;
+  int64_t Eexp;
+  const TileHdr *tiles;
+  const uint16_t *ent;
+  const int32_t *halo;
+  const void *H;
+  const void *Tin;
+  const float *loin;
+  void *Tout;
+  float *loout;
+  const void *alpha, *beta;
+  const void *rA, *rAT, *reA, *rTa, *rP;
+  double s0, s1, Tz;
+};
+
+hipError_t launch_geom(const GeomArgs &a, hipStream_t s);
+hipError_t launch_mass(const MassArgs &a, hipStream_t s);
+hipError_t launch_bnd(const BndArgs &a, hipStream_t s);
+hipError_t launch_dt(const DtArgs &a, hipStream_t s);
+hipError_t launch_node_arrays(const NodeArrArgs &a, hipStream_t s);
+hipError_t launch_expand_H(int prec, int64_t Eexp, int64_t E, const int32_t *eorig,
+                           const double *H0, const double *kscale, void *H, hipStream_t s);
+hipError_t launch_step(const StepArgs &a, hipStream_t s);
+hipError_t step_set_lds_limit(int prec, int ne, int tdk, int tdc, int bytes);
+
+// caller-order FP64 temperatures <-> internal working arrays
+hipError_t launch_set_T(int prec, int64_t N, const double *Tuser, const int32_t *perm,
+                        void *T, float *lo, int64_t ndir, const int32_t *dir_node,
+                        const double *dir_T, hipStream_t s);
+hipError_t launch_get_T(int prec, int64_t N, const int32_t *perm, const void *T,
+                        const float *lo, double *Tuser, hipStream_t s);
+hipError_t launch_check(int prec, int64_t N, const void *T, const float *lo, double lo_b,
+                        double hi_b, int *flag, hipStream_t s);
+// gather/scatter of raw working arrays between caller and internal order
+hipError_t launch_permute(int elem_bytes, int64_t N, const int32_t *perm, const void *src,
+                          void *dst, int to_internal, hipStream_t s);
+
+}  // namespace fed

@@ -1,0 +1,702 @@
+// HIP kernels of the FED-FEM library for gfx950 (MI355X).
+//
+// Pre-computation (Sec. 3.5 (i)) runs once in FP64.  The time step is one fused
+// kernel per step: a workgroup owns a tile of nodes, stages their temperatures
+// and those of the tile's halo in LDS, computes the loads of every element
+// touching its nodes (Eq. 17-20), sums them per node in ascending element order
+// through LDS slots (Eq. 10-11, no global K, no atomics), adds the surface loads
+// (Eq. 4, 5, 7) and updates the node explicitly (Eq. 16).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "fed_kernels.h"
+
+namespace fed {
+
+namespace {
+
+constexpr double kSigma = 5.67e-8;  // Stefan-Boltzmann constant (Sec. 2)
+
+__device__ __constant__ int8_t kHexS[8][3] = {
+    {-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+    {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+
+inline int blocks_for(int64_t n, int bs) {
+  int64_t b = (n + bs - 1) / bs;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// Largest eigenvalue of a symmetric 3x3 matrix by the cyclic Jacobi method
+// (plane rotations that annihilate one off-diagonal entry at a time, as in
+// Golub & Van Loan, Sec. 8.5).  Accurate to rounding also for repeated
+// eigenvalues, where the closed-form cubic solution loses half the digits.
+__device__ double sym3_lmax(double a00, double a11, double a22, double a01, double a12,
+                            double a02) {
+  double A[3][3] = {{a00, a01, a02}, {a01, a11, a12}, {a02, a12, a22}};
+  for (int sweep = 0; sweep < 12; sweep++) {
+    double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= 1e-34 * dia) break;
+    for (int p = 0; p < 2; p++)
+      for (int q = p + 1; q < 3; q++) {
+        double apq = A[p][q];
+        if (apq == 0.0) continue;
+        double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 3; k++) {  // columns p, q
+          double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; k++) {  // rows p, q
+          double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  double m = A[0][0];
+  if (A[1][1] > m) m = A[1][1];
+  if (A[2][2] > m) m = A[2][2];
+  return m;
+}
+
+__device__ void inverse3(const double J[3][3], double d, double R[3][3]) {
+  R[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / d;
+  R[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / d;
+  R[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / d;
+  R[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / d;
+  R[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / d;
+  R[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / d;
+  R[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / d;
+  R[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / d;
+  R[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / d;
+}
+
+__device__ double det3(const double J[3][3]) {
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry (Sec. 3.2).  With B = J^{-T} dN/dxi at the integration point, the
+// element load of Eq. 20 is F_e = W B^T D B T_e.  For the one-point hexahedron
+// dN_a/dxi(0) = s_a / 8 (s_a the corner signs), so
+//   F_a = s_a . Hhat (sum_b s_b T_b),  Hhat = W J^{-1} D J^{-T} / 64, W = 8 det J(0);
+// for the linear tetrahedron, with d_i = T_i - T_0 and J = [x_i - x_0],
+//   F_{1..3} = Hhat d,  F_0 = -(F_1 + F_2 + F_3),  Hhat = V J^{-1} D J^{-T}.
+// Hhat (6 numbers, symmetric) is the precomputed "G D B" of Eq. 19-22.
+__global__ void k_geom(GeomArgs a) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= a.E) return;
+  const int ne = a.ne;
+  double X[8][3];
+  for (int n = 0; n < ne; n++) {
+    int32_t k = a.conn[(int64_t)n * a.E + e];
+    X[n][0] = a.x[k];
+    X[n][1] = a.y[k];
+    X[n][2] = a.z[k];
+  }
+  int m = a.emat ? a.emat[e] : 0;
+  double dk[6];
+  for (int r = 0; r < 6; r++) dk[r] = a.ek ? a.ek[(int64_t)r * a.E + e] : a.mats[m].k[r];
+  double J[3][3], Ji[3][3], W, V, det;
+  double M3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // B B^T
+  if (ne == 8) {
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        double s = 0;
+        for (int n = 0; n < 8; n++) s += X[n][i] * kHexS[n][j];
+        J[i][j] = s / 8.0;
+      }
+    det = det3(J);
+    W = 8.0 * det;
+    // exact volume of the trilinear map: 2x2x2 Gauss points, unit weights
+    const double g = 0.57735026918962576451;  // 1/sqrt(3)
+    V = 0;
+    for (int qp = 0; qp < 8; qp++) {
+      double p0 = kHexS[qp][0] * g, p1 = kHexS[qp][1] * g, p2 = kHexS[qp][2] * g;
+      double Jq[3][3];
+      for (int i = 0; i < 3; i++) {
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int n = 0; n < 8; n++) {
+          double sx = kHexS[n][0], sy = kHexS[n][1], sz = kHexS[n][2];
+          s0 += X[n][i] * sx * (1 + sy * p1) * (1 + sz * p2);
+          s1 += X[n][i] * sy * (1 + sx * p0) * (1 + sz * p2);
+          s2 += X[n][i] * sz * (1 + sx * p0) * (1 + sy * p1);
+        }
+        Jq[i][0] = s0 / 8.0;
+        Jq[i][1] = s1 / 8.0;
+        Jq[i][2] = s2 / 8.0;
+      }
+      V += det3(Jq);
+    }
+    if (!(det > 0.0)) {
+      atomicAdd(a.nbad, 1);
+      det = 1.0;
+    }
+    inverse3(J, det, Ji);
+    // B B^T = J^{-T} (sum_a s_a s_a^T / 64) J^{-1}, formed from the columns of B
+    for (int n = 0; n < 8; n++) {
+      double b[3];
+      for (int i = 0; i < 3; i++)
+        b[i] = (Ji[0][i] * kHexS[n][0] + Ji[1][i] * kHexS[n][1] + Ji[2][i] * kHexS[n][2]) / 8.0;
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) M3[i][j] += b[i] * b[j];
+    }
+  } else {
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) J[i][j] = X[j + 1][i] - X[0][i];
+    det = det3(J);
+    V = fabs(det) / 6.0;
+    W = V;
+    if (det == 0.0) {
+      atomicAdd(a.nbad, 1);
+      det = 1.0;
+    }
+    inverse3(J, det, Ji);
+    double b[4][3];
+    for (int i = 0; i < 3; i++) {
+      b[0][i] = 0;
+      for (int n = 1; n < 4; n++) {
+        b[n][i] = Ji[n - 1][i];  // grad N_n = J^{-T} e_{n-1}
+        b[0][i] -= b[n][i];
+      }
+    }
+    for (int n = 0; n < 4; n++)
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) M3[i][j] += b[n][i] * b[n][j];
+  }
+  // Hhat = c * Ji D Ji^T,  c = W/64 (hex) or V (tet)
+  double D[3][3] = {{dk[0], dk[3], dk[5]}, {dk[3], dk[1], dk[4]}, {dk[5], dk[4], dk[2]}};
+  double c = ne == 8 ? W / 64.0 : V;
+  double T1[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      T1[i][j] = Ji[i][0] * D[0][j] + Ji[i][1] * D[1][j] + Ji[i][2] * D[2][j];
+  double Hm[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      Hm[i][j] = c * (T1[i][0] * Ji[j][0] + T1[i][1] * Ji[j][1] + T1[i][2] * Ji[j][2]);
+  a.H0[0 * a.E + e] = Hm[0][0];
+  a.H0[1 * a.E + e] = Hm[1][1];
+  a.H0[2 * a.E + e] = Hm[2][2];
+  a.H0[3 * a.E + e] = 0.5 * (Hm[0][1] + Hm[1][0]);
+  a.H0[4 * a.E + e] = 0.5 * (Hm[1][2] + Hm[2][1]);
+  a.H0[5 * a.E + e] = 0.5 * (Hm[0][2] + Hm[2][0]);
+  a.V[e] = V;
+  // stability: lambda_max(K_e) = W lambda_max(L^T B B^T L) with D = L L^T (Cholesky)
+  double l00 = dk[0];
+  bool spd = l00 > 0;
+  l00 = spd ? sqrt(l00) : 1.0;
+  double l10 = dk[3] / l00, l20 = dk[5] / l00;
+  double t11 = dk[1] - l10 * l10;
+  spd = spd && t11 > 0;
+  double l11 = t11 > 0 ? sqrt(t11) : 1.0;
+  double l21 = (dk[4] - l20 * l10) / l11;
+  double t22 = dk[2] - l20 * l20 - l21 * l21;
+  spd = spd && t22 > 0;
+  double l22 = t22 > 0 ? sqrt(t22) : 1.0;
+  if (!spd) atomicAdd(a.nnotspd, 1);
+  double L[3][3] = {{l00, 0, 0}, {l10, l11, 0}, {l20, l21, l22}};
+  double ML[3][3], A[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      ML[i][j] = M3[i][0] * L[0][j] + M3[i][1] * L[1][j] + M3[i][2] * L[2][j];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) A[i][j] = L[0][i] * ML[0][j] + L[1][i] * ML[1][j] + L[2][i] * ML[2][j];
+  double lm = sym3_lmax(A[0][0], A[1][1], A[2][2], 0.5 * (A[0][1] + A[1][0]),
+                        0.5 * (A[1][2] + A[2][1]), 0.5 * (A[0][2] + A[2][0]));
+  a.lamgeo[e] = (V > 0 ? W / V : 0.0) * lm;
+}
+
+// Lumped (diagonal) heat capacity (Sec. 3.1, Eq. 13-14): every element gives
+// rho V / n_e to each of its nodes; C_k(T) = M0_k + M1_k T.  Summed in
+// ascending element order per node.
+__global__ void k_mass(MassArgs a) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= a.N) return;
+  double m0 = 0, m1 = 0, cm = 0;
+  for (int64_t p = a.inc_ptr[k]; p < a.inc_ptr[k + 1]; p++) {
+    int32_t e = a.inc_elem[p];
+    const MatDev &mt = a.mats[a.emat ? a.emat[e] : 0];
+    double v = mt.rho * a.V[e] / a.ne;
+    double clo = mt.c0 + mt.c1 * a.T_lo, chi = mt.c0 + mt.c1 * a.T_hi;
+    m0 += v * mt.c0;
+    m1 += v * mt.c1;
+    cm += v * (clo < chi ? clo : chi);
+  }
+  a.M0[k] = m0;
+  a.M1[k] = m1;
+  a.Cmin[k] = cm;
+}
+
+// Face areas: triangles by the cross product, bilinear quadrilaterals by a
+// 2x2 Gauss rule on |x_u x x_v|.
+__global__ void k_face_area(BndArgs a) {
+  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= a.nf) return;
+  double X[4][3];
+  for (int b = 0; b < a.nfn; b++) {
+    int32_t k = a.faces[f * a.nfn + b];
+    X[b][0] = a.x[k];
+    X[b][1] = a.y[k];
+    X[b][2] = a.z[k];
+  }
+  double area = 0;
+  if (a.nfn == 3) {
+    double u[3], v[3];
+    for (int i = 0; i < 3; i++) {
+      u[i] = X[1][i] - X[0][i];
+      v[i] = X[2][i] - X[0][i];
+    }
+    double c0 = u[1] * v[2] - u[2] * v[1], c1 = u[2] * v[0] - u[0] * v[2],
+           c2 = u[0] * v[1] - u[1] * v[0];
+    area = 0.5 * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+  } else {
+    const double g = 0.57735026918962576451;
+    const double su[4] = {-1, 1, 1, -1}, sv[4] = {-1, -1, 1, 1};
+    for (int qp = 0; qp < 4; qp++) {
+      double pu = su[qp] * g, pv = sv[qp] * g;
+      double xu[3] = {0, 0, 0}, xv[3] = {0, 0, 0};
+      for (int b = 0; b < 4; b++) {
+        double du = su[b] * (1 + sv[b] * pv) * 0.25, dv = sv[b] * (1 + su[b] * pu) * 0.25;
+        for (int i = 0; i < 3; i++) {
+          xu[i] += X[b][i] * du;
+          xv[i] += X[b][i] * dv;
+        }
+      }
+      double c0 = xu[1] * xv[2] - xu[2] * xv[1], c1 = xu[2] * xv[0] - xu[0] * xv[2],
+             c2 = xu[0] * xv[1] - xu[1] * xv[0];
+      area += sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    }
+  }
+  a.farea[f] = area;
+}
+
+// Per boundary node: lumped convection h A, h A Ta, radiation sigma eps A and the
+// applied power (flux q A plus concentrated loads), each face giving |f| / n_f.
+__global__ void k_bnd_rec(BndArgs a) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= a.nrec) return;
+  double hA = 0, hAT = 0, eA = 0, P = 0;
+  for (int64_t p = a.rec_ptr[r]; p < a.rec_ptr[r + 1]; p++) {
+    int32_t it = a.rec_item[p];
+    if (it >= 0) {
+      double s = a.farea[it] / a.nfn;
+      double h = a.fh ? a.fh[it] : 0.0, Ta = a.fTa ? a.fTa[it] : 0.0;
+      double eps = a.feps ? a.feps[it] : 0.0, q = a.fq ? a.fq[it] : 0.0;
+      hA += h * s;
+      hAT += h * s * Ta;
+      eA += kSigma * eps * s;
+      P += q * s;
+    } else {
+      P += a.pt_W[-(it + 1)];
+    }
+  }
+  a.bhA[r] = hA;
+  a.bhAT[r] = hAT;
+  a.beA[r] = eA;
+  a.bP[r] = P;
+}
+
+// Stability bound (Sec. 3.4): per element lambda_e = lambda_max(K_e(T)) / (rho c V /
+// n_e) at the largest D and smallest c over [T_lo, T_hi]; per boundary node the
+// convection and linearised radiation rate; maxima per instance.
+__global__ void k_dt_elem(DtArgs a) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= a.E) return;
+  const MatDev &mt = a.mats[a.emat ? a.emat[e] : 0];
+  double slo = mt.s0 + mt.s1 * a.T_lo, shi = mt.s0 + mt.s1 * a.T_hi;
+  double clo = mt.c0 + mt.c1 * a.T_lo, chi = mt.c0 + mt.c1 * a.T_hi;
+  double smax = slo > shi ? slo : shi, cmin = clo < chi ? clo : chi;
+  double ks = a.kscale ? a.kscale[e] : 1.0;
+  double lam = a.ne * ks * smax * a.lamgeo[e] / (mt.rho * cmin);
+  int inst = a.elem_inst ? a.elem_inst[e] : 0;
+  if (lam > 0) atomicMax(&a.lamE[inst], (unsigned long long)__double_as_longlong(lam));
+}
+
+__global__ void k_dt_node(DtArgs a) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= a.nrec) return;
+  int32_t k = a.rec_node[r];
+  double d = a.T_hi - a.Tz;
+  double lam = (a.bhA[r] + 4.0 * a.beA[r] * d * d * d) / a.Cmin[k];
+  int inst = a.node_inst ? a.node_inst[k] : 0;
+  if (lam > 0) atomicMax(&a.lamB[inst], (unsigned long long)__double_as_longlong(lam));
+}
+
+// Working arrays of the step in precision R: per node alpha = M0 / dt and
+// beta = M1 / dt (the inverse of A / c(T) of Eq. 15-16: dT = (Q - F) / (alpha +
+// beta T)); alpha = +inf holds a Dirichlet node fixed.  Boundary records and the
+// expanded element operators are cast to R.
+template <typename R>
+__global__ void k_node_arrays(NodeArrArgs a) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  R *alpha = (R *)a.alpha, *beta = (R *)a.beta;
+  if (i < a.N) {
+    double dt = a.dt_inst[a.node_inst ? a.node_inst[i] : 0];
+    if (a.is_dir[i]) {
+      alpha[i] = (R)INFINITY;
+      beta[i] = 0;
+    } else {
+      alpha[i] = (R)(a.M0[i] / dt);
+      beta[i] = (R)(a.M1[i] / dt);
+    }
+  }
+  if (i < a.nrec) {
+    ((R *)a.rA)[i] = (R)a.bhA[i];
+    ((R *)a.rAT)[i] = (R)a.bhAT[i];
+    ((R *)a.reA)[i] = (R)a.beA[i];
+    ((R *)a.rTa)[i] = (R)a.bTa[i];
+    ((R *)a.rP)[i] = (R)a.bP[i];
+  }
+}
+
+template <typename R>
+__global__ void k_expand_H(int64_t Eexp, int64_t E, const int32_t *eorig, const double *H0,
+                           const double *kscale, R *H) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= Eexp) return;
+  int32_t e = eorig[i];
+  double ks = kscale ? kscale[e] : 1.0;
+  for (int r = 0; r < 6; r++) H[(int64_t)r * Eexp + i] = (R)(H0[(int64_t)r * E + e] * ks);
+}
+
+// ---------------------------------------------------------------------------
+// The step.  One workgroup per tile; the XCD-aware block->tile map keeps a run of
+// spatially adjacent tiles on one XCD (blocks are dealt to the 8 XCDs round
+// robin), so halo re-reads and the next step's re-reads of the same tiles hit
+// that XCD's L2.
+template <typename R, int NE>
+struct Elem;
+
+template <typename R>
+struct Elem<R, 8> {
+  // F_a = s_a . (s * Hhat u),  u = sum_b s_b T_b written as sums of edge
+  // differences (each a difference of nearby values, so exact or nearly so).
+  __device__ static void load(const R *Tl, const uint32_t *loc, R s0, R s1, bool tdk,
+                              const R h[6], R F[8]) {
+    R T0 = Tl[loc[0]], T1 = Tl[loc[1]], T2 = Tl[loc[2]], T3 = Tl[loc[3]];
+    R T4 = Tl[loc[4]], T5 = Tl[loc[5]], T6 = Tl[loc[6]], T7 = Tl[loc[7]];
+    R ux = ((T1 - T0) + (T2 - T3)) + ((T5 - T4) + (T6 - T7));
+    R uy = ((T3 - T0) + (T2 - T1)) + ((T7 - T4) + (T6 - T5));
+    R uz = ((T4 - T0) + (T5 - T1)) + ((T6 - T2) + (T7 - T3));
+    R s = s0;
+    if (tdk) s = s0 + s1 * ((((T0 + T1) + (T2 + T3)) + ((T4 + T5) + (T6 + T7))) * (R)0.125);
+    R qx = s * (h[0] * ux + h[3] * uy + h[5] * uz);
+    R qy = s * (h[3] * ux + h[1] * uy + h[4] * uz);
+    R qz = s * (h[5] * ux + h[4] * uy + h[2] * uz);
+    R a = qx + qy, b = qx - qy;
+    F[0] = -a - qz;
+    F[1] = b - qz;
+    F[2] = a - qz;
+    F[3] = -b - qz;
+    F[4] = -a + qz;
+    F[5] = b + qz;
+    F[6] = a + qz;
+    F[7] = -b + qz;
+  }
+};
+
+template <typename R>
+struct Elem<R, 4> {
+  __device__ static void load(const R *Tl, const uint32_t *loc, R s0, R s1, bool tdk,
+                              const R h[6], R F[4]) {
+    R T0 = Tl[loc[0]], T1 = Tl[loc[1]], T2 = Tl[loc[2]], T3 = Tl[loc[3]];
+    R d1 = T1 - T0, d2 = T2 - T0, d3 = T3 - T0;
+    R s = s0;
+    if (tdk) s = s0 + s1 * (((T0 + T1) + (T2 + T3)) * (R)0.25);
+    F[1] = s * (h[0] * d1 + h[3] * d2 + h[5] * d3);
+    F[2] = s * (h[3] * d1 + h[1] * d2 + h[4] * d3);
+    F[3] = s * (h[5] * d1 + h[4] * d2 + h[2] * d3);
+    F[0] = -((F[1] + F[2]) + F[3]);
+  }
+};
+
+template <int NE>
+__device__ inline void load_ent(const uint16_t *ent, int64_t i, uint32_t v[NE]);
+
+template <>
+__device__ inline void load_ent<8>(const uint16_t *ent, int64_t i, uint32_t v[8]) {
+  uint4 w = reinterpret_cast<const uint4 *>(ent)[i];
+  v[0] = w.x & 0xffff; v[1] = w.x >> 16; v[2] = w.y & 0xffff; v[3] = w.y >> 16;
+  v[4] = w.z & 0xffff; v[5] = w.z >> 16; v[6] = w.w & 0xffff; v[7] = w.w >> 16;
+}
+
+template <>
+__device__ inline void load_ent<4>(const uint16_t *ent, int64_t i, uint32_t v[4]) {
+  uint2 w = reinterpret_cast<const uint2 *>(ent)[i];
+  v[0] = w.x & 0xffff; v[1] = w.x >> 16; v[2] = w.y & 0xffff; v[3] = w.y >> 16;
+}
+
+// MODE: 0 plain (R = float or double), 1 compensated FP32 (hi, lo pair)
+template <typename R, int NE, int MODE, bool TDK, bool TDC>
+__global__ __launch_bounds__(1024) void k_step(StepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const int t = (b & 7) * a.nper + (b >> 3);
+  if (t >= a.nt) return;  // whole block leaves before any barrier
+  const TileHdr th = a.tiles[t];
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int nown = th.nown, ntouch = th.nown + th.nhalo;
+  R *Tl = reinterpret_cast<R *>(smem_raw);
+  R *slot = Tl + ntouch;
+  const R *Tin = (const R *)a.Tin;
+  R *Tout = (R *)a.Tout;
+  // stage T of owned and halo nodes; clear the slots
+  for (int j = tid; j < nown; j += bs) Tl[j] = Tin[th.nstart + j];
+  for (int j = tid; j < th.nhalo; j += bs) Tl[nown + j] = Tin[a.halo[th.hstart + j]];
+  const int nslot = a.maxinc * nown;
+  for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
+  __syncthreads();
+  // element loads into the node-local slots
+  const R *Hb = (const R *)a.H;
+  const R s0 = (R)a.s0, s1 = (R)a.s1;
+  const uint32_t pmask = (1u << a.pb) - 1u;
+  for (int i = tid; i < th.ecount; i += bs) {
+    const int64_t e = (int64_t)th.estart + i;
+    uint32_t v[NE], loc[NE];
+    load_ent<NE>(a.ent, e, v);
+#pragma unroll
+    for (int n = 0; n < NE; n++) loc[n] = v[n] >> a.pb;
+    R h[6];
+#pragma unroll
+    for (int r = 0; r < 6; r++) h[r] = Hb[(int64_t)r * a.Eexp + e];
+    R F[NE];
+    Elem<R, NE>::load(Tl, loc, s0, s1, TDK, h, F);
+#pragma unroll
+    for (int n = 0; n < NE; n++)
+      if (loc[n] < (uint32_t)nown) slot[(v[n] & pmask) * nown + loc[n]] = F[n];
+  }
+  __syncthreads();
+  // per node: sum in ascending element order, surface loads, explicit update
+  const R *alpha = (const R *)a.alpha, *beta = (const R *)a.beta;
+  const R *rA = (const R *)a.rA, *rAT = (const R *)a.rAT, *reA = (const R *)a.reA;
+  const R *rTa = (const R *)a.rTa, *rP = (const R *)a.rP;
+  const R Tz = (R)a.Tz;
+  for (int j = tid; j < nown; j += bs) {
+    const int k = th.nstart + j;
+    R F = slot[j];
+    for (int p = 1; p < a.maxinc; p++) F += slot[p * nown + j];
+    const R T = Tl[j];
+    R Q = 0;
+    if (j < th.nbnd) {
+      const int r = th.bstart + j;
+      R ta = rTa[r];
+      R x = T - Tz, y = ta - Tz;
+      // (T-Tz)^4 - (Ta-Tz)^4 in factored form
+      Q = (rAT[r] - rA[r] * T) - reA[r] * ((T - ta) * (x + y) * (x * x + y * y)) + rP[r];
+    }
+    R den = alpha[k];
+    if (TDC) den += beta[k] * T;
+    const R dT = (Q - F) / den;
+    if (MODE == 1) {
+      // compensated accumulation: T = hi + lo, Fast2Sum of hi and (dT + lo)
+      const float lo = a.loin[k];
+      const float yv = (float)dT + lo;
+      const float tv = (float)T + yv;
+      a.loout[k] = yv - (tv - (float)T);
+      Tout[k] = (R)tv;
+    } else {
+      Tout[k] = T + dT;
+    }
+  }
+}
+
+template <typename R, int NE, int MODE, bool TDK, bool TDC>
+hipError_t step_t(const StepArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_step<R, NE, MODE, TDK, TDC>), dim3(8 * a.nper), dim3(a.block),
+                     a.lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename R, int NE, int MODE, bool TDK, bool TDC>
+hipError_t step_attr(int bytes) {
+  return hipFuncSetAttribute((const void *)k_step<R, NE, MODE, TDK, TDC>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <typename R, int NE, int MODE>
+hipError_t step_dispatch_tt(const StepArgs &a, hipStream_t s) {
+  if (a.tdk) return a.tdc ? step_t<R, NE, MODE, true, true>(a, s) : step_t<R, NE, MODE, true, false>(a, s);
+  return a.tdc ? step_t<R, NE, MODE, false, true>(a, s) : step_t<R, NE, MODE, false, false>(a, s);
+}
+
+template <typename R, int NE, int MODE>
+hipError_t attr_dispatch_tt(int tdk, int tdc, int bytes) {
+  if (tdk) return tdc ? step_attr<R, NE, MODE, true, true>(bytes) : step_attr<R, NE, MODE, true, false>(bytes);
+  return tdc ? step_attr<R, NE, MODE, false, true>(bytes) : step_attr<R, NE, MODE, false, false>(bytes);
+}
+
+// caller order <-> internal order, FP64 in the caller's arrays
+template <typename R, int MODE>
+__global__ void k_set_T(int64_t N, const double *Tuser, const int32_t *perm, R *T, float *lo) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  double v = Tuser[k];
+  int32_t ki = perm[k];
+  R hv = (R)v;
+  T[ki] = hv;
+  if (MODE == 1) lo[ki] = (float)(v - (double)hv);
+}
+
+template <typename R, int MODE>
+__global__ void k_set_dir(int64_t ndir, const int32_t *node, const double *val, R *T, float *lo) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= ndir) return;
+  double v = val[i];
+  R hv = (R)v;
+  T[node[i]] = hv;
+  if (MODE == 1) lo[node[i]] = (float)(v - (double)hv);
+}
+
+template <typename R, int MODE>
+__global__ void k_get_T(int64_t N, const int32_t *perm, const R *T, const float *lo, double *Tuser) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  int32_t ki = perm[k];
+  double v = (double)T[ki];
+  if (MODE == 1) v += (double)lo[ki];
+  Tuser[k] = v;
+}
+
+template <typename R, int MODE>
+__global__ void k_check(int64_t N, const R *T, const float *lo, double lo_b, double hi_b, int *flag) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  double v = (double)T[k];
+  if (MODE == 1) v += (double)lo[k];
+  if (!(v >= lo_b && v <= hi_b)) atomicOr(flag, 1);  // also catches NaN
+}
+
+__global__ void k_permute(int eb, int64_t N, const int32_t *perm, const unsigned char *src,
+                          unsigned char *dst, int to_internal) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  int64_t ki = perm[k];
+  const unsigned char *s = src + (to_internal ? k : ki) * eb;
+  unsigned char *d = dst + (to_internal ? ki : k) * eb;
+  for (int i = 0; i < eb; i++) d[i] = s[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+hipError_t launch_geom(const GeomArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_geom, dim3(blocks_for(a.E, 128)), dim3(128), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass(const MassArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_mass, dim3(blocks_for(a.N, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bnd(const BndArgs &a, hipStream_t s) {
+  if (a.nf > 0) hipLaunchKernelGGL(k_face_area, dim3(blocks_for(a.nf, 256)), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.nrec > 0) hipLaunchKernelGGL(k_bnd_rec, dim3(blocks_for(a.nrec, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt(const DtArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt_elem, dim3(blocks_for(a.E, 256)), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.nrec > 0) hipLaunchKernelGGL(k_dt_node, dim3(blocks_for(a.nrec, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_arrays(const NodeArrArgs &a, hipStream_t s) {
+  int64_t n = a.N > a.nrec ? a.N : a.nrec;
+  if (a.prec == 1)
+    hipLaunchKernelGGL(k_node_arrays<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_node_arrays<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t launch_expand_H(int prec, int64_t Eexp, int64_t E, const int32_t *eorig,
+                           const double *H0, const double *kscale, void *H, hipStream_t s) {
+  if (prec == 1)
+    hipLaunchKernelGGL(k_expand_H<double>, dim3(blocks_for(Eexp, 256)), dim3(256), 0, s, Eexp, E,
+                       eorig, H0, kscale, (double *)H);
+  else
+    hipLaunchKernelGGL(k_expand_H<float>, dim3(blocks_for(Eexp, 256)), dim3(256), 0, s, Eexp, E,
+                       eorig, H0, kscale, (float *)H);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const StepArgs &a, hipStream_t s) {
+  if (a.prec == 1)
+    return a.ne == 8 ? step_dispatch_tt<double, 8, 0>(a, s) : step_dispatch_tt<double, 4, 0>(a, s);
+  if (a.prec == 0)
+    return a.ne == 8 ? step_dispatch_tt<float, 8, 1>(a, s) : step_dispatch_tt<float, 4, 1>(a, s);
+  return a.ne == 8 ? step_dispatch_tt<float, 8, 0>(a, s) : step_dispatch_tt<float, 4, 0>(a, s);
+}
+
+hipError_t step_set_lds_limit(int prec, int ne, int tdk, int tdc, int bytes) {
+  if (prec == 1)
+    return ne == 8 ? attr_dispatch_tt<double, 8, 0>(tdk, tdc, bytes) : attr_dispatch_tt<double, 4, 0>(tdk, tdc, bytes);
+  if (prec == 0)
+    return ne == 8 ? attr_dispatch_tt<float, 8, 1>(tdk, tdc, bytes) : attr_dispatch_tt<float, 4, 1>(tdk, tdc, bytes);
+  return ne == 8 ? attr_dispatch_tt<float, 8, 0>(tdk, tdc, bytes) : attr_dispatch_tt<float, 4, 0>(tdk, tdc, bytes);
+}
+
+hipError_t launch_set_T(int prec, int64_t N, const double *Tuser, const int32_t *perm, void *T,
+                        float *lo, int64_t ndir, const int32_t *dir_node, const double *dir_T,
+                        hipStream_t s) {
+  dim3 g(blocks_for(N, 256)), gd(blocks_for(ndir, 256)), b(256);
+  if (prec == 1) {
+    hipLaunchKernelGGL((k_set_T<double, 0>), g, b, 0, s, N, Tuser, perm, (double *)T, lo);
+    if (ndir) hipLaunchKernelGGL((k_set_dir<double, 0>), gd, b, 0, s, ndir, dir_node, dir_T, (double *)T, lo);
+  } else if (prec == 0) {
+    hipLaunchKernelGGL((k_set_T<float, 1>), g, b, 0, s, N, Tuser, perm, (float *)T, lo);
+    if (ndir) hipLaunchKernelGGL((k_set_dir<float, 1>), gd, b, 0, s, ndir, dir_node, dir_T, (float *)T, lo);
+  } else {
+    hipLaunchKernelGGL((k_set_T<float, 0>), g, b, 0, s, N, Tuser, perm, (float *)T, lo);
+    if (ndir) hipLaunchKernelGGL((k_set_dir<float, 0>), gd, b, 0, s, ndir, dir_node, dir_T, (float *)T, lo);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_get_T(int prec, int64_t N, const int32_t *perm, const void *T, const float *lo,
+                        double *Tuser, hipStream_t s) {
+  dim3 g(blocks_for(N, 256)), b(256);
+  if (prec == 1)
+    hipLaunchKernelGGL((k_get_T<double, 0>), g, b, 0, s, N, perm, (const double *)T, lo, Tuser);
+  else if (prec == 0)
+    hipLaunchKernelGGL((k_get_T<float, 1>), g, b, 0, s, N, perm, (const float *)T, lo, Tuser);
+  else
+    hipLaunchKernelGGL((k_get_T<float, 0>), g, b, 0, s, N, perm, (const float *)T, lo, Tuser);
+  return hipGetLastError();
+}
+
+hipError_t launch_check(int prec, int64_t N, const void *T, const float *lo, double lo_b,
+                        double hi_b, int *flag, hipStream_t s) {
+  dim3 g(blocks_for(N, 256)), b(256);
+  if (prec == 1)
+    hipLaunchKernelGGL((k_check<double, 0>), g, b, 0, s, N, (const double *)T, lo, lo_b, hi_b, flag);
+  else if (prec == 0)
+    hipLaunchKernelGGL((k_check<float, 1>), g, b, 0, s, N, (const float *)T, lo, lo_b, hi_b, flag);
+  else
+    hipLaunchKernelGGL((k_check<float, 0>), g, b, 0, s, N, (const float *)T, lo, lo_b, hi_b, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute(int elem_bytes, int64_t N, const int32_t *perm, const void *src,
+                          void *dst, int to_internal, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute, dim3(blocks_for(N, 256)), dim3(256), 0, s, elem_bytes, N, perm,
+                     (const unsigned char *)src, (unsigned char *)dst, to_internal);
+  return hipGetLastError();
+}
+
+}  // namespace fed

@@ -1,0 +1,257 @@
+// Host-side tiling of a mesh for the owner-computes step kernel.
+//
+// Nodes are split into compact tiles by recursive coordinate bisection (per
+// instance of a batched mesh).  A tile owns a contiguous range of internal node
+// ids and carries its own copy of every element incident to an owned node, so
+// one workgroup can compute all loads of its nodes from LDS without atomics.
+// Each element-node pair is tagged with the node-local position of the element
+// in the node's incidence list sorted by element id: the kernel writes the
+// element's contribution into that slot and sums slots in position order, so
+// every nodal sum runs in ascending element order whatever the tiling.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "fed_internal.h"
+
+namespace fed {
+
+namespace {
+
+struct Builder {
+  const TilingInput &in;
+  Tiling &out;
+  std::vector<int64_t> cptr;   // caller-order incidence CSR
+  std::vector<int32_t> celem;
+  std::vector<int8_t> ca;
+  std::vector<uint16_t> posEA; // [E * ne] position of e in the list of node conn[a,e]
+  std::vector<int32_t> stamp_own, stamp_touch;
+  int32_t stamp = 0;
+  int32_t touch_limit = 0;
+
+  explicit Builder(const TilingInput &i, Tiling &o) : in(i), out(o) {}
+
+  const int32_t &node(int64_t e, int a) const { return in.conn[(int64_t)a * in.E + e]; }
+
+  void incidence() {
+    const int64_t N = in.N, E = in.E;
+    const int ne = in.ne;
+    cptr.assign(N + 1, 0);
+    for (int64_t e = 0; e < E; e++)
+      for (int a = 0; a < ne; a++) cptr[node(e, a) + 1]++;
+    for (int64_t k = 0; k < N; k++) cptr[k + 1] += cptr[k];
+    celem.resize(cptr[N]);
+    ca.resize(cptr[N]);
+    posEA.resize((size_t)E * ne);
+    std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t e = 0; e < E; e++)
+      for (int a = 0; a < ne; a++) {
+        int32_t k = node(e, a);
+        int64_t p = fill[k]++;
+        celem[p] = (int32_t)e;
+        ca[p] = (int8_t)a;
+        posEA[e * ne + a] = (uint16_t)(p - cptr[k]);
+      }
+    int32_t mx = 0;
+    for (int64_t k = 0; k < N; k++) mx = std::max<int32_t>(mx, (int32_t)(cptr[k + 1] - cptr[k]));
+    out.maxinc = mx;
+    int pb = 1;
+    while ((1 << pb) < mx) pb++;
+    out.pb = pb;
+    touch_limit = 1 << (16 - pb);
+  }
+
+  // nown + nhalo of a candidate tile made of nodes ids[b, e)
+  int64_t touched(const std::vector<int32_t> &ids, size_t b, size_t e) {
+    ++stamp;
+    for (size_t i = b; i < e; i++) stamp_own[ids[i]] = stamp;
+    int64_t halo = 0;
+    for (size_t i = b; i < e; i++) {
+      int32_t k = ids[i];
+      for (int64_t p = cptr[k]; p < cptr[k + 1]; p++) {
+        int32_t el = celem[p];
+        for (int a = 0; a < in.ne; a++) {
+          int32_t j = node(el, a);
+          if (stamp_own[j] != stamp && stamp_touch[j] != stamp) {
+            stamp_touch[j] = stamp;
+            halo++;
+          }
+        }
+      }
+    }
+    return (int64_t)(e - b) + halo;
+  }
+
+  bool fits(const std::vector<int32_t> &ids, size_t b, size_t e) {
+    int64_t nown = (int64_t)(e - b);
+    int64_t nt = touched(ids, b, e);
+    int64_t lds = (int64_t)in.real_bytes * (nt + (int64_t)out.maxinc * nown);
+    return nt <= touch_limit && lds <= in.lds_budget;
+  }
+
+  // recursive coordinate bisection of ids[b, e) into leaves (DFS order)
+  bool rcb(std::vector<int32_t> &ids, size_t b0, size_t e0,
+           std::vector<std::pair<size_t, size_t>> &leaves) {
+    std::vector<std::pair<size_t, size_t>> stack{{b0, e0}};
+    const double *X[3] = {in.x, in.y, in.z};
+    while (!stack.empty()) {
+      auto [b, e] = stack.back();
+      stack.pop_back();
+      size_t n = e - b;
+      if (n == 0) continue;
+      if (n <= (size_t)in.target_nodes && fits(ids, b, e)) {
+        leaves.push_back({b, e});
+        continue;
+      }
+      if (n == 1) return false;
+      size_t L = std::max<size_t>(2, (n + in.target_nodes - 1) / in.target_nodes);
+      size_t nl = std::max<size_t>(1, n * (L / 2) / L);
+      double lo[3], hi[3];
+      for (int d = 0; d < 3; d++) lo[d] = hi[d] = X[d][ids[b]];
+      for (size_t i = b; i < e; i++)
+        for (int d = 0; d < 3; d++) {
+          lo[d] = std::min(lo[d], X[d][ids[i]]);
+          hi[d] = std::max(hi[d], X[d][ids[i]]);
+        }
+      int ax = 0;
+      for (int d = 1; d < 3; d++)
+        if (hi[d] - lo[d] > hi[ax] - lo[ax]) ax = d;
+      const double *c = X[ax];
+      std::nth_element(ids.begin() + b, ids.begin() + b + nl, ids.begin() + e,
+                       [c](int32_t p, int32_t q) { return c[p] < c[q] || (c[p] == c[q] && p < q); });
+      stack.push_back({b + nl, e});
+      stack.push_back({b, b + nl});
+    }
+    return true;
+  }
+
+  std::string run() {
+    const int64_t N = in.N, E = in.E;
+    const int ne = in.ne;
+    incidence();
+    stamp_own.assign(N, 0);
+    stamp_touch.assign(N, 0);
+    // groups: one per instance (caller node order inside), or one group
+    std::vector<int32_t> ids(N);
+    std::iota(ids.begin(), ids.end(), 0);
+    std::vector<size_t> gstart{0};
+    if (in.node_instance) {
+      std::stable_sort(ids.begin(), ids.end(), [&](int32_t p, int32_t q) {
+        return in.node_instance[p] < in.node_instance[q];
+      });
+      for (int64_t i = 1; i < N; i++)
+        if (in.node_instance[ids[i]] != in.node_instance[ids[i - 1]]) gstart.push_back(i);
+    }
+    gstart.push_back(N);
+    std::vector<std::pair<size_t, size_t>> leaves;
+    for (size_t g = 0; g + 1 < gstart.size(); g++)
+      if (!rcb(ids, gstart[g], gstart[g + 1], leaves))
+        return "a single node touches more nodes or LDS than one tile can hold "
+               "(node incidence too high)";
+    // internal order: tile by tile, boundary-record nodes first, caller id inside
+    out.nt = (int32_t)leaves.size();
+    out.tiles.resize(out.nt);
+    out.perm.assign(N, -1);
+    out.iperm.resize(N);
+    int32_t next = 0, bnext = 0;
+    for (int32_t t = 0; t < out.nt; t++) {
+      auto [b, e] = leaves[t];
+      std::sort(ids.begin() + b, ids.begin() + e, [&](int32_t p, int32_t q) {
+        bool bp = in.has_bnd && in.has_bnd[p], bq = in.has_bnd && in.has_bnd[q];
+        return bp != bq ? bp : p < q;
+      });
+      TileHdr &th = out.tiles[t];
+      th.nstart = next;
+      th.nown = (int32_t)(e - b);
+      th.nbnd = 0;
+      th.bstart = bnext;
+      for (size_t i = b; i < e; i++) {
+        int32_t k = ids[i];
+        if (in.has_bnd && in.has_bnd[k]) th.nbnd++;
+        out.perm[k] = next;
+        out.iperm[next] = k;
+        next++;
+      }
+      bnext += th.nbnd;
+    }
+    // per tile: incident elements, halo, packed entries
+    std::vector<int32_t> loc(N, -1), locstamp(N, -1);
+    std::vector<int32_t> telems, thalo;
+    out.halo.clear();
+    out.ent.clear();
+    out.eorig.clear();
+    out.eowner.clear();
+    out.ntouch_max = out.nown_max = 0;
+    int64_t lds_max = 0;
+    for (int32_t t = 0; t < out.nt; t++) {
+      TileHdr &th = out.tiles[t];
+      telems.clear();
+      thalo.clear();
+      for (int32_t j = 0; j < th.nown; j++) {
+        int32_t k = out.iperm[th.nstart + j];
+        for (int64_t p = cptr[k]; p < cptr[k + 1]; p++) telems.push_back(celem[p]);
+      }
+      std::sort(telems.begin(), telems.end());
+      telems.erase(std::unique(telems.begin(), telems.end()), telems.end());
+      for (int32_t el : telems)
+        for (int a = 0; a < ne; a++) {
+          int32_t ki = out.perm[node(el, a)];
+          bool own = ki >= th.nstart && ki < th.nstart + th.nown;
+          if (!own && locstamp[ki] != t) {
+            locstamp[ki] = t;
+            thalo.push_back(ki);
+          }
+        }
+      std::sort(thalo.begin(), thalo.end());
+      for (size_t h = 0; h < thalo.size(); h++) loc[thalo[h]] = th.nown + (int32_t)h;
+      th.hstart = (int32_t)out.halo.size();
+      th.nhalo = (int32_t)thalo.size();
+      out.halo.insert(out.halo.end(), thalo.begin(), thalo.end());
+      th.estart = (int32_t)out.eorig.size();
+      th.ecount = (int32_t)telems.size();
+      for (int32_t el : telems) {
+        out.eorig.push_back(el);
+        int32_t k0 = out.perm[node(el, 0)];
+        out.eowner.push_back(k0 >= th.nstart && k0 < th.nstart + th.nown ? 1 : 0);
+        for (int a = 0; a < ne; a++) {
+          int32_t ki = out.perm[node(el, a)];
+          int32_t l = (ki >= th.nstart && ki < th.nstart + th.nown) ? ki - th.nstart : loc[ki];
+          out.ent.push_back((uint16_t)(((uint32_t)l << out.pb) | posEA[(size_t)el * ne + a]));
+        }
+      }
+      int32_t ntouch = th.nown + th.nhalo;
+      out.ntouch_max = std::max(out.ntouch_max, ntouch);
+      out.nown_max = std::max(out.nown_max, th.nown);
+      lds_max = std::max<int64_t>(lds_max, (int64_t)in.real_bytes *
+                                               (ntouch + (int64_t)out.maxinc * th.nown));
+      if (ntouch > touch_limit) return "internal: tile exceeds the local index range";
+    }
+    out.lds_bytes = (int32_t)lds_max;
+    // incidence in internal node order
+    out.inc_ptr.assign(N + 1, 0);
+    out.inc_elem.resize(cptr[N]);
+    out.inc_a.resize(cptr[N]);
+    for (int64_t ki = 0; ki < N; ki++) {
+      int32_t k = out.iperm[ki];
+      int64_t cnt = cptr[k + 1] - cptr[k];
+      out.inc_ptr[ki + 1] = out.inc_ptr[ki] + cnt;
+      std::copy(celem.begin() + cptr[k], celem.begin() + cptr[k + 1],
+                out.inc_elem.begin() + out.inc_ptr[ki]);
+      std::copy(ca.begin() + cptr[k], ca.begin() + cptr[k + 1],
+                out.inc_a.begin() + out.inc_ptr[ki]);
+    }
+    (void)E;
+    return "";
+  }
+};
+
+}  // namespace
+
+std::string build_tiling(const TilingInput &in, Tiling &out) {
+  if (in.N <= 0 || in.E <= 0) return "empty mesh";
+  if (in.target_nodes < 1) return "tile_nodes must be positive";
+  Builder b(in, out);
+  return b.run();
+}
+
+}  // namespace fed

@@ -1,0 +1,171 @@
+"""Python front end of the FED-FEM GPU library.
+
+``Simulation`` marshals a problem description (the dict layout documented in
+``workloads.problems``) into the C ABI and exposes the three stages of the
+method: pre-computation (construction), initialisation
+(``set_temperature``) and time stepping (``step``).  PyTorch is used only for
+device memory and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+PRECISIONS = {"fp32c": L.FED_FP32C, "fp64": L.FED_FP64, "fp32": L.FED_FP32}
+
+
+def _ptr(a, t=C.c_double):
+    return None if a is None else a.ctypes.data_as(C.POINTER(t))
+
+
+def current_stream():
+    """hipStream_t of torch's current stream (None = default stream)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return None
+
+
+class Simulation:
+    def __init__(self, prob, prec="fp32c", tile_nodes=0, block_threads=0, allow_unstable=False,
+                 stream=None):
+        lib = L.lib()
+        self.prec = prec
+        self.prob = prob
+        f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+        keep = []   # arrays referenced by the ctypes structs until fed_create returns
+        x, y, z = f64(prob["x"]), f64(prob["y"]), f64(prob["z"])
+        conn = i32(prob["conn"])
+        keep += [x, y, z, conn]
+        self.N, self.E = x.size, conn.shape[1]
+        mesh = L.fed_mesh(L.FED_HEX8 if prob["elem"] == "hex8" else L.FED_TET4, self.N, self.E,
+                          _ptr(x), _ptr(y), _ptr(z), _ptr(conn, C.c_int32))
+        mats_in = prob["materials"]
+        arr = (L.fed_material * len(mats_in))()
+        for i, m in enumerate(mats_in):
+            arr[i].rho, arr[i].c0, arr[i].c1 = m["rho"], m["c0"], m["c1"]
+            for r in range(6):
+                arr[i].k[r] = m["k"][r]
+            arr[i].s0, arr[i].s1 = m["s0"], m["s1"]
+        emat = None if prob["elem_material"] is None else i32(prob["elem_material"])
+        ek = None if prob["elem_k"] is None else f64(prob["elem_k"])
+        ks = None if prob["elem_kscale"] is None else f64(prob["elem_kscale"])
+        keep += [emat, ek, ks]
+        mats = L.fed_materials(len(mats_in), arr, _ptr(emat, C.c_int32), _ptr(ek), _ptr(ks))
+        dn, dT = i32(prob["dir_nodes"]), f64(prob["dir_T"])
+        keep += [dn, dT]
+        faces = prob["faces"]
+        if faces is not None and faces.shape[0] > 0:
+            faces = i32(faces)
+            fh, fTa, feps, fq = (f64(prob[k]) for k in ("face_h", "face_Ta", "face_eps", "face_q"))
+            nf, nfn = faces.shape
+        else:
+            faces = fh = fTa = feps = fq = None
+            nf, nfn = 0, 4
+        keep += [faces, fh, fTa, feps, fq]
+        pn, pW = i32(prob["pt_nodes"]), f64(prob["pt_W"])
+        keep += [pn, pW]
+        bcs = L.fed_bcs(dn.size, _ptr(dn, C.c_int32), _ptr(dT), nf, nfn, _ptr(faces, C.c_int32),
+                        _ptr(fh), _ptr(fTa), _ptr(feps), _ptr(fq), pn.size, _ptr(pn, C.c_int32),
+                        _ptr(pW), float(prob["Tz"]))
+        inst = None if prob["node_instance"] is None else i32(prob["node_instance"])
+        keep.append(inst)
+        dt = 0.0 if prob["dt"] is None else float(prob["dt"])
+        opt = L.fed_options(PRECISIONS[prec], dt, float(prob["safety"]), float(prob["T_lo"]),
+                            float(prob["T_hi"]), int(bool(allow_unstable)),
+                            _ptr(inst, C.c_int32), int(tile_nodes), int(block_threads))
+        self.stream = current_stream() if stream is None else stream
+        ctx = C.c_void_p()
+        L.check(lib.fed_create(C.byref(mesh), C.byref(mats), C.byref(bcs), C.byref(opt),
+                               self.stream, C.byref(ctx)))
+        self._ctx = ctx
+        info = L.fed_info()
+        L.check(lib.fed_info_get(ctx, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in L.fed_info._fields_}
+        n = self.info["n_instances"]
+        self.dt_crit, self.dt = np.zeros(n), np.zeros(n)
+        L.check(lib.fed_dt(ctx, _ptr(self.dt_crit), _ptr(self.dt), n))
+
+    # ------------------------------------------------------------------
+    def _c(self):
+        if self._ctx is None:
+            raise RuntimeError("simulation closed")
+        return self._ctx
+
+    def set_temperature(self, T=None):
+        """Initialisation (Sec. 3.5 (ii)): T0 (caller order, FP64 numpy array or
+        CUDA tensor; default the problem's T0) with the Dirichlet values applied."""
+        T = self.prob["T0"] if T is None else T
+        if hasattr(T, "is_cuda") and T.is_cuda:
+            import torch
+            assert T.dtype == torch.float64 and T.is_contiguous() and T.numel() == self.N
+            L.check(L.lib().fed_set_temperature(self._c(), C.c_void_p(T.data_ptr()), 1, self.stream))
+        else:
+            Th = np.ascontiguousarray(T, dtype=np.float64)
+            assert Th.size == self.N
+            L.check(L.lib().fed_set_temperature(self._c(), Th.ctypes.data_as(C.c_void_p), 0,
+                                                self.stream))
+
+    def step(self, n, graph_steps=None):
+        """Enqueue n explicit steps (asynchronous)."""
+        if graph_steps:
+            L.check(L.lib().fed_step_graph(self._c(), int(n), int(graph_steps), self.stream))
+        else:
+            L.check(L.lib().fed_step(self._c(), int(n), self.stream))
+
+    def temperature(self, out=None):
+        """Current temperatures (FP64, caller order).  Synchronises; raises
+        FedError(FED_E_UNSTABLE) if the health check fired."""
+        if out is not None:
+            L.check(L.lib().fed_get_temperature(self._c(), C.c_void_p(out.data_ptr()), 1,
+                                                self.stream))
+            return out
+        T = np.empty(self.N)
+        L.check(L.lib().fed_get_temperature(self._c(), T.ctypes.data_as(C.c_void_p), 0,
+                                            self.stream))
+        return T
+
+    @property
+    def steps_taken(self):
+        v = C.c_int64()
+        L.check(L.lib().fed_steps_taken(self._c(), C.byref(v)))
+        return v.value
+
+    def get_state(self):
+        dt = np.float64 if self.prec == "fp64" else np.float32
+        hi, lo = np.empty(self.N, dt), np.empty(self.N, np.float32)
+        st = C.c_int64()
+        L.check(L.lib().fed_get_state(self._c(), hi.ctypes.data_as(C.c_void_p),
+                                      lo.ctypes.data_as(C.c_void_p), C.byref(st), self.stream))
+        return hi, lo, st.value
+
+    def set_state(self, hi, lo, step):
+        dt = np.float64 if self.prec == "fp64" else np.float32
+        hi = np.ascontiguousarray(hi, dtype=dt)
+        lo = np.ascontiguousarray(lo, dtype=np.float32)
+        L.check(L.lib().fed_set_state(self._c(), hi.ctypes.data_as(C.c_void_p),
+                                      lo.ctypes.data_as(C.c_void_p), int(step), self.stream))
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None:
+            L.lib().fed_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

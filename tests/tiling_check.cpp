@@ -1,0 +1,163 @@
+// Host-side invariant checker of the tiler (built with g++ and sanitizers by
+// tests/test_host_tiling.py; no HIP).  Usage:
+//   tiling_check <hex|tet> nx ny nz target [ninst]
+// Builds a structured box (or ninst disjoint copies), tiles it and checks that
+// every packed entry decodes to its node, that every owned node's slot
+// positions are 0..count-1 in ascending element order, that each element has
+// exactly one owner copy, and the size limits.  Prints "OK <tiles>" or fails.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <set>
+#include <vector>
+
+#include "../paper_1909_03355_amd/csrc/fed_internal.h"
+
+#define REQUIRE(c)                                                   \
+  do {                                                               \
+    if (!(c)) {                                                      \
+      std::fprintf(stderr, "check failed: %s (line %d)\n", #c, __LINE__); \
+      return 1;                                                      \
+    }                                                                \
+  } while (0)
+
+int main(int argc, char **argv) {
+  if (argc < 6) return 2;
+  bool hex = std::strcmp(argv[1], "hex") == 0;
+  int nx = std::atoi(argv[2]), ny = std::atoi(argv[3]), nz = std::atoi(argv[4]);
+  int target = std::atoi(argv[5]);
+  int ninst = argc > 6 ? std::atoi(argv[6]) : 1;
+  const int ne = hex ? 8 : 4;
+  auto nid = [&](int i, int j, int k) { return i + (nx + 1) * (j + (ny + 1) * k); };
+  const int np1 = (nx + 1) * (ny + 1) * (nz + 1);
+  std::vector<double> x, y, z;
+  std::vector<std::vector<int>> elems;
+  std::vector<int32_t> inst;
+  static const int S[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0},
+                              {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
+  static const int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  for (int c = 0; c < ninst; c++) {
+    int base = c * np1;
+    for (int k = 0; k <= nz; k++)
+      for (int j = 0; j <= ny; j++)
+        for (int i = 0; i <= nx; i++) {
+          x.push_back(i + 3.0 * c * nx);
+          y.push_back(j);
+          z.push_back(k);
+          inst.push_back(c);
+        }
+    for (int k = 0; k < nz; k++)
+      for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+          if (hex) {
+            std::vector<int> e;
+            for (auto &s : S) e.push_back(base + nid(i + s[0], j + s[1], k + s[2]));
+            elems.push_back(e);
+          } else {
+            for (auto &p : P) {
+              int o[3] = {0, 0, 0};
+              std::vector<int> e{base + nid(i, j, k)};
+              for (int ax : p) {
+                o[ax]++;
+                e.push_back(base + nid(i + o[0], j + o[1], k + o[2]));
+              }
+              elems.push_back(e);
+            }
+          }
+        }
+  }
+  const int64_t N = (int64_t)x.size(), E = (int64_t)elems.size();
+  std::vector<int32_t> conn(ne * E);
+  for (int64_t e = 0; e < E; e++)
+    for (int a = 0; a < ne; a++) conn[a * E + e] = elems[e][a];
+  std::vector<uint8_t> has_bnd(N, 0);
+  for (int64_t k = 0; k < N; k += 7) has_bnd[k] = 1;
+  fed::TilingInput in;
+  in.N = N;
+  in.E = E;
+  in.ne = ne;
+  in.x = x.data();
+  in.y = y.data();
+  in.z = z.data();
+  in.conn = conn.data();
+  in.node_instance = ninst > 1 ? inst.data() : nullptr;
+  in.has_bnd = has_bnd.data();
+  in.target_nodes = target;
+  fed::Tiling T;
+  std::string err = fed::build_tiling(in, T);
+  if (!err.empty()) {
+    std::fprintf(stderr, "tiling error: %s\n", err.c_str());
+    return 1;
+  }
+  // permutation and contiguous tiles
+  std::vector<int> seen(N, 0);
+  for (int64_t k = 0; k < N; k++) {
+    REQUIRE(T.perm[k] >= 0 && T.perm[k] < N);
+    REQUIRE(T.iperm[T.perm[k]] == k);
+    seen[T.perm[k]]++;
+  }
+  for (int64_t k = 0; k < N; k++) REQUIRE(seen[k] == 1);
+  int32_t next = 0, bnext = 0;
+  const uint32_t limit = 1u << (16 - T.pb);
+  std::vector<int> owners(E, 0);
+  for (int t = 0; t < T.nt; t++) {
+    const fed::TileHdr &th = T.tiles[t];
+    REQUIRE(th.nstart == next && th.nown > 0 && th.nown <= target);
+    REQUIRE(th.bstart == bnext);
+    next += th.nown;
+    bnext += th.nbnd;
+    for (int j = 0; j < th.nown; j++) {
+      int32_t k = T.iperm[th.nstart + j];
+      REQUIRE((j < th.nbnd) == (has_bnd[k] != 0));
+      if (ninst > 1) REQUIRE(inst[k] == inst[T.iperm[th.nstart]]);
+    }
+    REQUIRE((uint32_t)(th.nown + th.nhalo) <= limit);
+    REQUIRE(4LL * (th.nown + th.nhalo + (int64_t)T.maxinc * th.nown) <= T.lds_bytes);
+    // expected element set: incident elements of owned nodes
+    std::set<int32_t> want;
+    for (int j = 0; j < th.nown; j++) {
+      int32_t ki = th.nstart + j;
+      for (int64_t p = T.inc_ptr[ki]; p < T.inc_ptr[ki + 1]; p++) want.insert(T.inc_elem[p]);
+    }
+    REQUIRE((int)want.size() == th.ecount);
+    std::vector<std::vector<std::pair<int32_t, int>>> got(th.nown);  // (elem, pos)
+    int32_t prev = -1;
+    for (int i = 0; i < th.ecount; i++) {
+      int64_t ie = th.estart + i;
+      int32_t e = T.eorig[ie];
+      REQUIRE(e > prev && want.count(e));
+      prev = e;
+      owners[e] += T.eowner[ie];
+      for (int a = 0; a < ne; a++) {
+        uint32_t v = T.ent[ie * ne + a];
+        uint32_t loc = v >> T.pb, pos = v & ((1u << T.pb) - 1);
+        REQUIRE(loc < (uint32_t)(th.nown + th.nhalo));
+        int32_t ki = loc < (uint32_t)th.nown ? th.nstart + loc : T.halo[th.hstart + loc - th.nown];
+        REQUIRE(ki == T.perm[conn[a * E + e]]);
+        if (loc < (uint32_t)th.nown) {
+          REQUIRE((int)pos < T.maxinc);
+          got[loc].push_back({e, (int)pos});
+        }
+      }
+    }
+    for (int j = 0; j < th.nown; j++) {
+      int32_t ki = th.nstart + j;
+      int64_t cnt = T.inc_ptr[ki + 1] - T.inc_ptr[ki];
+      REQUIRE((int64_t)got[j].size() == cnt);
+      for (size_t q = 0; q < got[j].size(); q++) {
+        REQUIRE(got[j][q].second == (int)q);  // elements ascending == positions ascending
+        REQUIRE(got[j][q].first == T.inc_elem[T.inc_ptr[ki] + q]);
+      }
+    }
+    for (int h = 0; h < th.nhalo; h++) {
+      int32_t ki = T.halo[th.hstart + h];
+      REQUIRE(ki < th.nstart || ki >= th.nstart + th.nown);
+      if (h) REQUIRE(ki > T.halo[th.hstart + h - 1]);
+    }
+  }
+  REQUIRE(next == N);
+  for (int64_t e = 0; e < E; e++) REQUIRE(owners[e] == 1);
+  std::printf("OK %d tiles, %zu expanded elements, maxinc %d, pb %d\n", T.nt, T.eorig.size(),
+              T.maxinc, T.pb);
+  return 0;
+}
