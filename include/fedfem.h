@@ -117,7 +117,7 @@ typedef struct {
   const int32_t *node_instance; /* host, n_nodes instance ids of a batched mesh of
                                    independent instances (one dt per instance), or NULL */
   int32_t tile_nodes;        /* owned nodes per tile; 0 = default */
-  int32_t block_threads;     /* threads per tile workgroup (64..1024); 0 = default */
+  int32_t block_threads;     /* threads per tile workgroup (64..512, multiple of 64); 0 = default */
 } fed_options;
 
 typedef struct fed_ctx fed_ctx;

@@ -233,8 +233,8 @@ int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, cons
         return fail(FED_E_ARG, "node_instance[%lld] out of range", (long long)k);
   if (o->tile_nodes < 0) return fail(FED_E_ARG, "tile_nodes < 0");
   if (o->block_threads != 0 &&
-      (o->block_threads < 64 || o->block_threads > 1024 || o->block_threads % 64))
-    return fail(FED_E_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
+      (o->block_threads < 64 || o->block_threads > 512 || o->block_threads % 64))
+    return fail(FED_E_ARG, "block_threads must be a multiple of 64 in [64, 512]");
   return FED_OK;
 }
 

@@ -308,16 +308,40 @@ __global__ void k_bnd_rec(BndArgs a) {
 // n_e) at the largest D and smallest c over [T_lo, T_hi]; per boundary node the
 // convection and linearised radiation rate; maxima per instance.
 __global__ void k_dt_elem(DtArgs a) {
+  // one atomic per run of equal instances in a wave: elements of an instance
+  // are contiguous, so a wave-wide max for the wave's first instance plus
+  // per-thread atomics for the rest keeps contention low
+  __shared__ double smax[1024 / 64];
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= a.E) return;
-  const MatDev &mt = a.mats[a.emat ? a.emat[e] : 0];
-  double slo = mt.s0 + mt.s1 * a.T_lo, shi = mt.s0 + mt.s1 * a.T_hi;
-  double clo = mt.c0 + mt.c1 * a.T_lo, chi = mt.c0 + mt.c1 * a.T_hi;
-  double smax = slo > shi ? slo : shi, cmin = clo < chi ? clo : chi;
-  double ks = a.kscale ? a.kscale[e] : 1.0;
-  double lam = a.ne * ks * smax * a.lamgeo[e] / (mt.rho * cmin);
-  int inst = a.elem_inst ? a.elem_inst[e] : 0;
-  if (lam > 0) atomicMax(&a.lamE[inst], (unsigned long long)__double_as_longlong(lam));
+  double lam = 0;
+  int inst = -1;
+  if (e < a.E) {
+    const MatDev &mt = a.mats[a.emat ? a.emat[e] : 0];
+    double slo = mt.s0 + mt.s1 * a.T_lo, shi = mt.s0 + mt.s1 * a.T_hi;
+    double clo = mt.c0 + mt.c1 * a.T_lo, chi = mt.c0 + mt.c1 * a.T_hi;
+    double smax_ = slo > shi ? slo : shi, cmin = clo < chi ? clo : chi;
+    double ks = a.kscale ? a.kscale[e] : 1.0;
+    lam = a.ne * ks * smax_ * a.lamgeo[e] / (mt.rho * cmin);
+    inst = a.elem_inst ? a.elem_inst[e] : 0;
+  }
+  int64_t e0 = blockIdx.x * (int64_t)blockDim.x;
+  int inst0 = a.elem_inst ? a.elem_inst[e0] : 0;
+  bool same = inst == inst0;
+  double v = same ? lam : 0.0;
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_down(v, off, 64);
+    v = o > v ? o : v;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) smax[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); i++) m = smax[i] > m ? smax[i] : m;
+    if (m > 0) atomicMax(&a.lamE[inst0], (unsigned long long)__double_as_longlong(m));
+  }
+  if (!same && inst >= 0 && lam > 0)
+    atomicMax(&a.lamE[inst], (unsigned long long)__double_as_longlong(lam));
 }
 
 __global__ void k_dt_node(DtArgs a) {
@@ -418,25 +442,102 @@ struct Elem<R, 4> {
   }
 };
 
+// packed per-element entries: 8 x u16 (hexahedra) or 4 x u16 (tetrahedra)
 template <int NE>
-__device__ inline void load_ent(const uint16_t *ent, int64_t i, uint32_t v[NE]);
-
+struct Ent;
 template <>
-__device__ inline void load_ent<8>(const uint16_t *ent, int64_t i, uint32_t v[8]) {
-  uint4 w = reinterpret_cast<const uint4 *>(ent)[i];
-  v[0] = w.x & 0xffff; v[1] = w.x >> 16; v[2] = w.y & 0xffff; v[3] = w.y >> 16;
-  v[4] = w.z & 0xffff; v[5] = w.z >> 16; v[6] = w.w & 0xffff; v[7] = w.w >> 16;
+struct Ent<8> {
+  using T = uint4;
+  __device__ static void unpack(const uint4 &w, uint32_t v[8]) {
+    v[0] = w.x & 0xffff; v[1] = w.x >> 16; v[2] = w.y & 0xffff; v[3] = w.y >> 16;
+    v[4] = w.z & 0xffff; v[5] = w.z >> 16; v[6] = w.w & 0xffff; v[7] = w.w >> 16;
+  }
+};
+template <>
+struct Ent<4> {
+  using T = uint2;
+  __device__ static void unpack(const uint2 &w, uint32_t v[4]) {
+    v[0] = w.x & 0xffff; v[1] = w.x >> 16; v[2] = w.y & 0xffff; v[3] = w.y >> 16;
+  }
+};
+
+// element loads of one expanded element into its owned nodes' LDS slots
+template <typename R, int NE, bool TDK>
+__device__ inline void element_to_slots(const typename Ent<NE>::T &w, const R h[6], const R *Tl,
+                                        R *slot, int nown, int pb, uint32_t pmask, R s0, R s1) {
+  uint32_t v[NE], loc[NE];
+  Ent<NE>::unpack(w, v);
+#pragma unroll
+  for (int n = 0; n < NE; n++) loc[n] = v[n] >> pb;
+  R F[NE];
+  Elem<R, NE>::load(Tl, loc, s0, s1, TDK, h, F);
+#pragma unroll
+  for (int n = 0; n < NE; n++)
+    if (loc[n] < (uint32_t)nown) slot[(v[n] & pmask) * nown + loc[n]] = F[n];
 }
 
-template <>
-__device__ inline void load_ent<4>(const uint16_t *ent, int64_t i, uint32_t v[4]) {
-  uint2 w = reinterpret_cast<const uint2 *>(ent)[i];
-  v[0] = w.x & 0xffff; v[1] = w.x >> 16; v[2] = w.y & 0xffff; v[3] = w.y >> 16;
+// per-node coefficients of the update
+template <typename R>
+struct NodeData {
+  R alpha, beta, bA, bAT, beA, bTa, bP;
+  float lo;
+};
+
+template <typename R, int MODE, bool TDC>
+__device__ inline void load_node(const StepArgs &a, const TileHdr &th, int j, NodeData<R> &d) {
+  const int k = th.nstart + j;
+  d.alpha = ((const R *)a.alpha)[k];
+  d.beta = TDC ? ((const R *)a.beta)[k] : (R)0;
+  d.lo = MODE == 1 ? a.loin[k] : 0.0f;
+  if (j < th.nbnd) {
+    const int r = th.bstart + j;
+    d.bA = ((const R *)a.rA)[r];
+    d.bAT = ((const R *)a.rAT)[r];
+    d.beA = ((const R *)a.reA)[r];
+    d.bTa = ((const R *)a.rTa)[r];
+    d.bP = ((const R *)a.rP)[r];
+  }
 }
 
-// MODE: 0 plain (R = float or double), 1 compensated FP32 (hi, lo pair)
+// sum of the node's slots in ascending element order, surface loads, update
+template <typename R, int MODE, bool TDC>
+__device__ inline void node_update(const StepArgs &a, const TileHdr &th, int j, const NodeData<R> &d,
+                                   const R *Tl, const R *slot, R Tz) {
+  const int nown = th.nown, k = th.nstart + j;
+  R F = slot[j];
+  for (int p = 1; p < a.maxinc; p++) F += slot[p * nown + j];
+  const R T = Tl[j];
+  R Q = 0;
+  if (j < th.nbnd) {
+    R x = T - Tz, y = d.bTa - Tz;
+    // (T-Tz)^4 - (Ta-Tz)^4 in factored form
+    Q = (d.bAT - d.bA * T) - d.beA * ((T - d.bTa) * (x + y) * (x * x + y * y)) + d.bP;
+  }
+  R den = d.alpha;
+  if (TDC) den += d.beta * T;
+  const R dT = (Q - F) / den;
+  R *Tout = (R *)a.Tout;
+  if (MODE == 1) {
+    // compensated accumulation: T = hi + lo, Fast2Sum of hi and (dT + lo)
+    const float yv = (float)dT + d.lo;
+    const float tv = (float)T + yv;
+    a.loout[k] = yv - (tv - (float)T);
+    Tout[k] = (R)tv;
+  } else {
+    Tout[k] = T + dT;
+  }
+}
+
+constexpr int kMaxBlock = 512;
+
+// MODE: 0 plain (R = float or double), 1 compensated FP32 (hi, lo pair).
+// Loads that do not depend on T (element entries and operators, node
+// coefficients, boundary records) are issued first, for the first EPT elements
+// and NPT nodes of every thread, so their latency overlaps the T staging.
 template <typename R, int NE, int MODE, bool TDK, bool TDC>
-__global__ __launch_bounds__(1024) void k_step(StepArgs a) {
+__global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs a) {
+  constexpr int EPT = NE == 8 ? 4 : 8;
+  constexpr int NPT = 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int t = (b & 7) * a.nper + (b >> 3);
@@ -444,67 +545,65 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
   const TileHdr th = a.tiles[t];
   const int tid = threadIdx.x, bs = blockDim.x;
   const int nown = th.nown, ntouch = th.nown + th.nhalo;
+  using EntT = typename Ent<NE>::T;
+  const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
+  const R *Hb = (const R *)a.H;
+  // ---- T-independent loads ----
+  EntT ew[EPT];
+  R eh[EPT][6];
+#pragma unroll
+  for (int q = 0; q < EPT; q++) {
+    const int i = tid + q * bs;
+    if (i < th.ecount) {
+      const int64_t e = (int64_t)th.estart + i;
+      ew[q] = ent[e];
+#pragma unroll
+      for (int r = 0; r < 6; r++) eh[q][r] = Hb[(int64_t)r * a.Eexp + e];
+    }
+  }
+  NodeData<R> nd[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; q++) {
+    const int j = tid + q * bs;
+    if (j < nown) load_node<R, MODE, TDC>(a, th, j, nd[q]);
+  }
+  // ---- stage T of owned and halo nodes; clear the slots ----
   R *Tl = reinterpret_cast<R *>(smem_raw);
   R *slot = Tl + ntouch;
   const R *Tin = (const R *)a.Tin;
-  R *Tout = (R *)a.Tout;
-  // stage T of owned and halo nodes; clear the slots
   for (int j = tid; j < nown; j += bs) Tl[j] = Tin[th.nstart + j];
   for (int j = tid; j < th.nhalo; j += bs) Tl[nown + j] = Tin[a.halo[th.hstart + j]];
   const int nslot = a.maxinc * nown;
   for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
   __syncthreads();
-  // element loads into the node-local slots
-  const R *Hb = (const R *)a.H;
+  // ---- element loads into the node-local slots ----
   const R s0 = (R)a.s0, s1 = (R)a.s1;
   const uint32_t pmask = (1u << a.pb) - 1u;
-  for (int i = tid; i < th.ecount; i += bs) {
-    const int64_t e = (int64_t)th.estart + i;
-    uint32_t v[NE], loc[NE];
-    load_ent<NE>(a.ent, e, v);
 #pragma unroll
-    for (int n = 0; n < NE; n++) loc[n] = v[n] >> a.pb;
+  for (int q = 0; q < EPT; q++) {
+    const int i = tid + q * bs;
+    if (i < th.ecount)
+      element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nown, a.pb, pmask, s0, s1);
+  }
+  for (int i = tid + EPT * bs; i < th.ecount; i += bs) {
+    const int64_t e = (int64_t)th.estart + i;
     R h[6];
 #pragma unroll
     for (int r = 0; r < 6; r++) h[r] = Hb[(int64_t)r * a.Eexp + e];
-    R F[NE];
-    Elem<R, NE>::load(Tl, loc, s0, s1, TDK, h, F);
-#pragma unroll
-    for (int n = 0; n < NE; n++)
-      if (loc[n] < (uint32_t)nown) slot[(v[n] & pmask) * nown + loc[n]] = F[n];
+    element_to_slots<R, NE, TDK>(ent[e], h, Tl, slot, nown, a.pb, pmask, s0, s1);
   }
   __syncthreads();
-  // per node: sum in ascending element order, surface loads, explicit update
-  const R *alpha = (const R *)a.alpha, *beta = (const R *)a.beta;
-  const R *rA = (const R *)a.rA, *rAT = (const R *)a.rAT, *reA = (const R *)a.reA;
-  const R *rTa = (const R *)a.rTa, *rP = (const R *)a.rP;
+  // ---- per node: ordered sum, surface loads, explicit update ----
   const R Tz = (R)a.Tz;
-  for (int j = tid; j < nown; j += bs) {
-    const int k = th.nstart + j;
-    R F = slot[j];
-    for (int p = 1; p < a.maxinc; p++) F += slot[p * nown + j];
-    const R T = Tl[j];
-    R Q = 0;
-    if (j < th.nbnd) {
-      const int r = th.bstart + j;
-      R ta = rTa[r];
-      R x = T - Tz, y = ta - Tz;
-      // (T-Tz)^4 - (Ta-Tz)^4 in factored form
-      Q = (rAT[r] - rA[r] * T) - reA[r] * ((T - ta) * (x + y) * (x * x + y * y)) + rP[r];
-    }
-    R den = alpha[k];
-    if (TDC) den += beta[k] * T;
-    const R dT = (Q - F) / den;
-    if (MODE == 1) {
-      // compensated accumulation: T = hi + lo, Fast2Sum of hi and (dT + lo)
-      const float lo = a.loin[k];
-      const float yv = (float)dT + lo;
-      const float tv = (float)T + yv;
-      a.loout[k] = yv - (tv - (float)T);
-      Tout[k] = (R)tv;
-    } else {
-      Tout[k] = T + dT;
-    }
+#pragma unroll
+  for (int q = 0; q < NPT; q++) {
+    const int j = tid + q * bs;
+    if (j < nown) node_update<R, MODE, TDC>(a, th, j, nd[q], Tl, slot, Tz);
+  }
+  for (int j = tid + NPT * bs; j < nown; j += bs) {
+    NodeData<R> d;
+    load_node<R, MODE, TDC>(a, th, j, d);
+    node_update<R, MODE, TDC>(a, th, j, d, Tl, slot, Tz);
   }
 }
 
