@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--tile-nodes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--fuse", type=int, default=0, help="steps per kernel launch (0 = default)")
     ap.add_argument("--oracle-steps", type=int, default=200,
                     help="steps of the CPU oracle sample (timed baseline and error reference)")
     ap.add_argument("--no-oracle", action="store_true")
@@ -72,7 +73,8 @@ def main():
 
     res = {}
     for prec in (["fp32c"] if args.no_fp64 else ["fp32c", "fp64"]):
-        sim = Simulation(prob, prec=prec, tile_nodes=args.tile_nodes, block_threads=args.block)
+        sim = Simulation(prob, prec=prec, tile_nodes=args.tile_nodes, block_threads=args.block,
+                         fuse_steps=args.fuse)
         t = timed_run(sim, args.steps, args.warmup, args.graph_steps)
         res[prec] = dict(t=t, info=sim.info, dt=float(sim.dt[0]))
         sim.close()
@@ -107,8 +109,10 @@ def main():
     t = r32["t"]
     ms = t / args.steps * 1e3
     info = r32["info"]
-    alg = info["algorithmic_bytes_per_step"]
-    achieved = alg / (t / args.steps) / 1e9
+    K = info["fuse_steps"]
+    launches = -(-args.steps // K)
+    alg = info["algorithmic_bytes_per_launch"]
+    achieved = alg / (t / launches) / 1e9
     line = {
         "metric": "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error",
         "value": E * args.steps / t,
@@ -122,19 +126,24 @@ def main():
                                f"({E} elements, {N} nodes), orthotropic D(T), c(T), "
                                "convection+radiation+flux", "elements": E, "nodes": N,
                    "precision": "fp32c", "graph_steps": args.graph_steps,
-                   "tiles": info["n_tiles"], "block_threads": info["block_threads"]},
+                   "steps_per_launch": K, "tiles": info["n_tiles"],
+                   "block_threads": info["block_threads"]},
         "hbm_gbs_algorithmic": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "bytes_per_step_algorithmic": alg,
-                     "bytes_per_step_moved": info["moved_bytes_per_step"]},
+                     "kernel": "k_step", "us_per_launch": t / launches * 1e6,
+                     "bytes_per_launch_algorithmic": alg,
+                     "bytes_per_launch_moved": info["moved_bytes_per_launch"]},
         "cpu_baseline": cpu,
     }
     if "fp64" in res:
         t64 = res["fp64"]["t"]
+        i64 = res["fp64"]["info"]
+        l64 = -(-args.steps // i64["fuse_steps"])
         line["fp64"] = {"value": E * args.steps / t64, "ms_per_step": t64 / args.steps * 1e3,
-                        "hbm_gbs_algorithmic": res["fp64"]["info"]["algorithmic_bytes_per_step"]
-                        / (t64 / args.steps) / 1e9,
+                        "hbm_gbs_algorithmic": i64["algorithmic_bytes_per_launch"]
+                        / (t64 / l64) / 1e9,
+                        "steps_per_launch": i64["fuse_steps"],
                         "speedup_fp32c_over_fp64": t64 / t}
     if errs:
         line["err_max_vs_oracle"] = {k: v for k, v in errs.items()}

@@ -118,17 +118,22 @@ typedef struct {
                                    independent instances (one dt per instance), or NULL */
   int32_t tile_nodes;        /* owned nodes per tile; 0 = default */
   int32_t block_threads;     /* threads per tile workgroup (64..512, multiple of 64); 0 = default */
+  int32_t fuse_steps;        /* K: steps one kernel launch advances (1..4), each tile carrying
+                                K element rings of halo; 0 = default (1).  Results do not
+                                depend on K. */
 } fed_options;
 
 typedef struct fed_ctx fed_ctx;
 
-/* Sizes and per-step traffic of a context (for reporting). */
+/* Sizes and traffic of a context (for reporting). */
 typedef struct {
   int64_t n_nodes, n_elems, n_instances;
   int64_t n_tiles, n_elems_expanded, n_halo, n_bnd_nodes;
-  int32_t elem, prec, block_threads, lds_bytes;
-  double algorithmic_bytes_per_step; /* unique bytes one step must move (see DESIGN) */
-  double moved_bytes_per_step;       /* bytes requested including tile halo redundancy */
+  int32_t elem, prec, block_threads, lds_bytes, fuse_steps, pad_;
+  double algorithmic_bytes_per_launch; /* unique bytes one K-step launch must move: every
+                                          element's entries and operator, every node's state
+                                          and coefficients, every boundary record, once */
+  double moved_bytes_per_launch;       /* bytes a launch requests, halo copies included */
 } fed_info;
 
 /*
@@ -156,14 +161,17 @@ int fed_info_get(const fed_ctx *ctx, fed_info *out);
  * else a device pointer.  Resets the step counter. */
 int fed_set_temperature(fed_ctx *ctx, const double *T, int32_t on_device, void *stream);
 
-/* Time-stepping stage (Sec. 3.5 (iii)): enqueues nsteps explicit steps, each one
- * kernel launch that computes every element load, sums them per node in a fixed
- * order, adds the surface loads and updates T (Eq. 16), keeping Dirichlet nodes
- * fixed.  Asynchronous.  FED_E_STATE before fed_set_temperature. */
+/* Time-stepping stage (Sec. 3.5 (iii)): enqueues nsteps explicit steps.  Each
+ * kernel launch advances K steps (fewer for the remainder); every step computes
+ * every element load, sums the loads per node in ascending element order, adds
+ * the surface loads and updates T (Eq. 16), keeping Dirichlet nodes fixed.
+ * Asynchronous.  FED_E_STATE before fed_set_temperature. */
 int fed_step(fed_ctx *ctx, int64_t nsteps, void *stream);
 
-/* Same as fed_step, but replays a captured HIP graph of `graph_steps` launches
- * (0 = default) for the bulk of the steps. */
+/* Same as fed_step, but replays a captured HIP graph of about `graph_steps`
+ * steps (rounded to an even number of K-step launches; 0 = default) for the bulk
+ * of the steps.  The graph is captured on a private stream and launched on
+ * `stream`. */
 int fed_step_graph(fed_ctx *ctx, int64_t nsteps, int32_t graph_steps, void *stream);
 
 /* Copies the current temperatures (FP64, caller order; FP32C returns hi + lo) to

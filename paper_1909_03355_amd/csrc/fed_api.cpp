@@ -69,7 +69,7 @@ struct fed_ctx {
   // step working set
   fed::TileHdr *d_tiles = nullptr;
   uint16_t *d_ent = nullptr;
-  int32_t *d_halo = nullptr, *d_perm = nullptr, *d_eorig = nullptr;
+  int32_t *d_halo = nullptr, *d_perm = nullptr, *d_eorig = nullptr, *d_rec_of = nullptr;
   void *d_H = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
   void *d_rA = nullptr, *d_rAT = nullptr, *d_reA = nullptr, *d_rTa = nullptr, *d_rP = nullptr;
   void *d_T[2] = {nullptr, nullptr};
@@ -83,7 +83,7 @@ struct fed_ctx {
   double *d_M0 = nullptr, *d_M1 = nullptr;
   // scalars
   double s0 = 1, s1 = 0, Tz = -273.15, T_lo = 0, T_hi = 0;
-  int tdk = 0, tdc = 0, block = 256, nper = 1;
+  int tdk = 0, tdc = 0, block = 256, nper = 1, K = 1;
   std::vector<double> dt_crit, dt_used;
   int cur = 0;
   int64_t steps = 0;
@@ -95,10 +95,11 @@ struct fed_ctx {
   int gsteps = 0, gparity = -1;
   fed_info info{};
 
-  fed::StepArgs step_args(int parity) const {
+  fed::StepArgs step_args(int parity, int k) const {
     fed::StepArgs a{};
     a.prec = prec;
     a.ne = ne;
+    a.k = k;
     a.tdk = tdk;
     a.tdc = tdc;
     a.nt = til.nt;
@@ -111,6 +112,7 @@ struct fed_ctx {
     a.tiles = d_tiles;
     a.ent = d_ent;
     a.halo = d_halo;
+    a.rec_of = d_rec_of;
     a.H = d_H;
     a.Tin = d_T[parity];
     a.Tout = d_T[1 - parity];
@@ -232,6 +234,7 @@ int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, cons
       if (o->node_instance[k] < 0 || o->node_instance[k] >= m->n_nodes)
         return fail(FED_E_ARG, "node_instance[%lld] out of range", (long long)k);
   if (o->tile_nodes < 0) return fail(FED_E_ARG, "tile_nodes < 0");
+  if (o->fuse_steps < 0 || o->fuse_steps > 4) return fail(FED_E_ARG, "fuse_steps must be in 0..4");
   if (o->block_threads != 0 &&
       (o->block_threads < 64 || o->block_threads > 512 || o->block_threads % 64))
     return fail(FED_E_ARG, "block_threads must be a multiple of 64 in [64, 512]");
@@ -309,13 +312,17 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   ti.node_instance = o->node_instance;
   ti.has_bnd = has_bnd.data();
   ti.target_nodes = o->tile_nodes ? o->tile_nodes : 512;
+  ti.depth = o->fuse_steps ? o->fuse_steps : 1;
   ti.lds_budget = 64 * 1024;
   ti.real_bytes = c->rb;
+  // staged per updated node: alpha, beta, record id, and lo for FP32C
+  ti.upd_bytes = 2 * c->rb + 4 + (c->prec == FED_FP32C ? 4 : 0);
   std::string terr = fed::build_tiling(ti, c->til);
   if (!terr.empty()) return fail(FED_E_MESH, "tiling: %s", terr.c_str());
   fed::Tiling &T = c->til;
   c->Eexp = (int64_t)T.eorig.size();
   c->nper = (T.nt + 7) / 8;
+  c->K = T.depth;
   // boundary records in internal order + their (face | point) items
   std::vector<int32_t> rec_node;
   std::vector<std::vector<int32_t>> items_of(N);
@@ -338,6 +345,8 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   items_of.clear();
   items_of.shrink_to_fit();
   c->nrec = (int64_t)rec_node.size();
+  std::vector<int32_t> rec_of(N, -1);
+  for (size_t r = 0; r < rec_node.size(); r++) rec_of[rec_node[r]] = (int32_t)r;
   std::vector<int32_t> node_inst_int, elem_inst;
   if (o->node_instance) {
     node_inst_int.resize(N);
@@ -493,6 +502,7 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   if (T.halo.empty()) T.halo.push_back(0);  // keep a valid (unused) device array
   HIPCHK(upload(P, &c->d_halo, T.halo.data(), T.halo.size()));
   HIPCHK(upload(P, &c->d_perm, T.perm.data(), T.perm.size()));
+  HIPCHK(upload(P, &c->d_rec_of, rec_of.data(), rec_of.size()));
   HIPCHK(P.alloc(&c->d_T[0], (size_t)rb * N));
   HIPCHK(P.alloc(&c->d_T[1], (size_t)rb * N));
   if (c->prec == FED_FP32C) {
@@ -526,14 +536,27 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   I.prec = c->prec;
   I.block_threads = c->block;
   I.lds_bytes = T.lds_bytes;
-  // unique bytes of one step: per element its packed entries (2 B / node) and the
-  // 6-entry operator; per node T read + write (and lo read + write for FP32C),
-  // alpha (and beta when c depends on T); per boundary node its 5 coefficients.
+  // unique bytes of one launch (which advances K steps): per element its packed
+  // entries (2 B / node) and the 6-entry operator; per node T read + write (and
+  // lo read + write for FP32C), alpha (and beta when c depends on T); per
+  // boundary node its 5 coefficients.  "Moved" counts what the launch requests:
+  // every tile's copy of its elements, T (and lo) of its halo, the halo ids, the
+  // coefficients of every node it updates, and the tile headers.
+  I.fuse_steps = T.depth;
   double elem_b = 2.0 * ne + 6.0 * rb;
-  double node_b = 2.0 * rb + (c->prec == FED_FP32C ? 8.0 : 0.0) + rb + (c->tdc ? rb : 0.0);
-  I.algorithmic_bytes_per_step = elem_b * E + node_b * N + 5.0 * rb * nrec;
-  I.moved_bytes_per_step = elem_b * c->Eexp + node_b * N + 5.0 * rb * nrec +
-                           (4.0 + rb) * (double)nhalo + sizeof(fed::TileHdr) * T.nt;
+  double lo_b = c->prec == FED_FP32C ? 4.0 : 0.0;
+  double coef_b = rb + (c->tdc ? rb : 0.0);
+  double node_b = 2.0 * rb + 2.0 * lo_b + coef_b;
+  I.algorithmic_bytes_per_launch = elem_b * E + node_b * N + 5.0 * rb * nrec;
+  double moved = elem_b * c->Eexp + sizeof(fed::TileHdr) * T.nt;
+  for (const fed::TileHdr &th : T.tiles) {
+    int64_t nupd = th.cum_n[T.depth - 1], ntouch = th.cum_n[T.depth];
+    moved += (rb + 4.0) * (ntouch - th.nown) + rb * th.nown;   // T reads (+ halo ids)
+    moved += (lo_b + coef_b) * nupd + 4.0 * (nupd - th.nown);  // lo, coefficients, rec ids
+    moved += (rb + lo_b) * th.nown;                              // writes
+  }
+  moved += 5.0 * rb * nrec;
+  I.moved_bytes_per_launch = moved;
   *out = c.release();
   return FED_OK;
 }
@@ -578,10 +601,12 @@ int fed_step(fed_ctx *c, int64_t nsteps, void *stream) {
   if (!c->have_T) return fail(FED_E_STATE, "fed_set_temperature must come first");
   if (nsteps < 0) return fail(FED_E_ARG, "nsteps < 0");
   hipStream_t s = (hipStream_t)stream;
-  for (int64_t n = 0; n < nsteps; n++) {
-    fed::StepArgs a = c->step_args(c->cur);
+  for (int64_t n = nsteps; n > 0;) {
+    int k = (int)std::min<int64_t>(c->K, n);
+    fed::StepArgs a = c->step_args(c->cur, k);
     HIPCHK(fed::launch_step(a, s));
     c->cur ^= 1;
+    n -= k;
   }
   c->steps += nsteps;
   return FED_OK;
@@ -592,8 +617,11 @@ int fed_step_graph(fed_ctx *c, int64_t nsteps, int32_t graph_steps, void *stream
   if (!c->have_T) return fail(FED_E_STATE, "fed_set_temperature must come first");
   if (nsteps < 0 || graph_steps < 0) return fail(FED_E_ARG, "negative count");
   hipStream_t s = (hipStream_t)stream;
-  int gs = graph_steps ? graph_steps : 100;
-  gs += gs & 1;  // even, so every replay starts on the same buffer
+  // an even number of K-step launches, so every replay starts on the same buffer
+  int64_t want = graph_steps ? graph_steps : 100;
+  int launches = (int)std::max<int64_t>(2, (want + c->K - 1) / c->K);
+  launches += launches & 1;
+  int gs = launches * c->K;
   if (nsteps < gs) return fed_step(c, nsteps, stream);
   if (c->gexec && (c->gsteps != gs || c->gparity != c->cur)) c->drop_graph();
   if (!c->gexec) {
@@ -603,8 +631,8 @@ int fed_step_graph(fed_ctx *c, int64_t nsteps, int32_t graph_steps, void *stream
     hipStream_t cs = c->cap_stream;
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int par = c->cur;
-    for (int i = 0; i < gs; i++) {
-      fed::StepArgs a = c->step_args(par);
+    for (int i = 0; i < launches; i++) {
+      fed::StepArgs a = c->step_args(par, c->K);
       hipError_t e = fed::launch_step(a, cs);
       if (e != hipSuccess) {
         hipGraph_t g = nullptr;

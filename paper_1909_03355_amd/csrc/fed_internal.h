@@ -7,18 +7,27 @@
 
 namespace fed {
 
-// One tile = one workgroup per step.  A tile owns a contiguous range of
-// internal nodes and holds a copy of every element incident to them, so a step
-// needs no communication between workgroups besides the ping-pong T buffers.
+constexpr int kMaxDepth = 4;  // most steps one launch may fuse
+
+// One tile = one workgroup per launch.  A tile owns a contiguous range of
+// internal nodes.  Nodes get a level: 0 for owned nodes, l for nodes l element
+// rings away (up to the tiling depth K).  The tile holds a copy of every
+// element touching a node of level < K, so a launch can advance its nodes k <= K
+// steps with no communication between workgroups: sub-step s updates the nodes
+// of level <= k - s from the elements whose lowest node level is <= k - s.
+// Local node order: owned, then halo nodes by (level, id); elements by
+// (lowest level, id), so every sub-step works on a prefix of both.
 struct TileHdr {
   int32_t nstart;  // first owned internal node
   int32_t nown;    // owned nodes; the first nbnd carry a boundary record
   int32_t nbnd;
   int32_t bstart;  // index of the tile's first boundary record
   int32_t hstart;  // first entry of the tile's halo list
-  int32_t nhalo;   // halo nodes (touched but owned by other tiles)
+  int32_t nhalo;   // halo nodes (levels 1..K)
   int32_t estart;  // first expanded element of the tile
-  int32_t ecount;  // expanded elements of the tile
+  int32_t ecount;  // expanded elements of the tile (= cum_e[K-1])
+  int32_t cum_n[kMaxDepth + 1];  // local nodes of level <= l
+  int32_t cum_e[kMaxDepth];      // elements of lowest level <= l
 };
 
 struct TilingInput {
@@ -29,8 +38,10 @@ struct TilingInput {
   const int32_t *node_instance = nullptr;  // [N] or null
   const uint8_t *has_bnd = nullptr;        // [N] node carries a surface record
   int target_nodes = 512;                  // owned nodes per tile (upper bound)
+  int depth = 1;                           // K: steps one launch may fuse
   int lds_budget = 64 * 1024;              // bytes of LDS one workgroup may use
   int real_bytes = 4;                      // sizeof(working real)
+  int upd_bytes = 0;                       // LDS bytes per updated node besides its slots
 };
 
 struct Tiling {
@@ -39,7 +50,8 @@ struct Tiling {
   int32_t maxinc = 0;      // largest node incidence (slots per owned node)
   int32_t ntouch_max = 0;  // largest nown + nhalo over tiles
   int32_t nown_max = 0;
-  int32_t lds_bytes = 0;   // dynamic LDS per workgroup
+  int32_t depth = 1;
+  int32_t lds_bytes = 0;   // dynamic LDS per workgroup (launches fusing K steps)
   std::vector<int32_t> perm;   // caller node -> internal node
   std::vector<int32_t> iperm;  // internal node -> caller node
   std::vector<TileHdr> tiles;

@@ -84,6 +84,7 @@ struct NodeArrArgs {
 
 struct StepArgs {
   int prec, ne;
+  int k;                      // steps this launch advances (1..tiling depth)
   int tdk, tdc;               // temperature-dependent conductivity / capacity
   int nt, nper, block, lds;
   int pb, maxinc;
@@ -91,6 +92,7 @@ struct StepArgs {
   const TileHdr *tiles;
   const uint16_t *ent;
   const int32_t *halo;
+  const int32_t *rec_of;      // boundary record of an internal node, or -1
   const void *H;
   const void *Tin;
   const float *loin;

@@ -461,10 +461,13 @@ struct Ent<4> {
   }
 };
 
-// element loads of one expanded element into its owned nodes' LDS slots
+// element loads of one expanded element into the LDS slots of the nodes that
+// this sub-step updates (local index < nupd); slot (node j, position p) lives at
+// p * stride + j
 template <typename R, int NE, bool TDK>
 __device__ inline void element_to_slots(const typename Ent<NE>::T &w, const R h[6], const R *Tl,
-                                        R *slot, int nown, int pb, uint32_t pmask, R s0, R s1) {
+                                        R *slot, int stride, int nupd, int pb, uint32_t pmask,
+                                        R s0, R s1) {
   uint32_t v[NE], loc[NE];
   Ent<NE>::unpack(w, v);
 #pragma unroll
@@ -473,18 +476,268 @@ __device__ inline void element_to_slots(const typename Ent<NE>::T &w, const R h[
   Elem<R, NE>::load(Tl, loc, s0, s1, TDK, h, F);
 #pragma unroll
   for (int n = 0; n < NE; n++)
-    if (loc[n] < (uint32_t)nown) slot[(v[n] & pmask) * nown + loc[n]] = F[n];
+    if (loc[n] < (uint32_t)nupd) slot[(v[n] & pmask) * stride + loc[n]] = F[n];
 }
 
 // per-node coefficients of the update
 template <typename R>
 struct NodeData {
   R alpha, beta, bA, bAT, beA, bTa, bP;
+  int rec;
+};
+
+// coefficients of updated node j: alpha, beta from the LDS stage, the boundary
+// record (if any) from global memory
+template <typename R, bool TDC>
+__device__ inline void load_node(const StepArgs &a, const R *La, const R *Lb, const int *Lr, int j,
+                                 NodeData<R> &d) {
+  d.alpha = La[j];
+  d.beta = TDC ? Lb[j] : (R)0;
+  const int r = Lr[j];
+  d.rec = r;
+  if (r >= 0) {
+    d.bA = ((const R *)a.rA)[r];
+    d.bAT = ((const R *)a.rAT)[r];
+    d.beA = ((const R *)a.reA)[r];
+    d.bTa = ((const R *)a.rTa)[r];
+    d.bP = ((const R *)a.rP)[r];
+  }
+}
+
+// Sum of the node's slots in ascending element order (Eq. 10-11), surface loads
+// (Eq. 4, 5, 7) and the explicit update (Eq. 16): dT = (Q - F) / (alpha + beta T).
+// Returns the new hi (and lo for the compensated mode).
+template <typename R, int MODE, bool TDC>
+__device__ inline R node_update(const NodeData<R> &d, int j, int maxinc, int stride, R T, float lo,
+                                const R *slot, R Tz, float &lo_new) {
+  // the slots are read eight at a time (independent LDS reads in flight), then
+  // added in position order; positions past the node's incidence hold zeros
+  R F = 0;
+  for (int p0 = 0; p0 < maxinc; p0 += 8) {
+    R v[8];
+#pragma unroll
+    for (int p = 0; p < 8; p++) v[p] = p0 + p < maxinc ? slot[(p0 + p) * stride + j] : (R)0;
+    if (p0 == 0) {
+      F = v[0];
+    } else {
+      F += v[0];
+    }
+#pragma unroll
+    for (int p = 1; p < 8; p++) F += v[p];
+  }
+  R Q = 0;
+  if (d.rec >= 0) {
+    R x = T - Tz, y = d.bTa - Tz;
+    // (T-Tz)^4 - (Ta-Tz)^4 in factored form
+    Q = (d.bAT - d.bA * T) - d.beA * ((T - d.bTa) * (x + y) * (x * x + y * y)) + d.bP;
+  }
+  R den = d.alpha;
+  if (TDC) den += d.beta * T;
+  const R dT = (Q - F) / den;
+  if (MODE == 1) {
+    // compensated accumulation: T = hi + lo, Fast2Sum of hi and (dT + lo)
+    const float yv = (float)dT + lo;
+    const float tv = (float)T + yv;
+    lo_new = yv - (tv - (float)T);
+    return (R)tv;
+  }
+  lo_new = 0.0f;
+  return T + dT;
+}
+
+constexpr int kMaxBlock = 512;
+
+// Element loads of elements [i0, i1) of the tile, EPT per thread at a time:
+// all entry and operator loads are issued before the first element is
+// evaluated.
+template <typename R, int NE, bool TDK, int EPT>
+__device__ inline void elements_from_global(const StepArgs &a, const TileHdr &th, int i0, int i1,
+                                            const R *Tl, R *slot, int stride, int nupd,
+                                            uint32_t pmask, R s0, R s1) {
+  using EntT = typename Ent<NE>::T;
+  const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
+  const R *Hb = (const R *)a.H;
+  const int bs = blockDim.x;
+  for (int base = i0 + threadIdx.x; base < i1; base += EPT * bs) {
+    EntT w[EPT];
+    R h[EPT][6];
+#pragma unroll
+    for (int q = 0; q < EPT; q++) {
+      const int i = base + q * bs;
+      if (i < i1) {
+        const int64_t e = (int64_t)th.estart + i;
+        w[q] = ent[e];
+#pragma unroll
+        for (int r = 0; r < 6; r++) h[q][r] = Hb[(int64_t)r * a.Eexp + e];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; q++)
+      if (base + q * bs < i1)
+        element_to_slots<R, NE, TDK>(w[q], h[q], Tl, slot, stride, nupd, a.pb, pmask, s0, s1);
+  }
+}
+
+// One launch advances the tile's owned nodes a.k steps (temporal blocking).
+// MODE: 0 plain (R = float or double), 1 compensated FP32 (hi, lo pair).
+// Memory round trips are batched: the first EPT elements of every thread are
+// loaded before the T staging, the staging issues all its halo ids and then
+// all values at once, and per-node coefficients come from LDS.  EPT, SPT and
+// NPT are sized so that every variant fits 128 VGPRs (4 waves per SIMD)
+// without spilling.
+template <typename R, int NE, int MODE, bool TDK, bool TDC>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_step(
+    StepArgs a) {
+  constexpr int EPT = NE == 8 ? (sizeof(R) == 4 ? 4 : 2) : (sizeof(R) == 4 ? 6 : 2);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const int t = (b & 7) * a.nper + (b >> 3);
+  if (t >= a.nt) return;  // whole block leaves before any barrier
+  const TileHdr th = a.tiles[t];
+  // level counts are read through global memory: a run-time index into the
+  // local copy of the header would put the whole header in scratch
+  const int32_t *cum_n = a.tiles[t].cum_n, *cum_e = a.tiles[t].cum_e;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int k = a.k;
+  const int nown = th.nown;
+  const int nT = cum_n[k], nU = cum_n[k - 1], nE = cum_e[k - 1];
+  using EntT = typename Ent<NE>::T;
+  const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
+  const R *Hb = (const R *)a.H;
+  // ---- first sub-step's elements: loads issued before the staging ----
+  EntT ew[EPT];
+  R eh[EPT][6];
+#pragma unroll
+  for (int q = 0; q < EPT; q++) {
+    const int i = tid + q * bs;
+    if (i < nE) {
+      const int64_t e = (int64_t)th.estart + i;
+      ew[q] = ent[e];
+#pragma unroll
+      for (int r = 0; r < 6; r++) eh[q][r] = Hb[(int64_t)r * a.Eexp + e];
+    }
+  }
+  // ---- LDS: T of touched nodes; alpha, beta, record id, lo and slots of the
+  // nodes the launch updates ----
+  R *Tl = reinterpret_cast<R *>(smem_raw);
+  R *La = Tl + nT;
+  R *Lb = La + nU;
+  int *Lr = reinterpret_cast<int *>(Lb + nU);
+  float *Llo = reinterpret_cast<float *>(Lr + nU);
+  R *slot = reinterpret_cast<R *>(Llo + (MODE == 1 ? nU : 0));
+  if (sizeof(R) == 8)
+    slot = reinterpret_cast<R *>((reinterpret_cast<uintptr_t>(slot) + 7) & ~uintptr_t(7));
+  const R *Tin = (const R *)a.Tin;
+  const R *alpha = (const R *)a.alpha, *beta = (const R *)a.beta;
+  // SPT nodes per thread at a time: all halo ids, then all values
+  constexpr int SPT = 4;
+  for (int base = 0; base < nT; base += SPT * bs) {
+    int gi[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; q++) {
+      const int j = base + tid + q * bs;
+      gi[q] = j < nown ? th.nstart + j : (j < nT ? a.halo[th.hstart + j - nown] : 0);
+    }
+    R tv[SPT], av[SPT], bv[SPT];
+    float lv[SPT];
+    int rv[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; q++) {
+      const int j = base + tid + q * bs;
+      if (j < nT) tv[q] = Tin[gi[q]];
+      if (j < nU) {
+        av[q] = alpha[gi[q]];
+        if (TDC) bv[q] = beta[gi[q]];
+        if (MODE == 1) lv[q] = a.loin[gi[q]];
+        rv[q] = j < nown ? (j < th.nbnd ? th.bstart + j : -1) : a.rec_of[gi[q]];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < SPT; q++) {
+      const int j = base + tid + q * bs;
+      if (j < nT) Tl[j] = tv[q];
+      if (j < nU) {
+        La[j] = av[q];
+        if (TDC) Lb[j] = bv[q];
+        if (MODE == 1) Llo[j] = lv[q];
+        Lr[j] = rv[q];
+      }
+    }
+  }
+  const int nslot = a.maxinc * nU;
+  for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
+  __syncthreads();
+  const R s0 = (R)a.s0, s1 = (R)a.s1, Tz = (R)a.Tz;
+  const uint32_t pmask = (1u << a.pb) - 1u;
+  R *Tout = (R *)a.Tout;
+  // Sub-step s updates the nodes of level <= k - s from the elements whose
+  // lowest node level is <= k - s.  The first element phase (from the
+  // prefetched registers) is peeled off so those registers die before the loop.
+  {
+    const int nU1 = cum_n[k - 1], nE1 = cum_e[k - 1];
+#pragma unroll
+    for (int q = 0; q < EPT; q++)
+      if (tid + q * bs < nE1)
+        element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nU, nU1, a.pb, pmask, s0, s1);
+    elements_from_global<R, NE, TDK, EPT>(a, th, EPT * bs, nE1, Tl, slot, nU, nU1, pmask, s0, s1);
+  }
+  __syncthreads();
+  for (int s = 1;; s++) {
+    const int nUs = cum_n[k - s];
+    const bool last = s == k;  // then nUs == nown
+    // NPT nodes per thread at a time: coefficient and record loads first
+    constexpr int NPT = sizeof(R) == 4 ? 4 : 1;
+    for (int base = 0; base < nUs; base += NPT * bs) {
+      NodeData<R> d[NPT];
+#pragma unroll
+      for (int q = 0; q < NPT; q++) {
+        const int j = base + tid + q * bs;
+        if (j < nUs) load_node<R, TDC>(a, La, Lb, Lr, j, d[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < NPT; q++) {
+        const int j = base + tid + q * bs;
+        if (j >= nUs) continue;
+        const R T = Tl[j];
+        const float lo = MODE == 1 ? Llo[j] : 0.0f;
+        float lo_new;
+        const R Tn = node_update<R, MODE, TDC>(d[q], j, a.maxinc, nU, T, lo, slot, Tz, lo_new);
+        if (last) {
+          Tout[th.nstart + j] = Tn;
+          if (MODE == 1) a.loout[th.nstart + j] = lo_new;
+        } else {
+          Tl[j] = Tn;
+          if (MODE == 1) Llo[j] = lo_new;
+        }
+      }
+    }
+    if (last) break;
+    __syncthreads();
+    const int nUn = cum_n[k - s - 1], nEn = cum_e[k - s - 1];
+    elements_from_global<R, NE, TDK, EPT>(a, th, 0, nEn, Tl, slot, nU, nUn, pmask, s0, s1);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-step kernel: launches that advance a single step.  Same arithmetic as
+// k_step with k = 1, arranged for the shortest chain of memory round trips on
+// a lightly occupied chip: the entries and operators of the first EPT elements
+// and the coefficients of the first NPT nodes of every thread are loaded
+// before the T staging, there is no sub-step loop to keep them alive across,
+// and the compiler keeps the FP32 variants within 128 VGPRs.
+#ifndef FED_FASTDIV
+#define FED_FASTDIV 1
+#endif
+
+template <typename R>
+struct Node1 {
+  R alpha, beta, bA, bAT, beA, bTa, bP;
   float lo;
 };
 
 template <typename R, int MODE, bool TDC>
-__device__ inline void load_node(const StepArgs &a, const TileHdr &th, int j, NodeData<R> &d) {
+__device__ inline void load_node1(const StepArgs &a, const TileHdr &th, int j, Node1<R> &d) {
   const int k = th.nstart + j;
   d.alpha = ((const R *)a.alpha)[k];
   d.beta = TDC ? ((const R *)a.beta)[k] : (R)0;
@@ -499,10 +752,24 @@ __device__ inline void load_node(const StepArgs &a, const TileHdr &th, int j, No
   }
 }
 
-// sum of the node's slots in ascending element order, surface loads, update
+// (Q - F) / den; in FP32 with the hardware reciprocal-based quotient (a few
+// ulp, far below the compensated state's resolution of the increment)
+template <typename R>
+__device__ inline R quotient(R num, R den) {
+  return num / den;
+}
+template <>
+__device__ inline float quotient<float>(float num, float den) {
+#if FED_FASTDIV
+  return __fdividef(num, den);
+#else
+  return num / den;
+#endif
+}
+
 template <typename R, int MODE, bool TDC>
-__device__ inline void node_update(const StepArgs &a, const TileHdr &th, int j, const NodeData<R> &d,
-                                   const R *Tl, const R *slot, R Tz) {
+__device__ inline void update1(const StepArgs &a, const TileHdr &th, int j, const Node1<R> &d,
+                               const R *Tl, const R *slot, R Tz) {
   const int nown = th.nown, k = th.nstart + j;
   R F = slot[j];
   for (int p = 1; p < a.maxinc; p++) F += slot[p * nown + j];
@@ -515,7 +782,7 @@ __device__ inline void node_update(const StepArgs &a, const TileHdr &th, int j, 
   }
   R den = d.alpha;
   if (TDC) den += d.beta * T;
-  const R dT = (Q - F) / den;
+  const R dT = quotient<R>(Q - F, den);
   R *Tout = (R *)a.Tout;
   if (MODE == 1) {
     // compensated accumulation: T = hi + lo, Fast2Sum of hi and (dT + lo)
@@ -528,23 +795,19 @@ __device__ inline void node_update(const StepArgs &a, const TileHdr &th, int j, 
   }
 }
 
-constexpr int kMaxBlock = 512;
-
-// MODE: 0 plain (R = float or double), 1 compensated FP32 (hi, lo pair).
-// Loads that do not depend on T (element entries and operators, node
-// coefficients, boundary records) are issued first, for the first EPT elements
-// and NPT nodes of every thread, so their latency overlaps the T staging.
 template <typename R, int NE, int MODE, bool TDK, bool TDC>
-__global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs a) {
-  constexpr int EPT = NE == 8 ? 4 : 8;
-  constexpr int NPT = 4;
+__global__ __launch_bounds__(1024) void k_step1(StepArgs a) {
+  constexpr int EPT = NE == 8 ? (sizeof(R) == 4 ? 4 : 2) : (sizeof(R) == 4 ? 8 : 3);
+  constexpr int NPT = sizeof(R) == 4 ? 4 : 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int t = (b & 7) * a.nper + (b >> 3);
   if (t >= a.nt) return;  // whole block leaves before any barrier
   const TileHdr th = a.tiles[t];
+  const int nE = a.tiles[t].cum_e[0];            // elements touching owned nodes
+  const int nhalo = a.tiles[t].cum_n[1] - th.nown;  // first halo ring
   const int tid = threadIdx.x, bs = blockDim.x;
-  const int nown = th.nown, ntouch = th.nown + th.nhalo;
+  const int nown = th.nown, ntouch = nown + nhalo;
   using EntT = typename Ent<NE>::T;
   const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
   const R *Hb = (const R *)a.H;
@@ -554,25 +817,25 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs a) {
 #pragma unroll
   for (int q = 0; q < EPT; q++) {
     const int i = tid + q * bs;
-    if (i < th.ecount) {
+    if (i < nE) {
       const int64_t e = (int64_t)th.estart + i;
       ew[q] = ent[e];
 #pragma unroll
       for (int r = 0; r < 6; r++) eh[q][r] = Hb[(int64_t)r * a.Eexp + e];
     }
   }
-  NodeData<R> nd[NPT];
+  Node1<R> nd[NPT];
 #pragma unroll
   for (int q = 0; q < NPT; q++) {
     const int j = tid + q * bs;
-    if (j < nown) load_node<R, MODE, TDC>(a, th, j, nd[q]);
+    if (j < nown) load_node1<R, MODE, TDC>(a, th, j, nd[q]);
   }
-  // ---- stage T of owned and halo nodes; clear the slots ----
+  // ---- stage T of owned and first-ring halo nodes; clear the slots ----
   R *Tl = reinterpret_cast<R *>(smem_raw);
   R *slot = Tl + ntouch;
   const R *Tin = (const R *)a.Tin;
   for (int j = tid; j < nown; j += bs) Tl[j] = Tin[th.nstart + j];
-  for (int j = tid; j < th.nhalo; j += bs) Tl[nown + j] = Tin[a.halo[th.hstart + j]];
+  for (int j = tid; j < nhalo; j += bs) Tl[nown + j] = Tin[a.halo[th.hstart + j]];
   const int nslot = a.maxinc * nown;
   for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
   __syncthreads();
@@ -580,17 +843,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs a) {
   const R s0 = (R)a.s0, s1 = (R)a.s1;
   const uint32_t pmask = (1u << a.pb) - 1u;
 #pragma unroll
-  for (int q = 0; q < EPT; q++) {
-    const int i = tid + q * bs;
-    if (i < th.ecount)
-      element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nown, a.pb, pmask, s0, s1);
-  }
-  for (int i = tid + EPT * bs; i < th.ecount; i += bs) {
+  for (int q = 0; q < EPT; q++)
+    if (tid + q * bs < nE)
+      element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, s0, s1);
+  for (int i = tid + EPT * bs; i < nE; i += bs) {
     const int64_t e = (int64_t)th.estart + i;
     R h[6];
 #pragma unroll
     for (int r = 0; r < 6; r++) h[r] = Hb[(int64_t)r * a.Eexp + e];
-    element_to_slots<R, NE, TDK>(ent[e], h, Tl, slot, nown, a.pb, pmask, s0, s1);
+    element_to_slots<R, NE, TDK>(ent[e], h, Tl, slot, nown, nown, a.pb, pmask, s0, s1);
   }
   __syncthreads();
   // ---- per node: ordered sum, surface loads, explicit update ----
@@ -598,24 +859,31 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs a) {
 #pragma unroll
   for (int q = 0; q < NPT; q++) {
     const int j = tid + q * bs;
-    if (j < nown) node_update<R, MODE, TDC>(a, th, j, nd[q], Tl, slot, Tz);
+    if (j < nown) update1<R, MODE, TDC>(a, th, j, nd[q], Tl, slot, Tz);
   }
   for (int j = tid + NPT * bs; j < nown; j += bs) {
-    NodeData<R> d;
-    load_node<R, MODE, TDC>(a, th, j, d);
-    node_update<R, MODE, TDC>(a, th, j, d, Tl, slot, Tz);
+    Node1<R> d;
+    load_node1<R, MODE, TDC>(a, th, j, d);
+    update1<R, MODE, TDC>(a, th, j, d, Tl, slot, Tz);
   }
 }
 
 template <typename R, int NE, int MODE, bool TDK, bool TDC>
 hipError_t step_t(const StepArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_step<R, NE, MODE, TDK, TDC>), dim3(8 * a.nper), dim3(a.block),
-                     a.lds, s, a);
+  if (a.k == 1)
+    hipLaunchKernelGGL((k_step1<R, NE, MODE, TDK, TDC>), dim3(8 * a.nper), dim3(a.block),
+                       a.lds, s, a);
+  else
+    hipLaunchKernelGGL((k_step<R, NE, MODE, TDK, TDC>), dim3(8 * a.nper), dim3(a.block),
+                       a.lds, s, a);
   return hipGetLastError();
 }
 
 template <typename R, int NE, int MODE, bool TDK, bool TDC>
 hipError_t step_attr(int bytes) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_step1<R, NE, MODE, TDK, TDC>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void *)k_step<R, NE, MODE, TDK, TDC>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }

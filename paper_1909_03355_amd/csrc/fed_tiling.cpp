@@ -25,7 +25,6 @@ struct Builder {
   std::vector<int32_t> celem;
   std::vector<int8_t> ca;
   std::vector<uint16_t> posEA; // [E * ne] position of e in the list of node conn[a,e]
-  std::vector<int32_t> stamp_own, stamp_touch;
   int32_t stamp = 0;
   int32_t touch_limit = 0;
 
@@ -61,32 +60,40 @@ struct Builder {
     touch_limit = 1 << (16 - pb);
   }
 
-  // nown + nhalo of a candidate tile made of nodes ids[b, e)
-  int64_t touched(const std::vector<int32_t> &ids, size_t b, size_t e) {
+  // Levels around the candidate owned set ids[b, e): lev[l] receives the nodes
+  // (caller ids) of level l = 1..K, found by growing element rings.
+  std::vector<int32_t> lev[kMaxDepth + 1];
+  std::vector<int32_t> stamp_lvl;
+  void levels(const std::vector<int32_t> &ids, size_t b, size_t e) {
     ++stamp;
-    for (size_t i = b; i < e; i++) stamp_own[ids[i]] = stamp;
-    int64_t halo = 0;
-    for (size_t i = b; i < e; i++) {
-      int32_t k = ids[i];
-      for (int64_t p = cptr[k]; p < cptr[k + 1]; p++) {
-        int32_t el = celem[p];
-        for (int a = 0; a < in.ne; a++) {
-          int32_t j = node(el, a);
-          if (stamp_own[j] != stamp && stamp_touch[j] != stamp) {
-            stamp_touch[j] = stamp;
-            halo++;
+    lev[0].assign(ids.begin() + b, ids.begin() + e);
+    for (int32_t k : lev[0]) stamp_lvl[k] = stamp;
+    for (int l = 1; l <= in.depth; l++) {
+      lev[l].clear();
+      for (int32_t k : lev[l - 1])
+        for (int64_t p = cptr[k]; p < cptr[k + 1]; p++) {
+          int32_t el = celem[p];
+          for (int a = 0; a < in.ne; a++) {
+            int32_t j = node(el, a);
+            if (stamp_lvl[j] != stamp) {
+              stamp_lvl[j] = stamp;
+              lev[l].push_back(j);
+            }
           }
         }
-      }
     }
-    return (int64_t)(e - b) + halo;
   }
 
   bool fits(const std::vector<int32_t> &ids, size_t b, size_t e) {
-    int64_t nown = (int64_t)(e - b);
-    int64_t nt = touched(ids, b, e);
-    int64_t lds = (int64_t)in.real_bytes * (nt + (int64_t)out.maxinc * nown);
-    return nt <= touch_limit && lds <= in.lds_budget;
+    levels(ids, b, e);
+    int64_t nupd = 0, ntouch = 0;
+    for (int l = 0; l <= in.depth; l++) {
+      if (l < in.depth) nupd += (int64_t)lev[l].size();
+      ntouch += (int64_t)lev[l].size();
+    }
+    int64_t lds = (int64_t)in.real_bytes * ntouch +
+                  ((int64_t)in.upd_bytes + (int64_t)in.real_bytes * out.maxinc) * nupd + 8;
+    return ntouch <= touch_limit && lds <= in.lds_budget;
   }
 
   // recursive coordinate bisection of ids[b, e) into leaves (DFS order)
@@ -129,8 +136,7 @@ struct Builder {
     const int64_t N = in.N, E = in.E;
     const int ne = in.ne;
     incidence();
-    stamp_own.assign(N, 0);
-    stamp_touch.assign(N, 0);
+    stamp_lvl.assign(N, 0);
     // groups: one per instance (caller node order inside), or one group
     std::vector<int32_t> ids(N);
     std::iota(ids.begin(), ids.end(), 0);
@@ -174,9 +180,11 @@ struct Builder {
       }
       bnext += th.nbnd;
     }
-    // per tile: incident elements, halo, packed entries
-    std::vector<int32_t> loc(N, -1), locstamp(N, -1);
-    std::vector<int32_t> telems, thalo;
+    // per tile: node levels, elements within K - 1 rings, halo, packed entries
+    const int K = in.depth;
+    out.depth = K;
+    std::vector<int32_t> loc(N, -1), estamp(E, -1), minlev(E, 0);
+    std::vector<int32_t> telems;
     out.halo.clear();
     out.ent.clear();
     out.eorig.clear();
@@ -185,45 +193,72 @@ struct Builder {
     int64_t lds_max = 0;
     for (int32_t t = 0; t < out.nt; t++) {
       TileHdr &th = out.tiles[t];
-      telems.clear();
-      thalo.clear();
-      for (int32_t j = 0; j < th.nown; j++) {
-        int32_t k = out.iperm[th.nstart + j];
-        for (int64_t p = cptr[k]; p < cptr[k + 1]; p++) telems.push_back(celem[p]);
-      }
-      std::sort(telems.begin(), telems.end());
-      telems.erase(std::unique(telems.begin(), telems.end()), telems.end());
-      for (int32_t el : telems)
-        for (int a = 0; a < ne; a++) {
-          int32_t ki = out.perm[node(el, a)];
-          bool own = ki >= th.nstart && ki < th.nstart + th.nown;
-          if (!own && locstamp[ki] != t) {
-            locstamp[ki] = t;
-            thalo.push_back(ki);
-          }
-        }
-      std::sort(thalo.begin(), thalo.end());
-      for (size_t h = 0; h < thalo.size(); h++) loc[thalo[h]] = th.nown + (int32_t)h;
+      std::vector<int32_t> owned(th.nown);
+      for (int32_t j = 0; j < th.nown; j++) owned[j] = out.iperm[th.nstart + j];
+      levels(owned, 0, owned.size());
+      // local ids: owned by internal id, halo by (level, internal id)
+      for (int32_t j = 0; j < th.nown; j++) loc[owned[j]] = j;
+      int32_t next_loc = th.nown;
       th.hstart = (int32_t)out.halo.size();
-      th.nhalo = (int32_t)thalo.size();
-      out.halo.insert(out.halo.end(), thalo.begin(), thalo.end());
+      th.cum_n[0] = th.nown;
+      for (int l = 1; l <= K; l++) {
+        std::vector<int32_t> hl;
+        for (int32_t k : lev[l]) hl.push_back(out.perm[k]);
+        std::sort(hl.begin(), hl.end());
+        for (int32_t ki : hl) {
+          loc[out.iperm[ki]] = next_loc++;
+          out.halo.push_back(ki);
+        }
+        th.cum_n[l] = next_loc;
+      }
+      for (int l = K + 1; l <= kMaxDepth; l++) th.cum_n[l] = next_loc;
+      th.nhalo = next_loc - th.nown;
+      // elements touching a node of level < K, with their lowest node level
+      telems.clear();
+      for (int l = 0; l < K; l++)
+        for (int32_t k : lev[l])
+          for (int64_t p = cptr[k]; p < cptr[k + 1]; p++) {
+            int32_t el = celem[p];
+            if (estamp[el] != t) {
+              estamp[el] = t;
+              telems.push_back(el);
+            }
+          }
+      for (int32_t el : telems) {
+        int32_t m = kMaxDepth + 1;
+        for (int a = 0; a < ne; a++) {
+          int32_t lc = loc[node(el, a)];
+          int32_t lv = 0;
+          while (lc >= th.cum_n[lv]) lv++;
+          m = std::min(m, lv);
+        }
+        minlev[el] = m;
+      }
+      std::sort(telems.begin(), telems.end(), [&](int32_t p, int32_t q) {
+        return minlev[p] != minlev[q] ? minlev[p] < minlev[q] : p < q;
+      });
       th.estart = (int32_t)out.eorig.size();
       th.ecount = (int32_t)telems.size();
+      for (int l = 0; l < kMaxDepth; l++) {
+        int32_t c = 0;
+        for (int32_t el : telems) c += minlev[el] <= l;
+        th.cum_e[l] = l < K ? c : th.ecount;
+      }
       for (int32_t el : telems) {
         out.eorig.push_back(el);
         int32_t k0 = out.perm[node(el, 0)];
         out.eowner.push_back(k0 >= th.nstart && k0 < th.nstart + th.nown ? 1 : 0);
         for (int a = 0; a < ne; a++) {
-          int32_t ki = out.perm[node(el, a)];
-          int32_t l = (ki >= th.nstart && ki < th.nstart + th.nown) ? ki - th.nstart : loc[ki];
+          int32_t l = loc[node(el, a)];
           out.ent.push_back((uint16_t)(((uint32_t)l << out.pb) | posEA[(size_t)el * ne + a]));
         }
       }
-      int32_t ntouch = th.nown + th.nhalo;
+      int32_t ntouch = th.cum_n[K], nupd = th.cum_n[K - 1];
       out.ntouch_max = std::max(out.ntouch_max, ntouch);
       out.nown_max = std::max(out.nown_max, th.nown);
-      lds_max = std::max<int64_t>(lds_max, (int64_t)in.real_bytes *
-                                               (ntouch + (int64_t)out.maxinc * th.nown));
+      lds_max = std::max<int64_t>(lds_max, (int64_t)in.real_bytes * ntouch +
+                                               ((int64_t)in.upd_bytes + (int64_t)in.real_bytes *
+                                                out.maxinc) * nupd + 8);
       if (ntouch > touch_limit) return "internal: tile exceeds the local index range";
     }
     out.lds_bytes = (int32_t)lds_max;
@@ -250,6 +285,7 @@ struct Builder {
 std::string build_tiling(const TilingInput &in, Tiling &out) {
   if (in.N <= 0 || in.E <= 0) return "empty mesh";
   if (in.target_nodes < 1) return "tile_nodes must be positive";
+  if (in.depth < 1 || in.depth > kMaxDepth) return "fused steps out of range";
   Builder b(in, out);
   return b.run();
 }

@@ -33,8 +33,8 @@ def current_stream():
 
 
 class Simulation:
-    def __init__(self, prob, prec="fp32c", tile_nodes=0, block_threads=0, allow_unstable=False,
-                 stream=None):
+    def __init__(self, prob, prec="fp32c", tile_nodes=0, block_threads=0, fuse_steps=0,
+                 allow_unstable=False, stream=None):
         lib = L.lib()
         self.prec = prec
         self.prob = prob
@@ -80,7 +80,8 @@ class Simulation:
         dt = 0.0 if prob["dt"] is None else float(prob["dt"])
         opt = L.fed_options(PRECISIONS[prec], dt, float(prob["safety"]), float(prob["T_lo"]),
                             float(prob["T_hi"]), int(bool(allow_unstable)),
-                            _ptr(inst, C.c_int32), int(tile_nodes), int(block_threads))
+                            _ptr(inst, C.c_int32), int(tile_nodes), int(block_threads),
+                            int(fuse_steps))
         self.stream = current_stream() if stream is None else stream
         ctx = C.c_void_p()
         L.check(lib.fed_create(C.byref(mesh), C.byref(mats), C.byref(bcs), C.byref(opt),

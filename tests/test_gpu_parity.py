@@ -113,6 +113,21 @@ def test_tilings_are_bitwise_identical():
     assert np.array_equal(T, base)
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_fused_steps_are_bitwise_identical(prec):
+    """A launch that advances K steps (K element rings of halo per tile) gives
+    exactly the single-step result; step counts not divisible by K end with a
+    shorter launch."""
+    for p in (P.cube_nonlinear_hex(8, 37), P.cube_aniso_tet(5, 37)):
+        base, _ = _gpu_run(p, prec, 37, fuse_steps=1)
+        for K in (2, 3, 4):
+            T, s = _gpu_run(p, prec, 37, fuse_steps=K)
+            assert s.info["fuse_steps"] == K
+            assert np.array_equal(T, base), (p["name"], K)
+        T, _ = _gpu_run(p, prec, 37, fuse_steps=3, graph_steps=12, tile_nodes=50)
+        assert np.array_equal(T, base)
+
+
 def test_graph_and_repeat_bitwise():
     p = P.cube_nonlinear_hex(8, 90)
     a, _ = _gpu_run(p, "fp32c", 90)

@@ -29,6 +29,8 @@ def checker():
     ("hex", 5, 6, 7, 1000), ("hex", 5, 6, 7, 37), ("hex", 9, 9, 9, 64), ("hex", 1, 1, 1, 1),
     ("tet", 4, 5, 3, 50), ("tet", 6, 6, 6, 400), ("tet", 2, 2, 2, 3),
     ("hex", 4, 3, 5, 30, 5), ("tet", 3, 3, 3, 40, 4),
+    ("hex", 6, 7, 5, 40, 1, 2), ("hex", 9, 9, 9, 200, 1, 3), ("tet", 5, 4, 6, 60, 1, 2),
+    ("hex", 4, 3, 5, 30, 3, 2), ("tet", 4, 4, 4, 100, 2, 3), ("hex", 3, 3, 3, 500, 1, 4),
 ])
 def test_tiling_invariants(checker, args):
     r = subprocess.run([checker] + [str(a) for a in args], capture_output=True, text=True)

@@ -1,10 +1,14 @@
 // Host-side invariant checker of the tiler (built with g++ and sanitizers by
 // tests/test_host_tiling.py; no HIP).  Usage:
-//   tiling_check <hex|tet> nx ny nz target [ninst]
+//   tiling_check <hex|tet> nx ny nz target [ninst] [depth]
 // Builds a structured box (or ninst disjoint copies), tiles it and checks that
 // every packed entry decodes to its node, that every owned node's slot
 // positions are 0..count-1 in ascending element order, that each element has
-// exactly one owner copy, and the size limits.  Prints "OK <tiles>" or fails.
+// exactly one owner copy, the node levels (checked against a separate
+// breadth-first search), that every sub-step of a k-step launch finds all
+// elements of the nodes it updates in its element prefix, and the size limits.
+// Prints "OK <tiles>" or fails.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -27,6 +31,7 @@ int main(int argc, char **argv) {
   int nx = std::atoi(argv[2]), ny = std::atoi(argv[3]), nz = std::atoi(argv[4]);
   int target = std::atoi(argv[5]);
   int ninst = argc > 6 ? std::atoi(argv[6]) : 1;
+  int depth = argc > 7 ? std::atoi(argv[7]) : 1;
   const int ne = hex ? 8 : 4;
   auto nid = [&](int i, int j, int k) { return i + (nx + 1) * (j + (ny + 1) * k); };
   const int np1 = (nx + 1) * (ny + 1) * (nz + 1);
@@ -83,6 +88,8 @@ int main(int argc, char **argv) {
   in.node_instance = ninst > 1 ? inst.data() : nullptr;
   in.has_bnd = has_bnd.data();
   in.target_nodes = target;
+  in.depth = depth;
+  in.upd_bytes = 16;
   fed::Tiling T;
   std::string err = fed::build_tiling(in, T);
   if (!err.empty()) {
@@ -111,21 +118,64 @@ int main(int argc, char **argv) {
       REQUIRE((j < th.nbnd) == (has_bnd[k] != 0));
       if (ninst > 1) REQUIRE(inst[k] == inst[T.iperm[th.nstart]]);
     }
+    const int K = depth;
+    REQUIRE(th.cum_n[0] == th.nown && th.cum_n[K] == th.nown + th.nhalo);
     REQUIRE((uint32_t)(th.nown + th.nhalo) <= limit);
-    REQUIRE(4LL * (th.nown + th.nhalo + (int64_t)T.maxinc * th.nown) <= T.lds_bytes);
-    // expected element set: incident elements of owned nodes
-    std::set<int32_t> want;
+    REQUIRE(4LL * th.cum_n[K] + (16LL + 4LL * T.maxinc) * th.cum_n[K - 1] + 8 <= T.lds_bytes);
+    // independent BFS levels from the owned set (internal ids), capped at K
+    std::vector<int> lvl(N, -1);
+    std::vector<int32_t> front, nxt;
     for (int j = 0; j < th.nown; j++) {
-      int32_t ki = th.nstart + j;
-      for (int64_t p = T.inc_ptr[ki]; p < T.inc_ptr[ki + 1]; p++) want.insert(T.inc_elem[p]);
+      lvl[th.nstart + j] = 0;
+      front.push_back(th.nstart + j);
     }
-    REQUIRE((int)want.size() == th.ecount);
-    std::vector<std::vector<std::pair<int32_t, int>>> got(th.nown);  // (elem, pos)
+    for (int l = 1; l <= K; l++) {
+      nxt.clear();
+      for (int32_t ki : front)
+        for (int64_t p = T.inc_ptr[ki]; p < T.inc_ptr[ki + 1]; p++) {
+          int32_t e = T.inc_elem[p];
+          for (int a = 0; a < ne; a++) {
+            int32_t kj = T.perm[conn[a * E + e]];
+            if (lvl[kj] < 0) {
+              lvl[kj] = l;
+              nxt.push_back(kj);
+            }
+          }
+        }
+      front.swap(nxt);
+    }
+    auto local_level = [&](int32_t lc) {
+      int l = 0;
+      while (lc >= th.cum_n[l]) l++;
+      return l;
+    };
+    int64_t nlev = 0;
+    for (int64_t ki = 0; ki < N; ki++) nlev += lvl[ki] >= 0;
+    REQUIRE(nlev == th.cum_n[K]);
+    for (int h = 0; h < th.nhalo; h++) {
+      int32_t ki = T.halo[th.hstart + h];
+      REQUIRE(lvl[ki] == local_level(th.nown + h));
+      if (h && local_level(th.nown + h) == local_level(th.nown + h - 1))
+        REQUIRE(ki > T.halo[th.hstart + h - 1]);
+    }
+    // expected element set: elements touching a node of level < K
+    std::set<int32_t> want;
+    for (int64_t ki = 0; ki < N; ki++)
+      if (lvl[ki] >= 0 && lvl[ki] < K)
+        for (int64_t p = T.inc_ptr[ki]; p < T.inc_ptr[ki + 1]; p++) want.insert(T.inc_elem[p]);
+    REQUIRE((int)want.size() == th.ecount && th.cum_e[K - 1] == th.ecount);
+    std::vector<std::vector<std::pair<int32_t, int>>> got(th.cum_n[K - 1]);  // (elem, pos)
+    int prevlev = 0;
     int32_t prev = -1;
     for (int i = 0; i < th.ecount; i++) {
       int64_t ie = th.estart + i;
       int32_t e = T.eorig[ie];
-      REQUIRE(e > prev && want.count(e));
+      REQUIRE(want.count(e));
+      int ml = 99;
+      for (int a = 0; a < ne; a++) ml = std::min(ml, lvl[T.perm[conn[a * E + e]]]);
+      REQUIRE(ml >= prevlev && (ml > prevlev || e > prev));
+      for (int l = 0; l < K; l++) REQUIRE((i < th.cum_e[l]) == (ml <= l));
+      prevlev = ml;
       prev = e;
       owners[e] += T.eowner[ie];
       for (int a = 0; a < ne; a++) {
@@ -134,25 +184,31 @@ int main(int argc, char **argv) {
         REQUIRE(loc < (uint32_t)(th.nown + th.nhalo));
         int32_t ki = loc < (uint32_t)th.nown ? th.nstart + loc : T.halo[th.hstart + loc - th.nown];
         REQUIRE(ki == T.perm[conn[a * E + e]]);
-        if (loc < (uint32_t)th.nown) {
+        if (loc < (uint32_t)th.cum_n[K - 1]) {
           REQUIRE((int)pos < T.maxinc);
           got[loc].push_back({e, (int)pos});
         }
       }
     }
-    for (int j = 0; j < th.nown; j++) {
-      int32_t ki = th.nstart + j;
+    // every updated node sees its full incidence, in ascending element order, and
+    // in a k-step launch sub-step s finds it within the prefix cum_e[k - s]
+    for (int32_t lc = 0; lc < th.cum_n[K - 1]; lc++) {
+      int32_t ki = lc < th.nown ? th.nstart + lc : T.halo[th.hstart + lc - th.nown];
       int64_t cnt = T.inc_ptr[ki + 1] - T.inc_ptr[ki];
-      REQUIRE((int64_t)got[j].size() == cnt);
-      for (size_t q = 0; q < got[j].size(); q++) {
-        REQUIRE(got[j][q].second == (int)q);  // elements ascending == positions ascending
-        REQUIRE(got[j][q].first == T.inc_elem[T.inc_ptr[ki] + q]);
+      std::vector<std::pair<int32_t, int>> g = got[lc];
+      std::sort(g.begin(), g.end());
+      REQUIRE((int64_t)g.size() == cnt);
+      for (size_t q = 0; q < g.size(); q++) {
+        REQUIRE(g[q].second == (int)q);
+        REQUIRE(g[q].first == T.inc_elem[T.inc_ptr[ki] + q]);
       }
-    }
-    for (int h = 0; h < th.nhalo; h++) {
-      int32_t ki = T.halo[th.hstart + h];
-      REQUIRE(ki < th.nstart || ki >= th.nstart + th.nown);
-      if (h) REQUIRE(ki > T.halo[th.hstart + h - 1]);
+      int l = local_level(lc);
+      for (int i = 0; i < th.ecount; i++) {
+        int32_t e = T.eorig[th.estart + i];
+        bool touches = false;
+        for (int a = 0; a < ne; a++) touches |= T.perm[conn[a * E + e]] == ki;
+        if (touches) REQUIRE(i < th.cum_e[l]);
+      }
     }
   }
   REQUIRE(next == N);
