@@ -189,6 +189,37 @@ int fed_steps_taken(const fed_ctx *ctx, int64_t *steps);
 int fed_get_state(fed_ctx *ctx, void *hi, void *lo, int64_t *step, void *stream);
 int fed_set_state(fed_ctx *ctx, const void *hi, const void *lo, int64_t step, void *stream);
 
+/* Checkpointing for the adjoint: with every > 0, the state at step 0 (the one
+ * fed_set_temperature sets) and after every `every` steps is kept on the device
+ * (2 state vectors each; fed_step breaks its launches at those steps).  0 turns
+ * it off and frees the checkpoints.  Call before fed_set_temperature. */
+int fed_checkpoint_every(fed_ctx *ctx, int64_t every);
+
+/* Replaces per-element conductivity factors (kscale, n_elems, > 0), per-element
+ * heat capacities (elem_c, n_elems, > 0; the capacity c0 of each element, for
+ * materials with c1 = 0) and per-face convection coefficients (face_h, n_faces,
+ * >= 0); NULL leaves a set unchanged.  Re-derives on the GPU the element
+ * operators, the lumped capacity and the boundary coefficients (Sec. 3.5 (i))
+ * and re-checks the stability bound for the time step in use (FED_E_UNSTABLE
+ * if it is exceeded and allow_unstable is off).  Arrays are FP64, caller order,
+ * host memory if on_device == 0.  Synchronises `stream`. */
+int fed_set_params(fed_ctx *ctx, const double *kscale, const double *elem_c,
+                   const double *face_h, int32_t on_device, void *stream);
+
+/* Discrete adjoint of the steps taken since fed_set_temperature (not in the
+ * paper; it differentiates the explicit recursion of Sec. 3.1 exactly).  For a
+ * loss L with gradient dL_dT with respect to the current temperatures (FP64,
+ * n_nodes, caller order), runs the steps in reverse, recomputing each
+ * checkpoint segment, and returns dL/dlog k_e (g_logk, n_elems), dL/dc_e (g_c,
+ * n_elems), dL/dh_f (g_h, n_faces) and dL/dT0 (n_nodes; zero on Dirichlet
+ * nodes); any output may be NULL.  Pointers are host memory if on_device == 0,
+ * else device.  Requires a problem linear in T (s1 = 0, c1 = 0, no radiation)
+ * and checkpointing on (FED_E_STATE otherwise); FED_E_MESH if a tile needs more
+ * LDS than the adjoint kernel can take.  Synchronises `stream`; the forward
+ * state is left unchanged. */
+int fed_backward(fed_ctx *ctx, const double *dL_dT, double *g_logk, double *g_c, double *g_h,
+                 double *dL_dT0, int32_t on_device, void *stream);
+
 /* Destroys the context and frees its device memory (synchronises the device). */
 void fed_destroy(fed_ctx *ctx);
 

@@ -77,6 +77,11 @@ SIGNATURES = {
     "fed_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
                                 C.c_void_p]),
     "fed_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fed_checkpoint_every": (C.c_int, [C.c_void_p, C.c_int64]),
+    "fed_set_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                 C.c_void_p]),
+    "fed_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_int32, C.c_void_p]),
     "fed_destroy": (None, [C.c_void_p]),
     "fed_last_error": (C.c_char_p, []),
 }

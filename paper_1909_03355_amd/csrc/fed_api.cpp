@@ -70,6 +70,7 @@ struct fed_ctx {
   fed::TileHdr *d_tiles = nullptr;
   uint16_t *d_ent = nullptr;
   int32_t *d_halo = nullptr, *d_perm = nullptr, *d_eorig = nullptr, *d_rec_of = nullptr;
+  uint8_t *d_eowner = nullptr;
   void *d_H = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
   void *d_rA = nullptr, *d_rAT = nullptr, *d_reA = nullptr, *d_rTa = nullptr, *d_rP = nullptr;
   void *d_T[2] = {nullptr, nullptr};
@@ -78,9 +79,30 @@ struct fed_ctx {
   double *d_dir_T = nullptr;
   int *d_flag = nullptr;
   double *d_Tuser = nullptr;  // FP64 staging in caller order
-  // kept FP64 pre-computation
+  // kept FP64 pre-computation (re-derived by fed_set_params, used by the adjoint)
   double *d_H0 = nullptr, *d_kscale = nullptr, *d_V = nullptr;
-  double *d_M0 = nullptr, *d_M1 = nullptr;
+  double *d_M0 = nullptr, *d_M1 = nullptr, *d_Cmin = nullptr, *d_lamgeo = nullptr;
+  double *d_ec0 = nullptr;  // per-element heat capacity override (fed_set_params)
+  fed::MatDev *d_mats = nullptr;
+  int32_t *d_emat = nullptr, *d_ince = nullptr, *d_einst = nullptr, *d_ninst = nullptr;
+  int64_t *d_incp = nullptr;
+  int32_t *d_faces = nullptr, *d_recitem = nullptr, *d_recnode = nullptr;
+  int64_t *d_recptr = nullptr;
+  double *d_fh = nullptr, *d_fTa = nullptr, *d_feps = nullptr, *d_fq = nullptr, *d_farea = nullptr;
+  double *d_ptW = nullptr, *d_b64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double *d_dtinst = nullptr;
+  uint8_t *d_isdir = nullptr;
+  unsigned long long *d_lam = nullptr;
+  int64_t nf = 0;
+  int nfn = 4;
+  bool has_rad = false, allow_unstable = false;
+  // checkpoints (state after every ckpt_every steps) and adjoint work arrays
+  int64_t ckpt_every = 0;
+  std::vector<void *> ck_hi, ck_lo;
+  void *d_seg = nullptr, *d_lamb[2] = {nullptr, nullptr}, *d_rdt = nullptr, *d_mV = nullptr;
+  float *d_seglo[2] = {nullptr, nullptr}, *d_lamlo[2] = {nullptr, nullptr};
+  double *d_S0 = nullptr, *d_S1 = nullptr, *d_gk = nullptr, *d_gc = nullptr, *d_gh = nullptr;
+  int adj_lds = 0;
   // scalars
   double s0 = 1, s1 = 0, Tz = -273.15, T_lo = 0, T_hi = 0;
   int tdk = 0, tdc = 0, block = 256, nper = 1, K = 1;
@@ -148,6 +170,9 @@ struct fed_ctx {
 };
 
 namespace {
+
+int save_checkpoint(fed_ctx *c, int64_t i, hipStream_t s);
+int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s);
 
 template <typename T>
 hipError_t upload(DevPool &pool, T **d, const T *h, size_t n) {
@@ -379,9 +404,11 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   HIPCHK(upload(tmp, &d_z, m->z, N));
   HIPCHK(upload(tmp, &d_conn, m->conn, (size_t)ne * E));
   static_assert(sizeof(fed::MatDev) == sizeof(fed_material), "material layout");
-  HIPCHK(upload(tmp, &d_mats, reinterpret_cast<const fed::MatDev *>(mt->materials),
+  HIPCHK(upload(P, &d_mats, reinterpret_cast<const fed::MatDev *>(mt->materials),
                 (size_t)mt->n_materials));
-  if (mt->elem_material) HIPCHK(upload(tmp, &d_emat, mt->elem_material, (size_t)E));
+  if (mt->elem_material) HIPCHK(upload(P, &d_emat, mt->elem_material, (size_t)E));
+  c->d_mats = d_mats;
+  c->d_emat = d_emat;
   if (mt->elem_k) HIPCHK(upload(tmp, &d_ek, mt->elem_k, (size_t)6 * E));
   {
     std::vector<double> ks(E, 1.0);
@@ -394,7 +421,8 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   double *d_lamgeo;
   HIPCHK(P.alloc((void **)&c->d_H0, sizeof(double) * 6 * E));
   HIPCHK(P.alloc((void **)&c->d_V, sizeof(double) * E));
-  HIPCHK(tmp.alloc((void **)&d_lamgeo, sizeof(double) * E));
+  HIPCHK(P.alloc((void **)&d_lamgeo, sizeof(double) * E));
+  c->d_lamgeo = d_lamgeo;
   fed::GeomArgs ga{ne, E, d_x, d_y, d_z, d_conn, d_mats, d_emat, d_ek,
                    c->d_H0, c->d_V, d_lamgeo, d_cnt, d_cnt + 1};
   HIPCHK(fed::launch_geom(ga, s));
@@ -406,13 +434,16 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   // lumped capacity per internal node
   int64_t *d_incp;
   int32_t *d_ince;
-  HIPCHK(upload(tmp, &d_incp, T.inc_ptr.data(), T.inc_ptr.size()));
-  HIPCHK(upload(tmp, &d_ince, T.inc_elem.data(), T.inc_elem.size()));
+  HIPCHK(upload(P, &d_incp, T.inc_ptr.data(), T.inc_ptr.size()));
+  HIPCHK(upload(P, &d_ince, T.inc_elem.data(), T.inc_elem.size()));
+  c->d_incp = d_incp;
+  c->d_ince = d_ince;
   double *d_Cmin;
   HIPCHK(P.alloc((void **)&c->d_M0, sizeof(double) * N));
   HIPCHK(P.alloc((void **)&c->d_M1, sizeof(double) * N));
-  HIPCHK(tmp.alloc((void **)&d_Cmin, sizeof(double) * N));
-  fed::MassArgs ma{N, ne, d_incp, d_ince, d_mats, d_emat, c->d_V, o->T_lo, o->T_hi,
+  HIPCHK(P.alloc((void **)&d_Cmin, sizeof(double) * N));
+  c->d_Cmin = d_Cmin;
+  fed::MassArgs ma{N, ne, d_incp, d_ince, d_mats, d_emat, nullptr, c->d_V, o->T_lo, o->T_hi,
                    c->d_M0, c->d_M1, d_Cmin};
   HIPCHK(fed::launch_mass(ma, s));
   // boundary lumping
@@ -421,37 +452,60 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   double *d_fh = nullptr, *d_fTa = nullptr, *d_feps = nullptr, *d_fq = nullptr, *d_farea = nullptr;
   double *d_ptW = nullptr, *b64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   const int64_t nf = bc->n_faces;
+  c->nf = nf;
+  c->nfn = bc->face_nodes;
   if (nf > 0) {
-    HIPCHK(upload(tmp, &d_faces, bc->faces, (size_t)nf * bc->face_nodes));
-    if (bc->face_h) HIPCHK(upload(tmp, &d_fh, bc->face_h, (size_t)nf));
-    if (bc->face_Ta) HIPCHK(upload(tmp, &d_fTa, bc->face_Ta, (size_t)nf));
-    if (bc->face_eps) HIPCHK(upload(tmp, &d_feps, bc->face_eps, (size_t)nf));
-    if (bc->face_q) HIPCHK(upload(tmp, &d_fq, bc->face_q, (size_t)nf));
-    HIPCHK(tmp.alloc((void **)&d_farea, sizeof(double) * nf));
+    // every face array exists on the device (zeros for NULL) so that
+    // fed_set_params can replace h later
+    std::vector<double> zeros(nf, 0.0);
+    HIPCHK(upload(P, &d_faces, bc->faces, (size_t)nf * bc->face_nodes));
+    HIPCHK(upload(P, &d_fh, bc->face_h ? bc->face_h : zeros.data(), (size_t)nf));
+    HIPCHK(upload(P, &d_fTa, bc->face_Ta ? bc->face_Ta : zeros.data(), (size_t)nf));
+    HIPCHK(upload(P, &d_feps, bc->face_eps ? bc->face_eps : zeros.data(), (size_t)nf));
+    HIPCHK(upload(P, &d_fq, bc->face_q ? bc->face_q : zeros.data(), (size_t)nf));
+    HIPCHK(P.alloc((void **)&d_farea, sizeof(double) * nf));
+    if (bc->face_eps)
+      for (int64_t f = 0; f < nf; f++) c->has_rad |= bc->face_eps[f] > 0;
   }
-  if (bc->n_pt > 0) HIPCHK(upload(tmp, &d_ptW, bc->pt_W, (size_t)bc->n_pt));
+  if (bc->n_pt > 0) HIPCHK(upload(P, &d_ptW, bc->pt_W, (size_t)bc->n_pt));
   const int64_t nrec = c->nrec;
   if (nrec > 0) {
-    HIPCHK(upload(tmp, &d_recptr, rec_ptr.data(), rec_ptr.size()));
-    HIPCHK(upload(tmp, &d_recitem, rec_item.data(), rec_item.size()));
-    HIPCHK(upload(tmp, &d_recnode, rec_node.data(), rec_node.size()));
-    for (int i = 0; i < 4; i++) HIPCHK(tmp.alloc((void **)&b64[i], sizeof(double) * nrec));
-    HIPCHK(upload(tmp, &b64[4], rec_ta.data(), rec_ta.size()));
+    HIPCHK(upload(P, &d_recptr, rec_ptr.data(), rec_ptr.size()));
+    HIPCHK(upload(P, &d_recitem, rec_item.data(), rec_item.size()));
+    HIPCHK(upload(P, &d_recnode, rec_node.data(), rec_node.size()));
+    for (int i = 0; i < 4; i++) HIPCHK(P.alloc((void **)&b64[i], sizeof(double) * nrec));
+    HIPCHK(upload(P, &b64[4], rec_ta.data(), rec_ta.size()));
   }
+  c->d_faces = d_faces;
+  c->d_fh = d_fh;
+  c->d_fTa = d_fTa;
+  c->d_feps = d_feps;
+  c->d_fq = d_fq;
+  c->d_farea = d_farea;
+  c->d_ptW = d_ptW;
+  c->d_recptr = d_recptr;
+  c->d_recitem = d_recitem;
+  c->d_recnode = d_recnode;
+  for (int i = 0; i < 5; i++) c->d_b64[i] = b64[i];
   fed::BndArgs ba{nf, bc->face_nodes, d_faces, d_x, d_y, d_z, d_fh, d_fTa, d_feps, d_fq,
                   d_farea, nrec, d_recptr, d_recitem, d_ptW, b64[0], b64[1], b64[2], b64[3]};
   HIPCHK(fed::launch_bnd(ba, s));
   // stability bound per instance (Sec. 3.4)
   int32_t *d_einst = nullptr, *d_ninst = nullptr;
   if (o->node_instance) {
-    HIPCHK(upload(tmp, &d_einst, elem_inst.data(), elem_inst.size()));
+    HIPCHK(upload(P, &d_einst, elem_inst.data(), elem_inst.size()));
     HIPCHK(upload(P, &d_ninst, node_inst_int.data(), node_inst_int.size()));
   }
+  c->d_einst = d_einst;
+  c->d_ninst = d_ninst;
+  c->allow_unstable = o->allow_unstable != 0;
   unsigned long long *d_lam;
-  HIPCHK(tmp.alloc((void **)&d_lam, sizeof(unsigned long long) * 2 * c->ninst));
+  HIPCHK(P.alloc((void **)&d_lam, sizeof(unsigned long long) * 2 * c->ninst));
+  c->d_lam = d_lam;
   HIPCHK(hipMemsetAsync(d_lam, 0, sizeof(unsigned long long) * 2 * c->ninst, s));
-  fed::DtArgs da{ne, E, nrec, d_lamgeo, c->d_kscale, d_mats, d_emat, d_einst, d_recnode, d_ninst,
-                 b64[0], b64[2], d_Cmin, o->T_lo, o->T_hi, bc->Tz, d_lam, d_lam + c->ninst};
+  fed::DtArgs da{ne, E, nrec, d_lamgeo, c->d_kscale, d_mats, d_emat, nullptr, d_einst, d_recnode,
+                 d_ninst, b64[0], b64[2], d_Cmin, o->T_lo, o->T_hi, bc->Tz, d_lam,
+                 d_lam + c->ninst};
   HIPCHK(fed::launch_dt(da, s));
   std::vector<unsigned long long> lam(2 * c->ninst);
   HIPCHK(hipMemcpyAsync(lam.data(), d_lam, lam.size() * sizeof(unsigned long long),
@@ -480,8 +534,10 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   const int rb = c->rb;
   double *d_dtinst;
   uint8_t *d_isdir;
-  HIPCHK(upload(tmp, &d_dtinst, c->dt_used.data(), c->dt_used.size()));
-  HIPCHK(upload(tmp, &d_isdir, is_dir.data(), is_dir.size()));
+  HIPCHK(upload(P, &d_dtinst, c->dt_used.data(), c->dt_used.size()));
+  HIPCHK(upload(P, &d_isdir, is_dir.data(), is_dir.size()));
+  c->d_dtinst = d_dtinst;
+  c->d_isdir = d_isdir;
   HIPCHK(P.alloc(&c->d_alpha, (size_t)rb * N));
   if (c->tdc) HIPCHK(P.alloc(&c->d_beta, (size_t)rb * N));
   else {
@@ -494,6 +550,7 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
                       c->d_alpha, c->d_beta, c->d_rA, c->d_rAT, c->d_reA, c->d_rTa, c->d_rP};
   HIPCHK(fed::launch_node_arrays(na, s));
   HIPCHK(upload(P, &c->d_eorig, T.eorig.data(), T.eorig.size()));
+  HIPCHK(upload(P, &c->d_eowner, T.eowner.data(), T.eowner.size()));
   HIPCHK(P.alloc(&c->d_H, (size_t)rb * 6 * c->Eexp));
   HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->Eexp, E, c->d_eorig, c->d_H0,
                               c->d_kscale, c->d_H, s));
@@ -520,6 +577,12 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
     return fail(FED_E_MESH, "tile needs %d bytes of LDS", T.lds_bytes);
   HIPCHK(fed::step_set_lds_limit(c->prec == FED_FP64 ? 1 : (c->prec == FED_FP32C ? 0 : 2), ne,
                                  c->tdk, c->tdc, std::max(T.lds_bytes, 1)));
+  // LDS of the adjoint step: mu, T^n and the scaled increment of the touched
+  // nodes of the first ring, and the slots of the owned nodes
+  for (const fed::TileHdr &th : T.tiles)
+    c->adj_lds = std::max(c->adj_lds, rb * (3 * th.cum_n[1] + T.maxinc * th.nown));
+  if (c->adj_lds <= 64 * 1024)
+    HIPCHK(fed::adjoint_set_lds_limit(c->prec, ne, std::max(c->adj_lds, 1)));
   HIPCHK(hipStreamSynchronize(s));
   // ---- info -------------------------------------------------------------------
   fed_info &I = c->info;
@@ -589,18 +652,23 @@ int fed_set_temperature(fed_ctx *c, const double *T, int32_t on_device, void *st
   c->cur = 0;
   HIPCHK(fed::launch_set_T(c->prec, c->N, src, c->d_perm, c->d_T[0], c->d_lo[0], c->ndir,
                            c->d_dir_node, c->d_dir_T, s));
-  if (!on_device) HIPCHK(hipStreamSynchronize(s));  // the host buffer may be reused
   c->steps = 0;
   c->have_T = true;
   HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  if (c->ckpt_every > 0) {
+    int rc = save_checkpoint(c, 0, s);
+    if (rc) return rc;
+  }
+  if (!on_device) HIPCHK(hipStreamSynchronize(s));  // the host buffer may be reused
   return FED_OK;
 }
 
-int fed_step(fed_ctx *c, int64_t nsteps, void *stream) {
-  if (!c) return fail(FED_E_ARG, "null ctx");
-  if (!c->have_T) return fail(FED_E_STATE, "fed_set_temperature must come first");
-  if (nsteps < 0) return fail(FED_E_ARG, "nsteps < 0");
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// nsteps steps in launches of up to K steps, no checkpoint handling
+int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
   for (int64_t n = nsteps; n > 0;) {
     int k = (int)std::min<int64_t>(c->K, n);
     fed::StepArgs a = c->step_args(c->cur, k);
@@ -612,10 +680,52 @@ int fed_step(fed_ctx *c, int64_t nsteps, void *stream) {
   return FED_OK;
 }
 
+// copies the current state into checkpoint slot i (allocating it on first use)
+int save_checkpoint(fed_ctx *c, int64_t i, hipStream_t s) {
+  if ((int64_t)c->ck_hi.size() <= i) {
+    c->ck_hi.resize(i + 1, nullptr);
+    c->ck_lo.resize(i + 1, nullptr);
+  }
+  const size_t hb = (size_t)c->rb * c->N;
+  if (!c->ck_hi[i]) HIPCHK(c->pool.alloc(&c->ck_hi[i], hb));
+  HIPCHK(hipMemcpyAsync(c->ck_hi[i], c->d_T[c->cur], hb, hipMemcpyDeviceToDevice, s));
+  if (c->prec == FED_FP32C) {
+    if (!c->ck_lo[i]) HIPCHK(c->pool.alloc(&c->ck_lo[i], sizeof(float) * c->N));
+    HIPCHK(hipMemcpyAsync(c->ck_lo[i], c->d_lo[c->cur], sizeof(float) * c->N,
+                          hipMemcpyDeviceToDevice, s));
+  }
+  return FED_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fed_step(fed_ctx *c, int64_t nsteps, void *stream) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  if (!c->have_T) return fail(FED_E_STATE, "fed_set_temperature must come first");
+  if (nsteps < 0) return fail(FED_E_ARG, "nsteps < 0");
+  hipStream_t s = (hipStream_t)stream;
+  if (c->ckpt_every <= 0) return run_steps(c, nsteps, s);
+  // break the launches at checkpoint steps and save the state there
+  while (nsteps > 0) {
+    int64_t chunk = std::min(nsteps, c->ckpt_every - c->steps % c->ckpt_every);
+    int rc = run_steps(c, chunk, s);
+    if (rc) return rc;
+    nsteps -= chunk;
+    if (c->steps % c->ckpt_every == 0) {
+      rc = save_checkpoint(c, c->steps / c->ckpt_every, s);
+      if (rc) return rc;
+    }
+  }
+  return FED_OK;
+}
+
 int fed_step_graph(fed_ctx *c, int64_t nsteps, int32_t graph_steps, void *stream) {
   if (!c) return fail(FED_E_ARG, "null ctx");
   if (!c->have_T) return fail(FED_E_STATE, "fed_set_temperature must come first");
   if (nsteps < 0 || graph_steps < 0) return fail(FED_E_ARG, "negative count");
+  if (c->ckpt_every > 0) return fed_step(c, nsteps, stream);  // checkpoints break launches
   hipStream_t s = (hipStream_t)stream;
   // an even number of K-step launches, so every replay starts on the same buffer
   int64_t want = graph_steps ? graph_steps : 100;
@@ -650,7 +760,7 @@ int fed_step_graph(fed_ctx *c, int64_t nsteps, int32_t graph_steps, void *stream
   int64_t reps = nsteps / gs;
   for (int64_t r = 0; r < reps; r++) HIPCHK(hipGraphLaunch(c->gexec, s));
   c->steps += reps * gs;
-  return fed_step(c, nsteps - reps * gs, stream);
+  return run_steps(c, nsteps - reps * gs, s);
 }
 
 int fed_get_temperature(fed_ctx *c, double *T, int32_t on_device, void *stream) {
@@ -718,6 +828,211 @@ int fed_set_state(fed_ctx *c, const void *hi, const void *lo, int64_t step, void
   HIPCHK(hipStreamSynchronize(s));
   c->steps = step;
   c->have_T = true;
+  return FED_OK;
+}
+
+int fed_checkpoint_every(fed_ctx *c, int64_t every) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  if (every < 0) return fail(FED_E_ARG, "every < 0");
+  for (void *p : c->ck_hi) c->pool.release(p);
+  for (void *p : c->ck_lo) c->pool.release(p);
+  c->ck_hi.clear();
+  c->ck_lo.clear();
+  c->ckpt_every = every;
+  c->have_T = false;  // the checkpoint of step 0 is taken by fed_set_temperature
+  return FED_OK;
+}
+
+int fed_set_params(fed_ctx *c, const double *kscale, const double *elem_c, const double *face_h,
+                   int32_t on_device, void *stream) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t E = c->E, N = c->N, nf = c->nf;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+  // validate on the host
+  std::vector<double> ks, ec, fh;
+  if (kscale) {
+    ks.resize(E);
+    HIPCHK(hipMemcpy(ks.data(), kscale, sizeof(double) * E, kind));
+    for (int64_t e = 0; e < E; e++)
+      if (!(ks[e] > 0) || !std::isfinite(ks[e])) return fail(FED_E_ARG, "kscale[%lld] invalid", (long long)e);
+  }
+  if (elem_c) {
+    if (c->tdc) return fail(FED_E_ARG, "per-element heat capacity needs c1 = 0");
+    ec.resize(E);
+    HIPCHK(hipMemcpy(ec.data(), elem_c, sizeof(double) * E, kind));
+    for (int64_t e = 0; e < E; e++)
+      if (!(ec[e] > 0) || !std::isfinite(ec[e])) return fail(FED_E_ARG, "elem_c[%lld] invalid", (long long)e);
+  }
+  if (face_h) {
+    if (nf == 0) return fail(FED_E_ARG, "the problem has no faces");
+    fh.resize(nf);
+    HIPCHK(hipMemcpy(fh.data(), face_h, sizeof(double) * nf, kind));
+    for (int64_t f = 0; f < nf; f++)
+      if (!(fh[f] >= 0) || !std::isfinite(fh[f])) return fail(FED_E_ARG, "face_h[%lld] invalid", (long long)f);
+  }
+  // re-derive on the GPU
+  if (kscale) HIPCHK(hipMemcpyAsync(c->d_kscale, ks.data(), sizeof(double) * E, hipMemcpyHostToDevice, s));
+  if (elem_c) {
+    if (!c->d_ec0) HIPCHK(c->pool.alloc((void **)&c->d_ec0, sizeof(double) * E));
+    HIPCHK(hipMemcpyAsync(c->d_ec0, ec.data(), sizeof(double) * E, hipMemcpyHostToDevice, s));
+  }
+  if (face_h) HIPCHK(hipMemcpyAsync(c->d_fh, fh.data(), sizeof(double) * nf, hipMemcpyHostToDevice, s));
+  fed::MassArgs ma{N, c->ne, c->d_incp, c->d_ince, c->d_mats, c->d_emat, c->d_ec0, c->d_V,
+                   c->T_lo, c->T_hi, c->d_M0, c->d_M1, c->d_Cmin};
+  HIPCHK(fed::launch_mass(ma, s));
+  if (c->nrec > 0) {
+    fed::BndArgs ba{0, c->nfn, c->d_faces, nullptr, nullptr, nullptr, c->d_fh, c->d_fTa,
+                    c->d_feps, c->d_fq, c->d_farea, c->nrec, c->d_recptr, c->d_recitem,
+                    c->d_ptW, c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[3]};
+    HIPCHK(fed::launch_bnd(ba, s));  // nf = 0: face areas are kept, records recomputed
+  }
+  HIPCHK(hipMemsetAsync(c->d_lam, 0, sizeof(unsigned long long) * 2 * c->ninst, s));
+  fed::DtArgs da{c->ne, E, c->nrec, c->d_lamgeo, c->d_kscale, c->d_mats, c->d_emat, c->d_ec0,
+                 c->d_einst, c->d_recnode, c->d_ninst, c->d_b64[0], c->d_b64[2], c->d_Cmin,
+                 c->T_lo, c->T_hi, c->Tz, c->d_lam, c->d_lam + c->ninst};
+  HIPCHK(fed::launch_dt(da, s));
+  std::vector<unsigned long long> lam(2 * c->ninst);
+  HIPCHK(hipMemcpyAsync(lam.data(), c->d_lam, lam.size() * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int64_t i = 0; i < c->ninst; i++) {
+    double le, lb;
+    std::memcpy(&le, &lam[i], 8);
+    std::memcpy(&lb, &lam[c->ninst + i], 8);
+    c->dt_crit[i] = le + lb > 0 ? 2.0 / (le + lb) : INFINITY;
+    if (c->dt_used[i] > c->dt_crit[i] && !c->allow_unstable)
+      return fail(FED_E_UNSTABLE, "dt %.6g exceeds the new dt_crit %.6g (instance %lld)",
+                  c->dt_used[i], c->dt_crit[i], (long long)i);
+  }
+  fed::NodeArrArgs na{c->prec, N, c->nrec, c->d_M0, c->d_M1, c->d_dtinst, c->d_ninst, c->d_isdir,
+                      c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[4], c->d_b64[3],
+                      c->d_alpha, c->d_beta, c->d_rA, c->d_rAT, c->d_reA, c->d_rTa, c->d_rP};
+  HIPCHK(fed::launch_node_arrays(na, s));
+  HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->Eexp, E, c->d_eorig, c->d_H0,
+                              c->d_kscale, c->d_H, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return FED_OK;
+}
+
+int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, double *g_h,
+                 double *dL_dT0, int32_t on_device, void *stream) {
+  if (!c || !dL_dT) return fail(FED_E_ARG, "null argument");
+  if (!c->have_T) return fail(FED_E_STATE, "no forward run");
+  if (c->ckpt_every <= 0) return fail(FED_E_STATE, "checkpointing is off (fed_checkpoint_every)");
+  if (c->tdk || c->tdc || c->has_rad)
+    return fail(FED_E_ARG, "the adjoint covers problems linear in T (s1 = 0, c1 = 0, no radiation)");
+  if (c->adj_lds > 64 * 1024)
+    return fail(FED_E_MESH, "adjoint tiles need %d bytes of LDS; use smaller tile_nodes", c->adj_lds);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = c->N, E = c->E, ck = c->ckpt_every, steps = c->steps;
+  const int rb = c->rb;
+  DevPool &P = c->pool;
+  // work arrays, allocated on first use
+  if (!c->d_seg) {
+    HIPCHK(P.alloc(&c->d_seg, (size_t)rb * N * (ck + 1)));
+    for (int i = 0; i < 2; i++) {
+      HIPCHK(P.alloc(&c->d_lamb[i], (size_t)rb * N));
+      if (c->prec == FED_FP32C) {
+        HIPCHK(P.alloc((void **)&c->d_seglo[i], sizeof(float) * N));
+        HIPCHK(P.alloc((void **)&c->d_lamlo[i], sizeof(float) * N));
+      }
+    }
+    HIPCHK(P.alloc((void **)&c->d_S0, sizeof(double) * std::max<int64_t>(c->nrec, 1)));
+    HIPCHK(P.alloc((void **)&c->d_S1, sizeof(double) * std::max<int64_t>(c->nrec, 1)));
+    HIPCHK(P.alloc((void **)&c->d_gk, sizeof(double) * E));
+    HIPCHK(P.alloc((void **)&c->d_gc, sizeof(double) * E));
+    HIPCHK(P.alloc((void **)&c->d_gh, sizeof(double) * std::max<int64_t>(c->nf, 1)));
+    HIPCHK(P.alloc(&c->d_rdt, (size_t)rb * N));
+    HIPCHK(P.alloc(&c->d_mV, (size_t)rb * E));
+  }
+  HIPCHK(fed::launch_adjoint_coefs(c->prec == FED_FP64 ? 1 : 0, N, E, c->ne, c->d_dtinst,
+                                   c->d_ninst, c->d_mats, c->d_emat, c->d_V, c->d_rdt, c->d_mV, s));
+  HIPCHK(hipMemsetAsync(c->d_S0, 0, sizeof(double) * std::max<int64_t>(c->nrec, 1), s));
+  HIPCHK(hipMemsetAsync(c->d_S1, 0, sizeof(double) * std::max<int64_t>(c->nrec, 1), s));
+  HIPCHK(hipMemsetAsync(c->d_gk, 0, sizeof(double) * E, s));
+  HIPCHK(hipMemsetAsync(c->d_gc, 0, sizeof(double) * E, s));
+  // lambda^N = dL/dT^N in internal order
+  const double *src = dL_dT;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(c->d_Tuser, dL_dT, sizeof(double) * N, hipMemcpyHostToDevice, s));
+    src = c->d_Tuser;
+  }
+  HIPCHK(fed::launch_set_T(c->prec, N, src, c->d_perm, c->d_lamb[0], c->d_lamlo[0], 0, nullptr,
+                           nullptr, s));
+  int lc = 0;
+  auto seg = [&](int64_t i) {
+    return (void *)((char *)c->d_seg + (size_t)rb * N * i);
+  };
+  const int64_t nseg = (steps + ck - 1) / ck;
+  for (int64_t g = nseg - 1; g >= 0; g--) {
+    const int64_t n0 = g * ck, n1 = std::min(steps, n0 + ck);
+    if (g >= (int64_t)c->ck_hi.size() || !c->ck_hi[g])
+      return fail(FED_E_STATE, "checkpoint %lld missing", (long long)g);
+    // recompute the segment's states T^{n0..n1} from its checkpoint
+    HIPCHK(hipMemcpyAsync(seg(0), c->ck_hi[g], (size_t)rb * N, hipMemcpyDeviceToDevice, s));
+    if (c->prec == FED_FP32C)
+      HIPCHK(hipMemcpyAsync(c->d_seglo[0], c->ck_lo[g], sizeof(float) * N,
+                            hipMemcpyDeviceToDevice, s));
+    for (int64_t i = 0; i < n1 - n0; i++) {
+      fed::StepArgs a = c->step_args(0, 1);
+      a.Tin = seg(i);
+      a.Tout = seg(i + 1);
+      a.loin = c->d_seglo[i & 1];
+      a.loout = c->d_seglo[(i + 1) & 1];
+      HIPCHK(fed::launch_step(a, s));
+    }
+    // adjoint steps n1-1 .. n0
+    for (int64_t n = n1 - 1; n >= n0; n--) {
+      fed::AdjArgs a{};
+      a.prec = c->prec;
+      a.ne = c->ne;
+      a.nt = c->til.nt;
+      a.nper = c->nper;
+      a.block = c->block;
+      a.lds = c->adj_lds;
+      a.pb = c->til.pb;
+      a.maxinc = c->til.maxinc;
+      a.Eexp = c->Eexp;
+      a.tiles = c->d_tiles;
+      a.ent = c->d_ent;
+      a.halo = c->d_halo;
+      a.eorig = c->d_eorig;
+      a.eowner = c->d_eowner;
+      a.H = c->d_H;
+      a.alpha = c->d_alpha;
+      a.rdt = c->d_rdt;
+      a.mV = c->d_mV;
+      a.rA = c->d_rA;
+      a.lamin = c->d_lamb[lc];
+      a.lamloin = c->d_lamlo[lc];
+      a.lamout = c->d_lamb[1 - lc];
+      a.lamloout = c->d_lamlo[1 - lc];
+      a.Tn = seg(n - n0);
+      a.Tn1 = seg(n - n0 + 1);
+      a.g_logk = c->d_gk;
+      a.g_c = c->d_gc;
+      a.S0 = c->d_S0;
+      a.S1 = c->d_S1;
+      a.s0 = c->s0;
+      HIPCHK(fed::launch_adjoint(a, s));
+      lc ^= 1;
+    }
+  }
+  if (c->nf > 0)
+    HIPCHK(fed::launch_face_grad(c->nf, c->nfn, c->d_faces, c->d_perm, c->d_rec_of, c->d_farea,
+                                 c->d_fTa, c->d_S0, c->d_S1, c->d_gh, s));
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (g_logk) HIPCHK(hipMemcpyAsync(g_logk, c->d_gk, sizeof(double) * E, kind, s));
+  if (g_c) HIPCHK(hipMemcpyAsync(g_c, c->d_gc, sizeof(double) * E, kind, s));
+  if (g_h && c->nf > 0) HIPCHK(hipMemcpyAsync(g_h, c->d_gh, sizeof(double) * c->nf, kind, s));
+  if (dL_dT0) {
+    double *dst = on_device ? dL_dT0 : c->d_Tuser;
+    HIPCHK(fed::launch_get_T(c->prec, N, c->d_perm, c->d_lamb[lc], c->d_lamlo[lc], dst, s));
+    if (!on_device)
+      HIPCHK(hipMemcpyAsync(dL_dT0, c->d_Tuser, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
   return FED_OK;
 }
 

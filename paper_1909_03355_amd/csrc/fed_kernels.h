@@ -37,6 +37,7 @@ struct MassArgs {
   const int32_t *inc_elem;
   const MatDev *mats;
   const int32_t *emat;
+  const double *ec0;       // nullable, [E]: heat capacity c0 per element (c1 = 0)
   const double *V;
   double T_lo, T_hi;
   double *M0, *M1, *Cmin;  // internal node order
@@ -63,6 +64,7 @@ struct DtArgs {
   const double *lamgeo, *kscale;
   const MatDev *mats;
   const int32_t *emat;
+  const double *ec0;          // nullable per-element c0 override
   const int32_t *elem_inst;   // nullable
   const int32_t *rec_node;    // internal node of every record
   const int32_t *node_inst;   // nullable, internal order
@@ -103,6 +105,33 @@ struct StepArgs {
   double s0, s1, Tz;
 };
 
+// One step of the discrete adjoint of the explicit update, for problems that are
+// linear in T (constant D and c, no radiation).
+struct AdjArgs {
+  int prec, ne;
+  int nt, nper, block, lds;
+  int pb, maxinc;
+  int64_t Eexp;
+  const TileHdr *tiles;
+  const uint16_t *ent;
+  const int32_t *halo;
+  const int32_t *eorig;
+  const uint8_t *eowner;
+  const void *H;
+  const void *alpha;          // R[N]
+  const void *rdt;            // R[N]: 1 / dt of the node's instance
+  const void *mV;             // R[E]: rho V / n_e of every caller element
+  const void *rA;             // R[nrec]: h A of every boundary record
+  const void *lamin;          // R[N] lambda^{n+1} (hi)
+  const float *lamloin;       // lo part (compensated mode)
+  void *lamout;               // lambda^n
+  float *lamloout;
+  const void *Tn, *Tn1;       // R[N]: T^n and T^{n+1} (hi)
+  double *g_logk, *g_c;       // [E] caller element order
+  double *S0, *S1;            // [nrec]: sum of mu and of mu T^n
+  double s0;
+};
+
 hipError_t launch_geom(const GeomArgs &a, hipStream_t s);
 hipError_t launch_mass(const MassArgs &a, hipStream_t s);
 hipError_t launch_bnd(const BndArgs &a, hipStream_t s);
@@ -112,6 +141,17 @@ hipError_t launch_expand_H(int prec, int64_t Eexp, int64_t E, const int32_t *eor
                            const double *H0, const double *kscale, void *H, hipStream_t s);
 hipError_t launch_step(const StepArgs &a, hipStream_t s);
 hipError_t step_set_lds_limit(int prec, int ne, int tdk, int tdc, int bytes);
+hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s);
+hipError_t adjoint_set_lds_limit(int prec, int ne, int bytes);
+// g_h[f] = -|f|/n_f * sum over the face's nodes of (S1 - Ta_f S0)
+hipError_t launch_face_grad(int64_t nf, int nfn, const int32_t *faces, const int32_t *perm,
+                            const int32_t *rec_of, const double *farea, const double *fTa,
+                            const double *S0, const double *S1, double *g_h, hipStream_t s);
+// 1 / dt per internal node and rho V / n_e per caller element
+hipError_t launch_adjoint_coefs(int prec, int64_t N, int64_t E, int ne, const double *dt_inst,
+                                const int32_t *node_inst, const MatDev *mats,
+                                const int32_t *emat, const double *V, void *rdt, void *mV,
+                                hipStream_t s);
 
 // caller-order FP64 temperatures <-> internal working arrays
 hipError_t launch_set_T(int prec, int64_t N, const double *Tuser, const int32_t *perm,

@@ -225,8 +225,9 @@ __global__ void k_mass(MassArgs a) {
     int32_t e = a.inc_elem[p];
     const MatDev &mt = a.mats[a.emat ? a.emat[e] : 0];
     double v = mt.rho * a.V[e] / a.ne;
-    double clo = mt.c0 + mt.c1 * a.T_lo, chi = mt.c0 + mt.c1 * a.T_hi;
-    m0 += v * mt.c0;
+    const double c0 = a.ec0 ? a.ec0[e] : mt.c0;
+    double clo = c0 + mt.c1 * a.T_lo, chi = c0 + mt.c1 * a.T_hi;
+    m0 += v * c0;
     m1 += v * mt.c1;
     cm += v * (clo < chi ? clo : chi);
   }
@@ -318,7 +319,8 @@ __global__ void k_dt_elem(DtArgs a) {
   if (e < a.E) {
     const MatDev &mt = a.mats[a.emat ? a.emat[e] : 0];
     double slo = mt.s0 + mt.s1 * a.T_lo, shi = mt.s0 + mt.s1 * a.T_hi;
-    double clo = mt.c0 + mt.c1 * a.T_lo, chi = mt.c0 + mt.c1 * a.T_hi;
+    const double c0 = a.ec0 ? a.ec0[e] : mt.c0;
+    double clo = c0 + mt.c1 * a.T_lo, chi = c0 + mt.c1 * a.T_hi;
     double smax_ = slo > shi ? slo : shi, cmin = clo < chi ? clo : chi;
     double ks = a.kscale ? a.kscale[e] : 1.0;
     lam = a.ne * ks * smax_ * a.lamgeo[e] / (mt.rho * cmin);
@@ -900,6 +902,155 @@ hipError_t attr_dispatch_tt(int tdk, int tdc, int bytes) {
   return tdc ? step_attr<R, NE, MODE, false, true>(bytes) : step_attr<R, NE, MODE, false, false>(bytes);
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint step.  The forward step of a T-independent problem is
+//   T^{n+1} = T^n + (Q(T^n) - K T^n) / alpha,  Q = hAT_a - hA T + P,
+// alpha = C / dt (= +inf on Dirichlet nodes).  With mu = lambda^{n+1} / alpha
+// its transpose is lambda^n = lambda^{n+1} - K mu - hA mu (K symmetric), and
+// the parameter derivatives accumulated over the steps are
+//   d/d log k_e : -mu_e . K_e T^n_e        (K_e proportional to k_e)
+//   d/d c_e     : -(rho V_e / n_e) sum_a mu_a (T^{n+1}_a - T^n_a) / dt_a
+//   d/d h_f     : -|f|/n_f sum_{k in f} mu_k (T^n_k - Ta_f)  (via S0, S1)
+// The tile structure, the slot order of the nodal sums and the compensated
+// pair are those of the forward step.
+template <typename R, int NE>
+struct ElemAdj;
+
+template <typename R>
+struct ElemAdj<R, 8> {
+  __device__ static void u(const R *V, const uint32_t *loc, R &ux, R &uy, R &uz) {
+    R T0 = V[loc[0]], T1 = V[loc[1]], T2 = V[loc[2]], T3 = V[loc[3]];
+    R T4 = V[loc[4]], T5 = V[loc[5]], T6 = V[loc[6]], T7 = V[loc[7]];
+    ux = ((T1 - T0) + (T2 - T3)) + ((T5 - T4) + (T6 - T7));
+    uy = ((T3 - T0) + (T2 - T1)) + ((T7 - T4) + (T6 - T5));
+    uz = ((T4 - T0) + (T5 - T1)) + ((T6 - T2) + (T7 - T3));
+  }
+};
+
+template <typename R>
+struct ElemAdj<R, 4> {
+  __device__ static void u(const R *V, const uint32_t *loc, R &ux, R &uy, R &uz) {
+    R T0 = V[loc[0]];
+    ux = V[loc[1]] - T0;
+    uy = V[loc[2]] - T0;
+    uz = V[loc[3]] - T0;
+  }
+};
+
+template <typename R, int NE, int MODE>
+__global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const int t = (b & 7) * a.nper + (b >> 3);
+  if (t >= a.nt) return;
+  const TileHdr th = a.tiles[t];
+  const int nE = a.tiles[t].cum_e[0];
+  const int nhalo = a.tiles[t].cum_n[1] - th.nown;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int nown = th.nown, ntouch = nown + nhalo;
+  // LDS: mu, T^n and (T^{n+1} - T^n) / dt of touched nodes, slots of owned nodes
+  R *Lmu = reinterpret_cast<R *>(smem_raw);
+  R *LT = Lmu + ntouch;
+  R *Ld = LT + ntouch;
+  R *slot = Ld + ntouch;
+  const R *lam = (const R *)a.lamin, *alpha = (const R *)a.alpha, *rdt = (const R *)a.rdt;
+  const R *Tn = (const R *)a.Tn, *Tn1 = (const R *)a.Tn1;
+  for (int j = tid; j < ntouch; j += bs) {
+    const int g = j < nown ? th.nstart + j : a.halo[th.hstart + j - nown];
+    const R al = alpha[g];
+    Lmu[j] = lam[g] / al;  // 0 on Dirichlet nodes (alpha = +inf)
+    const R tn = Tn[g];
+    LT[j] = tn;
+    Ld[j] = (Tn1[g] - tn) * rdt[g];
+  }
+  const int nslot = a.maxinc * nown;
+  for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
+  __syncthreads();
+  using EntT = typename Ent<NE>::T;
+  const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
+  const R *Hb = (const R *)a.H;
+  const R *mV = (const R *)a.mV;
+  const R s0 = (R)a.s0;
+  const uint32_t pmask = (1u << a.pb) - 1u;
+  for (int i = tid; i < nE; i += bs) {
+    const int64_t e = (int64_t)th.estart + i;
+    R h[6];
+#pragma unroll
+    for (int r = 0; r < 6; r++) h[r] = Hb[(int64_t)r * a.Eexp + e];
+    const EntT w = ent[e];
+    // K_e mu_e into the owned nodes' slots (the forward element load with mu)
+    element_to_slots<R, NE, false>(w, h, Lmu, slot, nown, nown, a.pb, pmask, s0, (R)0);
+    if (a.eowner[e]) {
+      uint32_t v[NE], loc[NE];
+      Ent<NE>::unpack(w, v);
+#pragma unroll
+      for (int n = 0; n < NE; n++) loc[n] = v[n] >> a.pb;
+      R mx, my, mz, tx, ty, tz;
+      ElemAdj<R, NE>::u(Lmu, loc, mx, my, mz);
+      ElemAdj<R, NE>::u(LT, loc, tx, ty, tz);
+      // mu_e . K_e T_e = s0 (S mu)^T Hhat (S T)
+      const R qx = h[0] * tx + h[3] * ty + h[5] * tz;
+      const R qy = h[3] * tx + h[1] * ty + h[4] * tz;
+      const R qz = h[5] * tx + h[4] * ty + h[2] * tz;
+      const R gk = -s0 * (mx * qx + my * qy + mz * qz);
+      R gc = 0;
+#pragma unroll
+      for (int n = 0; n < NE; n++) gc += Lmu[loc[n]] * Ld[loc[n]];
+      const int32_t eo = a.eorig[e];
+      a.g_logk[eo] += (double)gk;
+      a.g_c[eo] += -(double)mV[eo] * (double)gc;
+    }
+  }
+  __syncthreads();
+  const R *rA = (const R *)a.rA;
+  R *lout = (R *)a.lamout;
+  for (int j = tid; j < nown; j += bs) {
+    const int k = th.nstart + j;
+    R F = slot[j];
+    for (int p = 1; p < a.maxinc; p++) F += slot[p * nown + j];
+    const R mu = Lmu[j];
+    R d = -F;
+    if (j < th.nbnd) {
+      const int r = th.bstart + j;
+      d -= rA[r] * mu;
+      a.S0[r] += (double)mu;
+      a.S1[r] += (double)mu * (double)LT[j];
+    }
+    const bool fixed = alpha[k] == (R)INFINITY;
+    if (MODE == 1) {
+      const float hi = (float)lam[k], lo = a.lamloin[k];
+      const float yv = (float)d + lo;
+      const float tv = hi + yv;
+      lout[k] = fixed ? (R)0 : (R)tv;
+      a.lamloout[k] = fixed ? 0.0f : yv - (tv - hi);
+    } else {
+      lout[k] = fixed ? (R)0 : lam[k] + d;
+    }
+  }
+}
+
+__global__ void k_face_grad(int64_t nf, int nfn, const int32_t *faces, const int32_t *perm,
+                            const int32_t *rec_of, const double *farea, const double *fTa,
+                            const double *S0, const double *S1, double *g_h) {
+  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  double ta = fTa ? fTa[f] : 0.0, acc = 0;
+  for (int b = 0; b < nfn; b++) {
+    int r = rec_of[perm[faces[f * nfn + b]]];
+    acc += S1[r] - ta * S0[r];
+  }
+  g_h[f] = -farea[f] / nfn * acc;
+}
+
+template <typename R>
+__global__ void k_adjoint_coefs(int64_t N, int64_t E, int ne, const double *dt_inst,
+                                const int32_t *node_inst, const MatDev *mats, const int32_t *emat,
+                                const double *V, R *rdt, R *mV) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) rdt[i] = (R)(1.0 / dt_inst[node_inst ? node_inst[i] : 0]);
+  if (i < E) mV[i] = (R)(mats[emat ? emat[i] : 0].rho * V[i] / ne);
+}
+
 // caller order <-> internal order, FP64 in the caller's arrays
 template <typename R, int MODE>
 __global__ void k_set_T(int64_t N, const double *Tuser, const int32_t *perm, R *T, float *lo) {
@@ -1063,6 +1214,56 @@ hipError_t launch_permute(int elem_bytes, int64_t N, const int32_t *perm, const 
                           void *dst, int to_internal, hipStream_t s) {
   hipLaunchKernelGGL(k_permute, dim3(blocks_for(N, 256)), dim3(256), 0, s, elem_bytes, N, perm,
                      (const unsigned char *)src, (unsigned char *)dst, to_internal);
+  return hipGetLastError();
+}
+
+}  // namespace fed
+
+namespace fed {
+
+hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s) {
+  dim3 g(8 * a.nper), b(a.block);
+  if (a.prec == 1) {
+    if (a.ne == 8) hipLaunchKernelGGL((k_adjoint1<double, 8, 0>), g, b, a.lds, s, a);
+    else hipLaunchKernelGGL((k_adjoint1<double, 4, 0>), g, b, a.lds, s, a);
+  } else if (a.prec == 0) {
+    if (a.ne == 8) hipLaunchKernelGGL((k_adjoint1<float, 8, 1>), g, b, a.lds, s, a);
+    else hipLaunchKernelGGL((k_adjoint1<float, 4, 1>), g, b, a.lds, s, a);
+  } else {
+    if (a.ne == 8) hipLaunchKernelGGL((k_adjoint1<float, 8, 0>), g, b, a.lds, s, a);
+    else hipLaunchKernelGGL((k_adjoint1<float, 4, 0>), g, b, a.lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t adjoint_set_lds_limit(int prec, int ne, int bytes) {
+  const void *f;
+  if (prec == 1) f = ne == 8 ? (const void *)k_adjoint1<double, 8, 0> : (const void *)k_adjoint1<double, 4, 0>;
+  else if (prec == 0) f = ne == 8 ? (const void *)k_adjoint1<float, 8, 1> : (const void *)k_adjoint1<float, 4, 1>;
+  else f = ne == 8 ? (const void *)k_adjoint1<float, 8, 0> : (const void *)k_adjoint1<float, 4, 0>;
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_face_grad(int64_t nf, int nfn, const int32_t *faces, const int32_t *perm,
+                            const int32_t *rec_of, const double *farea, const double *fTa,
+                            const double *S0, const double *S1, double *g_h, hipStream_t s) {
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_grad, dim3(blocks_for(nf, 256)), dim3(256), 0, s, nf, nfn, faces,
+                     perm, rec_of, farea, fTa, S0, S1, g_h);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_coefs(int prec, int64_t N, int64_t E, int ne, const double *dt_inst,
+                                const int32_t *node_inst, const MatDev *mats,
+                                const int32_t *emat, const double *V, void *rdt, void *mV,
+                                hipStream_t s) {
+  int64_t n = N > E ? N : E;
+  if (prec == 1)
+    hipLaunchKernelGGL(k_adjoint_coefs<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, N, E,
+                       ne, dt_inst, node_inst, mats, emat, V, (double *)rdt, (double *)mV);
+  else
+    hipLaunchKernelGGL(k_adjoint_coefs<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, N, E,
+                       ne, dt_inst, node_inst, mats, emat, V, (float *)rdt, (float *)mV);
   return hipGetLastError();
 }
 

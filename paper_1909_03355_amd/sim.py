@@ -154,6 +154,59 @@ class Simulation:
         L.check(L.lib().fed_set_state(self._c(), hi.ctypes.data_as(C.c_void_p),
                                       lo.ctypes.data_as(C.c_void_p), int(step), self.stream))
 
+    # ---- adjoint -------------------------------------------------------
+    def checkpoint_every(self, every):
+        """Keep the state every `every` steps for the adjoint (before
+        set_temperature; 0 turns it off)."""
+        L.check(L.lib().fed_checkpoint_every(self._c(), int(every)))
+
+    @staticmethod
+    def _arg(a):
+        """(pointer, on_device, keep-alive) for an FP64 array or CUDA tensor."""
+        if a is None:
+            return None, None, None
+        if hasattr(a, "is_cuda") and a.is_cuda:
+            import torch
+            t = a.detach().to(torch.float64).contiguous()
+            return C.c_void_p(t.data_ptr()), 1, t
+        h = np.ascontiguousarray(a, dtype=np.float64)
+        return h.ctypes.data_as(C.c_void_p), 0, h
+
+    def set_params(self, kscale=None, elem_c=None, face_h=None):
+        """Replace per-element conductivity factors, per-element heat capacities
+        and per-face convection coefficients; re-derives the precomputed arrays."""
+        args = [self._arg(a) for a in (kscale, elem_c, face_h)]
+        dev = {d for _, d, _ in args if d is not None}
+        if len(dev) > 1:
+            raise ValueError("pass all parameters on the host or all on the device")
+        on_dev = dev.pop() if dev else 0
+        L.check(L.lib().fed_set_params(self._c(), args[0][0], args[1][0], args[2][0], on_dev,
+                                       self.stream))
+
+    def backward(self, dL_dT):
+        """Discrete adjoint of the steps taken: returns dict(logk, c, h, T0) of
+        dL/dlog k_e, dL/dc_e, dL/dh_f and dL/dT0 (numpy, or CUDA tensors when
+        dL_dT is a CUDA tensor)."""
+        nf = 0 if self.prob["faces"] is None else self.prob["faces"].shape[0]
+        if hasattr(dL_dT, "is_cuda") and dL_dT.is_cuda:
+            import torch
+            g = dL_dT.detach().to(torch.float64).contiguous()
+            out = {k: torch.zeros(n, dtype=torch.float64, device=g.device)
+                   for k, n in (("logk", self.E), ("c", self.E), ("h", max(nf, 1)), ("T0", self.N))}
+            ptr = lambda t: C.c_void_p(t.data_ptr())
+            L.check(L.lib().fed_backward(self._c(), ptr(g), ptr(out["logk"]), ptr(out["c"]),
+                                         ptr(out["h"]) if nf else None, ptr(out["T0"]), 1,
+                                         self.stream))
+            out["h"] = out["h"][:nf]
+            return out
+        g = np.ascontiguousarray(dL_dT, dtype=np.float64)
+        out = {"logk": np.zeros(self.E), "c": np.zeros(self.E), "h": np.zeros(nf),
+               "T0": np.zeros(self.N)}
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+        L.check(L.lib().fed_backward(self._c(), ptr(g), ptr(out["logk"]), ptr(out["c"]),
+                                     ptr(out["h"]) if nf else None, ptr(out["T0"]), 0, self.stream))
+        return out
+
     def close(self):
         if getattr(self, "_ctx", None) is not None:
             L.lib().fed_destroy(self._ctx)

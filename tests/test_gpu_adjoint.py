@@ -1,0 +1,217 @@
+"""GPU adjoint (fed_backward) against the FP64 oracle adjoint, central finite
+differences of the forward, and the torch.autograd front end.
+
+Gradient norm: max_e |g - g_ref| / max_e |g_ref|.  Tolerances: FP64 1e-10,
+compensated FP32 1e-4 (FP32 forward and adjoint, FP64 accumulators)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from workloads import mesh as M, problems as P
+
+pytestmark = pytest.mark.gpu
+
+GTOL = {"fp64": 1e-10, "fp32c": 1e-4}
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _problem_dirichlet(n=5):
+    """Hexahedral box: per-element log-normal k, convection on five sides,
+    Dirichlet on the sixth, random T0, fixed dt."""
+    m = M.box_hex(n, n, n, 0.1, 0.1, 0.1)
+    p = P._base(m, "adj_dir")
+    p["materials"] = [P.material(1000.0, 1000.0, [1.0])]
+    g = np.random.default_rng(21)
+    p["elem_kscale"] = np.exp(0.5 * g.standard_normal(n ** 3))
+    faces, sides = M.box_side_faces(m)
+    P.set_faces(p, faces[sides != 0], h=g.uniform(5, 30, int((sides != 0).sum())), Ta=20.0)
+    left = np.nonzero(np.isclose(m["x"], 0.0))[0].astype(np.int32)
+    p["dir_nodes"], p["dir_T"] = left, np.full(left.size, 50.0)
+    p["T0"] = g.uniform(80, 100, m["x"].size)
+    p["dt"] = 2.0
+    return p
+
+
+def _loss_grad(T, sens, target):
+    lam = np.zeros(T.size)
+    lam[sens] = 2.0 * (T[sens] - target) / sens.size
+    return float(np.mean((T[sens] - target) ** 2)), lam
+
+
+def _gpu_adjoint(p, prec, nsteps, ckpt, lam_fn, **kw):
+    from paper_1909_03355_amd import Simulation
+    with Simulation(p, prec=prec, **kw) as s:
+        s.checkpoint_every(ckpt)
+        s.set_temperature()
+        s.step(nsteps)
+        T = s.temperature()
+        L, lam = lam_fn(T)
+        g = s.backward(lam)
+        # the forward state is untouched by the adjoint
+        assert np.array_equal(s.temperature(), T)
+    return T, L, g
+
+
+@pytest.mark.parametrize("case", ["dirichlet", "grf"])
+def test_adjoint_matches_oracle(case):
+    if case == "dirichlet":
+        p, nsteps, ckpt = _problem_dirichlet(), 37, 10
+    else:
+        p = P.adjoint_hex(6, 50, n_sensors=20, dt=4.0)
+        nsteps, ckpt = 50, 16
+    sens = np.random.default_rng(3).choice(p["x"].size, 20, replace=False)
+    target = np.full(sens.size, 60.0)
+    o = Oracle(p)
+    hist = o.run(nsteps, history=True)
+    _, lam = _loss_grad(hist[-1], sens, target)
+    ref = o.adjoint_linear(hist, lam)
+    for prec in ("fp64", "fp32c"):
+        T, _, g = _gpu_adjoint(p, prec, nsteps, ckpt, lambda T: _loss_grad(T, sens, target))
+        errs = {"logk": rel(g["logk"], ref["g_logk"]), "c": rel(g["c"], ref["g_c"]),
+                "h": rel(g["h"], ref["g_h"]), "T0": rel(g["T0"], ref["lam0"])}
+        print(case, prec, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        for k, v in errs.items():
+            assert v <= GTOL[prec], (prec, k, v)
+
+
+def test_adjoint_checkpoint_interval_and_fusion_do_not_matter():
+    p = _problem_dirichlet(4)
+    sens = np.arange(0, p["x"].size, 7)
+    fn = lambda T: _loss_grad(T, sens, np.full(sens.size, 70.0))
+    _, _, a = _gpu_adjoint(p, "fp32c", 23, 5, fn)
+    _, _, b = _gpu_adjoint(p, "fp32c", 23, 23, fn)
+    _, _, c = _gpu_adjoint(p, "fp32c", 23, 7, fn, fuse_steps=2)
+    for k in a:
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+
+
+def test_set_params_matches_oracle():
+    from paper_1909_03355_amd import Simulation
+    p = _problem_dirichlet(4)
+    g = np.random.default_rng(8)
+    ks = np.exp(0.3 * g.standard_normal(p["conn"].shape[1]))
+    ec = g.uniform(800, 1200, p["conn"].shape[1])
+    fh = g.uniform(1, 20, p["faces"].shape[0])
+    mats = [P.material(1000.0, c, [1.0]) for c in ec]
+    q = dict(p, elem_kscale=ks, face_h=fh, materials=mats,
+             elem_material=np.arange(ec.size, dtype=np.int32))
+    ref = Oracle(q).run(30)
+    with Simulation(p, prec="fp64") as s:
+        s.set_params(kscale=ks, elem_c=ec, face_h=fh)
+        s.set_temperature()
+        s.step(30)
+        assert rel(s.temperature(), ref) < 1e-12
+
+
+def test_adjoint_against_finite_differences():
+    """Central differences (eps = 1e-3 on log k, relative 1e-4 on c and h) of
+    the GPU FP64 forward loss against the GPU adjoint."""
+    from paper_1909_03355_amd import Simulation
+    p = P.adjoint_hex(6, 40, n_sensors=16, dt=4.0)
+    sens = p["meta"]["sensors"]
+    target = np.full(sens.size, 95.0)
+    _, _, g = _gpu_adjoint(p, "fp64", 40, 10, lambda T: _loss_grad(T, sens, target))
+    theta = np.log(p["elem_kscale"])
+    with Simulation(p, prec="fp64") as s:
+        def loss(ks=None, ec=None, fh=None):
+            s.set_params(kscale=ks, elem_c=ec, face_h=fh)
+            s.set_temperature()
+            s.step(40)
+            return _loss_grad(s.temperature(), sens, target)[0]
+        for e in np.argsort(-np.abs(g["logk"]))[:4]:
+            th = theta.copy()
+            th[e] += 1e-3
+            lp = loss(ks=np.exp(th))
+            th[e] -= 2e-3
+            lm = loss(ks=np.exp(th))
+            fd = (lp - lm) / 2e-3
+            assert abs(fd - g["logk"][e]) <= 1e-5 * abs(fd), (e, fd, g["logk"][e])
+        s.set_params(kscale=p["elem_kscale"])
+        c0 = np.full(p["conn"].shape[1], 1000.0)
+        e = int(np.argmax(np.abs(g["c"])))
+        cp, cm = c0.copy(), c0.copy()
+        cp[e] *= 1 + 1e-4
+        cm[e] *= 1 - 1e-4
+        fd = (loss(ec=cp) - loss(ec=cm)) / (2e-4 * 1000.0)
+        assert abs(fd - g["c"][e]) <= 1e-5 * abs(fd)
+        h0 = p["face_h"].copy()
+        f = int(np.argmax(np.abs(g["h"])))
+        hp, hm = h0.copy(), h0.copy()
+        hp[f] *= 1 + 1e-4
+        hm[f] *= 1 - 1e-4
+        fd = (loss(ec=c0, fh=hp) - loss(ec=c0, fh=hm)) / (2e-4 * h0[f])
+        assert abs(fd - g["h"][f]) <= 1e-5 * abs(fd)
+
+
+def test_autograd_function():
+    import torch
+    from paper_1909_03355_amd import Simulation
+    from paper_1909_03355_amd.autograd import run
+    p = P.adjoint_hex(5, 30, n_sensors=12, dt=4.0)
+    sens = torch.as_tensor(p["meta"]["sensors"], device="cuda", dtype=torch.long)
+    with Simulation(p, prec="fp64") as s:
+        s.checkpoint_every(8)
+        log_k = torch.tensor(np.log(p["elem_kscale"]), device="cuda", requires_grad=True)
+        T0 = torch.tensor(p["T0"], device="cuda", requires_grad=True)
+        T = run(s, 30, T0, log_k=log_k)
+        loss = ((T[sens] - 90.0) ** 2).mean()
+        loss.backward()
+    o = Oracle(p)
+    hist = o.run(30, history=True)
+    lam = np.zeros(o.N)
+    sn = p["meta"]["sensors"]
+    lam[sn] = 2.0 * (hist[-1][sn] - 90.0) / sn.size
+    ref = o.adjoint_linear(hist, lam)
+    assert rel(log_k.grad.cpu().numpy(), ref["g_logk"]) < 1e-10
+    assert rel(T0.grad.cpu().numpy(), ref["lam0"]) < 1e-10
+
+
+def test_adjoint_workload_full_size():
+    """The 48^3 workload, 2000 steps, checkpoints every 100: FP32C gradients
+    against the FP64 oracle adjoint, and against central differences
+    (eps = 1e-3) of the FP64 GPU forward on 32 seeded elements."""
+    from paper_1909_03355_amd import Simulation
+    p = P.adjoint_hex(48, 2000)
+    nsteps, ck = p["nsteps"], p["meta"]["ckpt_every"]
+    sens = p["meta"]["sensors"]
+    # target temperatures from a run with the second field
+    with Simulation(dict(p, elem_kscale=np.exp(p["meta"]["theta_target"])), prec="fp64") as s:
+        s.set_temperature()
+        s.step(nsteps)
+        target = s.temperature()[sens]
+    fn = lambda T: _loss_grad(T, sens, target)
+    T32, L32, g32 = _gpu_adjoint(p, "fp32c", nsteps, ck, fn)
+    o = Oracle(p)
+    hist = o.run(nsteps, history=True)
+    L, lam = _loss_grad(hist[-1], sens, target)
+    ref = o.adjoint_linear(hist, lam)
+    del hist
+    err = rel(g32["logk"], ref["g_logk"])
+    print(f"48^3 fp32c g_logk err {err:.2e}, loss {L32:.6e} vs {L:.6e}", flush=True)
+    assert err <= 1e-4
+    theta = np.log(p["elem_kscale"])
+    picks = np.random.default_rng(1909_0032).choice(theta.size, 32, replace=False)
+    with Simulation(p, prec="fp64") as s:
+        def loss(th):
+            s.set_params(kscale=np.exp(th))
+            s.set_temperature()
+            s.step(nsteps)
+            return fn(s.temperature())[0]
+        worst = 0.0
+        scale = np.max(np.abs(ref["g_logk"]))
+        for e in picks:
+            th = theta.copy()
+            th[e] += 1e-3
+            lp = loss(th)
+            th[e] -= 2e-3
+            lm = loss(th)
+            fd = (lp - lm) / 2e-3
+            worst = max(worst, abs(fd - g32["logk"][e]) / scale)
+    print(f"48^3 FD vs fp32c adjoint on 32 elements: {worst:.2e}", flush=True)
+    assert worst <= 1e-4
