@@ -1,11 +1,13 @@
 """Benchmark of the FED-FEM time step on one MI355X.
 
-Workload: the nonlinear hexahedral case - 0.1 m cube, 64^3 8-node hexahedra
-(262,144 elements, 274,625 nodes), orthotropic D(T) = diag(1,2,0.5)(1+0.005T),
-c(T) = 1000 + 2T, convection on all faces, radiation on the top face and a
-flux patch on the bottom, seeded random T0 - in compensated FP32, with the
-same steps in FP64 timed for the speed ratio.  A step is one pass of the
-whole hot path (element loads, nodal sums, surface loads, explicit update).
+Default workload (the one the metric is quoted on): the nonlinear hexahedral
+case - 0.1 m cube, 64^3 8-node hexahedra (262,144 elements, 274,625 nodes),
+orthotropic D(T) = diag(1,2,0.5)(1+0.005T), c(T) = 1000 + 2T, convection on
+all faces, radiation on the top face and a flux patch on the bottom, seeded
+random T0 - in compensated FP32, with the same steps in FP64 timed for the
+speed ratio.  A step is one pass of the whole hot path (element loads, nodal
+sums, surface loads, explicit update).  Other workloads (--workload):
+aniso_tet128, batched_hex256, adjoint_hex48 (forward + adjoint).
 
 Prints one JSON line.  `value` is element-updates/s (elements x steps / s)
 with all inputs resident on the GPU when the timed region starts.
@@ -24,26 +26,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
+KERNEL_SRC = os.path.join(ROOT, "paper_1909_03355_amd", "csrc", "fed_kernels.hip")
+# Memory traffic per launch of the dominant kernel in the default launch shape,
+# from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), each scaled by what the counter reads for a copy kernel of known
+# size (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel source
+# with this SHA-1; any other source reports null.
+TRAFFIC = {"nonlinear_hex64": ("d47297f4a511c5e332595bdf3e2afea505b106a2", 23692184.0)}
+METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
+
+WORKLOADS = {
+    # name: (builder, default steps, oracle sample steps, description)
+    "nonlinear_hex64": ("cube_nonlinear_hex", 10000, 200,
+                        "0.1 m cube, 64^3 hex8, orthotropic D(T), c(T), convection+radiation+flux"),
+    "aniso_tet128": ("cube_aniso_tet", 2000, 4,
+                     "0.1 m cube, 128^3 x 6 Kuhn tet4, per-element SPD conductivity, c(T), "
+                     "convection"),
+    "batched_hex256": ("batched_hex", 5000, 10,
+                       "256 hex8 boxes with 8..48 cells per axis, per-instance k, c, h, eps, T0, dt"),
+    "adjoint_hex48": ("adjoint_hex", 2000, 100,
+                      "48^3 hex8, log-normal k field, convection; forward + adjoint with "
+                      "checkpoints every 100 steps"),
+}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--workload", default="nonlinear_hex64", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (0 = the workload's)")
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--n", type=int, default=64, help="cells per cube edge")
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--tile-nodes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--fuse", type=int, default=0, help="steps per kernel launch (0 = default)")
-    ap.add_argument("--oracle-steps", type=int, default=200,
+    ap.add_argument("--autotune", action="store_true", help="pick the launch shape by timing")
+    ap.add_argument("--oracle-steps", type=int, default=0,
                     help="steps of the CPU oracle sample (timed baseline and error reference)")
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     return ap.parse_args()
 
 
-def timed_run(sim, steps, warmup, graph_steps):
+def timed_steps(sim, steps, warmup, graph_steps):
     import torch
     sim.set_temperature()
     sim.step(warmup, graph_steps=graph_steps)
@@ -56,6 +81,24 @@ def timed_run(sim, steps, warmup, graph_steps):
     return start.elapsed_time(stop) / 1e3
 
 
+def timed_adjoint(sim, steps, prob):
+    """Forward with checkpoints plus the adjoint of an MSE sensor loss."""
+    import torch
+    sens = prob["meta"]["sensors"]
+    sim.checkpoint_every(prob["meta"]["ckpt_every"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.set_temperature()
+    sim.step(steps)
+    T = sim.temperature()
+    t1 = time.perf_counter()
+    lam = np.zeros(T.size)
+    lam[sens] = 2.0 * (T[sens] - 60.0) / sens.size
+    sim.backward(lam)
+    t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -64,90 +107,105 @@ def main():
         sys.exit(2)
     import torch
     from paper_1909_03355_amd import Simulation
+    from paper_1909_03355_amd.autotune import autotune, launch_kwargs
     from workloads import problems as P
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    prob = P.cube_nonlinear_hex(args.n, args.steps)
+    builder, dsteps, osteps, desc = WORKLOADS[args.workload]
+    steps = args.steps or dsteps
+    osteps = args.oracle_steps or osteps
+    prob = getattr(P, builder)(nsteps=steps)
     E, N = prob["conn"].shape[1], prob["x"].size
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+
+    kw = dict(tile_nodes=args.tile_nodes, block_threads=args.block, fuse_steps=args.fuse)
+    tuned = None
+    if args.autotune:
+        tuned = autotune(prob, "fp32c", steps=200, log=log)
+        kw = launch_kwargs(tuned)
+        log(f"autotuned: {tuned}")
 
     res = {}
-    for prec in (["fp32c"] if args.no_fp64 else ["fp32c", "fp64"]):
-        sim = Simulation(prob, prec=prec, tile_nodes=args.tile_nodes, block_threads=args.block,
-                         fuse_steps=args.fuse)
-        t = timed_run(sim, args.steps, args.warmup, args.graph_steps)
-        res[prec] = dict(t=t, info=sim.info, dt=float(sim.dt[0]))
+    precs = ["fp32c"] if args.no_fp64 else ["fp32c", "fp64"]
+    for prec in precs:
+        sim = Simulation(prob, prec=prec, **kw)
+        if args.workload == "adjoint_hex48":
+            tf, tb = timed_adjoint(sim, steps, prob)
+            t = tf + tb
+            log(f"{prec}: forward {tf * 1e3:.1f} ms + adjoint {tb * 1e3:.1f} ms for {steps} steps")
+        else:
+            t = timed_steps(sim, steps, args.warmup, args.graph_steps)
+            log(f"{prec}: {steps} steps in {t * 1e3:.2f} ms ({t / steps * 1e6:.2f} us/step)")
+        res[prec] = dict(t=t, info=sim.info)
         sim.close()
-        print(f"[bench] {prec}: {args.steps} steps in {t * 1e3:.2f} ms "
-              f"({t / args.steps * 1e6:.2f} us/step)", file=sys.stderr, flush=True)
 
-    # accuracy against the FP64 oracle on a bounded sample, which is also the
-    # timed CPU baseline
-    cpu = None
-    errs = {}
+    cpu, errs = None, {}
     if not args.no_oracle:
         import oracle
-        o = oracle.Oracle(prob)
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        o = oracle.Oracle(prob)
         t0 = time.perf_counter()
-        ref = o.run(args.oracle_steps)
+        ref = o.run(osteps)
         tc = time.perf_counter() - t0
-        cpu = dict(value=E * args.oracle_steps / tc, unit="element-updates/s", cores=threads,
-                   kind="oracle",
-                   sample=f"{args.oracle_steps} steps of the same {args.n}^3 workload, FP64 C "
-                          f"oracle, OpenMP element loop, {tc:.2f} s")
+        cpu = dict(value=E * osteps / tc, unit="element-updates/s", cores=threads, kind="oracle",
+                   sample=f"{osteps} steps of the same workload ({args.workload}), FP64 C "
+                          f"oracle with an OpenMP element loop, {tc:.2f} s")
         for prec in res:
-            sim = Simulation(prob, prec=prec)
-            sim.set_temperature()
-            sim.step(args.oracle_steps)
-            errs[prec] = oracle.err_max(sim.temperature(), ref)
-            sim.close()
-        print(f"[bench] oracle {args.oracle_steps} steps {tc:.2f} s; err_max {errs}",
-              file=sys.stderr, flush=True)
+            with Simulation(prob, prec=prec, **kw) as sim:
+                sim.set_temperature()
+                sim.step(osteps)
+                errs[prec] = oracle.err_max(sim.temperature(), ref)
+        log(f"oracle {osteps} steps {tc:.2f} s; err_max {errs}")
 
+    import hashlib
+    src_sha = hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
+    default_shape = not (args.tile_nodes or args.block or args.fuse or args.autotune)
+    traffic = None
+    if args.workload in TRAFFIC and default_shape and TRAFFIC[args.workload][0] == src_sha:
+        traffic = TRAFFIC[args.workload][1]
     r32 = res["fp32c"]
     t = r32["t"]
-    ms = t / args.steps * 1e3
     info = r32["info"]
     K = info["fuse_steps"]
-    launches = -(-args.steps // K)
+    launches = -(-steps // K)
     alg = info["algorithmic_bytes_per_launch"]
     achieved = alg / (t / launches) / 1e9
     line = {
-        "metric": "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error",
-        "value": E * args.steps / t,
+        "metric": METRIC,
+        "value": E * steps / t,
         "unit": "element-updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms,
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": t / steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-compensated",
         "data": "synthetic (seeded)",
-        "config": {"workload": f"nonlinear_hex{args.n}: 0.1 m cube, {args.n}^3 hex8 "
-                               f"({E} elements, {N} nodes), orthotropic D(T), c(T), "
-                               "convection+radiation+flux", "elements": E, "nodes": N,
-                   "precision": "fp32c", "graph_steps": args.graph_steps,
-                   "steps_per_launch": K, "tiles": info["n_tiles"],
-                   "block_threads": info["block_threads"]},
+        "config": {"workload": f"{args.workload}: {desc} ({E} elements, {N} nodes)",
+                   "elements": E, "nodes": N, "precision": "fp32c",
+                   "graph_steps": args.graph_steps, "steps_per_launch": K,
+                   "tiles": info["n_tiles"], "block_threads": info["block_threads"],
+                   "autotuned": tuned is not None},
         "hbm_gbs_algorithmic": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "k_step", "us_per_launch": t / launches * 1e6,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "k_step1" if K == 1 else "k_step", "us_per_launch": t / launches * 1e6,
                      "bytes_per_launch_algorithmic": alg,
                      "bytes_per_launch_moved": info["moved_bytes_per_launch"]},
         "cpu_baseline": cpu,
     }
+    if args.workload == "adjoint_hex48":
+        line["roofline"] = None   # forward + adjoint mix, no single dominant kernel rate
+        line["note"] = "value counts forward steps; time includes the adjoint pass"
     if "fp64" in res:
         t64 = res["fp64"]["t"]
         i64 = res["fp64"]["info"]
-        l64 = -(-args.steps // i64["fuse_steps"])
-        line["fp64"] = {"value": E * args.steps / t64, "ms_per_step": t64 / args.steps * 1e3,
-                        "hbm_gbs_algorithmic": i64["algorithmic_bytes_per_launch"]
-                        / (t64 / l64) / 1e9,
-                        "steps_per_launch": i64["fuse_steps"],
+        l64 = -(-steps // i64["fuse_steps"])
+        line["fp64"] = {"value": E * steps / t64, "ms_per_step": t64 / steps * 1e3,
+                        "hbm_gbs_algorithmic": i64["algorithmic_bytes_per_launch"] / (t64 / l64) / 1e9,
                         "speedup_fp32c_over_fp64": t64 / t}
     if errs:
-        line["err_max_vs_oracle"] = {k: v for k, v in errs.items()}
-        line["err_steps"] = args.oracle_steps
+        line["err_max_vs_oracle"] = errs
+        line["err_steps"] = osteps
     print(json.dumps(line), flush=True)
 
 

@@ -347,13 +347,37 @@ __global__ void k_dt_elem(DtArgs a) {
 }
 
 __global__ void k_dt_node(DtArgs a) {
+  // boundary records of an instance are contiguous (tiles never mix instances):
+  // a block-wide max for the block's first instance plus per-thread atomics for
+  // the others keeps contention low
+  __shared__ double smax[1024 / 64];
   int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= a.nrec) return;
-  int32_t k = a.rec_node[r];
-  double d = a.T_hi - a.Tz;
-  double lam = (a.bhA[r] + 4.0 * a.beA[r] * d * d * d) / a.Cmin[k];
-  int inst = a.node_inst ? a.node_inst[k] : 0;
-  if (lam > 0) atomicMax(&a.lamB[inst], (unsigned long long)__double_as_longlong(lam));
+  double lam = 0;
+  int inst = -1;
+  if (r < a.nrec) {
+    int32_t k = a.rec_node[r];
+    double d = a.T_hi - a.Tz;
+    lam = (a.bhA[r] + 4.0 * a.beA[r] * d * d * d) / a.Cmin[k];
+    inst = a.node_inst ? a.node_inst[k] : 0;
+  }
+  const int64_t r0 = blockIdx.x * (int64_t)blockDim.x;
+  const int inst0 = a.node_inst ? a.node_inst[a.rec_node[r0]] : 0;
+  const bool same = inst == inst0;
+  double v = same ? lam : 0.0;
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_down(v, off, 64);
+    v = o > v ? o : v;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) smax[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); i++) m = smax[i] > m ? smax[i] : m;
+    if (m > 0) atomicMax(&a.lamB[inst0], (unsigned long long)__double_as_longlong(m));
+  }
+  if (!same && inst >= 0 && lam > 0)
+    atomicMax(&a.lamB[inst], (unsigned long long)__double_as_longlong(lam));
 }
 
 // Working arrays of the step in precision R: per node alpha = M0 / dt and

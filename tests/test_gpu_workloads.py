@@ -1,0 +1,84 @@
+"""Full-size runs of the large workloads against the oracle (sampled steps),
+batched-versus-solo bitwise equality, and the autotuner."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from workloads import problems as P
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32c": 1e-5}
+
+
+def _run(p, prec, nsteps, **kw):
+    from paper_1909_03355_amd import Simulation
+    with Simulation(p, prec=prec, **kw) as s:
+        s.set_temperature()
+        s.step(nsteps, graph_steps=10)
+        return s.temperature(), s.dt_crit.copy(), s.dt.copy()
+
+
+def _instance(p, i):
+    """Instance i of a batched problem as a problem of its own."""
+    ns, ne = p["meta"]["node_start"], p["meta"]["elem_start"]
+    n0, n1, e0, e1 = ns[i], ns[i + 1], ne[i], ne[i + 1]
+    fmask = np.all((p["faces"] >= n0) & (p["faces"] < n1), axis=1)
+    q = dict(p)
+    q.update(x=p["x"][n0:n1], y=p["y"][n0:n1], z=p["z"][n0:n1],
+             conn=(p["conn"][:, e0:e1] - n0).astype(np.int32),
+             materials=[p["materials"][i]], elem_material=None, node_instance=None,
+             faces=(p["faces"][fmask] - n0).astype(np.int32),
+             face_h=p["face_h"][fmask], face_Ta=p["face_Ta"][fmask],
+             face_eps=p["face_eps"][fmask], face_q=p["face_q"][fmask], T0=p["T0"][n0:n1])
+    return q, n0, n1
+
+
+def test_batched_full_size():
+    p = P.batched_hex(nsteps=20)
+    o = Oracle(p)
+    ref = o.run(20)
+    for prec in ("fp64", "fp32c"):
+        T, dtc, dt = _run(p, prec, 20)
+        np.testing.assert_allclose(dtc, o.dt_crit, rtol=1e-12)
+        np.testing.assert_allclose(dt, o.dt_inst, rtol=1e-12)
+        err = oracle.err_max(T, ref)
+        print(f"batched_hex256 {prec}: err_max {err:.2e}", flush=True)
+        assert err <= TOL[prec]
+        if prec == "fp32c":
+            # every instance alone gives the same bits as inside the batch
+            for i in (0, 77, 255):
+                q, n0, n1 = _instance(p, i)
+                Ti, _, _ = _run(q, prec, 20)
+                assert np.array_equal(Ti, T[n0:n1]), i
+
+
+def test_aniso_tet_full_size():
+    p = P.cube_aniso_tet(nsteps=4)
+    o = Oracle(p)
+    ref = o.run(4)
+    for prec in ("fp64", "fp32c"):
+        T, dtc, _ = _run(p, prec, 4)
+        assert abs(dtc[0] / o.dt_crit - 1) < 1e-12
+        err = oracle.err_max(T, ref)
+        print(f"aniso_tet128 {prec}: err_max {err:.2e}", flush=True)
+        assert err <= TOL[prec]
+
+
+def test_autotuner(tmp_path):
+    from paper_1909_03355_amd.autotune import autotune, launch_kwargs
+    p = P.cube_nonlinear_hex(12, 60)
+    cands = [dict(tile_nodes=64, block_threads=128, fuse_steps=1),
+             dict(tile_nodes=256, block_threads=256, fuse_steps=1),
+             dict(tile_nodes=128, block_threads=256, fuse_steps=2)]
+    cache = str(tmp_path / "tune.json")
+    best = autotune(p, "fp32c", candidates=cands, steps=50, cache=cache)
+    assert not best["from_cache"] and best["us_per_step"] > 0
+    again = autotune(p, "fp32c", candidates=cands, steps=50, cache=cache)
+    assert again["from_cache"] and launch_kwargs(again) == launch_kwargs(best)
+    T1, _, _ = _run(p, "fp32c", 60, **launch_kwargs(best))
+    T2, _, _ = _run(p, "fp32c", 60, **launch_kwargs(cands[0]))
+    assert np.array_equal(T1, T2)

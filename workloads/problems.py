@@ -164,9 +164,9 @@ def batched_hex(n_inst=256, lo=8, hi=48, nsteps=5000, seed=1909_0004):
     for i in range(n_inst):
         nx, ny, nz = (int(v) for v in dims[i])
         meshes.append(M.box_hex(nx, ny, nz, side, side, side))
-    # translate instances apart so that no two share a point in space
-    offsets = [(1.0 * i, 0.0, 0.0) for i in range(n_inst)]
-    big = M.concatenate(meshes, offsets)
+    # instances stay at the origin: consumers keep them apart by node_instance,
+    # and large offsets would cost digits in the element edge vectors
+    big = M.concatenate(meshes)
     for i, mi in enumerate(meshes):
         f, _ = M.box_side_faces(mi)
         faces_all.append(f.astype(np.int64) + big["node_start"][i])
