@@ -1,4 +1,5 @@
-"""Build libfedfem.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libfedfem.so (HIP, gfx950) in-tree with hipcc, and the small
+copy_calibrate program that scales the memory-traffic counters."""
 from __future__ import annotations
 
 import os
@@ -8,6 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfedfem.so")
+CALIB = os.path.join(HERE, "copy_calibrate")
 SOURCES = ["fed_api.cpp", "fed_kernels.hip", "fed_tiling.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -17,9 +19,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wno-unused-result"]
 
 
-def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", LIB + ".tmp"]
+def _hipcc(args, out, verbose):
+    cmd = [HIPCC] + args + ["-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -29,7 +30,14 @@ def build(verbose=False):
         raise RuntimeError(f"hipcc failed ({r.returncode}):\n{err}")
     if verbose and err.strip():
         print(err)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build(verbose=False):
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    _hipcc(FLAGS + srcs, LIB, verbose)
+    exe_flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
+    _hipcc(exe_flags + [os.path.join(CSRC, "copy_calibrate.hip")], CALIB, verbose)
     return LIB
 
 
