@@ -54,8 +54,8 @@ def lib():
         L.orc_loads.argtypes = [P, _d, _d, _d, _d]
         L.orc_surface.argtypes = [P, _d, _d]
         L.orc_run.argtypes = [P, _d, C.c_int64, _d, _d, _d, _d, _d, _d]
-        L.orc_adjoint_linear.argtypes = [P, _d, C.c_int64, _i8, _d, _d, _d, _d,
-                                         _d, _d, _d, _d]
+        L.orc_adjoint.restype = C.c_int
+        L.orc_adjoint.argtypes = [P, _d, C.c_int64, _i8, _d, _d, _d, _d]
         _LIB = L
     return _LIB
 
@@ -251,24 +251,25 @@ class Oracle:
                       _p(w["C"]), _p(w["Q"]), _p(w["Tn"]), _p(hist))
         return hist if history else T
 
-    def adjoint_linear(self, hist, lam_final):
-        """Exact discrete adjoint of ``run`` for T-independent problems.
+    def adjoint(self, hist, lam_final):
+        """Exact discrete adjoint of ``run`` (the transpose of its recursion,
+        including the temperature dependence of D, c and radiation).
 
         Returns dict(g_logk[E], g_c[E], g_h[F], lam0[N]) for a loss whose
-        gradient with respect to the final temperatures is ``lam_final``.
+        gradient with respect to the final temperatures is ``lam_final``:
+        derivatives with respect to the log of the per-element conductivity
+        factors, the per-element heat capacities c0, the per-face convection
+        coefficients and the initial temperatures (0 on Dirichlet nodes).
         """
-        if np.any(self.s1 != 0) or np.any(self.c1 != 0) or np.any(self.feps != 0):
-            raise ValueError("the oracle adjoint covers T-independent problems only")
         nsteps = hist.shape[0] - 1
         hist = np.ascontiguousarray(hist, dtype=np.float64)
         lam = _f64(lam_final).copy()
         g_logk, g_c = np.zeros(self.E), np.zeros(self.E)
         g_h = np.zeros(self.faces.shape[0])
-        w = self._buffers()
-        mu = np.zeros(self.N)
-        lib().orc_adjoint_linear(C.byref(self._s), _p(hist), nsteps, _p(self.is_dir, _i8),
-                                 _p(lam), _p(g_logk), _p(g_c), _p(g_h), _p(w["Fe"]),
-                                 _p(w["F"]), _p(w["C"]), _p(mu))
+        rc = lib().orc_adjoint(C.byref(self._s), _p(hist), nsteps, _p(self.is_dir, _i8),
+                               _p(lam), _p(g_logk), _p(g_c), _p(g_h))
+        if rc != 0:
+            raise MemoryError("oracle adjoint: out of memory")
         return dict(g_logk=g_logk, g_c=g_c, g_h=g_h, lam0=lam)
 
 

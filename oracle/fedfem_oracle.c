@@ -332,58 +332,118 @@ void orc_run(const orc_problem *P, double *T, int64_t nsteps, double *Fe, double
   }
 }
 
-/*
- * Discrete adjoint of orc_run for problems that are linear in T (s1 = 0,
- * c1 = 0, no radiation).  Given hist (T^0..T^nsteps) and lam = dL/dT^nsteps,
- * runs the steps in reverse:
- *   mu      = dt * lam / C            (zero on Dirichlet nodes)
- *   g_logk += -mu_e . K_e T^n_e        (K_e = W B^T D B, d K_e / d log k_e = K_e)
- *   g_c    += -lam_k (T^{n+1}_k - T^n_k) / C_k * rho V_e / ne
- *   g_h    += -mu_k |f| / n_f (T^n_k - Ta_f)
- *   lam    <- lam - (K + H) mu,  then zero on Dirichlet nodes
- * On return lam holds dL/dT^0.  Requires is_dir[N] (1 on Dirichlet nodes).
- */
-void orc_adjoint_linear(const orc_problem *P, const double *hist, int64_t nsteps,
-                        const int8_t *is_dir, double *lam, double *g_logk,
-                        double *g_c, double *g_h, double *Fe, double *F, double *C,
-                        double *mu) {
+/* s K0_e v_e = W B^T (s Dk) B v_e: the element operator at a given factor s
+ * applied to the nodal values v (the adjoint needs it with s taken from T^n
+ * while v is the adjoint field). */
+static void element_apply(const orc_problem *P, int64_t e, const double *v, double s,
+                          double *out) {
   int ne = P->ne;
-  int64_t N = P->N, E = P->E;
+  int64_t E = P->E;
+  double ve[8];
+  for (int a = 0; a < ne; a++) ve[a] = v[P->conn[(int64_t)a * E + e]];
+  const double *Dk = P->Dk;
+  double D[3][3];
+  D[0][0] = Dk[0 * E + e] * s;
+  D[1][1] = Dk[1 * E + e] * s;
+  D[2][2] = Dk[2 * E + e] * s;
+  D[0][1] = D[1][0] = Dk[3 * E + e] * s;
+  D[1][2] = D[2][1] = Dk[4 * E + e] * s;
+  D[0][2] = D[2][0] = Dk[5 * E + e] * s;
+  const double *Be = P->B + e * 3 * ne;
+  double g[3], q[3];
+  for (int i = 0; i < 3; i++) {
+    g[i] = 0;
+    for (int a = 0; a < ne; a++) g[i] += Be[i * ne + a] * ve[a];
+  }
+  for (int i = 0; i < 3; i++) q[i] = D[i][0] * g[0] + D[i][1] * g[1] + D[i][2] * g[2];
+  for (int a = 0; a < ne; a++) {
+    double s2 = 0;
+    for (int i = 0; i < 3; i++) s2 += P->W[e] * Be[i * ne + a] * q[i];
+    out[a] = s2;
+  }
+}
+
+/*
+ * Discrete adjoint of orc_run (not in the paper: the exact transpose of its
+ * explicit recursion).  One step, for a node k that is not Dirichlet, is
+ *   T'_k = T_k + dt_k r_k(T) / C_k(T_k),   r = Q(T) - F(T),
+ * with F_e = s_e K0_e T_e, s_e = s0_e + s1_e Tbar_e (K0_e the element matrix at
+ * s = 1, symmetric), C_k = sum_e m_e (c0_e + c1_e T_k), m_e = rho_e V_e / n_e,
+ * and Q_k = sum_f share_f [-h_f (T_k - Ta_f) - sigma eps_f ((T_k - Tz)^4 -
+ * (Ta_f - Tz)^4) + q_f] + P_k.  Dirichlet nodes are reset to their values, so
+ * their rows of the Jacobian vanish.  With lam = dL/dT', mu_k = dt_k lam_k / C_k
+ * (0 on Dirichlet nodes) and dT = T' - T:
+ *   dL/dT_j = lam_j (1 - dT_j C'_j / C_j)          C'_j = sum_{e owns j} m_e c1_e
+ *           - sum_{e owns j} [ s_e (K0_e mu_e)_j + s1_e / n_e (mu_e . K0_e T_e) ]
+ *           - mu_j sum_{f owns j} share_f (h_f + 4 sigma eps_f (T_j - Tz)^3),
+ * set to 0 on Dirichlet nodes (their values are data, not state), and the
+ * parameter derivatives accumulated over the steps are
+ *   d/d log k_e (k_e scales K0_e):  -mu_e . F_e
+ *   d/d c0_e:                       -m_e sum_{k of e, not Dirichlet} lam_k dT_k / C_k
+ *   d/d h_f:                        -share_f sum_{k of f} mu_k (T_k - Ta_f).
+ * Runs the steps in reverse from hist (T^0..T^nsteps); on return lam holds
+ * dL/dT^0.  is_dir[N] is 1 on Dirichlet nodes.  Returns 0, or -1 if a work
+ * array could not be allocated.
+ */
+int orc_adjoint(const orc_problem *P, const double *hist, int64_t nsteps, const int8_t *is_dir,
+                double *lam, double *g_logk, double *g_c, double *g_h) {
+  const int ne = P->ne;
+  const int64_t N = P->N, E = P->E;
+  double *Fe = malloc(sizeof(double) * E * ne), *F = malloc(sizeof(double) * N);
+  double *C = malloc(sizeof(double) * N), *Cp = calloc(N, sizeof(double));
+  double *mu = malloc(sizeof(double) * N), *out = malloc(sizeof(double) * N);
+  int rc = 0;
+  if (!Fe || !F || !C || !Cp || !mu || !out) {
+    rc = -1;
+    goto done;
+  }
+  for (int64_t e = 0; e < E; e++)
+    for (int a = 0; a < ne; a++)
+      Cp[P->conn[(int64_t)a * E + e]] += P->rho[e] * P->V[e] / ne * P->c1[e];
   for (int64_t n = nsteps - 1; n >= 0; n--) {
     const double *Tn = hist + n * N, *Tn1 = hist + (n + 1) * N;
-    orc_loads(P, Tn, Fe, F, C); /* C at T^n (constant here); Fe unused */
-    for (int64_t k = 0; k < N; k++) mu[k] = is_dir[k] ? 0.0 : P->dt[k] * lam[k] / C[k];
-    /* element terms */
+    orc_loads(P, Tn, Fe, F, C); /* F_e and C at T^n */
+    for (int64_t k = 0; k < N; k++) {
+      mu[k] = is_dir[k] ? 0.0 : P->dt[k] * lam[k] / C[k];
+      out[k] = is_dir[k] ? 0.0 : lam[k] * (1.0 - (Tn1[k] - Tn[k]) * Cp[k] / C[k]);
+    }
     for (int64_t e = 0; e < E; e++) {
-      double KT[8];
-      element_load(P, e, Tn, KT); /* K_e T^n_e */
-      double dot = 0;
+      double Tbar = 0, muF = 0, gc = 0, Kmu[8];
+      int32_t kk[8];
       for (int a = 0; a < ne; a++) {
-        int32_t k = P->conn[(int64_t)a * E + e];
-        dot += mu[k] * KT[a];
-        if (!is_dir[k])
-          g_c[e] += -lam[k] * (Tn1[k] - Tn[k]) / C[k] * P->rho[e] * P->V[e] / ne;
+        kk[a] = P->conn[(int64_t)a * E + e];
+        Tbar += Tn[kk[a]];
       }
-      g_logk[e] += -dot;
+      Tbar /= ne;
+      const double se = P->s0[e] + P->s1[e] * Tbar;
+      element_apply(P, e, mu, se, Kmu); /* s_e K0_e mu_e */
+      for (int a = 0; a < ne; a++) {
+        muF += mu[kk[a]] * Fe[e * ne + a];
+        if (!is_dir[kk[a]]) gc += lam[kk[a]] * (Tn1[kk[a]] - Tn[kk[a]]) / C[kk[a]];
+      }
+      /* mu_e . K0_e T_e = mu_e . F_e / s_e */
+      const double spread = P->s1[e] / ne * (muF / se);
+      for (int a = 0; a < ne; a++) out[kk[a]] -= Kmu[a] + spread;
+      g_logk[e] += -muF;
+      g_c[e] += -P->rho[e] * P->V[e] / ne * gc;
     }
     for (int64_t f = 0; f < P->nf; f++) {
-      double share = P->farea[f] / P->nfn;
+      const double share = P->farea[f] / P->nfn;
       for (int b = 0; b < P->nfn; b++) {
-        int32_t k = P->faces[f * P->nfn + b];
+        const int32_t k = P->faces[f * P->nfn + b];
+        const double d = Tn[k] - P->Tz;
+        out[k] -= mu[k] * share * (P->fh[f] + 4.0 * P->sigma * P->feps[f] * d * d * d);
         g_h[f] += -mu[k] * share * (Tn[k] - P->fTa[f]);
       }
     }
-    /* lam <- lam - K mu - H mu (K symmetric) */
-    orc_loads(P, mu, Fe, F, C); /* F = K mu; C discarded */
-    for (int64_t k = 0; k < N; k++) lam[k] -= F[k];
-    for (int64_t f = 0; f < P->nf; f++) {
-      double share = P->farea[f] / P->nfn;
-      for (int b = 0; b < P->nfn; b++) {
-        int32_t k = P->faces[f * P->nfn + b];
-        lam[k] -= share * P->fh[f] * mu[k];
-      }
-    }
-    for (int64_t k = 0; k < N; k++)
-      if (is_dir[k]) lam[k] = 0.0;
+    for (int64_t k = 0; k < N; k++) lam[k] = is_dir[k] ? 0.0 : out[k];
   }
+done:
+  free(Fe);
+  free(F);
+  free(C);
+  free(Cp);
+  free(mu);
+  free(out);
+  return rc;
 }

@@ -70,7 +70,7 @@ def test_adjoint_matches_oracle(case):
     o = Oracle(p)
     hist = o.run(nsteps, history=True)
     _, lam = _loss_grad(hist[-1], sens, target)
-    ref = o.adjoint_linear(hist, lam)
+    ref = o.adjoint(hist, lam)
     for prec in ("fp64", "fp32c"):
         T, _, g = _gpu_adjoint(p, prec, nsteps, ckpt, lambda T: _loss_grad(T, sens, target))
         errs = {"logk": rel(g["logk"], ref["g_logk"]), "c": rel(g["c"], ref["g_c"]),
@@ -167,7 +167,7 @@ def test_autograd_function():
     lam = np.zeros(o.N)
     sn = p["meta"]["sensors"]
     lam[sn] = 2.0 * (hist[-1][sn] - 90.0) / sn.size
-    ref = o.adjoint_linear(hist, lam)
+    ref = o.adjoint(hist, lam)
     assert rel(log_k.grad.cpu().numpy(), ref["g_logk"]) < 1e-10
     assert rel(T0.grad.cpu().numpy(), ref["lam0"]) < 1e-10
 
@@ -190,7 +190,7 @@ def test_adjoint_workload_full_size():
     o = Oracle(p)
     hist = o.run(nsteps, history=True)
     L, lam = _loss_grad(hist[-1], sens, target)
-    ref = o.adjoint_linear(hist, lam)
+    ref = o.adjoint(hist, lam)
     del hist
     err = rel(g32["logk"], ref["g_logk"])
     print(f"48^3 fp32c g_logk err {err:.2e}, loss {L32:.6e} vs {L:.6e}", flush=True)

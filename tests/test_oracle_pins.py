@@ -409,7 +409,7 @@ def test_adjoint_matches_finite_differences():
     hist = o.run(nsteps, history=True)
     lam = np.zeros(o.N)
     lam[sens] = hist[-1][sens] - target
-    g = o.adjoint_linear(hist, lam)
+    g = o.adjoint(hist, lam)
     eps = 1e-4
     theta = np.log(p["elem_kscale"])
     for e in (0, 13, 37, 63):
@@ -456,8 +456,116 @@ def test_adjoint_transpose_identity():
     w = g.standard_normal(o.N)
     Jv = o.run(1, T0=T + v, apply_initial=False) - o.run(1, T0=T, apply_initial=False)
     hist = o.run(1, T0=T, apply_initial=False, history=True)
-    JTw = o.adjoint_linear(hist, w)["lam0"]
+    JTw = o.adjoint(hist, w)["lam0"]
     assert abs(w @ Jv - JTw @ v) < 1e-12 * abs(w @ Jv)
+
+
+def _nonlinear_adjoint_problem(elem):
+    """Box with D(T) = Dk (1 + 0.005 T), c(T) = c0 + 2 T, radiation on the top,
+    convection on five sides, a Dirichlet side, a point load, per-element k
+    factors and a fixed dt at half the critical step."""
+    n = 3
+    kk = [1.0] if elem == "hex8" else [3.0, 2.0, 1.5, 0.4, -0.3, 0.2]
+    mat = P.material(1000.0, 900.0, kk, c1=2.0, s0=1.0, s1=0.005)
+    p, m = H.box_problem(elem, n, side=0.1, mat=mat)
+    g = np.random.default_rng(12)
+    p["elem_kscale"] = np.exp(0.4 * g.standard_normal(p["conn"].shape[1]))
+    if elem == "hex8":
+        faces, sides = M.box_side_faces(m)
+    else:
+        faces = M.boundary_faces(m)
+        c = np.stack([m["x"][faces].mean(1), m["y"][faces].mean(1), m["z"][faces].mean(1)], 1)
+        sides = np.where(np.isclose(c[:, 0], 0.0), 0, np.where(np.isclose(c[:, 2], 0.1), 5, 1))
+    keep = sides != 0
+    faces, sides = faces[keep], sides[keep]
+    top = sides == 5
+    P.set_faces(p, faces, h=g.uniform(5, 30, faces.shape[0]), Ta=20.0,
+                eps=np.where(top, 0.8, 0.0), q=np.where(top, 0.0, 500.0))
+    left = np.nonzero(np.isclose(m["x"], 0.0))[0].astype(np.int32)
+    p["dir_nodes"], p["dir_T"] = left, np.full(left.size, 40.0)
+    p["pt_nodes"], p["pt_W"] = np.array([m["x"].size - 1], np.int32), np.array([2.0])
+    p["T0"] = g.uniform(150, 300, m["x"].size)
+    p["T_lo"], p["T_hi"] = 0.0, 400.0
+    p["dt"] = 0.5 * Oracle(p).dt_crit
+    return p
+
+
+@pytest.mark.parametrize("elem", ["hex8", "tet4"])
+def test_nonlinear_adjoint_matches_finite_differences(elem):
+    """Every Jacobian term of the nonlinear step (k(Tbar), c(T), radiation)
+    enters the gradients: central differences of the oracle's own forward run
+    against its adjoint, for log k, c0, h and T0."""
+    p = _nonlinear_adjoint_problem(elem)
+    nsteps = 40
+    o = Oracle(p)
+    sens = np.arange(1, o.N, 3)
+    sens = sens[~np.isin(sens, o.dir_nodes)]
+    target = np.full(sens.size, 100.0)
+    hist = o.run(nsteps, history=True)
+    lam = np.zeros(o.N)
+    lam[sens] = hist[-1][sens] - target
+    g = o.adjoint(hist, lam)
+
+    def close(fd, ad, scale):
+        assert abs(fd - ad) <= 2e-6 * max(abs(fd), 1e-3 * scale), (fd, ad)
+
+    eps = 1e-4
+    theta = np.log(p["elem_kscale"])
+    for e in (0, 7, o.E - 1, int(np.argmax(np.abs(g["g_logk"])))):
+        Ls = []
+        for d in (eps, -eps):
+            th = theta.copy()
+            th[e] += d
+            Ls.append(_loss(dict(p, elem_kscale=np.exp(th)), sens, target, nsteps)[0])
+        close((Ls[0] - Ls[1]) / (2 * eps), g["g_logk"][e], np.abs(g["g_logk"]).max())
+    # c0 of one element (per-element materials with the same c1 and D(T))
+    e = int(np.argmax(np.abs(g["g_c"])))
+    m0 = p["materials"][0]
+    mats = [dict(m0) for _ in range(o.E)]
+    base = dict(p, materials=mats, elem_material=np.arange(o.E, dtype=np.int32))
+    Ls = []
+    for d in (1e-3, -1e-3):
+        mm = [dict(x) for x in mats]
+        mm[e]["c0"] = m0["c0"] * (1 + d)
+        Ls.append(_loss(dict(base, materials=mm), sens, target, nsteps)[0])
+    close((Ls[0] - Ls[1]) / (2e-3 * m0["c0"]), g["g_c"][e], np.abs(g["g_c"]).max())
+    # h of the face with the largest derivative (a radiating one among them)
+    for f in (int(np.argmax(np.abs(g["g_h"]))), int(np.nonzero(p["face_eps"] > 0)[0][0])):
+        Ls = []
+        for d in (1e-3, -1e-3):
+            hh = p["face_h"].copy()
+            hh[f] *= (1 + d)
+            Ls.append(_loss(dict(p, face_h=hh), sens, target, nsteps)[0])
+        close((Ls[0] - Ls[1]) / (2e-3 * p["face_h"][f]), g["g_h"][f], np.abs(g["g_h"]).max())
+    # initial temperatures of free nodes (one under radiation)
+    rad_nodes = np.unique(p["faces"][p["face_eps"] > 0])
+    free = [k for k in (int(rad_nodes[-1]), o.N // 2, o.N - 1) if k not in set(o.dir_nodes)]
+    for k in free:
+        Ls = []
+        for d in (1e-3, -1e-3):
+            T0 = p["T0"].copy()
+            T0[k] += d
+            Ls.append(_loss(dict(p, T0=T0), sens, target, nsteps)[0])
+        close((Ls[0] - Ls[1]) / 2e-3, g["lam0"][k], np.abs(g["lam0"]).max())
+    assert np.all(g["lam0"][o.dir_nodes] == 0.0)
+
+
+def test_nonlinear_adjoint_transpose_identity():
+    """<w, J v> = <J^T w, v> for the Jacobian J of one nonlinear step, with J v
+    from a central difference of the step (error O(eps^2))."""
+    p = _nonlinear_adjoint_problem("hex8")
+    o = Oracle(p)
+    g = np.random.default_rng(5)
+    T = o.initial()
+    v = g.standard_normal(o.N)
+    v[o.dir_nodes] = 0.0
+    w = g.standard_normal(o.N)
+    eps = 1e-3
+    Jv = (o.run(1, T0=T + eps * v, apply_initial=False)
+          - o.run(1, T0=T - eps * v, apply_initial=False)) / (2 * eps)
+    hist = o.run(1, T0=T, apply_initial=False, history=True)
+    JTw = o.adjoint(hist, w)["lam0"]
+    assert abs(w @ Jv - JTw @ v) < 1e-8 * np.abs(w) @ np.abs(Jv)
 
 
 def test_error_norms():
