@@ -35,7 +35,9 @@ class _Problem(C.Structure):
                 ("faces", _i32), ("farea", _d), ("fh", _d), ("fTa", _d), ("feps", _d),
                 ("fq", _d), ("pt_nodes", _i32), ("pt_W", _d),
                 ("dir_nodes", _i32), ("dir_T", _d), ("dt", _d),
-                ("Tz", C.c_double), ("sigma", C.c_double)]
+                ("Tz", C.c_double), ("sigma", C.c_double),
+                ("nkt", C.c_int32), ("nct", C.c_int32),
+                ("kt_T", _d), ("kt_f", _d), ("ct_T", _d), ("ct_f", _d)]
 
 
 def lib():
@@ -99,6 +101,10 @@ class Oracle:
         if prob["elem_kscale"] is not None:
             Dk = Dk * _f64(prob["elem_kscale"])[None, :]
         self.Dk = np.ascontiguousarray(Dk)
+        # optional shared multiplier tables: D(T) = Dk fk(Tbar), c(T) = c0 fc(T)
+        kt, ct = prob.get("k_table"), prob.get("c_table")
+        self.kt = None if kt is None else (_f64(kt[0]), _f64(kt[1]))
+        self.ct = None if ct is None else (_f64(ct[0]), _f64(ct[1]))
         # boundary faces
         if prob["faces"] is not None and prob["faces"].shape[0] > 0:
             self.faces = np.ascontiguousarray(prob["faces"], dtype=np.int32)
@@ -152,6 +158,12 @@ class Oracle:
         s.dir_nodes, s.dir_T = _p(self.dir_nodes, _i32), _p(self.dir_T)
         s.dt = _p(self.dt)
         s.Tz, s.sigma = self.Tz, SIGMA_SB
+        s.nkt = 0 if self.kt is None else self.kt[0].size
+        s.nct = 0 if self.ct is None else self.ct[0].size
+        if self.kt is not None:
+            s.kt_T, s.kt_f = _p(self.kt[0]), _p(self.kt[1])
+        if self.ct is not None:
+            s.ct_T, s.ct_f = _p(self.ct[0]), _p(self.ct[1])
         self._s = s
 
     def _buffers(self):
@@ -189,6 +201,18 @@ class Oracle:
         smax = np.maximum(self.s0 + self.s1 * Tlo, self.s0 + self.s1 * Thi)
         smin = np.minimum(self.s0 + self.s1 * Tlo, self.s0 + self.s1 * Thi)
         cmin = np.minimum(self.c0 + self.c1 * Tlo, self.c0 + self.c1 * Thi)
+        # a piecewise-linear table takes its extremes at the ends of the range
+        # or at breakpoints inside it
+        def extremes(tab):
+            Tt, f = tab
+            pts = np.concatenate([[Tlo, Thi], Tt[(Tt > Tlo) & (Tt < Thi)]])
+            v = np.interp(pts, Tt, f)
+            return v.min(), v.max()
+        if self.kt is not None:
+            lo_, hi_ = extremes(self.kt)
+            smax, smin = np.full(self.E, hi_), np.full(self.E, lo_)
+        if self.ct is not None:
+            cmin = self.c0 * extremes(self.ct)[0]
         if np.any(smin <= 0) or np.any(cmin <= 0):
             raise ValueError("conductivity or heat capacity not positive on [T_lo, T_hi]")
         lam_e = np.zeros(self.E)

@@ -246,7 +246,50 @@ typedef struct {
   const double *dir_T;
   const double *dt; /* per node */
   double Tz, sigma;
+  /* optional piecewise-linear multiplier tables (n points, T increasing):
+   * with nkt > 0, D_e(T) = Dk_e * fk(Tbar) replaces s0 + s1 Tbar; with nct > 0,
+   * c_e(T) = c0_e * fc(T) replaces c0 + c1 T */
+  int32_t nkt, nct;
+  const double *kt_T, *kt_f, *ct_T, *ct_f;
 } orc_problem;
+
+/* Piecewise-linear interpolation in a table, constant beyond its ends;
+ * *slope receives the derivative (0 beyond the ends; the left segment's at a
+ * breakpoint). */
+static double table_eval(int32_t n, const double *Tt, const double *f, double T, double *slope) {
+  if (T <= Tt[0]) {
+    *slope = 0.0;
+    return f[0];
+  }
+  if (T >= Tt[n - 1]) {
+    *slope = 0.0;
+    return f[n - 1];
+  }
+  int i = 1;
+  while (T > Tt[i]) i++;
+  const double h = Tt[i] - Tt[i - 1];
+  *slope = (f[i] - f[i - 1]) / h;
+  return f[i - 1] + (T - Tt[i - 1]) / h * (f[i] - f[i - 1]);
+}
+
+/* conductivity factor s_e(Tbar) and its derivative */
+static double kfac(const orc_problem *P, int64_t e, double Tbar, double *ds) {
+  if (P->nkt > 0) return table_eval(P->nkt, P->kt_T, P->kt_f, Tbar, ds);
+  *ds = P->s1[e];
+  return P->s0[e] + P->s1[e] * Tbar;
+}
+
+/* specific heat c_e(T) and its derivative */
+static double cfun(const orc_problem *P, int64_t e, double T, double *dc) {
+  if (P->nct > 0) {
+    double sl;
+    const double v = table_eval(P->nct, P->ct_T, P->ct_f, T, &sl);
+    *dc = P->c0[e] * sl;
+    return P->c0[e] * v;
+  }
+  *dc = P->c1[e];
+  return P->c0[e] + P->c1[e] * T;
+}
 
 /* Element load F_e = G D(Tbar) B T_e with G = W B^T (Eq. 19-20). */
 static void element_load(const orc_problem *P, int64_t e, const double *T, double *Fe) {
@@ -258,7 +301,8 @@ static void element_load(const orc_problem *P, int64_t e, const double *T, doubl
     Tbar += Te[a];
   }
   Tbar /= ne;
-  double s = P->s0[e] + P->s1[e] * Tbar;
+  double ds;
+  double s = kfac(P, e, Tbar, &ds);
   const double *Dk = P->Dk;
   double D[3][3];
   D[0][0] = Dk[0 * E + e] * s;
@@ -294,7 +338,8 @@ void orc_loads(const orc_problem *P, const double *T, double *Fe, double *F, dou
     for (int a = 0; a < ne; a++) {
       int32_t k = P->conn[(int64_t)a * E + e];
       F[k] += Fe[e * ne + a];
-      C[k] += P->rho[e] * P->V[e] / ne * (P->c0[e] + P->c1[e] * T[k]);
+      double dc;
+      C[k] += P->rho[e] * P->V[e] / ne * cfun(P, e, T[k], &dc);
     }
 }
 
@@ -367,19 +412,21 @@ static void element_apply(const orc_problem *P, int64_t e, const double *v, doub
  * Discrete adjoint of orc_run (not in the paper: the exact transpose of its
  * explicit recursion).  One step, for a node k that is not Dirichlet, is
  *   T'_k = T_k + dt_k r_k(T) / C_k(T_k),   r = Q(T) - F(T),
- * with F_e = s_e K0_e T_e, s_e = s0_e + s1_e Tbar_e (K0_e the element matrix at
- * s = 1, symmetric), C_k = sum_e m_e (c0_e + c1_e T_k), m_e = rho_e V_e / n_e,
+ * with F_e = s_e(Tbar_e) K0_e T_e (s_e = s0_e + s1_e Tbar_e or the k table;
+ * K0_e the element matrix at s = 1, symmetric), C_k = sum_e m_e c_e(T_k)
+ * (c_e = c0_e + c1_e T or c0_e times the c table), m_e = rho_e V_e / n_e,
  * and Q_k = sum_f share_f [-h_f (T_k - Ta_f) - sigma eps_f ((T_k - Tz)^4 -
  * (Ta_f - Tz)^4) + q_f] + P_k.  Dirichlet nodes are reset to their values, so
  * their rows of the Jacobian vanish.  With lam = dL/dT', mu_k = dt_k lam_k / C_k
  * (0 on Dirichlet nodes) and dT = T' - T:
- *   dL/dT_j = lam_j (1 - dT_j C'_j / C_j)          C'_j = sum_{e owns j} m_e c1_e
- *           - sum_{e owns j} [ s_e (K0_e mu_e)_j + s1_e / n_e (mu_e . K0_e T_e) ]
+ *   dL/dT_j = lam_j (1 - dT_j C'_j / C_j)          C'_j = sum_{e owns j} m_e c_e'(T_j)
+ *           - sum_{e owns j} [ s_e (K0_e mu_e)_j + s_e'(Tbar_e) / n_e (mu_e . K0_e T_e) ]
  *           - mu_j sum_{f owns j} share_f (h_f + 4 sigma eps_f (T_j - Tz)^3),
  * set to 0 on Dirichlet nodes (their values are data, not state), and the
  * parameter derivatives accumulated over the steps are
  *   d/d log k_e (k_e scales K0_e):  -mu_e . F_e
- *   d/d c0_e:                       -m_e sum_{k of e, not Dirichlet} lam_k dT_k / C_k
+ *   d/d c0_e:                       -m_e sum_{k of e, not Dirichlet} lam_k dT_k / C_k dc_e/dc0_e(T_k)
+ *                                   (dc_e/dc0_e = 1, or the c table's value)
  *   d/d h_f:                        -share_f sum_{k of f} mu_k (T_k - Ta_f).
  * Runs the steps in reverse from hist (T^0..T^nsteps); on return lam holds
  * dL/dT^0.  is_dir[N] is 1 on Dirichlet nodes.  Returns 0, or -1 if a work
@@ -397,12 +444,17 @@ int orc_adjoint(const orc_problem *P, const double *hist, int64_t nsteps, const 
     rc = -1;
     goto done;
   }
-  for (int64_t e = 0; e < E; e++)
-    for (int a = 0; a < ne; a++)
-      Cp[P->conn[(int64_t)a * E + e]] += P->rho[e] * P->V[e] / ne * P->c1[e];
   for (int64_t n = nsteps - 1; n >= 0; n--) {
     const double *Tn = hist + n * N, *Tn1 = hist + (n + 1) * N;
     orc_loads(P, Tn, Fe, F, C); /* F_e and C at T^n */
+    memset(Cp, 0, sizeof(double) * N);
+    for (int64_t e = 0; e < E; e++)
+      for (int a = 0; a < ne; a++) {
+        const int32_t k = P->conn[(int64_t)a * E + e];
+        double dc;
+        (void)cfun(P, e, Tn[k], &dc);
+        Cp[k] += P->rho[e] * P->V[e] / ne * dc;
+      }
     for (int64_t k = 0; k < N; k++) {
       mu[k] = is_dir[k] ? 0.0 : P->dt[k] * lam[k] / C[k];
       out[k] = is_dir[k] ? 0.0 : lam[k] * (1.0 - (Tn1[k] - Tn[k]) * Cp[k] / C[k]);
@@ -415,14 +467,18 @@ int orc_adjoint(const orc_problem *P, const double *hist, int64_t nsteps, const 
         Tbar += Tn[kk[a]];
       }
       Tbar /= ne;
-      const double se = P->s0[e] + P->s1[e] * Tbar;
+      double dse;
+      const double se = kfac(P, e, Tbar, &dse);
       element_apply(P, e, mu, se, Kmu); /* s_e K0_e mu_e */
       for (int a = 0; a < ne; a++) {
         muF += mu[kk[a]] * Fe[e * ne + a];
-        if (!is_dir[kk[a]]) gc += lam[kk[a]] * (Tn1[kk[a]] - Tn[kk[a]]) / C[kk[a]];
+        /* dc_e/dc0_e at T_k: 1, or the c table's value */
+        double sl, dcdc0 = 1.0;
+        if (P->nct > 0) dcdc0 = table_eval(P->nct, P->ct_T, P->ct_f, Tn[kk[a]], &sl);
+        if (!is_dir[kk[a]]) gc += lam[kk[a]] * (Tn1[kk[a]] - Tn[kk[a]]) / C[kk[a]] * dcdc0;
       }
       /* mu_e . K0_e T_e = mu_e . F_e / s_e */
-      const double spread = P->s1[e] / ne * (muF / se);
+      const double spread = dse / ne * (muF / se);
       for (int a = 0; a < ne; a++) out[kk[a]] -= Kmu[a] + spread;
       g_logk[e] += -muF;
       g_c[e] += -P->rho[e] * P->V[e] / ne * gc;

@@ -48,3 +48,34 @@ def box_problem(elem, n, side=1.0, mat=None, nsteps=1):
     p["materials"] = [mat or P.material(rho=1000.0, c0=1000.0, k=[1.0])]
     p["nsteps"] = nsteps
     return p, m
+
+
+def nonlinear_adjoint_problem(elem):
+    """Box with D(T) = Dk (1 + 0.005 T), c(T) = c0 + 2 T, radiation on the top,
+    convection on five sides, a Dirichlet side, a point load, per-element k
+    factors and a fixed dt at half the critical step."""
+    n = 3
+    kk = [1.0] if elem == "hex8" else [3.0, 2.0, 1.5, 0.4, -0.3, 0.2]
+    mat = P.material(1000.0, 900.0, kk, c1=2.0, s0=1.0, s1=0.005)
+    p, m = box_problem(elem, n, side=0.1, mat=mat)
+    g = np.random.default_rng(12)
+    p["elem_kscale"] = np.exp(0.4 * g.standard_normal(p["conn"].shape[1]))
+    if elem == "hex8":
+        faces, sides = M.box_side_faces(m)
+    else:
+        faces = M.boundary_faces(m)
+        c = np.stack([m["x"][faces].mean(1), m["y"][faces].mean(1), m["z"][faces].mean(1)], 1)
+        sides = np.where(np.isclose(c[:, 0], 0.0), 0, np.where(np.isclose(c[:, 2], 0.1), 5, 1))
+    keep = sides != 0
+    faces, sides = faces[keep], sides[keep]
+    top = sides == 5
+    P.set_faces(p, faces, h=g.uniform(5, 30, faces.shape[0]), Ta=20.0,
+                eps=np.where(top, 0.8, 0.0), q=np.where(top, 0.0, 500.0))
+    left = np.nonzero(np.isclose(m["x"], 0.0))[0].astype(np.int32)
+    p["dir_nodes"], p["dir_T"] = left, np.full(left.size, 40.0)
+    p["pt_nodes"], p["pt_W"] = np.array([m["x"].size - 1], np.int32), np.array([2.0])
+    p["T0"] = g.uniform(150, 300, m["x"].size)
+    p["T_lo"], p["T_hi"] = 0.0, 400.0
+    from oracle import Oracle
+    p["dt"] = 0.5 * Oracle(p).dt_crit
+    return p

@@ -380,6 +380,117 @@ def test_single_hex_boundary_recursion():
 
 
 # ----------------------------------------------------------------------------
+# piecewise-linear property tables (shared multipliers of D and c)
+def _table_problem(elem="hex8"):
+    p = H.nonlinear_adjoint_problem(elem)
+    p["materials"] = [dict(m, s0=1.0, s1=0.0, c1=0.0) for m in p["materials"]]
+    return p
+
+
+def test_tables_equal_to_linear_laws_reproduce_them():
+    """A two-point k table on s0 + s1 T and a c table on 1 + (c1/c0) T, both
+    spanning the temperatures, give the linear-law run to rounding."""
+    lin = H.nonlinear_adjoint_problem("hex8")
+    m = lin["materials"][0]
+    Tt = np.array([-500.0, 1500.0])
+    tab = dict(_table_problem(), k_table=(Tt, m["s0"] + m["s1"] * Tt),
+               c_table=(Tt, 1.0 + m["c1"] / m["c0"] * Tt))
+    a, b = Oracle(lin).run(40), Oracle(tab).run(40)
+    assert np.max(np.abs(a - b)) < 1e-11 * np.max(np.abs(a))
+
+
+def test_table_segment_selection_and_clamping():
+    """Temperatures inside one segment of a kinked table follow that segment's
+    linear law; a table lying entirely below the temperatures acts as its last
+    value (clamped), one above them as its first."""
+    p = _table_problem()
+    o = Oracle(p)
+    assert o.initial().min() >= 40.0      # T0 in [150, 300], Dirichlet side 40
+    Tt = np.array([-100.0, 20.0, 1000.0, 2000.0])
+    f = np.array([0.4, 1.0, 1.0 + 0.004 * 980.0, 9.0])   # slope 0.004 on [20, 1000]
+    seg = Oracle(dict(p, materials=[dict(p["materials"][0], s0=1.0 - 0.004 * 20.0, s1=0.004)]))
+    got = Oracle(dict(p, k_table=(Tt, f))).run(30)
+    ref = seg.run(30)
+    assert 20.0 < ref.min() and ref.max() < 1000.0   # the run stays in the [20, 1000] segment
+    assert np.max(np.abs(got - ref)) < 1e-11 * np.max(np.abs(ref))
+    for Tt2, f2, s in ((np.array([-50.0, 0.0]), np.array([5.0, 2.5]), 2.5),
+                       (np.array([5000.0, 6000.0]), np.array([0.7, 3.0]), 0.7)):
+        got = Oracle(dict(p, k_table=(Tt2, f2), c_table=(Tt2, f2))).run(30)
+        const = dict(p, materials=[dict(p["materials"][0], s0=s, c0=p["materials"][0]["c0"] * s)])
+        ref = Oracle(const).run(30)
+        assert np.max(np.abs(got - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_c_table_single_hex_recursion():
+    """One hexahedron, uniform temperature, convection on all faces: every node
+    follows T' = T - dt A h (T - Ta) / (rho c0 fc(T) a^3 / 8) with fc
+    interpolated independently by numpy."""
+    a, h, Ta, rho, c0 = 0.05, 40.0, 10.0, 2000.0, 500.0
+    m = M.box_hex(1, 1, 1, a, a, a)
+    p = P._base(m, "one_ctab")
+    p["materials"] = [P.material(rho, c0, [5.0])]
+    faces, _ = M.box_side_faces(m)
+    P.set_faces(p, faces, h=h, Ta=Ta)
+    Tt, f = np.array([0.0, 100.0, 200.0, 320.0]), np.array([1.0, 1.6, 1.1, 2.0])
+    p["c_table"] = (Tt, f)
+    p["T0"] = np.full(8, 300.0)
+    p["T_lo"], p["T_hi"] = 0.0, 300.0
+    o = Oracle(p)
+    T = 300.0
+    A = 3 * a * a / 4
+    for _ in range(200):
+        T = T + o.dt[0] * A * (-h * (T - Ta)) / (rho * c0 * np.interp(T, Tt, f) * a ** 3 / 8)
+    assert T < 200.0                       # the run crosses two kinks
+    assert np.max(np.abs(o.run(200) - T)) < 1e-11 * T
+
+
+def test_table_adjoint_matches_finite_differences():
+    """Kinked k and c tables: the adjoint's table slopes against central
+    differences of the forward run (log k, c0, h and T0)."""
+    p = _table_problem("hex8")
+    p["k_table"] = (np.array([0.0, 120.0, 220.0, 400.0]), np.array([0.8, 1.5, 1.2, 2.2]))
+    p["c_table"] = (np.array([0.0, 160.0, 260.0, 400.0]), np.array([1.0, 1.8, 1.3, 1.9]))
+    p["dt"] = 0.5 * Oracle(p).dt_crit
+    nsteps = 30
+    o = Oracle(p)
+    sens = np.arange(1, o.N, 3)
+    sens = sens[~np.isin(sens, o.dir_nodes)]
+    target = np.full(sens.size, 100.0)
+    hist = o.run(nsteps, history=True)
+    lam = np.zeros(o.N)
+    lam[sens] = hist[-1][sens] - target
+    g = o.adjoint(hist, lam)
+    theta = np.log(p["elem_kscale"])
+    for e in (3, int(np.argmax(np.abs(g["g_logk"])))):
+        Ls = []
+        for d in (1e-4, -1e-4):
+            th = theta.copy()
+            th[e] += d
+            Ls.append(_loss(dict(p, elem_kscale=np.exp(th)), sens, target, nsteps)[0])
+        fd = (Ls[0] - Ls[1]) / 2e-4
+        assert abs(fd - g["g_logk"][e]) <= 2e-6 * max(abs(fd), 1e-3 * np.abs(g["g_logk"]).max())
+    for k in (o.N // 2, o.N - 1):
+        Ls = []
+        for d in (1e-3, -1e-3):
+            T0 = p["T0"].copy()
+            T0[k] += d
+            Ls.append(_loss(dict(p, T0=T0), sens, target, nsteps)[0])
+        fd = (Ls[0] - Ls[1]) / 2e-3
+        assert abs(fd - g["lam0"][k]) <= 2e-6 * max(abs(fd), 1e-3 * np.abs(g["lam0"]).max())
+    e = int(np.argmax(np.abs(g["g_c"])))
+    m0 = p["materials"][0]
+    base = dict(p, materials=[dict(m0) for _ in range(o.E)],
+                elem_material=np.arange(o.E, dtype=np.int32))
+    Ls = []
+    for d in (1e-3, -1e-3):
+        mm = [dict(m0) for _ in range(o.E)]
+        mm[e]["c0"] = m0["c0"] * (1 + d)
+        Ls.append(_loss(dict(base, materials=mm), sens, target, nsteps)[0])
+    fd = (Ls[0] - Ls[1]) / (2e-3 * m0["c0"])
+    assert abs(fd - g["g_c"][e]) <= 2e-6 * abs(fd)
+
+
+# ----------------------------------------------------------------------------
 # adjoint
 def _adjoint_problem():
     n = 4
@@ -460,42 +571,12 @@ def test_adjoint_transpose_identity():
     assert abs(w @ Jv - JTw @ v) < 1e-12 * abs(w @ Jv)
 
 
-def _nonlinear_adjoint_problem(elem):
-    """Box with D(T) = Dk (1 + 0.005 T), c(T) = c0 + 2 T, radiation on the top,
-    convection on five sides, a Dirichlet side, a point load, per-element k
-    factors and a fixed dt at half the critical step."""
-    n = 3
-    kk = [1.0] if elem == "hex8" else [3.0, 2.0, 1.5, 0.4, -0.3, 0.2]
-    mat = P.material(1000.0, 900.0, kk, c1=2.0, s0=1.0, s1=0.005)
-    p, m = H.box_problem(elem, n, side=0.1, mat=mat)
-    g = np.random.default_rng(12)
-    p["elem_kscale"] = np.exp(0.4 * g.standard_normal(p["conn"].shape[1]))
-    if elem == "hex8":
-        faces, sides = M.box_side_faces(m)
-    else:
-        faces = M.boundary_faces(m)
-        c = np.stack([m["x"][faces].mean(1), m["y"][faces].mean(1), m["z"][faces].mean(1)], 1)
-        sides = np.where(np.isclose(c[:, 0], 0.0), 0, np.where(np.isclose(c[:, 2], 0.1), 5, 1))
-    keep = sides != 0
-    faces, sides = faces[keep], sides[keep]
-    top = sides == 5
-    P.set_faces(p, faces, h=g.uniform(5, 30, faces.shape[0]), Ta=20.0,
-                eps=np.where(top, 0.8, 0.0), q=np.where(top, 0.0, 500.0))
-    left = np.nonzero(np.isclose(m["x"], 0.0))[0].astype(np.int32)
-    p["dir_nodes"], p["dir_T"] = left, np.full(left.size, 40.0)
-    p["pt_nodes"], p["pt_W"] = np.array([m["x"].size - 1], np.int32), np.array([2.0])
-    p["T0"] = g.uniform(150, 300, m["x"].size)
-    p["T_lo"], p["T_hi"] = 0.0, 400.0
-    p["dt"] = 0.5 * Oracle(p).dt_crit
-    return p
-
-
 @pytest.mark.parametrize("elem", ["hex8", "tet4"])
 def test_nonlinear_adjoint_matches_finite_differences(elem):
     """Every Jacobian term of the nonlinear step (k(Tbar), c(T), radiation)
     enters the gradients: central differences of the oracle's own forward run
     against its adjoint, for log k, c0, h and T0."""
-    p = _nonlinear_adjoint_problem(elem)
+    p = H.nonlinear_adjoint_problem(elem)
     nsteps = 40
     o = Oracle(p)
     sens = np.arange(1, o.N, 3)
@@ -553,7 +634,7 @@ def test_nonlinear_adjoint_matches_finite_differences(elem):
 def test_nonlinear_adjoint_transpose_identity():
     """<w, J v> = <J^T w, v> for the Jacobian J of one nonlinear step, with J v
     from a central difference of the step (error O(eps^2))."""
-    p = _nonlinear_adjoint_problem("hex8")
+    p = H.nonlinear_adjoint_problem("hex8")
     o = Oracle(p)
     g = np.random.default_rng(5)
     T = o.initial()
