@@ -36,17 +36,19 @@ TRAFFIC = {"nonlinear_hex64": ("d47297f4a511c5e332595bdf3e2afea505b106a2", 23692
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
 
 WORKLOADS = {
-    # name: (builder, default steps, oracle sample steps, description)
+    # name: (builder, default steps, oracle sample steps, description, default launch shape)
     "nonlinear_hex64": ("cube_nonlinear_hex", 10000, 200,
-                        "0.1 m cube, 64^3 hex8, orthotropic D(T), c(T), convection+radiation+flux"),
+                        "0.1 m cube, 64^3 hex8, orthotropic D(T), c(T), convection+radiation+flux",
+                        dict()),
     "aniso_tet128": ("cube_aniso_tet", 2000, 4,
                      "0.1 m cube, 128^3 x 6 Kuhn tet4, per-element SPD conductivity, c(T), "
-                     "convection"),
+                     "convection", dict(tile_nodes=1024, block_threads=512)),
     "batched_hex256": ("batched_hex", 5000, 10,
-                       "256 hex8 boxes with 8..48 cells per axis, per-instance k, c, h, eps, T0, dt"),
+                       "256 hex8 boxes with 8..48 cells per axis, per-instance k, c, h, eps, T0, dt",
+                       dict(tile_nodes=1024, block_threads=512)),
     "adjoint_hex48": ("adjoint_hex", 2000, 100,
                       "48^3 hex8, log-normal k field, convection; forward + adjoint with "
-                      "checkpoints every 100 steps"),
+                      "checkpoints every 100 steps", dict()),
 }
 
 
@@ -61,6 +63,8 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--fuse", type=int, default=0, help="steps per kernel launch (0 = default)")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape by timing")
+    ap.add_argument("--resident", choices=["default", "on", "off"], default="default",
+                    help="resident stepping (one launch for all steps, tiles held in registers)")
     ap.add_argument("--oracle-steps", type=int, default=0,
                     help="steps of the CPU oracle sample (timed baseline and error reference)")
     ap.add_argument("--no-oracle", action="store_true")
@@ -112,14 +116,20 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    builder, dsteps, osteps, desc = WORKLOADS[args.workload]
+    builder, dsteps, osteps, desc, shape = WORKLOADS[args.workload]
     steps = args.steps or dsteps
     osteps = args.oracle_steps or osteps
     prob = getattr(P, builder)(nsteps=steps)
     E, N = prob["conn"].shape[1], prob["x"].size
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
 
-    kw = dict(tile_nodes=args.tile_nodes, block_threads=args.block, fuse_steps=args.fuse)
+    kw = dict(shape)
+    for k, v in (("tile_nodes", args.tile_nodes), ("block_threads", args.block),
+                 ("fuse_steps", args.fuse)):
+        if v:
+            kw[k] = v
+    if args.resident != "default":
+        kw["resident"] = args.resident == "on"
     tuned = None
     if args.autotune:
         tuned = autotune(prob, "fp32c", steps=200, log=log)
@@ -160,7 +170,8 @@ def main():
 
     import hashlib
     src_sha = hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
-    default_shape = not (args.tile_nodes or args.block or args.fuse or args.autotune)
+    default_shape = not (args.tile_nodes or args.block or args.fuse or args.autotune
+                         or args.resident != "default")
     traffic = None
     if args.workload in TRAFFIC and default_shape and TRAFFIC[args.workload][0] == src_sha:
         traffic = TRAFFIC[args.workload][1]
@@ -168,8 +179,17 @@ def main():
     t = r32["t"]
     info = r32["info"]
     K = info["fuse_steps"]
-    launches = -(-steps // K)
-    alg = info["algorithmic_bytes_per_launch"]
+    resident = bool(info["resident"])
+    if resident:
+        # one launch runs all the timed steps: the tile data is loaded once, then
+        # every step moves only the halo exchange
+        launches = 1
+        alg = info["algorithmic_bytes_per_launch"] + steps * info["exchange_bytes_per_step"]
+        kernel = "k_resident"
+    else:
+        launches = -(-steps // K)
+        alg = info["algorithmic_bytes_per_launch"]
+        kernel = "k_step1" if K == 1 else "k_step"
     achieved = alg / (t / launches) / 1e9
     line = {
         "metric": METRIC,
@@ -182,13 +202,14 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": f"{args.workload}: {desc} ({E} elements, {N} nodes)",
                    "elements": E, "nodes": N, "precision": "fp32c",
-                   "graph_steps": args.graph_steps, "steps_per_launch": K,
+                   "graph_steps": args.graph_steps,
+                   "steps_per_launch": steps if resident else K, "resident": resident,
                    "tiles": info["n_tiles"], "block_threads": info["block_threads"],
                    "autotuned": tuned is not None},
         "hbm_gbs_algorithmic": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "k_step1" if K == 1 else "k_step", "us_per_launch": t / launches * 1e6,
+                     "kernel": kernel, "us_per_launch": t / launches * 1e6,
                      "bytes_per_launch_algorithmic": alg,
                      "bytes_per_launch_moved": info["moved_bytes_per_launch"]},
         "cpu_baseline": cpu,
@@ -199,9 +220,14 @@ def main():
     if "fp64" in res:
         t64 = res["fp64"]["t"]
         i64 = res["fp64"]["info"]
-        l64 = -(-steps // i64["fuse_steps"])
+        if i64["resident"]:
+            b64 = i64["algorithmic_bytes_per_launch"] + steps * i64["exchange_bytes_per_step"]
+            l64 = 1
+        else:
+            b64 = i64["algorithmic_bytes_per_launch"]
+            l64 = -(-steps // i64["fuse_steps"])
         line["fp64"] = {"value": E * steps / t64, "ms_per_step": t64 / steps * 1e3,
-                        "hbm_gbs_algorithmic": i64["algorithmic_bytes_per_launch"] / (t64 / l64) / 1e9,
+                        "hbm_gbs_algorithmic": b64 / (t64 / l64) / 1e9,
                         "speedup_fp32c_over_fp64": t64 / t}
     if errs:
         line["err_max_vs_oracle"] = errs

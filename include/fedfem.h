@@ -116,11 +116,21 @@ typedef struct {
   int32_t allow_unstable;    /* 1: accept dt > dt_crit */
   const int32_t *node_instance; /* host, n_nodes instance ids of a batched mesh of
                                    independent instances (one dt per instance), or NULL */
-  int32_t tile_nodes;        /* owned nodes per tile; 0 = default */
-  int32_t block_threads;     /* threads per tile workgroup (64..512, multiple of 64); 0 = default */
+  int32_t tile_nodes;        /* owned nodes per tile; 0 = default (512; resident: the node
+                                count over the number of resident workgroups) */
+  int32_t block_threads;     /* threads per tile workgroup, a multiple of 64 in [64, 1024]
+                                ([64, 512] when fuse_steps > 1); 0 = default (256;
+                                resident: 1024) */
   int32_t fuse_steps;        /* K: steps one kernel launch advances (1..4), each tile carrying
                                 K element rings of halo; 0 = default (1).  Results do not
                                 depend on K. */
+  int32_t resident;          /* 1: resident stepping - one cooperative launch runs all the
+                                steps of a fed_step call, every tile's workgroup holding its
+                                elements and nodes in registers for the whole launch and
+                                exchanging only halo temperatures with its neighbours through
+                                memory.  Needs every tile resident at once (FED_E_MESH at
+                                fed_create if the mesh does not fit) and K = 1.  Results are
+                                bitwise identical to resident = 0 on the same tiles. */
 } fed_options;
 
 typedef struct fed_ctx fed_ctx;
@@ -129,11 +139,14 @@ typedef struct fed_ctx fed_ctx;
 typedef struct {
   int64_t n_nodes, n_elems, n_instances;
   int64_t n_tiles, n_elems_expanded, n_halo, n_bnd_nodes;
-  int32_t elem, prec, block_threads, lds_bytes, fuse_steps, pad_;
+  int32_t elem, prec, block_threads, lds_bytes, fuse_steps, resident;
   double algorithmic_bytes_per_launch; /* unique bytes one K-step launch must move: every
                                           element's entries and operator, every node's state
                                           and coefficients, every boundary record, once */
   double moved_bytes_per_launch;       /* bytes a launch requests, halo copies included */
+  double exchange_bytes_per_step;      /* resident stepping: bytes one step moves through
+                                          memory (tagged halo reads and export writes); 0
+                                          else */
 } fed_info;
 
 /*
@@ -177,7 +190,8 @@ int fed_step_graph(fed_ctx *ctx, int64_t nsteps, int32_t graph_steps, void *stre
 /* Copies the current temperatures (FP64, caller order; FP32C returns hi + lo) to
  * T (host if on_device == 0).  Synchronises `stream`, then runs the health check
  * (all temperatures finite and within [T_lo - w, T_hi + w], w = T_hi - T_lo);
- * returns FED_E_UNSTABLE if it fired. */
+ * returns FED_E_UNSTABLE if it fired, and FED_E_HIP if a resident launch had to
+ * give up waiting for a neighbouring tile (its results are then invalid). */
 int fed_get_temperature(fed_ctx *ctx, double *T, int32_t on_device, void *stream);
 
 /* Number of steps taken since fed_set_temperature. */
@@ -205,6 +219,21 @@ int fed_checkpoint_every(fed_ctx *ctx, int64_t every);
  * host memory if on_device == 0.  Synchronises `stream`. */
 int fed_set_params(fed_ctx *ctx, const double *kscale, const double *elem_c,
                    const double *face_h, int32_t on_device, void *stream);
+
+/* Time-varying boundary conditions (the paper's explicit scheme takes the
+ * loads of Eq. 4, 5, 7 at the start of every step; Sec. 1 and 5 name real-time
+ * use): replaces the per-face ambient temperatures (face_Ta, n_faces), heat
+ * fluxes (face_q, n_faces) and concentrated loads (pt_W, n_pt, W; a source that
+ * moves along nodes listed at fed_create) for the steps that follow; NULL
+ * leaves a set unchanged.  Re-derives the boundary records on the GPU without
+ * allocating; the stability bound does not depend on these values.  Radiating
+ * faces that share a node must keep a common Ta.  Arrays are FP64, caller
+ * order, host memory (validated, and `stream` synchronised before returning)
+ * if on_device == 0, else device memory (not validated; asynchronous on
+ * `stream`).  Errors: FED_E_ARG (a set the problem does not have, non-finite
+ * values, radiating faces at a node with different Ta), FED_E_HIP. */
+int fed_set_bc(fed_ctx *ctx, const double *face_Ta, const double *face_q, const double *pt_W,
+               int32_t on_device, void *stream);
 
 /* Discrete adjoint of the steps taken since fed_set_temperature (not in the
  * paper; it differentiates the explicit recursion of Sec. 3.1 exactly).  For a

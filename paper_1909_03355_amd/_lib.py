@@ -50,7 +50,8 @@ class fed_options(C.Structure):
     _fields_ = [("prec", C.c_int32), ("dt", C.c_double), ("safety", C.c_double),
                 ("T_lo", C.c_double), ("T_hi", C.c_double), ("allow_unstable", C.c_int32),
                 ("node_instance", _i32), ("tile_nodes", C.c_int32),
-                ("block_threads", C.c_int32), ("fuse_steps", C.c_int32)]
+                ("block_threads", C.c_int32), ("fuse_steps", C.c_int32),
+                ("resident", C.c_int32)]
 
 
 class fed_info(C.Structure):
@@ -58,9 +59,10 @@ class fed_info(C.Structure):
                 ("n_tiles", C.c_int64), ("n_elems_expanded", C.c_int64),
                 ("n_halo", C.c_int64), ("n_bnd_nodes", C.c_int64),
                 ("elem", C.c_int32), ("prec", C.c_int32), ("block_threads", C.c_int32),
-                ("lds_bytes", C.c_int32), ("fuse_steps", C.c_int32), ("pad_", C.c_int32),
+                ("lds_bytes", C.c_int32), ("fuse_steps", C.c_int32), ("resident", C.c_int32),
                 ("algorithmic_bytes_per_launch", C.c_double),
-                ("moved_bytes_per_launch", C.c_double)]
+                ("moved_bytes_per_launch", C.c_double),
+                ("exchange_bytes_per_step", C.c_double)]
 
 
 # name -> (restype, argtypes) of every symbol the header declares
@@ -80,6 +82,8 @@ SIGNATURES = {
     "fed_checkpoint_every": (C.c_int, [C.c_void_p, C.c_int64]),
     "fed_set_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.c_void_p]),
+    "fed_set_bc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                             C.c_void_p]),
     "fed_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_int32, C.c_void_p]),
     "fed_destroy": (None, [C.c_void_p]),

@@ -1,7 +1,9 @@
 """Autotuner for the launch shape of the step kernel.
 
-Times a set of (tile_nodes, block_threads, fuse_steps) candidates on the
-actual problem with graph-replayed steps and returns the fastest.  Results are
+Times a set of launch shapes - (tile_nodes, block_threads, fuse_steps) with
+one kernel launch per K steps, and resident stepping (one launch for all the
+steps, tiles held in registers) where the mesh fits the GPU's resident
+workgroups - on the actual problem and returns the fastest.  Results are
 cached in a JSON file keyed by element type, precision, problem size (rounded
 to a power of two) and GPU architecture, so a repeated run of a similar
 problem skips the search.  Every candidate gives bitwise-identical
@@ -15,7 +17,8 @@ import math
 import os
 
 DEFAULT_CANDIDATES = [dict(tile_nodes=t, block_threads=b, fuse_steps=k)
-                      for k in (1, 2) for t in (256, 512, 1024) for b in (256, 512)]
+                      for k in (1, 2) for t in (256, 512, 1024) for b in (256, 512)] + \
+                     [dict(resident=True, block_threads=b) for b in (1024, 512)]
 # meshes whose set-up takes seconds: the shapes that won on smaller meshes
 LARGE_CANDIDATES = [dict(tile_nodes=t, block_threads=b, fuse_steps=1)
                     for t, b in ((512, 256), (1024, 256), (1024, 512), (256, 256))]
@@ -91,4 +94,5 @@ def autotune(prob, prec="fp32c", candidates=None, steps=200, cache=DEFAULT_CACHE
 
 
 def launch_kwargs(tuned):
-    return {k: tuned[k] for k in ("tile_nodes", "block_threads", "fuse_steps")}
+    return {k: tuned[k] for k in ("tile_nodes", "block_threads", "fuse_steps", "resident")
+            if k in tuned}

@@ -79,6 +79,14 @@ struct fed_ctx {
   double *d_dir_T = nullptr;
   int *d_flag = nullptr;
   double *d_Tuser = nullptr;  // FP64 staging in caller order
+  // resident stepping: exported nodes, tagged exchange buffers, the next tag,
+  // the wait-error flag
+  bool resident = false;
+  uint8_t *d_exported = nullptr;
+  unsigned long long *d_X[2] = {nullptr, nullptr};
+  unsigned xtag = 1;
+  int *d_rerr = nullptr;
+  int res_lds = 0;
   // kept FP64 pre-computation (re-derived by fed_set_params, used by the adjoint)
   double *d_H0 = nullptr, *d_kscale = nullptr, *d_V = nullptr;
   double *d_M0 = nullptr, *d_M1 = nullptr, *d_Cmin = nullptr, *d_lamgeo = nullptr;
@@ -93,8 +101,12 @@ struct fed_ctx {
   double *d_dtinst = nullptr;
   uint8_t *d_isdir = nullptr;
   unsigned long long *d_lam = nullptr;
-  int64_t nf = 0;
+  int64_t nf = 0, npt = 0;
   int nfn = 4;
+  // host copy of the faces and their emissivities (radiation ambients must
+  // stay single-valued per node when fed_set_bc changes them)
+  std::vector<int32_t> h_faces;
+  std::vector<double> h_feps;
   bool has_rad = false, allow_unstable = false;
   // checkpoints (state after every ckpt_every steps) and adjoint work arrays
   int64_t ckpt_every = 0;
@@ -102,7 +114,7 @@ struct fed_ctx {
   void *d_seg = nullptr, *d_lamb[2] = {nullptr, nullptr}, *d_rdt = nullptr, *d_mV = nullptr;
   float *d_seglo[2] = {nullptr, nullptr}, *d_lamlo[2] = {nullptr, nullptr};
   double *d_S0 = nullptr, *d_S1 = nullptr, *d_gk = nullptr, *d_gc = nullptr, *d_gh = nullptr;
-  int adj_lds = 0;
+  int adj_lds = 0, max_lds = 64 * 1024;
   // scalars
   double s0 = 1, s1 = 0, Tz = -273.15, T_lo = 0, T_hi = 0;
   int tdk = 0, tdc = 0, block = 256, nper = 1, K = 1;
@@ -261,8 +273,71 @@ int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, cons
   if (o->tile_nodes < 0) return fail(FED_E_ARG, "tile_nodes < 0");
   if (o->fuse_steps < 0 || o->fuse_steps > 4) return fail(FED_E_ARG, "fuse_steps must be in 0..4");
   if (o->block_threads != 0 &&
-      (o->block_threads < 64 || o->block_threads > 512 || o->block_threads % 64))
-    return fail(FED_E_ARG, "block_threads must be a multiple of 64 in [64, 512]");
+      (o->block_threads < 64 || o->block_threads > 1024 || o->block_threads % 64))
+    return fail(FED_E_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
+  if (o->fuse_steps > 1 && o->block_threads > 512)
+    return fail(FED_E_ARG, "block_threads must be <= 512 when fuse_steps > 1");
+  if (o->resident != 0 && o->resident != 1) return fail(FED_E_ARG, "resident must be 0 or 1");
+  if (o->resident && o->fuse_steps > 1) return fail(FED_E_ARG, "resident stepping needs fuse_steps <= 1");
+  return FED_OK;
+}
+
+// Exported nodes and exchange buffers of resident stepping; checks that every
+// tile fits the kernel's registers and that all tiles are resident at once.
+// *exch receives the bytes one step moves through memory.
+int setup_resident(fed_ctx *c, int n_cu, double *exch) {
+  const fed::Tiling &T = c->til;
+  const int64_t N = c->N;
+  const fed::ResCaps cap = fed::resident_caps(c->prec, c->ne);
+  for (int32_t t = 0; t < T.nt; t++) {
+    const fed::TileHdr &th = T.tiles[t];
+    const int nE = th.cum_e[0], nhalo = th.cum_n[1] - th.nown;
+    if (th.nown > cap.npt * c->block || nE > cap.ept * c->block || nhalo > cap.hpt * c->block)
+      return fail(FED_E_MESH,
+                  "resident stepping: tile %d (%d nodes, %d elements, %d halo nodes) exceeds the "
+                  "%d threads' registers (%d / %d / %d per thread); use more tiles or resident = 0",
+                  t, th.nown, nE, nhalo, c->block, cap.npt, cap.ept, cap.hpt);
+  }
+  std::vector<uint8_t> exported(N, 0);
+  int64_t halo_total = 0;
+  for (int32_t t = 0; t < T.nt; t++) {
+    const fed::TileHdr &th = T.tiles[t];
+    const int nhalo = th.cum_n[1] - th.nown;
+    halo_total += nhalo;
+    for (int j = 0; j < nhalo; j++) exported[T.halo[th.hstart + j]] = 1;
+  }
+  DevPool &P = c->pool;
+  HIPCHK(upload(P, &c->d_exported, exported.data(), exported.size()));
+  const int words = c->prec == FED_FP64 ? 2 : 1;
+  for (int i = 0; i < 2; i++) {
+    HIPCHK(P.alloc((void **)&c->d_X[i], sizeof(unsigned long long) * words * N));
+    HIPCHK(hipMemset(c->d_X[i], 0, sizeof(unsigned long long) * words * N));  // tag 0: never wanted
+  }
+  HIPCHK(P.alloc((void **)&c->d_rerr, sizeof(int)));
+  HIPCHK(hipMemset(c->d_rerr, 0, sizeof(int)));
+  // LDS of the resident kernel: T of the touched nodes, the slots of the owned
+  // nodes and the 5 boundary coefficients of the owned boundary nodes
+  int64_t lds = 0;
+  for (const fed::TileHdr &th : T.tiles)
+    lds = std::max<int64_t>(lds, (int64_t)c->rb * (th.cum_n[1] + (int64_t)T.maxinc * th.nown +
+                                                    5LL * th.nbnd) + 16);
+  if (lds > c->max_lds)
+    return fail(FED_E_MESH, "resident stepping: a tile needs %lld bytes of LDS (the GPU has %d)",
+                (long long)lds, c->max_lds);
+  c->res_lds = (int)lds;
+  int per_cu = 0;
+  fed::StepArgs a0 = c->step_args(0, 1);
+  a0.lds = c->res_lds;
+  HIPCHK(fed::resident_prepare(a0, &per_cu));
+  const int64_t grid = 8LL * c->nper;
+  if (per_cu < 1 || grid > (int64_t)per_cu * n_cu)
+    return fail(FED_E_MESH,
+                "resident stepping: %lld workgroups of %d threads and %d bytes of LDS, but the GPU "
+                "holds %d at once (%d per CU); use larger tiles, fewer threads or resident = 0",
+                (long long)grid, c->block, c->res_lds, per_cu * n_cu, per_cu);
+  int64_t nexp = 0;
+  for (uint8_t v : exported) nexp += v;
+  *exch = 8.0 * words * (double)(halo_total + nexp);  // tagged words read and written
   return FED_OK;
 }
 
@@ -295,7 +370,8 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   c->s1 = mt->materials[0].s1;
   c->tdk = c->s1 != 0.0;
   for (int i = 0; i < mt->n_materials; i++) c->tdc |= mt->materials[i].c1 != 0.0;
-  c->block = o->block_threads ? o->block_threads : 256;
+  c->resident = o->resident == 1;
+  c->block = o->block_threads ? o->block_threads : (c->resident ? 1024 : 256);
 
   // ---- host index work: boundary records, instances, tiling ---------------
   std::vector<uint8_t> has_bnd(N, 0);
@@ -326,6 +402,11 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
         if (o->node_instance[m->conn[(int64_t)a * E + e]] != o->node_instance[m->conn[e]])
           return fail(FED_E_ARG, "element %lld spans two instances", (long long)e);
   }
+  int dev = 0, n_cu = 1, max_lds = 64 * 1024;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  c->max_lds = max_lds;
   fed::TilingInput ti;
   ti.N = N;
   ti.E = E;
@@ -342,7 +423,28 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   ti.real_bytes = c->rb;
   // staged per updated node: alpha, beta, record id, and lo for FP32C
   ti.upd_bytes = 2 * c->rb + 4 + (c->prec == FED_FP32C ? 4 : 0);
-  std::string terr = fed::build_tiling(ti, c->til);
+  // resident stepping: one workgroup per CU for every 1024 threads a CU holds,
+  // tiles as large as the node count over that many workgroups; only T of the
+  // touched nodes and the slots live in LDS
+  const int res_per_cu = std::max(1, 1024 / c->block);
+  if (c->resident) {
+    const int64_t wgs = (int64_t)n_cu * res_per_cu;
+    if (!o->tile_nodes) ti.target_nodes = (int32_t)std::max<int64_t>(1, (N + wgs - 1) / wgs);
+    ti.depth = 1;
+    ti.lds_budget = max_lds;
+    ti.upd_bytes = 0;
+  }
+  std::string terr;
+  for (int attempt = 0;; attempt++) {
+    terr = fed::build_tiling(ti, c->til);
+    if (!terr.empty() || !c->resident || o->tile_nodes) break;
+    // resident: grow the tiles until the grid (tiles rounded up to whole XCD
+    // rounds) fits the resident workgroups; instances split separately can
+    // leave more tiles than the node count over the tile size
+    const int64_t wgs = (int64_t)n_cu * res_per_cu, grid = 8LL * ((c->til.nt + 7) / 8);
+    if (grid <= wgs || attempt >= 8) break;
+    ti.target_nodes = (int32_t)std::min<double>(1e9, ti.target_nodes * 1.05 * (double)grid / wgs + 1);
+  }
   if (!terr.empty()) return fail(FED_E_MESH, "tiling: %s", terr.c_str());
   fed::Tiling &T = c->til;
   c->Eexp = (int64_t)T.eorig.size();
@@ -466,7 +568,11 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
     HIPCHK(P.alloc((void **)&d_farea, sizeof(double) * nf));
     if (bc->face_eps)
       for (int64_t f = 0; f < nf; f++) c->has_rad |= bc->face_eps[f] > 0;
+    c->h_faces.assign(bc->faces, bc->faces + (size_t)nf * bc->face_nodes);
+    c->h_feps.assign(nf, 0.0);
+    if (bc->face_eps) c->h_feps.assign(bc->face_eps, bc->face_eps + nf);
   }
+  c->npt = bc->n_pt;
   if (bc->n_pt > 0) HIPCHK(upload(P, &d_ptW, bc->pt_W, (size_t)bc->n_pt));
   const int64_t nrec = c->nrec;
   if (nrec > 0) {
@@ -488,7 +594,8 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   c->d_recnode = d_recnode;
   for (int i = 0; i < 5; i++) c->d_b64[i] = b64[i];
   fed::BndArgs ba{nf, bc->face_nodes, d_faces, d_x, d_y, d_z, d_fh, d_fTa, d_feps, d_fq,
-                  d_farea, nrec, d_recptr, d_recitem, d_ptW, b64[0], b64[1], b64[2], b64[3]};
+                  d_farea, nrec, d_recptr, d_recitem, d_ptW, b64[0], b64[1], b64[2], b64[3],
+                  nullptr};
   HIPCHK(fed::launch_bnd(ba, s));
   // stability bound per instance (Sec. 3.4)
   int32_t *d_einst = nullptr, *d_ninst = nullptr;
@@ -573,7 +680,7 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   HIPCHK(P.alloc((void **)&c->d_flag, sizeof(int)));
   HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
   HIPCHK(P.alloc((void **)&c->d_Tuser, sizeof(double) * N));
-  if (T.lds_bytes > 64 * 1024)
+  if (T.lds_bytes > max_lds)
     return fail(FED_E_MESH, "tile needs %d bytes of LDS", T.lds_bytes);
   HIPCHK(fed::step_set_lds_limit(c->prec == FED_FP64 ? 1 : (c->prec == FED_FP32C ? 0 : 2), ne,
                                  c->tdk, c->tdc, std::max(T.lds_bytes, 1)));
@@ -581,8 +688,13 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   // nodes of the first ring, and the slots of the owned nodes
   for (const fed::TileHdr &th : T.tiles)
     c->adj_lds = std::max(c->adj_lds, rb * (3 * th.cum_n[1] + T.maxinc * th.nown));
-  if (c->adj_lds <= 64 * 1024)
+  if (c->adj_lds <= max_lds)
     HIPCHK(fed::adjoint_set_lds_limit(c->prec, ne, std::max(c->adj_lds, 1)));
+  double exch_bytes = 0;
+  if (c->resident) {
+    int rc2 = setup_resident(c.get(), n_cu, &exch_bytes);
+    if (rc2) return rc2;
+  }
   HIPCHK(hipStreamSynchronize(s));
   // ---- info -------------------------------------------------------------------
   fed_info &I = c->info;
@@ -606,6 +718,8 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   // every tile's copy of its elements, T (and lo) of its halo, the halo ids, the
   // coefficients of every node it updates, and the tile headers.
   I.fuse_steps = T.depth;
+  I.resident = c->resident ? 1 : 0;
+  I.exchange_bytes_per_step = exch_bytes;
   double elem_b = 2.0 * ne + 6.0 * rb;
   double lo_b = c->prec == FED_FP32C ? 4.0 : 0.0;
   double coef_b = rb + (c->tdc ? rb : 0.0);
@@ -655,6 +769,7 @@ int fed_set_temperature(fed_ctx *c, const double *T, int32_t on_device, void *st
   c->steps = 0;
   c->have_T = true;
   HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  if (c->resident) HIPCHK(hipMemsetAsync(c->d_rerr, 0, sizeof(int), s));
   if (c->ckpt_every > 0) {
     int rc = save_checkpoint(c, 0, s);
     if (rc) return rc;
@@ -669,6 +784,23 @@ namespace {
 
 // nsteps steps in launches of up to K steps, no checkpoint handling
 int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
+  if (c->resident) {
+    for (int64_t n = nsteps; n > 0;) {
+      const int k = (int)std::min<int64_t>(n, 1 << 30);
+      fed::StepArgs a = c->step_args(c->cur, 1);
+      a.lds = c->res_lds;
+      const int fin = c->cur ^ (k & 1);
+      fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
+                     c->d_T[fin], c->d_lo[fin]};
+      HIPCHK(fed::launch_resident(a, r, s));
+      // the launch wrote tags up to xtag + k: the next one starts beyond them
+      c->xtag += (unsigned)k + 1u;
+      c->cur = fin;
+      n -= k;
+    }
+    c->steps += nsteps;
+    return FED_OK;
+  }
   for (int64_t n = nsteps; n > 0;) {
     int k = (int)std::min<int64_t>(c->K, n);
     fed::StepArgs a = c->step_args(c->cur, k);
@@ -725,7 +857,8 @@ int fed_step_graph(fed_ctx *c, int64_t nsteps, int32_t graph_steps, void *stream
   if (!c) return fail(FED_E_ARG, "null ctx");
   if (!c->have_T) return fail(FED_E_STATE, "fed_set_temperature must come first");
   if (nsteps < 0 || graph_steps < 0) return fail(FED_E_ARG, "negative count");
-  if (c->ckpt_every > 0) return fed_step(c, nsteps, stream);  // checkpoints break launches
+  // checkpoints break launches; a resident launch already runs all the steps
+  if (c->ckpt_every > 0 || c->resident) return fed_step(c, nsteps, stream);
   hipStream_t s = (hipStream_t)stream;
   // an even number of K-step launches, so every replay starts on the same buffer
   int64_t want = graph_steps ? graph_steps : 100;
@@ -776,7 +909,12 @@ int fed_get_temperature(fed_ctx *c, double *T, int32_t on_device, void *stream) 
   if (!on_device)
     HIPCHK(hipMemcpyAsync(T, c->d_Tuser, sizeof(double) * c->N, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  int rerr = 0;
+  if (c->resident) HIPCHK(hipMemcpyAsync(&rerr, c->d_rerr, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (rerr)
+    return fail(FED_E_HIP, "resident stepping: a tile gave up waiting for a neighbouring tile; "
+                           "the temperatures are invalid");
   if (flag)
     return fail(FED_E_UNSTABLE,
                 "health check: a temperature is non-finite or outside [%g, %g] after %lld steps",
@@ -825,6 +963,7 @@ int fed_set_state(fed_ctx *c, const void *hi, const void *lo, int64_t step, void
   }
   HIPCHK(hipFreeAsync(tmp, s));
   HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  if (c->resident) HIPCHK(hipMemsetAsync(c->d_rerr, 0, sizeof(int), s));
   HIPCHK(hipStreamSynchronize(s));
   c->steps = step;
   c->have_T = true;
@@ -884,7 +1023,7 @@ int fed_set_params(fed_ctx *c, const double *kscale, const double *elem_c, const
   if (c->nrec > 0) {
     fed::BndArgs ba{0, c->nfn, c->d_faces, nullptr, nullptr, nullptr, c->d_fh, c->d_fTa,
                     c->d_feps, c->d_fq, c->d_farea, c->nrec, c->d_recptr, c->d_recitem,
-                    c->d_ptW, c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[3]};
+                    c->d_ptW, c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[3], nullptr};
     HIPCHK(fed::launch_bnd(ba, s));  // nf = 0: face areas are kept, records recomputed
   }
   HIPCHK(hipMemsetAsync(c->d_lam, 0, sizeof(unsigned long long) * 2 * c->ninst, s));
@@ -915,14 +1054,61 @@ int fed_set_params(fed_ctx *c, const double *kscale, const double *elem_c, const
   return FED_OK;
 }
 
+int fed_set_bc(fed_ctx *c, const double *face_Ta, const double *face_q, const double *pt_W,
+               int32_t on_device, void *stream) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  if ((face_Ta || face_q) && c->nf == 0) return fail(FED_E_ARG, "the problem has no faces");
+  if (pt_W && c->npt == 0) return fail(FED_E_ARG, "the problem has no point loads");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nf = c->nf;
+  if (!on_device) {
+    for (int64_t f = 0; f < nf; f++) {
+      if (face_Ta && !std::isfinite(face_Ta[f])) return fail(FED_E_ARG, "face_Ta[%lld] invalid", (long long)f);
+      if (face_q && !std::isfinite(face_q[f])) return fail(FED_E_ARG, "face_q[%lld] invalid", (long long)f);
+    }
+    for (int64_t i = 0; pt_W && i < c->npt; i++)
+      if (!std::isfinite(pt_W[i])) return fail(FED_E_ARG, "pt_W[%lld] invalid", (long long)i);
+    if (face_Ta && c->has_rad) {
+      // radiating faces that share a node must share Ta (one radiation ambient per node)
+      std::vector<double> ta(c->N, 0.0);
+      std::vector<uint8_t> set(c->N, 0);
+      for (int64_t f = 0; f < nf; f++) {
+        if (!(c->h_feps[f] > 0)) continue;
+        for (int b = 0; b < c->nfn; b++) {
+          const int32_t k = c->h_faces[f * c->nfn + b];
+          if (set[k] && ta[k] != face_Ta[f])
+            return fail(FED_E_ARG, "radiating faces at node %d have different Ta", k);
+          set[k] = 1;
+          ta[k] = face_Ta[f];
+        }
+      }
+    }
+  }
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (face_Ta) HIPCHK(hipMemcpyAsync(c->d_fTa, face_Ta, sizeof(double) * nf, kind, s));
+  if (face_q) HIPCHK(hipMemcpyAsync(c->d_fq, face_q, sizeof(double) * nf, kind, s));
+  if (pt_W) HIPCHK(hipMemcpyAsync(c->d_ptW, pt_W, sizeof(double) * c->npt, kind, s));
+  if (c->nrec > 0 && (face_Ta || face_q || pt_W)) {
+    fed::BndArgs ba{0, c->nfn, c->d_faces, nullptr, nullptr, nullptr, c->d_fh, c->d_fTa,
+                    c->d_feps, c->d_fq, c->d_farea, c->nrec, c->d_recptr, c->d_recitem,
+                    c->d_ptW, c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[3], c->d_b64[4]};
+    HIPCHK(fed::launch_bnd(ba, s));
+    fed::NodeArrArgs na{c->prec, c->N, c->nrec, c->d_M0, c->d_M1, c->d_dtinst, c->d_ninst,
+                        c->d_isdir, c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[4],
+                        c->d_b64[3], c->d_alpha, c->d_beta, c->d_rA, c->d_rAT, c->d_reA,
+                        c->d_rTa, c->d_rP};
+    HIPCHK(fed::launch_node_arrays(na, s));
+  }
+  if (!on_device) HIPCHK(hipStreamSynchronize(s));  // the host arrays may be reused
+  return FED_OK;
+}
+
 int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, double *g_h,
                  double *dL_dT0, int32_t on_device, void *stream) {
   if (!c || !dL_dT) return fail(FED_E_ARG, "null argument");
   if (!c->have_T) return fail(FED_E_STATE, "no forward run");
   if (c->ckpt_every <= 0) return fail(FED_E_STATE, "checkpointing is off (fed_checkpoint_every)");
-  if (c->tdk || c->tdc || c->has_rad)
-    return fail(FED_E_ARG, "the adjoint covers problems linear in T (s1 = 0, c1 = 0, no radiation)");
-  if (c->adj_lds > 64 * 1024)
+  if (c->adj_lds > c->max_lds)
     return fail(FED_E_MESH, "adjoint tiles need %d bytes of LDS; use smaller tile_nodes", c->adj_lds);
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = c->N, E = c->E, ck = c->ckpt_every, steps = c->steps;
@@ -1015,6 +1201,12 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       a.S0 = c->d_S0;
       a.S1 = c->d_S1;
       a.s0 = c->s0;
+      a.tdk = c->tdk;
+      a.tdc = c->tdc;
+      a.s1 = c->s1;
+      a.Tz = c->Tz;
+      a.beta = c->d_beta;
+      a.reA = c->d_reA;
       HIPCHK(fed::launch_adjoint(a, s));
       lc ^= 1;
     }

@@ -56,6 +56,8 @@ struct BndArgs {
   const int32_t *rec_item;
   const double *pt_W;
   double *bhA, *bhAT, *beA, *bP;
+  double *bTa;             // nullable: radiation ambient of the record (the Ta of
+                           // its first radiating face), recomputed when given
 };
 
 struct DtArgs {
@@ -130,6 +132,12 @@ struct AdjArgs {
   double *g_logk, *g_c;       // [E] caller element order
   double *S0, *S1;            // [nrec]: sum of mu and of mu T^n
   double s0;
+  // temperature dependence: D(T) = Dk (s0 + s1 Tbar) when tdk, capacity
+  // alpha + beta T when tdc, radiation sigma eps A per boundary record
+  int tdk, tdc;
+  double s1, Tz;
+  const void *beta;           // R[N]
+  const void *reA;            // R[nrec]
 };
 
 hipError_t launch_geom(const GeomArgs &a, hipStream_t s);
@@ -139,7 +147,33 @@ hipError_t launch_dt(const DtArgs &a, hipStream_t s);
 hipError_t launch_node_arrays(const NodeArrArgs &a, hipStream_t s);
 hipError_t launch_expand_H(int prec, int64_t Eexp, int64_t E, const int32_t *eorig,
                            const double *H0, const double *kscale, void *H, hipStream_t s);
+// Resident stepping: one cooperative launch advances nsteps steps.  Every tile
+// keeps its element operators and node coefficients in registers for the whole
+// launch.  The temperatures of exported nodes (those in another tile's halo)
+// are passed through two exchange buffers of tagged words: 64 bits holding the
+// step number and the value (FP32) or half of it (FP64, two words), so a
+// reader polls the data itself until it carries the step it needs.
+struct ResArgs {
+  int nsteps;
+  int spin_limit;             // polls of a halo word before the wait gives up
+  unsigned tag0;              // words written at step s carry tag0 + s + 1
+  const uint8_t *exported;    // per internal node: 1 if in another tile's halo
+  unsigned long long *X[2];   // exchange buffers, N (FP32) or 2 N (FP64) words each
+  int *err;                   // set to 1 when a wait gives up
+  void *Tfin;                 // final hi (the T buffer of parity cur ^ (nsteps & 1))
+  float *lofin;               // final lo (FP32C)
+};
+
+// register capacity of the resident kernel per thread (elements, nodes, halo ids)
+struct ResCaps {
+  int ept, npt, hpt;
+};
+ResCaps resident_caps(int prec, int ne);
 hipError_t launch_step(const StepArgs &a, hipStream_t s);
+hipError_t launch_resident(const StepArgs &a, const ResArgs &r, hipStream_t s);
+// LDS limit of the resident kernel; *blocks_per_cu receives how many of its
+// workgroups of a.block threads one CU holds at once
+hipError_t resident_prepare(const StepArgs &a, int *blocks_per_cu);
 hipError_t step_set_lds_limit(int prec, int ne, int tdk, int tdc, int bytes);
 hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s);
 hipError_t adjoint_set_lds_limit(int prec, int ne, int bytes);

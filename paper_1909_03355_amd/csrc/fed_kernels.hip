@@ -284,7 +284,8 @@ __global__ void k_face_area(BndArgs a) {
 __global__ void k_bnd_rec(BndArgs a) {
   int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= a.nrec) return;
-  double hA = 0, hAT = 0, eA = 0, P = 0;
+  double hA = 0, hAT = 0, eA = 0, P = 0, rTa = 0;
+  bool rad = false;
   for (int64_t p = a.rec_ptr[r]; p < a.rec_ptr[r + 1]; p++) {
     int32_t it = a.rec_item[p];
     if (it >= 0) {
@@ -295,6 +296,10 @@ __global__ void k_bnd_rec(BndArgs a) {
       hAT += h * s * Ta;
       eA += kSigma * eps * s;
       P += q * s;
+      if (eps > 0 && !rad) {
+        rad = true;
+        rTa = Ta;
+      }
     } else {
       P += a.pt_W[-(it + 1)];
     }
@@ -303,6 +308,7 @@ __global__ void k_bnd_rec(BndArgs a) {
   a.bhAT[r] = hAT;
   a.beA[r] = eA;
   a.bP[r] = P;
+  if (a.bTa) a.bTa[r] = rTa;
 }
 
 // Stability bound (Sec. 3.4): per element lambda_e = lambda_max(K_e(T)) / (rho c V /
@@ -793,15 +799,13 @@ __device__ inline float quotient<float>(float num, float den) {
 #endif
 }
 
+// Surface loads (Eq. 4, 5, 7) and the explicit update (Eq. 16) of one node with
+// temperature T (hi) and conductive load F: dT = (Q - F) / (alpha + beta T).
+// Returns the new hi; lo_new receives the new lo of the compensated mode.
 template <typename R, int MODE, bool TDC>
-__device__ inline void update1(const StepArgs &a, const TileHdr &th, int j, const Node1<R> &d,
-                               const R *Tl, const R *slot, R Tz) {
-  const int nown = th.nown, k = th.nstart + j;
-  R F = slot[j];
-  for (int p = 1; p < a.maxinc; p++) F += slot[p * nown + j];
-  const R T = Tl[j];
+__device__ inline R advance(const Node1<R> &d, bool bnd, R T, R F, R Tz, float &lo_new) {
   R Q = 0;
-  if (j < th.nbnd) {
+  if (bnd) {
     R x = T - Tz, y = d.bTa - Tz;
     // (T-Tz)^4 - (Ta-Tz)^4 in factored form
     Q = (d.bAT - d.bA * T) - d.beA * ((T - d.bTa) * (x + y) * (x * x + y * y)) + d.bP;
@@ -809,16 +813,35 @@ __device__ inline void update1(const StepArgs &a, const TileHdr &th, int j, cons
   R den = d.alpha;
   if (TDC) den += d.beta * T;
   const R dT = quotient<R>(Q - F, den);
-  R *Tout = (R *)a.Tout;
   if (MODE == 1) {
     // compensated accumulation: T = hi + lo, Fast2Sum of hi and (dT + lo)
     const float yv = (float)dT + d.lo;
     const float tv = (float)T + yv;
-    a.loout[k] = yv - (tv - (float)T);
-    Tout[k] = (R)tv;
-  } else {
-    Tout[k] = T + dT;
+    lo_new = yv - (tv - (float)T);
+    return (R)tv;
   }
+  lo_new = 0.0f;
+  return T + dT;
+}
+
+// conductive load of owned node j: its slots summed in position (= ascending
+// element) order
+template <typename R>
+__device__ inline R slot_sum(const R *slot, int j, int nown, int maxinc) {
+  R F = slot[j];
+  for (int p = 1; p < maxinc; p++) F += slot[p * nown + j];
+  return F;
+}
+
+template <typename R, int MODE, bool TDC>
+__device__ inline void update1(const StepArgs &a, const TileHdr &th, int j, const Node1<R> &d,
+                               const R *Tl, const R *slot, R Tz) {
+  const int k = th.nstart + j;
+  const R F = slot_sum(slot, j, th.nown, a.maxinc);
+  float lo_new;
+  const R hi = advance<R, MODE, TDC>(d, j < th.nbnd, Tl[j], F, Tz, lo_new);
+  ((R *)a.Tout)[k] = hi;
+  if (MODE == 1) a.loout[k] = lo_new;
 }
 
 template <typename R, int NE, int MODE, bool TDK, bool TDC>
@@ -927,13 +950,18 @@ hipError_t attr_dispatch_tt(int tdk, int tdc, int bytes) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint step.  The forward step of a T-independent problem is
-//   T^{n+1} = T^n + (Q(T^n) - K T^n) / alpha,  Q = hAT_a - hA T + P,
-// alpha = C / dt (= +inf on Dirichlet nodes).  With mu = lambda^{n+1} / alpha
-// its transpose is lambda^n = lambda^{n+1} - K mu - hA mu (K symmetric), and
-// the parameter derivatives accumulated over the steps are
-//   d/d log k_e : -mu_e . K_e T^n_e        (K_e proportional to k_e)
-//   d/d c_e     : -(rho V_e / n_e) sum_a mu_a (T^{n+1}_a - T^n_a) / dt_a
+// Adjoint step (not in the paper: the exact transpose of the explicit step).
+// The forward step of a node that is not Dirichlet is
+//   T' = T + (Q(T) - F(T)) / den,  den = alpha + beta T  (= C / dt),
+// F_e = s_e K0_e T_e with s_e = s0 + s1 Tbar_e, and Q holding convection
+// -hA (T - Ta), radiation -sigma eps A ((T - Tz)^4 - (Ta - Tz)^4) and fixed
+// inputs.  With mu = lambda^{n+1} / den (0 on Dirichlet nodes, den = +inf)
+// and dT = T^{n+1} - T^n its transpose is
+//   lambda^n_j = lambda_j - sum_{e owns j} [s_e (K0_e mu_e)_j + s1 / n_e (mu_e . K0_e T_e)]
+//              - mu_j (hA_j + 4 sigma eps A_j (T_j - Tz)^3) - mu_j beta_j dT_j,
+// (K0_e symmetric) and the parameter derivatives accumulated over the steps are
+//   d/d log k_e : -s_e mu_e . K0_e T^n_e
+//   d/d c_e     : -(rho V_e / n_e) sum_a mu_a dT_a / dt_a
 //   d/d h_f     : -|f|/n_f sum_{k in f} mu_k (T^n_k - Ta_f)  (via S0, S1)
 // The tile structure, the slot order of the nodal sums and the compensated
 // pair are those of the forward step.
@@ -978,12 +1006,15 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   R *Ld = LT + ntouch;
   R *slot = Ld + ntouch;
   const R *lam = (const R *)a.lamin, *alpha = (const R *)a.alpha, *rdt = (const R *)a.rdt;
+  const R *beta = (const R *)a.beta;
   const R *Tn = (const R *)a.Tn, *Tn1 = (const R *)a.Tn1;
+  const bool tdk = a.tdk != 0, tdc = a.tdc != 0;
   for (int j = tid; j < ntouch; j += bs) {
     const int g = j < nown ? th.nstart + j : a.halo[th.hstart + j - nown];
-    const R al = alpha[g];
-    Lmu[j] = lam[g] / al;  // 0 on Dirichlet nodes (alpha = +inf)
     const R tn = Tn[g];
+    R den = alpha[g];
+    if (tdc) den += beta[g] * tn;
+    Lmu[j] = lam[g] / den;  // 0 on Dirichlet nodes (alpha = +inf)
     LT[j] = tn;
     Ld[j] = (Tn1[g] - tn) * rdt[g];
   }
@@ -994,7 +1025,7 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
   const R *Hb = (const R *)a.H;
   const R *mV = (const R *)a.mV;
-  const R s0 = (R)a.s0;
+  const R s0 = (R)a.s0, s1 = (R)a.s1;
   const uint32_t pmask = (1u << a.pb) - 1u;
   for (int i = tid; i < nE; i += bs) {
     const int64_t e = (int64_t)th.estart + i;
@@ -1002,31 +1033,53 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
 #pragma unroll
     for (int r = 0; r < 6; r++) h[r] = Hb[(int64_t)r * a.Eexp + e];
     const EntT w = ent[e];
-    // K_e mu_e into the owned nodes' slots (the forward element load with mu)
-    element_to_slots<R, NE, false>(w, h, Lmu, slot, nown, nown, a.pb, pmask, s0, (R)0);
-    if (a.eowner[e]) {
-      uint32_t v[NE], loc[NE];
-      Ent<NE>::unpack(w, v);
+    uint32_t v[NE], loc[NE];
+    Ent<NE>::unpack(w, v);
 #pragma unroll
-      for (int n = 0; n < NE; n++) loc[n] = v[n] >> a.pb;
+    for (int n = 0; n < NE; n++) loc[n] = v[n] >> a.pb;
+    const bool owner = a.eowner[e] != 0;
+    // s_e at the element mean of T^n (summed as in the forward load)
+    R se = s0;
+    if (tdk) {
+      R sum;
+      if (NE == 8)
+        sum = ((LT[loc[0]] + LT[loc[1]]) + (LT[loc[2]] + LT[loc[3]])) +
+              ((LT[loc[4]] + LT[loc[5]]) + (LT[loc[6]] + LT[loc[7]]));
+      else
+        sum = (LT[loc[0]] + LT[loc[1]]) + (LT[loc[2]] + LT[loc[3]]);
+      se = s0 + s1 * (sum * ((R)1 / (R)NE));
+    }
+    // mu_e . K0_e T_e = (S mu)^T Hhat (S T)
+    R muKT = 0;
+    if (tdk || owner) {
       R mx, my, mz, tx, ty, tz;
       ElemAdj<R, NE>::u(Lmu, loc, mx, my, mz);
       ElemAdj<R, NE>::u(LT, loc, tx, ty, tz);
-      // mu_e . K_e T_e = s0 (S mu)^T Hhat (S T)
       const R qx = h[0] * tx + h[3] * ty + h[5] * tz;
       const R qy = h[3] * tx + h[1] * ty + h[4] * tz;
       const R qz = h[5] * tx + h[4] * ty + h[2] * tz;
-      const R gk = -s0 * (mx * qx + my * qy + mz * qz);
+      muKT = mx * qx + my * qy + mz * qz;
+    }
+    // s_e K0_e mu_e (the forward element load with mu at factor s_e), plus the
+    // k(Tbar) term spread evenly over the element's nodes
+    R F[NE];
+    Elem<R, NE>::load(Lmu, loc, se, (R)0, false, h, F);
+    const R spread = tdk ? s1 * ((R)1 / (R)NE) * muKT : (R)0;
+#pragma unroll
+    for (int n = 0; n < NE; n++)
+      if (loc[n] < (uint32_t)nown) slot[(v[n] & pmask) * nown + loc[n]] = F[n] + spread;
+    if (owner) {
       R gc = 0;
 #pragma unroll
       for (int n = 0; n < NE; n++) gc += Lmu[loc[n]] * Ld[loc[n]];
       const int32_t eo = a.eorig[e];
-      a.g_logk[eo] += (double)gk;
+      a.g_logk[eo] += -(double)se * (double)muKT;
       a.g_c[eo] += -(double)mV[eo] * (double)gc;
     }
   }
   __syncthreads();
-  const R *rA = (const R *)a.rA;
+  const R *rA = (const R *)a.rA, *reA = (const R *)a.reA;
+  const R Tz = (R)a.Tz;
   R *lout = (R *)a.lamout;
   for (int j = tid; j < nown; j += bs) {
     const int k = th.nstart + j;
@@ -1036,10 +1089,12 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
     R d = -F;
     if (j < th.nbnd) {
       const int r = th.bstart + j;
-      d -= rA[r] * mu;
+      const R x = LT[j] - Tz;
+      d -= (rA[r] + (R)4 * reA[r] * (x * x * x)) * mu;
       a.S0[r] += (double)mu;
       a.S1[r] += (double)mu * (double)LT[j];
     }
+    if (tdc) d -= beta[k] * (Tn1[k] - LT[j]) * mu;
     const bool fixed = alpha[k] == (R)INFINITY;
     if (MODE == 1) {
       const float hi = (float)lam[k], lo = a.lamloin[k];
@@ -1124,6 +1179,243 @@ __global__ void k_permute(int eb, int64_t N, const int32_t *perm, const unsigned
   const unsigned char *s = src + (to_internal ? k : ki) * eb;
   unsigned char *d = dst + (to_internal ? ki : k) * eb;
   for (int i = 0; i < eb; i++) d[i] = s[i];
+}
+
+// ---------------------------------------------------------------------------
+// Resident stepping.  One cooperative launch advances r.nsteps steps, with
+// every tile's workgroup resident for the whole launch.  A tile keeps its
+// elements' entries and operators and its nodes' coefficients and state in
+// registers, so a step reads from memory only the halo temperatures and
+// writes only the exported ones (owned nodes in another tile's halo).
+// Step s >= 1 reads the halo from exchange buffer X[s & 1], polling each word
+// until it carries tag0 + s; step s writes its exports, tagged tag0 + s + 1, to
+// X[(s + 1) & 1]; step 0 reads the halo from the state Tin.  A word a reader
+// finds with the tag it wants was written after the writer's tile had read
+// every value it needed from the reader's tile for the previous step (each
+// tile reads at least one value of every neighbour, and the relation is
+// symmetric: an element joins an owned node of each tile), so a buffer is
+// never overwritten while still in use and no flags or fences are needed.
+// Tags grow from launch to launch, so a stale word never matches.  The element
+// loads, the ordered nodal sums and the update are those of k_step1 on the
+// same tiles, so both give bitwise-identical temperatures.
+
+// register capacity per thread: elements, owned nodes, halo ids
+template <typename R, int NE>
+struct ResCap {
+  static constexpr int EPT = NE == 8 ? 2 : (sizeof(R) == 4 ? 8 : 4);
+  static constexpr int NPT = NE == 8 ? 2 : 1;
+  static constexpr int HPT = 2;
+};
+
+// Makes the packed entries opaque to the optimiser once per step, so it keeps
+// them packed in registers instead of hoisting their unpacked form (four times
+// the registers) out of the step loop.  Emits no instruction.
+__device__ inline void keep_packed(uint4 &w) {
+  uint32_t x = w.x, y = w.y, z = w.z, v = w.w;
+  asm volatile("" : "+v"(x), "+v"(y), "+v"(z), "+v"(v));
+  w = make_uint4(x, y, z, v);
+}
+__device__ inline void keep_packed(uint2 &w) {
+  uint32_t x = w.x, y = w.y;
+  asm volatile("" : "+v"(x), "+v"(y));
+  w = make_uint2(x, y);
+}
+
+// 64-bit loads and stores, single-copy atomic and coherent across the XCDs'
+// L2 caches
+__device__ inline unsigned long long ld_word(const unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_word(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long tagged(unsigned tag, uint32_t bits) {
+  return ((unsigned long long)tag << 32) | bits;
+}
+
+// tagged words of one value: 1 for float, 2 (low, high half) for double
+template <typename R>
+struct Words;
+template <>
+struct Words<float> {
+  static constexpr int W = 1;
+  __device__ static void put(unsigned long long *X, int k, unsigned tag, float v) {
+    st_word(X + k, tagged(tag, __float_as_uint(v)));
+  }
+  // true once the word carries `tag`; then v holds the value
+  __device__ static bool get(const unsigned long long *X, int k, unsigned tag, float &v) {
+    const unsigned long long w = ld_word(X + k);
+    v = __uint_as_float((uint32_t)w);
+    return (unsigned)(w >> 32) == tag;
+  }
+};
+template <>
+struct Words<double> {
+  static constexpr int W = 2;
+  __device__ static void put(unsigned long long *X, int k, unsigned tag, double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    st_word(X + 2 * (int64_t)k, tagged(tag, (uint32_t)b));
+    st_word(X + 2 * (int64_t)k + 1, tagged(tag, (uint32_t)(b >> 32)));
+  }
+  __device__ static bool get(const unsigned long long *X, int k, unsigned tag, double &v) {
+    const unsigned long long w0 = ld_word(X + 2 * (int64_t)k), w1 = ld_word(X + 2 * (int64_t)k + 1);
+    v = __longlong_as_double((long long)(((w1 & 0xffffffffull) << 32) | (w0 & 0xffffffffull)));
+    return (unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag;
+  }
+};
+
+template <typename R, int NE, int MODE, bool TDK, bool TDC>
+__global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
+  constexpr int EPT = ResCap<R, NE>::EPT, NPT = ResCap<R, NE>::NPT, HPT = ResCap<R, NE>::HPT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const int t = (b & 7) * a.nper + (b >> 3);
+  if (t >= a.nt) return;  // no tile: nobody reads from it
+  const TileHdr th = a.tiles[t];
+  const int nE = a.tiles[t].cum_e[0];
+  const int nhalo = a.tiles[t].cum_n[1] - th.nown;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int nown = th.nown, ntouch = nown + nhalo;
+  using EntT = typename Ent<NE>::T;
+  const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
+  const R *Hb = (const R *)a.H;
+  EntT ew[EPT];
+  R eh[EPT][6];
+#pragma unroll
+  for (int q = 0; q < EPT; q++) {
+    const int i = tid + q * bs;
+    if (i < nE) {
+      const int64_t e = (int64_t)th.estart + i;
+      ew[q] = ent[e];
+#pragma unroll
+      for (int c = 0; c < 6; c++) eh[q][c] = Hb[(int64_t)c * a.Eexp + e];
+    }
+  }
+  const R *Tin = (const R *)a.Tin;
+  // per owned node in registers: alpha, beta, lo, hi, exported; the boundary
+  // records (5 coefficients of the first nbnd nodes) live in LDS
+  R al[NPT], be[NPT], hi[NPT];
+  float lo[NPT];
+  bool ex[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; q++) {
+    const int j = tid + q * bs;
+    ex[q] = false;
+    if (j < nown) {
+      const int k = th.nstart + j;
+      al[q] = ((const R *)a.alpha)[k];
+      be[q] = TDC ? ((const R *)a.beta)[k] : (R)0;
+      lo[q] = MODE == 1 ? a.loin[k] : 0.0f;
+      hi[q] = Tin[k];
+      ex[q] = r.exported[k] != 0;
+    }
+  }
+  int hid[HPT];
+#pragma unroll
+  for (int q = 0; q < HPT; q++) {
+    const int j = tid + q * bs;
+    hid[q] = j < nhalo ? a.halo[th.hstart + j] : 0;
+  }
+  R *Tl = reinterpret_cast<R *>(smem_raw);
+  R *slot = Tl + ntouch;
+  R *Lbnd = slot + a.maxinc * nown;  // [5][nbnd]: hA, hA Ta, sigma eps A, radiation Ta, power
+  const int nbnd = th.nbnd;
+  for (int j = tid; j < nbnd; j += bs) {
+    const int rr = th.bstart + j;
+    Lbnd[j] = ((const R *)a.rA)[rr];
+    Lbnd[nbnd + j] = ((const R *)a.rAT)[rr];
+    Lbnd[2 * nbnd + j] = ((const R *)a.reA)[rr];
+    Lbnd[3 * nbnd + j] = ((const R *)a.rTa)[rr];
+    Lbnd[4 * nbnd + j] = ((const R *)a.rP)[rr];
+  }
+  // slots past a node's incidence are never written and stay zero
+  for (int j = tid; j < a.maxinc * nown; j += bs) slot[j] = (R)0;
+  const R s0 = (R)a.s0, s1 = (R)a.s1, Tz = (R)a.Tz;
+  const uint32_t pmask = (1u << a.pb) - 1u;
+  for (int s = 0; s < r.nsteps; s++) {
+    // ---- stage T: owned from registers, halo from the state or the exchange ----
+#pragma unroll
+    for (int q = 0; q < NPT; q++) {
+      const int j = tid + q * bs;
+      if (j < nown) Tl[j] = hi[q];
+    }
+    R hv[HPT];
+    if (s == 0) {
+#pragma unroll
+      for (int q = 0; q < HPT; q++) hv[q] = tid + q * bs < nhalo ? Tin[hid[q]] : (R)0;
+    } else {
+      const unsigned long long *X = r.X[s & 1];
+      const unsigned want = r.tag0 + (unsigned)s;
+      unsigned pending = 0;
+#pragma unroll
+      for (int q = 0; q < HPT; q++)
+        if (tid + q * bs < nhalo) pending |= 1u << q;
+      for (int it = 0; pending; it++) {
+#pragma unroll
+        for (int q = 0; q < HPT; q++)
+          if ((pending >> q) & 1u)
+            if (Words<R>::get(X, hid[q], want, hv[q])) pending &= ~(1u << q);
+        if (!pending) break;
+        if (it >= r.spin_limit || __hip_atomic_load(r.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          __hip_atomic_store(r.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < HPT; q++) {
+      const int j = tid + q * bs;
+      if (j < nhalo) Tl[nown + j] = hv[q];
+    }
+    __syncthreads();
+    // ---- element loads into the node-local slots ----
+#pragma unroll
+    for (int q = 0; q < EPT; q++)
+      if (tid + q * bs < nE) {
+        keep_packed(ew[q]);
+        element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, s0, s1);
+      }
+    __syncthreads();
+    // ---- per node: ordered sum, surface loads, explicit update, export ----
+    // (the next staging writes only Tl, which nothing reads after the barrier
+    // above; the next slot writes come after the next staging's barrier)
+    unsigned long long *Xw = r.X[(s + 1) & 1];
+    const unsigned tag = r.tag0 + (unsigned)s + 1u;
+#pragma unroll
+    for (int q = 0; q < NPT; q++) {
+      const int j = tid + q * bs;
+      if (j < nown) {
+        const R F = slot_sum(slot, j, nown, a.maxinc);
+        Node1<R> d;
+        d.alpha = al[q];
+        d.beta = be[q];
+        d.lo = lo[q];
+        const bool bnd = j < nbnd;
+        if (bnd) {
+          d.bA = Lbnd[j];
+          d.bAT = Lbnd[nbnd + j];
+          d.beA = Lbnd[2 * nbnd + j];
+          d.bTa = Lbnd[3 * nbnd + j];
+          d.bP = Lbnd[4 * nbnd + j];
+        }
+        float lo_new;
+        hi[q] = advance<R, MODE, TDC>(d, bnd, hi[q], F, Tz, lo_new);
+        lo[q] = lo_new;
+        if (ex[q]) Words<R>::put(Xw, th.nstart + j, tag, hi[q]);
+      }
+    }
+  }
+  // ---- final state of the owned nodes ----
+  R *Tf = (R *)r.Tfin;
+#pragma unroll
+  for (int q = 0; q < NPT; q++) {
+    const int j = tid + q * bs;
+    if (j < nown) {
+      Tf[th.nstart + j] = hi[q];
+      if (MODE == 1) r.lofin[th.nstart + j] = lo[q];
+    }
+  }
 }
 
 }  // namespace
@@ -1244,6 +1536,46 @@ hipError_t launch_permute(int elem_bytes, int64_t N, const int32_t *perm, const 
 }  // namespace fed
 
 namespace fed {
+
+template <typename R, int NE, int MODE, bool TDK, bool TDC>
+const void *resident_fn() {
+  return (const void *)k_resident<R, NE, MODE, TDK, TDC>;
+}
+
+template <typename R, int NE, int MODE>
+const void *resident_tt(int tdk, int tdc) {
+  if (tdk) return tdc ? resident_fn<R, NE, MODE, true, true>() : resident_fn<R, NE, MODE, true, false>();
+  return tdc ? resident_fn<R, NE, MODE, false, true>() : resident_fn<R, NE, MODE, false, false>();
+}
+
+const void *resident_kernel(const StepArgs &a) {
+  if (a.prec == 1) return a.ne == 8 ? resident_tt<double, 8, 0>(a.tdk, a.tdc) : resident_tt<double, 4, 0>(a.tdk, a.tdc);
+  if (a.prec == 0) return a.ne == 8 ? resident_tt<float, 8, 1>(a.tdk, a.tdc) : resident_tt<float, 4, 1>(a.tdk, a.tdc);
+  return a.ne == 8 ? resident_tt<float, 8, 0>(a.tdk, a.tdc) : resident_tt<float, 4, 0>(a.tdk, a.tdc);
+}
+
+ResCaps resident_caps(int prec, int ne) {
+  if (prec == 1)
+    return ne == 8 ? ResCaps{ResCap<double, 8>::EPT, ResCap<double, 8>::NPT, ResCap<double, 8>::HPT}
+                   : ResCaps{ResCap<double, 4>::EPT, ResCap<double, 4>::NPT, ResCap<double, 4>::HPT};
+  return ne == 8 ? ResCaps{ResCap<float, 8>::EPT, ResCap<float, 8>::NPT, ResCap<float, 8>::HPT}
+                 : ResCaps{ResCap<float, 4>::EPT, ResCap<float, 4>::NPT, ResCap<float, 4>::HPT};
+}
+
+hipError_t resident_prepare(const StepArgs &a, int *blocks_per_cu) {
+  const void *f = resident_kernel(a);
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, a.block, a.lds);
+}
+
+hipError_t launch_resident(const StepArgs &a, const ResArgs &r, hipStream_t s) {
+  StepArgs aa = a;
+  ResArgs rr = r;
+  void *args[] = {(void *)&aa, (void *)&rr};
+  return hipLaunchCooperativeKernel(resident_kernel(a), dim3(8 * a.nper), dim3(a.block), args,
+                                    (unsigned)a.lds, s);
+}
 
 hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s) {
   dim3 g(8 * a.nper), b(a.block);

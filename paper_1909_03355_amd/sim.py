@@ -34,7 +34,7 @@ def current_stream():
 
 class Simulation:
     def __init__(self, prob, prec="fp32c", tile_nodes=0, block_threads=0, fuse_steps=0,
-                 allow_unstable=False, stream=None):
+                 allow_unstable=False, stream=None, resident=False):
         lib = L.lib()
         self.prec = prec
         self.prob = prob
@@ -81,7 +81,7 @@ class Simulation:
         opt = L.fed_options(PRECISIONS[prec], dt, float(prob["safety"]), float(prob["T_lo"]),
                             float(prob["T_hi"]), int(bool(allow_unstable)),
                             _ptr(inst, C.c_int32), int(tile_nodes), int(block_threads),
-                            int(fuse_steps))
+                            int(fuse_steps), int(bool(resident)))
         self.stream = current_stream() if stream is None else stream
         ctx = C.c_void_p()
         L.check(lib.fed_create(C.byref(mesh), C.byref(mats), C.byref(bcs), C.byref(opt),
@@ -182,6 +182,19 @@ class Simulation:
         on_dev = dev.pop() if dev else 0
         L.check(L.lib().fed_set_params(self._c(), args[0][0], args[1][0], args[2][0], on_dev,
                                        self.stream))
+
+    def set_bc(self, face_Ta=None, face_q=None, pt_W=None):
+        """Time-varying boundary conditions: replace the per-face ambient
+        temperatures, heat fluxes and concentrated loads for the steps that
+        follow (numpy arrays, validated; or CUDA tensors, asynchronous)."""
+        args = [self._arg(a) for a in (face_Ta, face_q, pt_W)]
+        dev = {d for _, d, _ in args if d is not None}
+        if len(dev) > 1:
+            raise ValueError("pass all arrays on the host or all on the device")
+        on_dev = dev.pop() if dev else 0
+        L.check(L.lib().fed_set_bc(self._c(), args[0][0], args[1][0], args[2][0], on_dev,
+                                   self.stream))
+        self._keep_bc = args  # device tensors stay alive until the copies have run
 
     def backward(self, dL_dT):
         """Discrete adjoint of the steps taken: returns dict(logk, c, h, T0) of

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import Oracle
+from tests import helpers as H
 from workloads import mesh as M, problems as P
 
 pytestmark = pytest.mark.gpu
@@ -76,6 +77,49 @@ def test_adjoint_matches_oracle(case):
         errs = {"logk": rel(g["logk"], ref["g_logk"]), "c": rel(g["c"], ref["g_c"]),
                 "h": rel(g["h"], ref["g_h"]), "T0": rel(g["T0"], ref["lam0"])}
         print(case, prec, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        for k, v in errs.items():
+            assert v <= GTOL[prec], (prec, k, v)
+
+
+@pytest.mark.parametrize("elem", ["hex8", "tet4"])
+def test_nonlinear_adjoint_matches_oracle(elem):
+    """D(T), c(T) and radiation: every Jacobian term of the step, against the
+    oracle adjoint (itself pinned by central differences)."""
+    p = H.nonlinear_adjoint_problem(elem)
+    nsteps, ckpt = 40, 15
+    o = Oracle(p)
+    sens = np.arange(1, o.N, 3)
+    target = np.full(sens.size, 100.0)
+    hist = o.run(nsteps, history=True)
+    _, lam = _loss_grad(hist[-1], sens, target)
+    ref = o.adjoint(hist, lam)
+    for prec in ("fp64", "fp32c"):
+        _, _, g = _gpu_adjoint(p, prec, nsteps, ckpt, lambda T: _loss_grad(T, sens, target))
+        errs = {"logk": rel(g["logk"], ref["g_logk"]), "c": rel(g["c"], ref["g_c"]),
+                "h": rel(g["h"], ref["g_h"]), "T0": rel(g["T0"], ref["lam0"])}
+        print("nonlinear", elem, prec, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        for k, v in errs.items():
+            assert v <= GTOL[prec], (prec, k, v)
+
+
+def test_nonlinear_hex_workload_adjoint():
+    """The nonlinear hexahedral workload at 16^3 (orthotropic D(T), c(T),
+    convection, radiation on the top, flux patch), 300 steps, checkpoints every
+    64: gradients with respect to log k, c and h against the oracle."""
+    p = P.cube_nonlinear_hex(16, 300)
+    nsteps = 300
+    o = Oracle(p)
+    sens = np.random.default_rng(17).choice(o.N, 64, replace=False)
+    target = np.full(sens.size, 30.0)
+    hist = o.run(nsteps, history=True)
+    _, lam = _loss_grad(hist[-1], sens, target)
+    ref = o.adjoint(hist, lam)
+    del hist
+    for prec in ("fp64", "fp32c"):
+        _, _, g = _gpu_adjoint(p, prec, nsteps, 64, lambda T: _loss_grad(T, sens, target))
+        errs = {"logk": rel(g["logk"], ref["g_logk"]), "c": rel(g["c"], ref["g_c"]),
+                "h": rel(g["h"], ref["g_h"]), "T0": rel(g["T0"], ref["lam0"])}
+        print("nonlinear_hex16", prec, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
         for k, v in errs.items():
             assert v <= GTOL[prec], (prec, k, v)
 

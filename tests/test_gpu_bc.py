@@ -1,0 +1,118 @@
+"""Time-varying boundary conditions (fed_set_bc): ambient temperatures, fluxes
+and concentrated loads replaced between steps, against the oracle run through
+the same schedule (err_max <= 1e-12 FP64, <= 1e-5 compensated FP32)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from workloads import mesh as M, problems as P
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32c": 1e-5}
+
+
+def _sim(p, prec, **kw):
+    from paper_1909_03355_amd import Simulation
+    return Simulation(p, prec=prec, **kw)
+
+
+def _oracle_schedule(p, schedule):
+    """schedule: list of (problem overrides, steps); the oracle continues from
+    the previous temperatures with the new boundary data."""
+    T = Oracle(p).initial()
+    for over, n in schedule:
+        T = Oracle(dict(p, **over)).run(n, T0=T, apply_initial=False)
+    return T
+
+
+def test_step_change_of_ambient_and_flux():
+    p = P.cube_nonlinear_hex(8, 60)
+    Ta2 = p["face_Ta"] + 25.0                       # radiating faces keep a common Ta
+    q2 = 3.0 * p["face_q"] + np.where(p["face_eps"] > 0, 2000.0, 0.0)
+    ref = _oracle_schedule(p, [({}, 30), (dict(face_Ta=Ta2, face_q=q2), 30)])
+    for prec in ("fp64", "fp32c"):
+        out = []
+        for kw in (dict(), dict(resident=True)):
+            with _sim(p, prec, **kw) as s:
+                s.set_temperature()
+                s.step(30, graph_steps=10)
+                s.set_bc(face_Ta=Ta2, face_q=q2)
+                s.step(30, graph_steps=10)
+                out.append(s.temperature())
+        err = oracle.err_max(out[0], ref)
+        print(f"step change {prec}: err_max {err:.2e}", flush=True)
+        assert err <= TOL[prec]
+        assert np.array_equal(out[0], out[1])
+
+
+def test_moving_point_source():
+    """A 5 W source that moves one node per step along a line of nodes listed
+    at creation (all other listed loads zero)."""
+    n = 6
+    m = M.box_hex(n, n, n, 0.1, 0.1, 0.1)
+    p = P._base(m, "moving_source")
+    p["materials"] = [P.material(2700.0, 900.0, [200.0], c1=0.5)]
+    faces, _ = M.box_side_faces(m)
+    P.set_faces(p, faces, h=25.0, Ta=20.0)
+    line = np.nonzero(np.isclose(m["y"], 0.05) & np.isclose(m["z"], 0.05))[0]
+    line = line[np.argsort(m["x"][line])].astype(np.int32)
+    p["pt_nodes"], p["pt_W"] = line, np.zeros(line.size)
+    p["T0"] = np.full(m["x"].size, 20.0)
+    p["T_lo"], p["T_hi"] = 0.0, 200.0
+    nsteps = 2 * line.size
+    loads = [np.where(np.arange(line.size) == i % line.size, 5.0, 0.0) for i in range(nsteps)]
+    ref = _oracle_schedule(p, [(dict(pt_W=w), 1) for w in loads])
+    for prec in ("fp64", "fp32c"):
+        with _sim(p, prec) as s:
+            s.set_temperature()
+            for w in loads:
+                s.set_bc(pt_W=w)
+                s.step(1)
+            err = oracle.err_max(s.temperature(), ref)
+        print(f"moving source {prec}: err_max {err:.2e}", flush=True)
+        assert err <= TOL[prec]
+
+
+def test_device_arrays_match_host_arrays():
+    import torch
+    p = P.cube_nonlinear_hex(6, 20)
+    Ta2 = p["face_Ta"] - 10.0
+    q2 = 0.5 * p["face_q"]
+    out = []
+    for dev in (False, True):
+        with _sim(p, "fp32c") as s:
+            s.set_temperature()
+            s.step(10)
+            if dev:
+                s.set_bc(face_Ta=torch.tensor(Ta2, device="cuda"),
+                         face_q=torch.tensor(q2, device="cuda"))
+            else:
+                s.set_bc(face_Ta=Ta2, face_q=q2)
+            s.step(10)
+            out.append(s.temperature())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_set_bc_errors():
+    from paper_1909_03355_amd import FedError
+    from paper_1909_03355_amd import _lib as L
+    p = P.cube_nonlinear_hex(4, 10)
+    with _sim(p, "fp32c") as s:
+        bad = p["face_Ta"].copy()
+        top = np.nonzero(p["face_eps"] > 0)[0]
+        bad[top[0]] += 1.0              # one radiating face with its own Ta
+        with pytest.raises(FedError) as ei:
+            s.set_bc(face_Ta=bad)
+        assert ei.value.code == L.FED_E_ARG
+        with pytest.raises(FedError) as ei:
+            s.set_bc(pt_W=np.ones(3))   # the problem has no point loads
+        assert ei.value.code == L.FED_E_ARG
+        q = p["face_q"].copy()
+        q[0] = np.nan
+        with pytest.raises(FedError) as ei:
+            s.set_bc(face_q=q)
+        assert ei.value.code == L.FED_E_ARG

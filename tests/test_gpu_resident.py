@@ -1,0 +1,120 @@
+"""Resident stepping (one cooperative launch for all the steps of a call, each
+tile's elements and nodes held in registers, halo temperatures exchanged
+through memory with per-tile step flags) against the one-step-per-launch
+kernel (bitwise: same element loads, same ordered nodal sums, same update)
+and the FP64 oracle (err_max <= 1e-12 FP64, <= 1e-5 compensated FP32)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from workloads import problems as P
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32c": 1e-5}
+
+
+def _sim(p, prec, **kw):
+    from paper_1909_03355_amd import Simulation
+    return Simulation(p, prec=prec, **kw)
+
+
+def _run(p, prec, nsteps, graph_steps=None, **kw):
+    with _sim(p, prec, **kw) as s:
+        s.set_temperature()
+        s.step(nsteps, graph_steps=graph_steps)
+        return s.temperature(), dict(s.info)
+
+
+CASES = {
+    "nonlinear_hex12": lambda n: P.cube_nonlinear_hex(12, n),
+    "aniso_tet6": lambda n: P.cube_aniso_tet(6, n),
+    "batched6": lambda n: P.batched_hex(n_inst=6, lo=2, hi=7, nsteps=n),
+    "standin_td_dirichlet_points": lambda n: P.paper_standin(n=6, td=True, nsteps=n),
+    "plain_hex10": lambda n: P.cube_plain(10, n),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64", "fp32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_resident_bitwise_equals_launch_per_step(case, prec):
+    p = CASES[case](61)
+    print(f"resident {case} {prec}", flush=True)
+    base, _ = _run(p, prec, 61)
+    # default resident tiles (one per CU), and small tiles with 4 workgroups per CU
+    for kw in (dict(), dict(tile_nodes=40, block_threads=256)):
+        T, info = _run(p, prec, 61, resident=True, **kw)
+        assert info["resident"] == 1 and info["exchange_bytes_per_step"] > 0
+        assert np.array_equal(T, base), kw
+
+
+def test_resident_split_calls_graph_and_resume():
+    """Odd and even step counts per call (the final buffer alternates), a graph
+    request (served by resident launches), zero steps, and an exact resume."""
+    p = P.cube_nonlinear_hex(10, 50)
+    base, _ = _run(p, "fp32c", 50)
+    with _sim(p, "fp32c", resident=True) as s:
+        s.set_temperature()
+        s.step(17)
+        s.step(0)
+        s.step(3, graph_steps=2)
+        hi, lo, st = s.get_state()
+        s.step(20, graph_steps=10)
+        s.step(10)
+        assert s.steps_taken == 50
+        assert np.array_equal(s.temperature(), base)
+    with _sim(p, "fp32c", resident=True) as s:
+        s.set_state(hi, lo, st)
+        s.step(30)
+        assert np.array_equal(s.temperature(), base)
+
+
+def test_resident_adjoint_bitwise():
+    """fed_backward on a resident context (checkpoints break the resident
+    launches; the segments are recomputed one step per launch)."""
+    p = P.adjoint_hex(8, 40, n_sensors=16)
+    sens = p["meta"]["sensors"]
+    out = []
+    for res in (False, True):
+        with _sim(p, "fp32c", resident=res) as s:
+            s.checkpoint_every(15)
+            s.set_temperature()
+            s.step(40)
+            T = s.temperature()
+            lam = np.zeros(T.size)
+            lam[sens] = 2.0 * (T[sens] - 60.0) / sens.size
+            out.append((T, s.backward(lam)))
+    assert np.array_equal(out[0][0], out[1][0])
+    for k in out[0][1]:
+        assert np.array_equal(out[0][1][k], out[1][1][k]), k
+
+
+def test_resident_rejects_meshes_that_do_not_fit():
+    from paper_1909_03355_amd import FedError
+    from paper_1909_03355_amd import _lib as L
+    p = P.cube_nonlinear_hex(12, 10)
+    # one tile of 2197 nodes exceeds the registers of 256 threads
+    with pytest.raises(FedError) as ei:
+        _sim(p, "fp32c", resident=True, tile_nodes=4000, block_threads=256)
+    assert ei.value.code == L.FED_E_MESH
+    # K > 1 is not available in resident stepping
+    with pytest.raises(FedError) as ei:
+        _sim(p, "fp32c", resident=True, fuse_steps=2)
+    assert ei.value.code == L.FED_E_ARG
+
+
+def test_resident_hex64_full_size():
+    """The 64^3 workload, 200 steps, resident with the default tiles: bitwise
+    equal to the one-step kernel and within tolerance of the oracle."""
+    p = P.cube_nonlinear_hex(64, 200)
+    ref = Oracle(p).run(200)
+    for prec in ("fp64", "fp32c"):
+        T, info = _run(p, prec, 200, resident=True)
+        err = oracle.err_max(T, ref)
+        print(f"hex64 resident {prec}: tiles {info['n_tiles']} err_max {err:.3e}", flush=True)
+        assert err <= TOL[prec]
+        base, _ = _run(p, prec, 200, graph_steps=100)
+        assert np.array_equal(T, base)

@@ -213,6 +213,21 @@ int main(int argc, char **argv) {
   }
   REQUIRE(next == N);
   for (int64_t e = 0; e < E; e++) REQUIRE(owners[e] == 1);
+  // tiles whose first halo ring holds a node of tile u: the relation the
+  // resident step's neighbour waits are built from must be symmetric
+  std::vector<int32_t> owner_of(N);
+  for (int t = 0; t < T.nt; t++)
+    for (int j = 0; j < T.tiles[t].nown; j++) owner_of[T.tiles[t].nstart + j] = t;
+  std::set<std::pair<int32_t, int32_t>> rel;
+  for (int t = 0; t < T.nt; t++) {
+    const fed::TileHdr &th = T.tiles[t];
+    for (int h = 0; h < th.cum_n[1] - th.nown; h++) {
+      const int32_t u = owner_of[T.halo[th.hstart + h]];
+      REQUIRE(u != t);
+      rel.insert({t, u});
+    }
+  }
+  for (const auto &pr : rel) REQUIRE(rel.count({pr.second, pr.first}));
   std::printf("OK %d tiles, %zu expanded elements, maxinc %d, pb %d\n", T.nt, T.eorig.size(),
               T.maxinc, T.pb);
   return 0;
