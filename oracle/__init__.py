@@ -50,6 +50,8 @@ def lib():
         L = C.CDLL(path)
         L.orc_geometry.restype = C.c_int64
         L.orc_geometry.argtypes = [C.c_int, C.c_int64, _d, _d, _d, _i32, _d, _d, _d, _d]
+        L.orc_geometry_mean.restype = C.c_int64
+        L.orc_geometry_mean.argtypes = [C.c_int64, _d, _d, _d, _i32, _d, _d, _d, _d]
         L.orc_face_areas.restype = None
         L.orc_face_areas.argtypes = [C.c_int, C.c_int64, _d, _d, _d, _i32, _d]
         P = C.POINTER(_Problem)
@@ -86,8 +88,15 @@ class Oracle:
         self.W = np.zeros(self.E)
         self.V = np.zeros(self.E)
         self.detJ0 = np.zeros(self.E)
-        self.n_bad = L.orc_geometry(self.ne, self.E, _p(x), _p(y), _p(z), _p(conn, _i32),
-                                    _p(self.B), _p(self.W), _p(self.V), _p(self.detJ0))
+        # hexahedra: centre-point B (Eq. 17), or the element-mean gradient
+        # ("hex_gradient": "mean", the uniform-gradient hexahedron)
+        self.hex_gradient = prob.get("hex_gradient", "centre")
+        if self.ne == 8 and self.hex_gradient == "mean":
+            self.n_bad = L.orc_geometry_mean(self.E, _p(x), _p(y), _p(z), _p(conn, _i32),
+                                             _p(self.B), _p(self.W), _p(self.V), _p(self.detJ0))
+        else:
+            self.n_bad = L.orc_geometry(self.ne, self.E, _p(x), _p(y), _p(z), _p(conn, _i32),
+                                        _p(self.B), _p(self.W), _p(self.V), _p(self.detJ0))
         mats = prob["materials"]
         mid = prob["elem_material"]
         mid = np.zeros(self.E, np.int64) if mid is None else np.asarray(mid, np.int64)

@@ -181,6 +181,60 @@ int64_t orc_geometry(int ne, int64_t E, const double *x, const double *y,
   return bad;
 }
 
+/*
+ * Uniform-gradient (mean) hexahedron, an alternative to the centre point of
+ * Eq. 17 for distorted hexahedra: B_e is the gradient operator averaged over
+ * the element, Bbar = (1/V) integral of B dV, and W = V, so K_e = V Bbar^T D
+ * Bbar.  B det J is a polynomial of degree <= 3 in each natural coordinate
+ * (cofactors of J times the shape-function derivatives), so the 2x2x2 Gauss
+ * rule integrates it exactly.  By the divergence theorem Bbar reproduces any
+ * linear field exactly on every hexahedron.  Same outputs and return value as
+ * orc_geometry (hexahedra only).
+ */
+int64_t orc_geometry_mean(int64_t E, const double *x, const double *y, const double *z,
+                          const int32_t *conn, double *B, double *W, double *V, double *detJ0) {
+  int64_t bad = 0;
+  const double g = 1.0 / sqrt(3.0);
+  for (int64_t e = 0; e < E; e++) {
+    double X[8][3];
+    for (int a = 0; a < 8; a++) {
+      int32_t k = conn[(int64_t)a * E + e];
+      X[a][0] = x[k];
+      X[a][1] = y[k];
+      X[a][2] = z[k];
+    }
+    double dN0[8][3], J0[3][3];
+    const double zero[3] = {0, 0, 0};
+    hex_dN(zero, dN0);
+    hex_jac(X, dN0, J0);
+    detJ0[e] = det3(J0);
+    if (!(detJ0[e] > 0)) bad++;
+    double S[3][8] = {{0}}, vol = 0;
+    for (int q = 0; q < 8; q++) {
+      double p[3] = {HEX_S[q][0] * g, HEX_S[q][1] * g, HEX_S[q][2] * g};
+      double dN[8][3], J[3][3], Ji[3][3];
+      hex_dN(p, dN);
+      hex_jac(X, dN, J);
+      double d = det3(J);
+      if (!(d > 0)) bad++;
+      vol += d;
+      inv3(J, d == 0 ? 1.0 : d, Ji);
+      /* B det J at the point: B[i][a] = sum_j Ji[j][i] dN[a][j] */
+      for (int i = 0; i < 3; i++)
+        for (int a = 0; a < 8; a++) {
+          double t = 0;
+          for (int j = 0; j < 3; j++) t += Ji[j][i] * dN[a][j];
+          S[i][a] += t * d;
+        }
+    }
+    V[e] = vol;
+    W[e] = vol;
+    for (int i = 0; i < 3; i++)
+      for (int a = 0; a < 8; a++) B[(e * 3 + i) * 8 + a] = S[i][a] / (vol == 0 ? 1.0 : vol);
+  }
+  return bad;
+}
+
 /* Area of every boundary face: planar triangles by the cross product,
  * bilinear quadrilaterals by 2x2 Gauss quadrature of |x_u x x_v|. */
 void orc_face_areas(int nfn, int64_t nf, const double *x, const double *y,

@@ -232,6 +232,78 @@ def test_patch_distorted_hex_known_result():
 
 
 # ----------------------------------------------------------------------------
+# uniform-gradient (element-mean) hexahedron
+def _mean_gradient_numpy(X, order=4):
+    """(1/V) integral of the gradient operator over a trilinear hexahedron by
+    an order-4 Gauss rule, with J from the interpolant's derivatives at each
+    point (independent of the oracle's 2x2x2 rule); returns (Bbar 3x8, V)."""
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    S = M.HEX_SIGNS.astype(float)
+    acc, vol = np.zeros((3, 8)), 0.0
+    for a_, wa in zip(xg, wg):
+        for b_, wb in zip(xg, wg):
+            for c_, wc in zip(xg, wg):
+                p = np.array([a_, b_, c_])
+                dN = np.empty((8, 3))
+                for j in range(3):
+                    others = [k for k in range(3) if k != j]
+                    dN[:, j] = S[:, j] * np.prod(1.0 + S[:, others] * p[others], axis=1) / 8.0
+                J = X.T @ dN
+                d = np.linalg.det(J)
+                acc += wa * wb * wc * d * np.linalg.solve(J.T, dN.T)
+                vol += wa * wb * wc * d
+    return acc / vol, vol
+
+
+def test_mean_gradient_hex_against_higher_order_quadrature():
+    """The oracle's element-mean gradient (exact 2x2x2 rule) equals an
+    order-4 Gauss integration of the gradient operator on distorted
+    hexahedra, and satisfies sum_a b_a = 0, sum_a b_a x_a^T = I."""
+    for seed in range(4):
+        X = H.distorted_hex(seed, amp=0.2)
+        p = H.single_element("hex8", X)
+        p["hex_gradient"] = "mean"
+        o = Oracle(p)
+        Bref, Vref = _mean_gradient_numpy(X)
+        B = o.B.reshape(3, 8)
+        assert np.max(np.abs(B - Bref)) < 1e-12 * np.max(np.abs(Bref))
+        assert abs(o.V[0] - Vref) < 1e-13 and abs(o.W[0] - Vref) < 1e-13
+        assert np.max(np.abs(B.sum(1))) < 1e-12
+        assert np.max(np.abs(B @ X - np.eye(3))) < 1e-12
+
+
+def test_mean_gradient_equals_centre_on_affine_grids():
+    """On parallelepipeds the gradient is constant, so the mean-gradient run
+    equals the centre-point run of Eq. 17 to rounding."""
+    n = 4
+    m = M.box_hex(n, n, n, 0.1, 0.1, 0.1)
+    A = np.array([[1.0, 0.3, 0.1], [0.0, 0.9, 0.2], [0.1, 0.0, 1.1]])
+    X = np.stack([m["x"], m["y"], m["z"]], 1) @ A.T
+    m = dict(m, x=X[:, 0].copy(), y=X[:, 1].copy(), z=X[:, 2].copy())
+    p = P._base(m, "affine_mean")
+    p["materials"] = [H.aniso_material(rho=1000.0, c0=900.0)]
+    p["T0"] = np.random.default_rng(2).uniform(0, 100, X.shape[0])
+    a = Oracle(p).run(50)
+    b = Oracle(dict(p, hex_gradient="mean")).run(50)
+    assert np.max(np.abs(a - b)) < 1e-11 * np.max(np.abs(a))
+
+
+def test_patch_distorted_hex_mean_gradient():
+    """Sec. 4.1's patch test on the distorted 7-hexahedron patch of Fig. 2(c),
+    which the centre-point hexahedron fails: the mean-gradient hexahedron
+    reproduces the linear field."""
+    x, y, z = M.patch_nodes(os.path.join(H.GOLDEN, "patch_nodes.txt"))
+    p = P._base(M.patch_hex(x, y, z), "patch_hex_mean")
+    p["materials"] = [P.material(1.0, 1.0, [1.0])]
+    p["hex_gradient"] = "mean"
+    lin = 200 * x + 100 * y + 200 * z
+    F, _ = Oracle(p).loads(lin)
+    assert np.max(np.abs(F[8:])) < 1e-10
+    o, T = _linear_patch(p, np.arange(8), lin)
+    assert np.max(np.abs(T - lin)) < 1e-9
+
+
+# ----------------------------------------------------------------------------
 # workload 1 reduces to 1-D FTCS at every step (exact identity)
 def test_cube_plain_equals_ftcs():
     p = P.cube_plain(10, 1000)
