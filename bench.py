@@ -27,19 +27,22 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
 KERNEL_SRC = os.path.join(ROOT, "paper_1909_03355_amd", "csrc", "fed_kernels.hip")
-# Memory traffic per launch of the dominant kernel in the default launch shape,
-# from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch), each scaled by what the counter reads for a copy kernel of known
-# size (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel source
-# with this SHA-1; any other source reports null.
-TRAFFIC = {"nonlinear_hex64": ("d47297f4a511c5e332595bdf3e2afea505b106a2", 23692184.0)}
+# Memory traffic of the dominant kernel in the default launch shape, from
+# rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by what the counter reads for a copy kernel of known size
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0): bytes per launch for a one-step kernel;
+# for resident stepping (one launch for all steps) bytes once per launch plus
+# bytes per step, from runs of two step counts.  Valid only for the kernel
+# source with this SHA-1; any other source reports null.
+#   workload -> (sha1, kernel, bytes per launch or once, bytes per step)
+TRAFFIC = {}
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
 
 WORKLOADS = {
     # name: (builder, default steps, oracle sample steps, description, default launch shape)
     "nonlinear_hex64": ("cube_nonlinear_hex", 10000, 200,
                         "0.1 m cube, 64^3 hex8, orthotropic D(T), c(T), convection+radiation+flux",
-                        dict()),
+                        dict(resident=True)),
     "aniso_tet128": ("cube_aniso_tet", 2000, 4,
                      "0.1 m cube, 128^3 x 6 Kuhn tet4, per-element SPD conductivity, c(T), "
                      "convection", dict(tile_nodes=1024, block_threads=512)),
@@ -48,7 +51,7 @@ WORKLOADS = {
                        dict(tile_nodes=1024, block_threads=512)),
     "adjoint_hex48": ("adjoint_hex", 2000, 100,
                       "48^3 hex8, log-normal k field, convection; forward + adjoint with "
-                      "checkpoints every 100 steps", dict()),
+                      "checkpoints every 100 steps", dict(resident=True)),
 }
 
 
@@ -172,9 +175,6 @@ def main():
     src_sha = hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
     default_shape = not (args.tile_nodes or args.block or args.fuse or args.autotune
                          or args.resident != "default")
-    traffic = None
-    if args.workload in TRAFFIC and default_shape and TRAFFIC[args.workload][0] == src_sha:
-        traffic = TRAFFIC[args.workload][1]
     r32 = res["fp32c"]
     t = r32["t"]
     info = r32["info"]
@@ -182,15 +182,21 @@ def main():
     resident = bool(info["resident"])
     if resident:
         # one launch runs all the timed steps: the tile data is loaded once, then
-        # every step moves only the halo exchange
+        # every step moves only the tagged halo exchange
         launches = 1
         alg = info["algorithmic_bytes_per_launch"] + steps * info["exchange_bytes_per_step"]
+        moved = info["moved_bytes_per_launch"] + steps * info["exchange_bytes_per_step"]
         kernel = "k_resident"
     else:
         launches = -(-steps // K)
         alg = info["algorithmic_bytes_per_launch"]
+        moved = info["moved_bytes_per_launch"]
         kernel = "k_step1" if K == 1 else "k_step"
     achieved = alg / (t / launches) / 1e9
+    traffic = None
+    tr = TRAFFIC.get(args.workload)
+    if tr and default_shape and tr[0] == src_sha and tr[1] == kernel:
+        traffic = tr[2] + (steps * tr[3] if resident else 0.0)
     line = {
         "metric": METRIC,
         "value": E * steps / t,
@@ -211,9 +217,28 @@ def main():
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": kernel, "us_per_launch": t / launches * 1e6,
                      "bytes_per_launch_algorithmic": alg,
-                     "bytes_per_launch_moved": info["moved_bytes_per_launch"]},
+                     "bytes_per_launch_moved": moved},
         "cpu_baseline": cpu,
     }
+    if resident and args.workload != "adjoint_hex48":
+        # the per-step working set of the method (every element operator and
+        # node state, once) processed per step, for comparison with the
+        # streaming kernel that moves it from memory every step
+        line["working_set_gbs_per_step"] = info["algorithmic_bytes_per_launch"] * steps / t / 1e9
+        # the one-step-per-launch kernel on the same problem, same run
+        kw1 = {k: v for k, v in kw.items() if k != "resident"}
+        sim = Simulation(prob, prec="fp32c", **kw1)
+        n1 = min(steps, 2000)
+        t1 = timed_steps(sim, n1, min(args.warmup, 200), args.graph_steps)
+        i1 = sim.info
+        sim.close()
+        a1 = i1["algorithmic_bytes_per_launch"] / (t1 / n1) / 1e9
+        line["streaming_kernel"] = {"kernel": "k_step1", "us_per_step": t1 / n1 * 1e6,
+                                    "steps": n1, "tiles": i1["n_tiles"],
+                                    "roofline_achieved_gbs": a1,
+                                    "roofline_frac": a1 / PEAK_HBM_GBS,
+                                    "resident_speedup": (t1 / n1) / (t / steps)}
+        log(f"streaming k_step1: {t1 / n1 * 1e6:.2f} us/step")
     if args.workload == "adjoint_hex48":
         line["roofline"] = None   # forward + adjoint mix, no single dominant kernel rate
         line["note"] = "value counts forward steps; time includes the adjoint pass"

@@ -72,7 +72,8 @@ typedef struct {
  * conductivity D(T) = k * (s0 + s1 T) with k the symmetric tensor
  * [xx, yy, zz, xy, yz, xz].  Orthotropic: zero off-diagonals; isotropic: equal
  * diagonals.  D is evaluated at the element's mean nodal temperature and c at the
- * node (Sec. 4.2.2).  s0 and s1 must be the same for every material. */
+ * node (Sec. 4.2.2).  Materials may differ in every field (different s0, s1
+ * cost 2 values per element and step, and rule out resident stepping). */
 typedef struct {
   double rho, c0, c1;
   double k[6];
@@ -86,6 +87,16 @@ typedef struct {
   const double *elem_k;            /* host, 6 * n_elems per-element k tensor (rows of
                                       length n_elems) replacing the material's, or NULL */
   const double *elem_kscale;       /* host, n_elems positive factors on D, or NULL */
+  /* Optional piecewise-linear multiplier tables shared by all materials
+   * (temperature-dependent properties given as tables, Sec. 4.2.2): n points
+   * (2..16, T strictly increasing, f > 0), linear between points and constant
+   * beyond the ends.  With a k table, D_e(T) = k_e * fk(Tbar) and every material
+   * must have s0 = 1, s1 = 0; with a c table, c_e(T) = c0_e * fc(T) and every
+   * material must have c1 = 0.  n = 0: no table. */
+  int32_t n_ktab;
+  const double *ktab_T, *ktab_f;   /* host, n_ktab each */
+  int32_t n_ctab;
+  const double *ctab_T, *ctab_f;   /* host, n_ctab each */
 } fed_materials;
 
 /* Boundary conditions (Sec. 2, Eq. 3-7).  Faces are lumped to their nodes with
@@ -131,6 +142,12 @@ typedef struct {
                                 memory.  Needs every tile resident at once (FED_E_MESH at
                                 fed_create if the mesh does not fit) and K = 1.  Results are
                                 bitwise identical to resident = 0 on the same tiles. */
+  int32_t hex_gradient;      /* hexahedra: 0 = gradient at the element centre (Eq. 17, the
+                                paper's one-point rule); 1 = uniform gradient (the mean of
+                                B over the element, W = V), which reproduces linear fields
+                                on distorted hexahedra (the patch test of Sec. 4.1); 27
+                                values per element instead of 6, one step per launch
+                                (fuse_steps <= 1, resident = 0).  Ignored for tetrahedra. */
 } fed_options;
 
 typedef struct fed_ctx fed_ctx;

@@ -36,7 +36,9 @@ class fed_material(C.Structure):
 
 class fed_materials(C.Structure):
     _fields_ = [("n_materials", C.c_int32), ("materials", C.POINTER(fed_material)),
-                ("elem_material", _i32), ("elem_k", _d), ("elem_kscale", _d)]
+                ("elem_material", _i32), ("elem_k", _d), ("elem_kscale", _d),
+                ("n_ktab", C.c_int32), ("ktab_T", _d), ("ktab_f", _d),
+                ("n_ctab", C.c_int32), ("ctab_T", _d), ("ctab_f", _d)]
 
 
 class fed_bcs(C.Structure):
@@ -51,7 +53,7 @@ class fed_options(C.Structure):
                 ("T_lo", C.c_double), ("T_hi", C.c_double), ("allow_unstable", C.c_int32),
                 ("node_instance", _i32), ("tile_nodes", C.c_int32),
                 ("block_threads", C.c_int32), ("fuse_steps", C.c_int32),
-                ("resident", C.c_int32)]
+                ("resident", C.c_int32), ("hex_gradient", C.c_int32)]
 
 
 class fed_info(C.Structure):

@@ -115,6 +115,14 @@ struct fed_ctx {
   float *d_seglo[2] = {nullptr, nullptr}, *d_lamlo[2] = {nullptr, nullptr};
   double *d_S0 = nullptr, *d_S1 = nullptr, *d_gk = nullptr, *d_gc = nullptr, *d_gh = nullptr;
   int adj_lds = 0, max_lds = 64 * 1024;
+  // conductivity/capacity laws: per-element (s0, s1) when the materials differ,
+  // shared multiplier tables (step precision) and their extremes on [T_lo, T_hi]
+  void *d_esk = nullptr, *d_ktab = nullptr, *d_ctab = nullptr;
+  int nkt = 0, nct = 0;
+  double fk_max = 1.0, fc_min = 1.0;
+  // element operator: 0 the folded 3x3 (6 values), 1 the uniform-gradient
+  // hexahedron (27 values)
+  int op = 0, hw = 6;
   // scalars
   double s0 = 1, s1 = 0, Tz = -273.15, T_lo = 0, T_hi = 0;
   int tdk = 0, tdc = 0, block = 256, nper = 1, K = 1;
@@ -162,6 +170,12 @@ struct fed_ctx {
     a.s0 = s0;
     a.s1 = s1;
     a.Tz = Tz;
+    a.esk = d_esk;
+    a.ktab = d_ktab;
+    a.ctab = d_ctab;
+    a.nkt = nkt;
+    a.nct = nct;
+    a.op = op;
     return a;
   }
 
@@ -216,12 +230,25 @@ int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, cons
       return fail(FED_E_ARG, "material %d: rho must be positive and values finite", i);
     for (int r = 0; r < 6; r++)
       if (!finite(q.k[r])) return fail(FED_E_ARG, "material %d: non-finite k", i);
-    if (q.s0 != mt->materials[0].s0 || q.s1 != mt->materials[0].s1)
-      return fail(FED_E_ARG, "all materials must share s0 and s1");
+    if (mt->n_ktab && (q.s0 != 1.0 || q.s1 != 0.0))
+      return fail(FED_E_ARG, "material %d: a k table needs s0 = 1 and s1 = 0", i);
+    if (mt->n_ctab && q.c1 != 0.0)
+      return fail(FED_E_ARG, "material %d: a c table needs c1 = 0", i);
     double clo = q.c0 + q.c1 * o->T_lo, chi = q.c0 + q.c1 * o->T_hi;
     double slo = q.s0 + q.s1 * o->T_lo, shi = q.s0 + q.s1 * o->T_hi;
     if (!(clo > 0 && chi > 0)) return fail(FED_E_ARG, "material %d: c(T) not positive on [T_lo, T_hi]", i);
     if (!(slo > 0 && shi > 0)) return fail(FED_E_ARG, "material %d: D(T) not positive on [T_lo, T_hi]", i);
+  }
+  for (int w = 0; w < 2; w++) {
+    const int32_t n = w ? mt->n_ctab : mt->n_ktab;
+    const double *tT = w ? mt->ctab_T : mt->ktab_T, *tf = w ? mt->ctab_f : mt->ktab_f;
+    if (n == 0) continue;
+    if (n < 2 || n > 16 || !tT || !tf)
+      return fail(FED_E_ARG, "%s table: need 2..16 points", w ? "c" : "k");
+    for (int i = 0; i < n; i++)
+      if (!finite(tT[i]) || !(tf[i] > 0) || !finite(tf[i]) || (i && !(tT[i] > tT[i - 1])))
+        return fail(FED_E_ARG, "%s table: T must increase strictly and f be positive and finite",
+                    w ? "c" : "k");
   }
   if (mt->elem_material)
     for (int64_t e = 0; e < m->n_elems; e++)
@@ -279,6 +306,10 @@ int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, cons
     return fail(FED_E_ARG, "block_threads must be <= 512 when fuse_steps > 1");
   if (o->resident != 0 && o->resident != 1) return fail(FED_E_ARG, "resident must be 0 or 1");
   if (o->resident && o->fuse_steps > 1) return fail(FED_E_ARG, "resident stepping needs fuse_steps <= 1");
+  if (o->hex_gradient != 0 && o->hex_gradient != 1) return fail(FED_E_ARG, "hex_gradient must be 0 or 1");
+  if (o->hex_gradient == 1 && m->elem == FED_HEX8 && (o->fuse_steps > 1 || o->resident))
+    return fail(FED_E_ARG, "the uniform-gradient hexahedron runs one step per launch "
+                           "(fuse_steps <= 1, resident = 0)");
   return FED_OK;
 }
 
@@ -368,9 +399,38 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   c->T_hi = o->T_hi;
   c->s0 = mt->materials[0].s0;
   c->s1 = mt->materials[0].s1;
-  c->tdk = c->s1 != 0.0;
-  for (int i = 0; i < mt->n_materials; i++) c->tdc |= mt->materials[i].c1 != 0.0;
+  bool mixed_k = false;
+  for (int i = 0; i < mt->n_materials; i++) {
+    c->tdk |= mt->materials[i].s1 != 0.0;
+    c->tdc |= mt->materials[i].c1 != 0.0;
+    mixed_k |= mt->materials[i].s0 != c->s0 || mt->materials[i].s1 != c->s1;
+  }
+  c->tdk |= mt->n_ktab > 0;
+  c->tdc |= mt->n_ctab > 0;
+  c->nkt = mt->n_ktab;
+  c->nct = mt->n_ctab;
+  // a table's extremes on [T_lo, T_hi] are at the ends or at breakpoints inside
+  auto table_extreme = [&](int n, const double *tT, const double *tf, bool want_max) {
+    auto at = [&](double T) {
+      if (T <= tT[0]) return tf[0];
+      if (T >= tT[n - 1]) return tf[n - 1];
+      int i = 1;
+      while (T > tT[i]) i++;
+      return tf[i - 1] + (T - tT[i - 1]) / (tT[i] - tT[i - 1]) * (tf[i] - tf[i - 1]);
+    };
+    double v = at(o->T_lo), w = at(o->T_hi);
+    double r = want_max ? std::max(v, w) : std::min(v, w);
+    for (int i = 0; i < n; i++)
+      if (tT[i] > o->T_lo && tT[i] < o->T_hi) r = want_max ? std::max(r, tf[i]) : std::min(r, tf[i]);
+    return r;
+  };
+  if (c->nkt) c->fk_max = table_extreme(c->nkt, mt->ktab_T, mt->ktab_f, true);
+  if (c->nct) c->fc_min = table_extreme(c->nct, mt->ctab_T, mt->ctab_f, false);
+  if (mixed_k && o->resident)
+    return fail(FED_E_ARG, "resident stepping needs materials that share s0 and s1");
   c->resident = o->resident == 1;
+  c->op = (ne == FED_HEX8 && o->hex_gradient == 1) ? 1 : 0;
+  c->hw = c->op ? 27 : 6;
   c->block = o->block_threads ? o->block_threads : (c->resident ? 1024 : 256);
 
   // ---- host index work: boundary records, instances, tiling ---------------
@@ -521,12 +581,12 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   HIPCHK(tmp.alloc((void **)&d_cnt, 2 * sizeof(int)));
   HIPCHK(hipMemsetAsync(d_cnt, 0, 2 * sizeof(int), s));
   double *d_lamgeo;
-  HIPCHK(P.alloc((void **)&c->d_H0, sizeof(double) * 6 * E));
+  HIPCHK(P.alloc((void **)&c->d_H0, sizeof(double) * c->hw * E));
   HIPCHK(P.alloc((void **)&c->d_V, sizeof(double) * E));
   HIPCHK(P.alloc((void **)&d_lamgeo, sizeof(double) * E));
   c->d_lamgeo = d_lamgeo;
   fed::GeomArgs ga{ne, E, d_x, d_y, d_z, d_conn, d_mats, d_emat, d_ek,
-                   c->d_H0, c->d_V, d_lamgeo, d_cnt, d_cnt + 1};
+                   c->d_H0, c->op, c->d_V, d_lamgeo, d_cnt, d_cnt + 1};
   HIPCHK(fed::launch_geom(ga, s));
   int cnt[2];
   HIPCHK(hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, s));
@@ -546,7 +606,7 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   HIPCHK(P.alloc((void **)&d_Cmin, sizeof(double) * N));
   c->d_Cmin = d_Cmin;
   fed::MassArgs ma{N, ne, d_incp, d_ince, d_mats, d_emat, nullptr, c->d_V, o->T_lo, o->T_hi,
-                   c->d_M0, c->d_M1, d_Cmin};
+                   c->d_M0, c->d_M1, d_Cmin, c->fc_min};
   HIPCHK(fed::launch_mass(ma, s));
   // boundary lumping
   int32_t *d_faces = nullptr, *d_recitem = nullptr, *d_recnode = nullptr;
@@ -612,7 +672,7 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   HIPCHK(hipMemsetAsync(d_lam, 0, sizeof(unsigned long long) * 2 * c->ninst, s));
   fed::DtArgs da{ne, E, nrec, d_lamgeo, c->d_kscale, d_mats, d_emat, nullptr, d_einst, d_recnode,
                  d_ninst, b64[0], b64[2], d_Cmin, o->T_lo, o->T_hi, bc->Tz, d_lam,
-                 d_lam + c->ninst};
+                 d_lam + c->ninst, c->fk_max, c->fc_min};
   HIPCHK(fed::launch_dt(da, s));
   std::vector<unsigned long long> lam(2 * c->ninst);
   HIPCHK(hipMemcpyAsync(lam.data(), d_lam, lam.size() * sizeof(unsigned long long),
@@ -658,9 +718,31 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   HIPCHK(fed::launch_node_arrays(na, s));
   HIPCHK(upload(P, &c->d_eorig, T.eorig.data(), T.eorig.size()));
   HIPCHK(upload(P, &c->d_eowner, T.eowner.data(), T.eowner.size()));
-  HIPCHK(P.alloc(&c->d_H, (size_t)rb * 6 * c->Eexp));
-  HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->Eexp, E, c->d_eorig, c->d_H0,
+  HIPCHK(P.alloc(&c->d_H, (size_t)rb * c->hw * c->Eexp));
+  HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->hw, c->op ? 21 : 0, c->Eexp, E,
+                              c->d_eorig, c->d_H0,
                               c->d_kscale, c->d_H, s));
+  if (mixed_k) {
+    HIPCHK(P.alloc(&c->d_esk, (size_t)rb * 2 * c->Eexp));
+    HIPCHK(fed::launch_expand_sk(c->prec == FED_FP64 ? 1 : 0, c->Eexp, c->d_eorig, d_mats, d_emat,
+                                 c->d_esk, s));
+  }
+  for (int w = 0; w < 2; w++) {
+    const int32_t n = w ? c->nct : c->nkt;
+    if (!n) continue;
+    const double *tT = w ? mt->ctab_T : mt->ktab_T, *tf = w ? mt->ctab_f : mt->ktab_f;
+    void **dst = w ? &c->d_ctab : &c->d_ktab;
+    if (rb == 8) {
+      std::vector<double> v(tT, tT + n);
+      v.insert(v.end(), tf, tf + n);
+      HIPCHK(upload(P, (double **)dst, v.data(), v.size()));
+    } else {
+      std::vector<float> v;
+      for (int i = 0; i < n; i++) v.push_back((float)tT[i]);
+      for (int i = 0; i < n; i++) v.push_back((float)tf[i]);
+      HIPCHK(upload(P, (float **)dst, v.data(), v.size()));
+    }
+  }
   HIPCHK(upload(P, &c->d_tiles, T.tiles.data(), T.tiles.size()));
   HIPCHK(upload(P, &c->d_ent, T.ent.data(), T.ent.size()));
   if (T.halo.empty()) T.halo.push_back(0);  // keep a valid (unused) device array
@@ -683,13 +765,14 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   if (T.lds_bytes > max_lds)
     return fail(FED_E_MESH, "tile needs %d bytes of LDS", T.lds_bytes);
   HIPCHK(fed::step_set_lds_limit(c->prec == FED_FP64 ? 1 : (c->prec == FED_FP32C ? 0 : 2), ne,
-                                 c->tdk, c->tdc, std::max(T.lds_bytes, 1)));
+                                 c->tdk, c->tdc, c->d_esk || c->d_ktab || c->d_ctab, c->op,
+                                 std::max(T.lds_bytes, 1)));
   // LDS of the adjoint step: mu, T^n and the scaled increment of the touched
   // nodes of the first ring, and the slots of the owned nodes
   for (const fed::TileHdr &th : T.tiles)
     c->adj_lds = std::max(c->adj_lds, rb * (3 * th.cum_n[1] + T.maxinc * th.nown));
   if (c->adj_lds <= max_lds)
-    HIPCHK(fed::adjoint_set_lds_limit(c->prec, ne, std::max(c->adj_lds, 1)));
+    HIPCHK(fed::adjoint_set_lds_limit(c->prec, ne, c->op, std::max(c->adj_lds, 1)));
   double exch_bytes = 0;
   if (c->resident) {
     int rc2 = setup_resident(c.get(), n_cu, &exch_bytes);
@@ -720,7 +803,7 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   I.fuse_steps = T.depth;
   I.resident = c->resident ? 1 : 0;
   I.exchange_bytes_per_step = exch_bytes;
-  double elem_b = 2.0 * ne + 6.0 * rb;
+  double elem_b = 2.0 * ne + c->hw * rb + (c->d_esk ? 2.0 * rb : 0.0);
   double lo_b = c->prec == FED_FP32C ? 4.0 : 0.0;
   double coef_b = rb + (c->tdc ? rb : 0.0);
   double node_b = 2.0 * rb + 2.0 * lo_b + coef_b;
@@ -791,7 +874,7 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
       a.lds = c->res_lds;
       const int fin = c->cur ^ (k & 1);
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
-                     c->d_T[fin], c->d_lo[fin]};
+                     c->d_T[fin], c->d_lo[fin], nullptr, 0};
       HIPCHK(fed::launch_resident(a, r, s));
       // the launch wrote tags up to xtag + k: the next one starts beyond them
       c->xtag += (unsigned)k + 1u;
@@ -1018,7 +1101,7 @@ int fed_set_params(fed_ctx *c, const double *kscale, const double *elem_c, const
   }
   if (face_h) HIPCHK(hipMemcpyAsync(c->d_fh, fh.data(), sizeof(double) * nf, hipMemcpyHostToDevice, s));
   fed::MassArgs ma{N, c->ne, c->d_incp, c->d_ince, c->d_mats, c->d_emat, c->d_ec0, c->d_V,
-                   c->T_lo, c->T_hi, c->d_M0, c->d_M1, c->d_Cmin};
+                   c->T_lo, c->T_hi, c->d_M0, c->d_M1, c->d_Cmin, c->fc_min};
   HIPCHK(fed::launch_mass(ma, s));
   if (c->nrec > 0) {
     fed::BndArgs ba{0, c->nfn, c->d_faces, nullptr, nullptr, nullptr, c->d_fh, c->d_fTa,
@@ -1029,7 +1112,7 @@ int fed_set_params(fed_ctx *c, const double *kscale, const double *elem_c, const
   HIPCHK(hipMemsetAsync(c->d_lam, 0, sizeof(unsigned long long) * 2 * c->ninst, s));
   fed::DtArgs da{c->ne, E, c->nrec, c->d_lamgeo, c->d_kscale, c->d_mats, c->d_emat, c->d_ec0,
                  c->d_einst, c->d_recnode, c->d_ninst, c->d_b64[0], c->d_b64[2], c->d_Cmin,
-                 c->T_lo, c->T_hi, c->Tz, c->d_lam, c->d_lam + c->ninst};
+                 c->T_lo, c->T_hi, c->Tz, c->d_lam, c->d_lam + c->ninst, c->fk_max, c->fc_min};
   HIPCHK(fed::launch_dt(da, s));
   std::vector<unsigned long long> lam(2 * c->ninst);
   HIPCHK(hipMemcpyAsync(lam.data(), c->d_lam, lam.size() * sizeof(unsigned long long),
@@ -1048,7 +1131,8 @@ int fed_set_params(fed_ctx *c, const double *kscale, const double *elem_c, const
                       c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[4], c->d_b64[3],
                       c->d_alpha, c->d_beta, c->d_rA, c->d_rAT, c->d_reA, c->d_rTa, c->d_rP};
   HIPCHK(fed::launch_node_arrays(na, s));
-  HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->Eexp, E, c->d_eorig, c->d_H0,
+  HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->hw, c->op ? 21 : 0, c->Eexp, E,
+                              c->d_eorig, c->d_H0,
                               c->d_kscale, c->d_H, s));
   HIPCHK(hipStreamSynchronize(s));
   return FED_OK;
@@ -1160,13 +1244,27 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
     if (c->prec == FED_FP32C)
       HIPCHK(hipMemcpyAsync(c->d_seglo[0], c->ck_lo[g], sizeof(float) * N,
                             hipMemcpyDeviceToDevice, s));
-    for (int64_t i = 0; i < n1 - n0; i++) {
+    if (c->resident && n1 > n0) {
+      // one resident launch recomputes the segment, storing every step's hi
+      const int k = (int)(n1 - n0);
       fed::StepArgs a = c->step_args(0, 1);
-      a.Tin = seg(i);
-      a.Tout = seg(i + 1);
-      a.loin = c->d_seglo[i & 1];
-      a.loout = c->d_seglo[(i + 1) & 1];
-      HIPCHK(fed::launch_step(a, s));
+      a.lds = c->res_lds;
+      a.Tin = seg(0);
+      a.loin = c->d_seglo[0];
+      a.Tout = seg(1);  // not used by the resident kernel
+      fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
+                     seg(k), c->d_seglo[k & 1], c->d_seg, N};
+      HIPCHK(fed::launch_resident(a, r, s));
+      c->xtag += (unsigned)k + 1u;
+    } else {
+      for (int64_t i = 0; i < n1 - n0; i++) {
+        fed::StepArgs a = c->step_args(0, 1);
+        a.Tin = seg(i);
+        a.Tout = seg(i + 1);
+        a.loin = c->d_seglo[i & 1];
+        a.loout = c->d_seglo[(i + 1) & 1];
+        HIPCHK(fed::launch_step(a, s));
+      }
     }
     // adjoint steps n1-1 .. n0
     for (int64_t n = n1 - 1; n >= n0; n--) {
@@ -1207,6 +1305,12 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       a.Tz = c->Tz;
       a.beta = c->d_beta;
       a.reA = c->d_reA;
+      a.esk = c->d_esk;
+      a.ktab = c->d_ktab;
+      a.ctab = c->d_ctab;
+      a.nkt = c->nkt;
+      a.nct = c->nct;
+      a.op = c->op;
       HIPCHK(fed::launch_adjoint(a, s));
       lc ^= 1;
     }

@@ -23,7 +23,10 @@ struct GeomArgs {
   const MatDev *mats;
   const int32_t *emat;     // nullable
   const double *ek;        // nullable, [6 * E]
-  double *H0;              // [6 * E] symmetric operator without per-element factor
+  double *H0;              // [W * E] element operator without per-element factor: W = 6
+                           // (folded 3x3), or 27 (uniform-gradient hexahedron: 21 mean
+                           // gradient values, then V D)
+  int hexmean;             // hexahedra: 1 = uniform gradient, 0 = centre point (Eq. 17)
   double *V;               // [E] exact volume
   double *lamgeo;          // [E] W / V * lambda_max(L^T B B^T L), k = L L^T
   int *nbad;               // inverted / degenerate element count
@@ -41,6 +44,7 @@ struct MassArgs {
   const double *V;
   double T_lo, T_hi;
   double *M0, *M1, *Cmin;  // internal node order
+  double fc_min;           // smallest value of the c table on [T_lo, T_hi] (1 without)
 };
 
 struct BndArgs {
@@ -73,6 +77,7 @@ struct DtArgs {
   const double *bhA, *beA, *Cmin;
   double T_lo, T_hi, Tz;
   unsigned long long *lamE, *lamB;  // per instance, bit patterns of positive doubles
+  double fk_max, fc_min;      // extremes of the D and c tables on [T_lo, T_hi] (1 without)
 };
 
 struct NodeArrArgs {
@@ -105,6 +110,11 @@ struct StepArgs {
   const void *alpha, *beta;
   const void *rA, *rAT, *reA, *rTa, *rP;
   double s0, s1, Tz;
+  // conductivity and capacity laws beyond the shared linear ones
+  const void *esk;            // nullable R[2][Eexp]: (s0, s1) of each expanded element
+  const void *ktab, *ctab;    // nullable R[2 n]: shared multiplier tables of D and c
+  int nkt, nct;
+  int op;                     // element operator: 0 folded 3x3, 1 uniform-gradient hexahedron
 };
 
 // One step of the discrete adjoint of the explicit update, for problems that are
@@ -138,6 +148,9 @@ struct AdjArgs {
   double s1, Tz;
   const void *beta;           // R[N]
   const void *reA;            // R[nrec]
+  const void *esk, *ktab, *ctab;  // as in StepArgs
+  int nkt, nct;
+  int op;
 };
 
 hipError_t launch_geom(const GeomArgs &a, hipStream_t s);
@@ -145,7 +158,12 @@ hipError_t launch_mass(const MassArgs &a, hipStream_t s);
 hipError_t launch_bnd(const BndArgs &a, hipStream_t s);
 hipError_t launch_dt(const DtArgs &a, hipStream_t s);
 hipError_t launch_node_arrays(const NodeArrArgs &a, hipStream_t s);
-hipError_t launch_expand_H(int prec, int64_t Eexp, int64_t E, const int32_t *eorig,
+// (s0, s1) of the material of every expanded element, in the step precision
+hipError_t launch_expand_sk(int prec, int64_t Eexp, const int32_t *eorig, const MatDev *mats,
+                            const int32_t *emat, void *esk, hipStream_t s);
+// H = H0 of each expanded element's original (W values), rows >= from scaled by
+// the element's conductivity factor
+hipError_t launch_expand_H(int prec, int W, int from, int64_t Eexp, int64_t E, const int32_t *eorig,
                            const double *H0, const double *kscale, void *H, hipStream_t s);
 // Resident stepping: one cooperative launch advances nsteps steps.  Every tile
 // keeps its element operators and node coefficients in registers for the whole
@@ -162,6 +180,9 @@ struct ResArgs {
   int *err;                   // set to 1 when a wait gives up
   void *Tfin;                 // final hi (the T buffer of parity cur ^ (nsteps & 1))
   float *lofin;               // final lo (FP32C)
+  void *seg;                  // nullable: hi after step s goes to seg + (s + 1) * N (the
+                              // adjoint's segment recompute)
+  int64_t segN;
 };
 
 // register capacity of the resident kernel per thread (elements, nodes, halo ids)
@@ -174,9 +195,9 @@ hipError_t launch_resident(const StepArgs &a, const ResArgs &r, hipStream_t s);
 // LDS limit of the resident kernel; *blocks_per_cu receives how many of its
 // workgroups of a.block threads one CU holds at once
 hipError_t resident_prepare(const StepArgs &a, int *blocks_per_cu);
-hipError_t step_set_lds_limit(int prec, int ne, int tdk, int tdc, int bytes);
+hipError_t step_set_lds_limit(int prec, int ne, int tdk, int tdc, int gen, int op, int bytes);
 hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s);
-hipError_t adjoint_set_lds_limit(int prec, int ne, int bytes);
+hipError_t adjoint_set_lds_limit(int prec, int ne, int op, int bytes);
 // g_h[f] = -|f|/n_f * sum over the face's nodes of (S1 - Ta_f S0)
 hipError_t launch_face_grad(int64_t nf, int nfn, const int32_t *faces, const int32_t *perm,
                             const int32_t *rec_of, const double *farea, const double *fTa,

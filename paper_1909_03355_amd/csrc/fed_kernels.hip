@@ -116,7 +116,7 @@ __global__ void k_geom(GeomArgs a) {
     det = det3(J);
     W = 8.0 * det;
     // exact volume of the trilinear map: 2x2x2 Gauss points, unit weights
-    const double g = 0.57735026918962576451;  // 1/sqrt(3)
+    const double g = 0.57735026918962576451;  // 1/sqrt(3), Gauss point of the 2-point rule
     V = 0;
     for (int qp = 0; qp < 8; qp++) {
       double p0 = kHexS[qp][0] * g, p1 = kHexS[qp][1] * g, p2 = kHexS[qp][2] * g;
@@ -140,13 +140,53 @@ __global__ void k_geom(GeomArgs a) {
       det = 1.0;
     }
     inverse3(J, det, Ji);
-    // B B^T = J^{-T} (sum_a s_a s_a^T / 64) J^{-1}, formed from the columns of B
-    for (int n = 0; n < 8; n++) {
-      double b[3];
-      for (int i = 0; i < 3; i++)
-        b[i] = (Ji[0][i] * kHexS[n][0] + Ji[1][i] * kHexS[n][1] + Ji[2][i] * kHexS[n][2]) / 8.0;
-      for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) M3[i][j] += b[i] * b[j];
+    if (a.hexmean) {
+      // uniform gradient: mean of B over the element, 2x2x2 Gauss of B det J
+      // (exact: a polynomial of degree <= 3 per natural coordinate), W = V
+      double S[8][3] = {};
+      for (int qp = 0; qp < 8; qp++) {
+        double p0 = kHexS[qp][0] * g, p1 = kHexS[qp][1] * g, p2 = kHexS[qp][2] * g;
+        double dN[8][3], Jq[3][3], Jqi[3][3];
+        for (int n = 0; n < 8; n++) {
+          double sx = kHexS[n][0], sy = kHexS[n][1], sz = kHexS[n][2];
+          dN[n][0] = sx * (1 + sy * p1) * (1 + sz * p2) / 8.0;
+          dN[n][1] = sy * (1 + sx * p0) * (1 + sz * p2) / 8.0;
+          dN[n][2] = sz * (1 + sx * p0) * (1 + sy * p1) / 8.0;
+        }
+        for (int i = 0; i < 3; i++)
+          for (int j = 0; j < 3; j++) {
+            double t = 0;
+            for (int n = 0; n < 8; n++) t += X[n][i] * dN[n][j];
+            Jq[i][j] = t;
+          }
+        double dq = det3(Jq);
+        if (!(dq > 0.0)) {
+          atomicAdd(a.nbad, 1);
+          dq = 1.0;
+        }
+        inverse3(Jq, dq, Jqi);
+        for (int n = 0; n < 8; n++)
+          for (int i = 0; i < 3; i++)
+            S[n][i] += (Jqi[0][i] * dN[n][0] + Jqi[1][i] * dN[n][1] + Jqi[2][i] * dN[n][2]) * dq;
+      }
+      W = V;
+      for (int n = 0; n < 8; n++) {
+        double b[3];
+        for (int i = 0; i < 3; i++) b[i] = S[n][i] / V;
+        if (n < 7)
+          for (int i = 0; i < 3; i++) a.H0[(int64_t)(3 * n + i) * a.E + e] = b[i];
+        for (int i = 0; i < 3; i++)
+          for (int j = 0; j < 3; j++) M3[i][j] += b[i] * b[j];
+      }
+    } else {
+      // B B^T = J^{-T} (sum_a s_a s_a^T / 64) J^{-1}, formed from the columns of B
+      for (int n = 0; n < 8; n++) {
+        double b[3];
+        for (int i = 0; i < 3; i++)
+          b[i] = (Ji[0][i] * kHexS[n][0] + Ji[1][i] * kHexS[n][1] + Ji[2][i] * kHexS[n][2]) / 8.0;
+        for (int i = 0; i < 3; i++)
+          for (int j = 0; j < 3; j++) M3[i][j] += b[i] * b[j];
+      }
     }
   } else {
     for (int i = 0; i < 3; i++)
@@ -182,12 +222,16 @@ __global__ void k_geom(GeomArgs a) {
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++)
       Hm[i][j] = c * (T1[i][0] * Ji[j][0] + T1[i][1] * Ji[j][1] + T1[i][2] * Ji[j][2]);
-  a.H0[0 * a.E + e] = Hm[0][0];
-  a.H0[1 * a.E + e] = Hm[1][1];
-  a.H0[2 * a.E + e] = Hm[2][2];
-  a.H0[3 * a.E + e] = 0.5 * (Hm[0][1] + Hm[1][0]);
-  a.H0[4 * a.E + e] = 0.5 * (Hm[1][2] + Hm[2][1]);
-  a.H0[5 * a.E + e] = 0.5 * (Hm[0][2] + Hm[2][0]);
+  if (ne == 8 && a.hexmean) {
+    for (int r = 0; r < 6; r++) a.H0[(int64_t)(21 + r) * a.E + e] = V * dk[r];
+  } else {
+    a.H0[0 * a.E + e] = Hm[0][0];
+    a.H0[1 * a.E + e] = Hm[1][1];
+    a.H0[2 * a.E + e] = Hm[2][2];
+    a.H0[3 * a.E + e] = 0.5 * (Hm[0][1] + Hm[1][0]);
+    a.H0[4 * a.E + e] = 0.5 * (Hm[1][2] + Hm[2][1]);
+    a.H0[5 * a.E + e] = 0.5 * (Hm[0][2] + Hm[2][0]);
+  }
   a.V[e] = V;
   // stability: lambda_max(K_e) = W lambda_max(L^T B B^T L) with D = L L^T (Cholesky)
   double l00 = dk[0];
@@ -229,7 +273,7 @@ __global__ void k_mass(MassArgs a) {
     double clo = c0 + mt.c1 * a.T_lo, chi = c0 + mt.c1 * a.T_hi;
     m0 += v * c0;
     m1 += v * mt.c1;
-    cm += v * (clo < chi ? clo : chi);
+    cm += v * (clo < chi ? clo : chi) * a.fc_min;
   }
   a.M0[k] = m0;
   a.M1[k] = m1;
@@ -327,7 +371,7 @@ __global__ void k_dt_elem(DtArgs a) {
     double slo = mt.s0 + mt.s1 * a.T_lo, shi = mt.s0 + mt.s1 * a.T_hi;
     const double c0 = a.ec0 ? a.ec0[e] : mt.c0;
     double clo = c0 + mt.c1 * a.T_lo, chi = c0 + mt.c1 * a.T_hi;
-    double smax_ = slo > shi ? slo : shi, cmin = clo < chi ? clo : chi;
+    double smax_ = (slo > shi ? slo : shi) * a.fk_max, cmin = (clo < chi ? clo : chi) * a.fc_min;
     double ks = a.kscale ? a.kscale[e] : 1.0;
     lam = a.ne * ks * smax_ * a.lamgeo[e] / (mt.rho * cmin);
     inst = a.elem_inst ? a.elem_inst[e] : 0;
@@ -414,13 +458,24 @@ __global__ void k_node_arrays(NodeArrArgs a) {
 }
 
 template <typename R>
-__global__ void k_expand_H(int64_t Eexp, int64_t E, const int32_t *eorig, const double *H0,
-                           const double *kscale, R *H) {
+__global__ void k_expand_sk(int64_t Eexp, const int32_t *eorig, const MatDev *mats,
+                            const int32_t *emat, R *esk) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= Eexp) return;
+  const MatDev &mt = mats[emat ? emat[eorig[i]] : 0];
+  esk[i] = (R)mt.s0;
+  esk[Eexp + i] = (R)mt.s1;
+}
+
+template <typename R>
+__global__ void k_expand_H(int W, int from, int64_t Eexp, int64_t E, const int32_t *eorig,
+                           const double *H0, const double *kscale, R *H) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= Eexp) return;
   int32_t e = eorig[i];
   double ks = kscale ? kscale[e] : 1.0;
-  for (int r = 0; r < 6; r++) H[(int64_t)r * Eexp + i] = (R)(H0[(int64_t)r * E + e] * ks);
+  for (int r = 0; r < W; r++)
+    H[(int64_t)r * Eexp + i] = (R)(r >= from ? H0[(int64_t)r * E + e] * ks : H0[(int64_t)r * E + e]);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,6 +483,43 @@ __global__ void k_expand_H(int64_t Eexp, int64_t E, const int32_t *eorig, const 
 // spatially adjacent tiles on one XCD (blocks are dealt to the 8 XCDs round
 // robin), so halo re-reads and the next step's re-reads of the same tiles hit
 // that XCD's L2.
+// Piecewise-linear table of n breakpoints T_i (increasing) followed by n
+// values, constant beyond its ends; slope receives the derivative (0 beyond
+// the ends, the left segment's at a breakpoint).
+template <typename R>
+__device__ inline R table_eval(const R *tab, int n, R T, R &slope) {
+#pragma clang fp contract(off)
+  if (!(T > tab[0])) {
+    slope = (R)0;
+    return tab[n];
+  }
+  if (!(T < tab[n - 1])) {
+    slope = (R)0;
+    return tab[2 * n - 1];
+  }
+  int i = 1;
+  while (T > tab[i]) i++;
+  const R h = tab[i] - tab[i - 1], df = tab[n + i] - tab[n + i - 1];
+  slope = df / h;
+  return fma((T - tab[i - 1]) / h, df, tab[n + i - 1]);
+}
+
+// Conductivity factor s(Tbar) of an element: s0 + s1 Tbar, or the shared
+// multiplier table when n > 0 (Sec. 4.2.2's temperature-dependent k)
+template <typename R>
+struct KLaw {
+  R s0, s1;
+  const R *tab;
+  int n;
+  __device__ R operator()(R Tbar) const {
+    if (n) {
+      R sl;
+      return table_eval(tab, n, Tbar, sl);
+    }
+    return fma(s1, Tbar, s0);
+  }
+};
+
 template <typename R, int NE>
 struct Elem;
 
@@ -435,15 +527,18 @@ template <typename R>
 struct Elem<R, 8> {
   // F_a = s_a . (s * Hhat u),  u = sum_b s_b T_b written as sums of edge
   // differences (each a difference of nearby values, so exact or nearly so).
-  __device__ static void load(const R *Tl, const uint32_t *loc, R s0, R s1, bool tdk,
+  __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
                               const R h[6], R F[8]) {
+    // rounding fixed by the source in every kernel that inlines this (no
+    // FMA contraction), so all step kernels agree bit for bit
+    #pragma clang fp contract(off)
     R T0 = Tl[loc[0]], T1 = Tl[loc[1]], T2 = Tl[loc[2]], T3 = Tl[loc[3]];
     R T4 = Tl[loc[4]], T5 = Tl[loc[5]], T6 = Tl[loc[6]], T7 = Tl[loc[7]];
     R ux = ((T1 - T0) + (T2 - T3)) + ((T5 - T4) + (T6 - T7));
     R uy = ((T3 - T0) + (T2 - T1)) + ((T7 - T4) + (T6 - T5));
     R uz = ((T4 - T0) + (T5 - T1)) + ((T6 - T2) + (T7 - T3));
-    R s = s0;
-    if (tdk) s = s0 + s1 * ((((T0 + T1) + (T2 + T3)) + ((T4 + T5) + (T6 + T7))) * (R)0.125);
+    R s = kl.s0;
+    if (tdk) s = kl((((T0 + T1) + (T2 + T3)) + ((T4 + T5) + (T6 + T7))) * (R)0.125);
     R qx = s * (h[0] * ux + h[3] * uy + h[5] * uz);
     R qy = s * (h[3] * ux + h[1] * uy + h[4] * uz);
     R qz = s * (h[5] * ux + h[4] * uy + h[2] * uz);
@@ -461,16 +556,73 @@ struct Elem<R, 8> {
 
 template <typename R>
 struct Elem<R, 4> {
-  __device__ static void load(const R *Tl, const uint32_t *loc, R s0, R s1, bool tdk,
+  __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
                               const R h[6], R F[4]) {
+    #pragma clang fp contract(off)
     R T0 = Tl[loc[0]], T1 = Tl[loc[1]], T2 = Tl[loc[2]], T3 = Tl[loc[3]];
     R d1 = T1 - T0, d2 = T2 - T0, d3 = T3 - T0;
-    R s = s0;
-    if (tdk) s = s0 + s1 * (((T0 + T1) + (T2 + T3)) * (R)0.25);
+    R s = kl.s0;
+    if (tdk) s = kl(((T0 + T1) + (T2 + T3)) * (R)0.25);
     F[1] = s * (h[0] * d1 + h[3] * d2 + h[5] * d3);
     F[2] = s * (h[3] * d1 + h[1] * d2 + h[4] * d3);
     F[3] = s * (h[5] * d1 + h[4] * d2 + h[2] * d3);
     F[0] = -((F[1] + F[2]) + F[3]);
+  }
+};
+
+// Uniform-gradient (element-mean) hexahedron: F_a = b_a . q with
+// q = s (V D) g and g = sum_b b_b T_b, where b_a are the columns of the mean
+// gradient operator (b_7 = -(b_0 + ... + b_6), so g = sum_{a<7} b_a (T_a - T_7)).
+// hb holds b_0..b_6 (21 values, b_a at 3a..3a+2) and V D (xx, yy, zz, xy, yz,
+// xz) with the per-element conductivity factor folded in.
+template <typename R>
+struct ElemMean {
+  __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
+                              const R hb[27], R F[8]) {
+    #pragma clang fp contract(off)
+    R T[8];
+#pragma unroll
+    for (int n = 0; n < 8; n++) T[n] = Tl[loc[n]];
+    R gx = 0, gy = 0, gz = 0;
+#pragma unroll
+    for (int n = 0; n < 7; n++) {
+      const R d = T[n] - T[7];
+      gx += hb[3 * n] * d;
+      gy += hb[3 * n + 1] * d;
+      gz += hb[3 * n + 2] * d;
+    }
+    R s = kl.s0;
+    if (tdk) s = kl((((T[0] + T[1]) + (T[2] + T[3])) + ((T[4] + T[5]) + (T[6] + T[7]))) * (R)0.125);
+    const R *vd = hb + 21;
+    const R qx = s * (vd[0] * gx + vd[3] * gy + vd[5] * gz);
+    const R qy = s * (vd[3] * gx + vd[1] * gy + vd[4] * gz);
+    const R qz = s * (vd[5] * gx + vd[4] * gy + vd[2] * gz);
+    R sum = 0;
+#pragma unroll
+    for (int n = 0; n < 7; n++) {
+      F[n] = (hb[3 * n] * qx + hb[3 * n + 1] * qy) + hb[3 * n + 2] * qz;
+      sum += F[n];
+    }
+    F[7] = -sum;
+  }
+};
+
+// element operator by kind: OP 0 the folded 3x3 operator of Eq. 17-22 (6
+// values), OP 1 the uniform-gradient hexahedron (27 values)
+template <typename R, int NE, int OP>
+struct Op {
+  static constexpr int W = 6;
+  __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
+                              const R *h, R *F) {
+    Elem<R, NE>::load(Tl, loc, kl, tdk, h, F);
+  }
+};
+template <typename R>
+struct Op<R, 8, 1> {
+  static constexpr int W = 27;
+  __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
+                              const R *h, R *F) {
+    ElemMean<R>::load(Tl, loc, kl, tdk, h, F);
   }
 };
 
@@ -496,19 +648,50 @@ struct Ent<4> {
 // element loads of one expanded element into the LDS slots of the nodes that
 // this sub-step updates (local index < nupd); slot (node j, position p) lives at
 // p * stride + j
-template <typename R, int NE, bool TDK>
-__device__ inline void element_to_slots(const typename Ent<NE>::T &w, const R h[6], const R *Tl,
+template <typename R, int NE, bool TDK, int OP = 0>
+__device__ inline void element_to_slots(const typename Ent<NE>::T &w, const R *h, const R *Tl,
                                         R *slot, int stride, int nupd, int pb, uint32_t pmask,
-                                        R s0, R s1) {
+                                        const KLaw<R> &kl) {
   uint32_t v[NE], loc[NE];
   Ent<NE>::unpack(w, v);
 #pragma unroll
   for (int n = 0; n < NE; n++) loc[n] = v[n] >> pb;
   R F[NE];
-  Elem<R, NE>::load(Tl, loc, s0, s1, TDK, h, F);
+  Op<R, NE, OP>::load(Tl, loc, kl, TDK, h, F);
 #pragma unroll
   for (int n = 0; n < NE; n++)
     if (loc[n] < (uint32_t)nupd) slot[(v[n] & pmask) * stride + loc[n]] = F[n];
+}
+
+// law of expanded element e: the shared one, or the element's material's
+// (s0, s1) when the materials differ in their k(T)
+template <bool GEN, typename R, typename Args>
+__device__ inline KLaw<R> elem_law(const Args &a, const KLaw<R> &kl, int64_t e) {
+  KLaw<R> k = kl;
+  if (GEN && a.esk) {
+    k.s0 = ((const R *)a.esk)[e];
+    k.s1 = ((const R *)a.esk)[a.Eexp + e];
+  }
+  return k;
+}
+
+// GEN: the kernel instance for tables and per-element laws; the others compile
+// the shared linear law only
+template <typename R, bool GEN>
+__device__ inline KLaw<R> step_law(const StepArgs &a) {
+  if (GEN) return KLaw<R>{(R)a.s0, (R)a.s1, (const R *)a.ktab, a.nkt};
+  return KLaw<R>{(R)a.s0, (R)a.s1, nullptr, 0};
+}
+
+// capacity denominator alpha + beta T, or alpha times the shared c table
+template <typename R>
+__device__ inline R cap_den(R alpha, R beta, R T, const R *ctab, int nct) {
+#pragma clang fp contract(off)
+  if (nct) {
+    R sl;
+    return alpha * table_eval(ctab, nct, T, sl);
+  }
+  return fma(beta, T, alpha);
 }
 
 // per-node coefficients of the update
@@ -541,7 +724,8 @@ __device__ inline void load_node(const StepArgs &a, const R *La, const R *Lb, co
 // Returns the new hi (and lo for the compensated mode).
 template <typename R, int MODE, bool TDC>
 __device__ inline R node_update(const NodeData<R> &d, int j, int maxinc, int stride, R T, float lo,
-                                const R *slot, R Tz, float &lo_new) {
+                                const R *slot, R Tz, const R *ctab, int nct, float &lo_new) {
+#pragma clang fp contract(off)
   // the slots are read eight at a time (independent LDS reads in flight), then
   // added in position order; positions past the node's incidence hold zeros
   R F = 0;
@@ -564,7 +748,7 @@ __device__ inline R node_update(const NodeData<R> &d, int j, int maxinc, int str
     Q = (d.bAT - d.bA * T) - d.beA * ((T - d.bTa) * (x + y) * (x * x + y * y)) + d.bP;
   }
   R den = d.alpha;
-  if (TDC) den += d.beta * T;
+  if (TDC) den = cap_den(d.alpha, d.beta, T, ctab, nct);
   const R dT = (Q - F) / den;
   if (MODE == 1) {
     // compensated accumulation: T = hi + lo, Fast2Sum of hi and (dT + lo)
@@ -582,10 +766,10 @@ constexpr int kMaxBlock = 512;
 // Element loads of elements [i0, i1) of the tile, EPT per thread at a time:
 // all entry and operator loads are issued before the first element is
 // evaluated.
-template <typename R, int NE, bool TDK, int EPT>
+template <typename R, int NE, bool TDK, bool GEN, int EPT>
 __device__ inline void elements_from_global(const StepArgs &a, const TileHdr &th, int i0, int i1,
                                             const R *Tl, R *slot, int stride, int nupd,
-                                            uint32_t pmask, R s0, R s1) {
+                                            uint32_t pmask, const KLaw<R> &kl) {
   using EntT = typename Ent<NE>::T;
   const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
   const R *Hb = (const R *)a.H;
@@ -606,7 +790,8 @@ __device__ inline void elements_from_global(const StepArgs &a, const TileHdr &th
 #pragma unroll
     for (int q = 0; q < EPT; q++)
       if (base + q * bs < i1)
-        element_to_slots<R, NE, TDK>(w[q], h[q], Tl, slot, stride, nupd, a.pb, pmask, s0, s1);
+        element_to_slots<R, NE, TDK>(w[q], h[q], Tl, slot, stride, nupd, a.pb, pmask,
+                                     elem_law<GEN>(a, kl, (int64_t)th.estart + base + q * bs));
   }
 }
 
@@ -617,7 +802,7 @@ __device__ inline void elements_from_global(const StepArgs &a, const TileHdr &th
 // all values at once, and per-node coefficients come from LDS.  EPT, SPT and
 // NPT are sized so that every variant fits 128 VGPRs (4 waves per SIMD)
 // without spilling.
-template <typename R, int NE, int MODE, bool TDK, bool TDC>
+template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_step(
     StepArgs a) {
   constexpr int EPT = NE == 8 ? (sizeof(R) == 4 ? 4 : 2) : (sizeof(R) == 4 ? 6 : 2);
@@ -699,7 +884,8 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
   const int nslot = a.maxinc * nU;
   for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
   __syncthreads();
-  const R s0 = (R)a.s0, s1 = (R)a.s1, Tz = (R)a.Tz;
+  const KLaw<R> kl = step_law<R, GEN>(a);
+  const R Tz = (R)a.Tz;
   const uint32_t pmask = (1u << a.pb) - 1u;
   R *Tout = (R *)a.Tout;
   // Sub-step s updates the nodes of level <= k - s from the elements whose
@@ -710,8 +896,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
     for (int q = 0; q < EPT; q++)
       if (tid + q * bs < nE1)
-        element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nU, nU1, a.pb, pmask, s0, s1);
-    elements_from_global<R, NE, TDK, EPT>(a, th, EPT * bs, nE1, Tl, slot, nU, nU1, pmask, s0, s1);
+        element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nU, nU1, a.pb, pmask,
+                                     elem_law<GEN>(a, kl, (int64_t)th.estart + tid + q * bs));
+    elements_from_global<R, NE, TDK, GEN, EPT>(a, th, EPT * bs, nE1, Tl, slot, nU, nU1, pmask, kl);
   }
   __syncthreads();
   for (int s = 1;; s++) {
@@ -733,7 +920,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
         const R T = Tl[j];
         const float lo = MODE == 1 ? Llo[j] : 0.0f;
         float lo_new;
-        const R Tn = node_update<R, MODE, TDC>(d[q], j, a.maxinc, nU, T, lo, slot, Tz, lo_new);
+        const R Tn = node_update<R, MODE, TDC>(d[q], j, a.maxinc, nU, T, lo, slot, Tz,
+                                               GEN ? (const R *)a.ctab : nullptr, GEN ? a.nct : 0,
+                                               lo_new);
         if (last) {
           Tout[th.nstart + j] = Tn;
           if (MODE == 1) a.loout[th.nstart + j] = lo_new;
@@ -746,7 +935,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
     if (last) break;
     __syncthreads();
     const int nUn = cum_n[k - s - 1], nEn = cum_e[k - s - 1];
-    elements_from_global<R, NE, TDK, EPT>(a, th, 0, nEn, Tl, slot, nU, nUn, pmask, s0, s1);
+    elements_from_global<R, NE, TDK, GEN, EPT>(a, th, 0, nEn, Tl, slot, nU, nUn, pmask, kl);
     __syncthreads();
   }
 }
@@ -803,7 +992,9 @@ __device__ inline float quotient<float>(float num, float den) {
 // temperature T (hi) and conductive load F: dT = (Q - F) / (alpha + beta T).
 // Returns the new hi; lo_new receives the new lo of the compensated mode.
 template <typename R, int MODE, bool TDC>
-__device__ inline R advance(const Node1<R> &d, bool bnd, R T, R F, R Tz, float &lo_new) {
+__device__ inline R advance(const Node1<R> &d, bool bnd, R T, R F, R Tz, const R *ctab, int nct,
+                           float &lo_new) {
+#pragma clang fp contract(off)
   R Q = 0;
   if (bnd) {
     R x = T - Tz, y = d.bTa - Tz;
@@ -811,7 +1002,7 @@ __device__ inline R advance(const Node1<R> &d, bool bnd, R T, R F, R Tz, float &
     Q = (d.bAT - d.bA * T) - d.beA * ((T - d.bTa) * (x + y) * (x * x + y * y)) + d.bP;
   }
   R den = d.alpha;
-  if (TDC) den += d.beta * T;
+  if (TDC) den = cap_den(d.alpha, d.beta, T, ctab, nct);
   const R dT = quotient<R>(Q - F, den);
   if (MODE == 1) {
     // compensated accumulation: T = hi + lo, Fast2Sum of hi and (dT + lo)
@@ -833,21 +1024,24 @@ __device__ inline R slot_sum(const R *slot, int j, int nown, int maxinc) {
   return F;
 }
 
-template <typename R, int MODE, bool TDC>
+template <typename R, int MODE, bool TDC, bool GEN>
 __device__ inline void update1(const StepArgs &a, const TileHdr &th, int j, const Node1<R> &d,
                                const R *Tl, const R *slot, R Tz) {
   const int k = th.nstart + j;
   const R F = slot_sum(slot, j, th.nown, a.maxinc);
   float lo_new;
-  const R hi = advance<R, MODE, TDC>(d, j < th.nbnd, Tl[j], F, Tz, lo_new);
+  const R hi = advance<R, MODE, TDC>(d, j < th.nbnd, Tl[j], F, Tz, GEN ? (const R *)a.ctab : nullptr,
+                                     GEN ? a.nct : 0, lo_new);
   ((R *)a.Tout)[k] = hi;
   if (MODE == 1) a.loout[k] = lo_new;
 }
 
-template <typename R, int NE, int MODE, bool TDK, bool TDC>
+template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN, int OP = 0>
 __global__ __launch_bounds__(1024) void k_step1(StepArgs a) {
-  constexpr int EPT = NE == 8 ? (sizeof(R) == 4 ? 4 : 2) : (sizeof(R) == 4 ? 8 : 3);
-  constexpr int NPT = sizeof(R) == 4 ? 4 : 2;
+  constexpr int HW = Op<R, NE, OP>::W;  // operator values per element
+  constexpr int EPT = OP == 1 ? 1
+                      : NE == 8 ? (sizeof(R) == 4 ? 4 : 2) : (sizeof(R) == 4 ? (TDK ? 6 : 8) : 3);
+  constexpr int NPT = OP == 1 ? (sizeof(R) == 4 ? 2 : 1) : (sizeof(R) == 4 ? 4 : 2);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int t = (b & 7) * a.nper + (b >> 3);
@@ -862,7 +1056,7 @@ __global__ __launch_bounds__(1024) void k_step1(StepArgs a) {
   const R *Hb = (const R *)a.H;
   // ---- T-independent loads ----
   EntT ew[EPT];
-  R eh[EPT][6];
+  R eh[EPT][HW];
 #pragma unroll
   for (int q = 0; q < EPT; q++) {
     const int i = tid + q * bs;
@@ -870,7 +1064,7 @@ __global__ __launch_bounds__(1024) void k_step1(StepArgs a) {
       const int64_t e = (int64_t)th.estart + i;
       ew[q] = ent[e];
 #pragma unroll
-      for (int r = 0; r < 6; r++) eh[q][r] = Hb[(int64_t)r * a.Eexp + e];
+      for (int r = 0; r < HW; r++) eh[q][r] = Hb[(int64_t)r * a.Eexp + e];
     }
   }
   Node1<R> nd[NPT];
@@ -889,18 +1083,20 @@ __global__ __launch_bounds__(1024) void k_step1(StepArgs a) {
   for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
   __syncthreads();
   // ---- element loads into the node-local slots ----
-  const R s0 = (R)a.s0, s1 = (R)a.s1;
+  const KLaw<R> kl = step_law<R, GEN>(a);
   const uint32_t pmask = (1u << a.pb) - 1u;
 #pragma unroll
   for (int q = 0; q < EPT; q++)
     if (tid + q * bs < nE)
-      element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, s0, s1);
+      element_to_slots<R, NE, TDK, OP>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask,
+                                       elem_law<GEN>(a, kl, (int64_t)th.estart + tid + q * bs));
   for (int i = tid + EPT * bs; i < nE; i += bs) {
     const int64_t e = (int64_t)th.estart + i;
-    R h[6];
+    R h[HW];
 #pragma unroll
-    for (int r = 0; r < 6; r++) h[r] = Hb[(int64_t)r * a.Eexp + e];
-    element_to_slots<R, NE, TDK>(ent[e], h, Tl, slot, nown, nown, a.pb, pmask, s0, s1);
+    for (int r = 0; r < HW; r++) h[r] = Hb[(int64_t)r * a.Eexp + e];
+    element_to_slots<R, NE, TDK, OP>(ent[e], h, Tl, slot, nown, nown, a.pb, pmask,
+                                     elem_law<GEN>(a, kl, e));
   }
   __syncthreads();
   // ---- per node: ordered sum, surface loads, explicit update ----
@@ -908,45 +1104,54 @@ __global__ __launch_bounds__(1024) void k_step1(StepArgs a) {
 #pragma unroll
   for (int q = 0; q < NPT; q++) {
     const int j = tid + q * bs;
-    if (j < nown) update1<R, MODE, TDC>(a, th, j, nd[q], Tl, slot, Tz);
+    if (j < nown) update1<R, MODE, TDC, GEN>(a, th, j, nd[q], Tl, slot, Tz);
   }
   for (int j = tid + NPT * bs; j < nown; j += bs) {
     Node1<R> d;
     load_node1<R, MODE, TDC>(a, th, j, d);
-    update1<R, MODE, TDC>(a, th, j, d, Tl, slot, Tz);
+    update1<R, MODE, TDC, GEN>(a, th, j, d, Tl, slot, Tz);
   }
 }
 
-template <typename R, int NE, int MODE, bool TDK, bool TDC>
+template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN, int OP = 0>
 hipError_t step_t(const StepArgs &a, hipStream_t s) {
   if (a.k == 1)
-    hipLaunchKernelGGL((k_step1<R, NE, MODE, TDK, TDC>), dim3(8 * a.nper), dim3(a.block),
+    hipLaunchKernelGGL((k_step1<R, NE, MODE, TDK, TDC, GEN, OP>), dim3(8 * a.nper), dim3(a.block),
                        a.lds, s, a);
-  else
-    hipLaunchKernelGGL((k_step<R, NE, MODE, TDK, TDC>), dim3(8 * a.nper), dim3(a.block),
+  else if (OP == 0)  // the host allows K > 1 with the folded operator only
+    hipLaunchKernelGGL((k_step<R, NE, MODE, TDK, TDC, GEN>), dim3(8 * a.nper), dim3(a.block),
                        a.lds, s, a);
   return hipGetLastError();
 }
 
-template <typename R, int NE, int MODE, bool TDK, bool TDC>
+template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN, int OP = 0>
 hipError_t step_attr(int bytes) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_step1<R, NE, MODE, TDK, TDC>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_step1<R, NE, MODE, TDK, TDC, GEN, OP>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)k_step<R, NE, MODE, TDK, TDC>,
+  if (e != hipSuccess || OP != 0) return e;
+  return hipFuncSetAttribute((const void *)k_step<R, NE, MODE, TDK, TDC, GEN>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+// tables or per-element laws run the general instance (T-dependent k and c,
+// which covers every law); the others the instance of their linear law; the
+// uniform-gradient hexahedron runs the general instance of its operator
 template <typename R, int NE, int MODE>
 hipError_t step_dispatch_tt(const StepArgs &a, hipStream_t s) {
-  if (a.tdk) return a.tdc ? step_t<R, NE, MODE, true, true>(a, s) : step_t<R, NE, MODE, true, false>(a, s);
-  return a.tdc ? step_t<R, NE, MODE, false, true>(a, s) : step_t<R, NE, MODE, false, false>(a, s);
+  if (NE == 8 && a.op == 1) return step_t<R, 8, MODE, true, true, true, 1>(a, s);
+  if (a.esk || a.ktab || a.ctab) return step_t<R, NE, MODE, true, true, true>(a, s);
+  if (a.tdk)
+    return a.tdc ? step_t<R, NE, MODE, true, true, false>(a, s) : step_t<R, NE, MODE, true, false, false>(a, s);
+  return a.tdc ? step_t<R, NE, MODE, false, true, false>(a, s) : step_t<R, NE, MODE, false, false, false>(a, s);
 }
 
 template <typename R, int NE, int MODE>
-hipError_t attr_dispatch_tt(int tdk, int tdc, int bytes) {
-  if (tdk) return tdc ? step_attr<R, NE, MODE, true, true>(bytes) : step_attr<R, NE, MODE, true, false>(bytes);
-  return tdc ? step_attr<R, NE, MODE, false, true>(bytes) : step_attr<R, NE, MODE, false, false>(bytes);
+hipError_t attr_dispatch_tt(int tdk, int tdc, int gen, int op, int bytes) {
+  if (NE == 8 && op == 1) return step_attr<R, 8, MODE, true, true, true, 1>(bytes);
+  if (gen) return step_attr<R, NE, MODE, true, true, true>(bytes);
+  if (tdk)
+    return tdc ? step_attr<R, NE, MODE, true, true, false>(bytes) : step_attr<R, NE, MODE, true, false, false>(bytes);
+  return tdc ? step_attr<R, NE, MODE, false, true, false>(bytes) : step_attr<R, NE, MODE, false, false, false>(bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -989,8 +1194,48 @@ struct ElemAdj<R, 4> {
   }
 };
 
-template <typename R, int NE, int MODE>
+// mu_e . K0_e T_e for the element operator kinds (K0_e at s = 1)
+template <typename R, int NE, int OP>
+struct AdjDot {
+  __device__ static R dot(const R *Lmu, const R *LT, const uint32_t *loc, const R *h) {
+    // (S mu)^T Hhat (S T)
+    R mx, my, mz, tx, ty, tz;
+    ElemAdj<R, NE>::u(Lmu, loc, mx, my, mz);
+    ElemAdj<R, NE>::u(LT, loc, tx, ty, tz);
+    const R qx = h[0] * tx + h[3] * ty + h[5] * tz;
+    const R qy = h[3] * tx + h[1] * ty + h[4] * tz;
+    const R qz = h[5] * tx + h[4] * ty + h[2] * tz;
+    return mx * qx + my * qy + mz * qz;
+  }
+};
+template <typename R>
+struct AdjDot<R, 8, 1> {
+  __device__ static R dot(const R *Lmu, const R *LT, const uint32_t *loc, const R *h) {
+    // (Bbar mu)^T (V D) (Bbar T)
+    R g[2][3] = {};
+    const R *V2[2] = {Lmu, LT};
+#pragma unroll
+    for (int w = 0; w < 2; w++) {
+      const R t7 = V2[w][loc[7]];
+#pragma unroll
+      for (int n = 0; n < 7; n++) {
+        const R d = V2[w][loc[n]] - t7;
+        g[w][0] += h[3 * n] * d;
+        g[w][1] += h[3 * n + 1] * d;
+        g[w][2] += h[3 * n + 2] * d;
+      }
+    }
+    const R *vd = h + 21;
+    const R qx = vd[0] * g[1][0] + vd[3] * g[1][1] + vd[5] * g[1][2];
+    const R qy = vd[3] * g[1][0] + vd[1] * g[1][1] + vd[4] * g[1][2];
+    const R qz = vd[5] * g[1][0] + vd[4] * g[1][1] + vd[2] * g[1][2];
+    return g[0][0] * qx + g[0][1] * qy + g[0][2] * qz;
+  }
+};
+
+template <typename R, int NE, int MODE, int OP = 0>
 __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
+  constexpr int HW = Op<R, NE, OP>::W;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int t = (b & 7) * a.nper + (b >> 3);
@@ -1009,14 +1254,18 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   const R *beta = (const R *)a.beta;
   const R *Tn = (const R *)a.Tn, *Tn1 = (const R *)a.Tn1;
   const bool tdk = a.tdk != 0, tdc = a.tdc != 0;
+  const R *ctab = (const R *)a.ctab;
   for (int j = tid; j < ntouch; j += bs) {
     const int g = j < nown ? th.nstart + j : a.halo[th.hstart + j - nown];
     const R tn = Tn[g];
     R den = alpha[g];
-    if (tdc) den += beta[g] * tn;
+    if (tdc) den = cap_den(alpha[g], beta[g], tn, ctab, a.nct);
     Lmu[j] = lam[g] / den;  // 0 on Dirichlet nodes (alpha = +inf)
     LT[j] = tn;
-    Ld[j] = (Tn1[g] - tn) * rdt[g];
+    // increment per time step, times dc/dc0 (1, or the c table's value)
+    R dcdc0 = (R)1, sl;
+    if (a.nct) dcdc0 = table_eval(ctab, a.nct, tn, sl);
+    Ld[j] = (Tn1[g] - tn) * rdt[g] * dcdc0;
   }
   const int nslot = a.maxinc * nown;
   for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
@@ -1025,21 +1274,22 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
   const R *Hb = (const R *)a.H;
   const R *mV = (const R *)a.mV;
-  const R s0 = (R)a.s0, s1 = (R)a.s1;
+  const KLaw<R> kl = KLaw<R>{(R)a.s0, (R)a.s1, (const R *)a.ktab, a.nkt};
   const uint32_t pmask = (1u << a.pb) - 1u;
   for (int i = tid; i < nE; i += bs) {
     const int64_t e = (int64_t)th.estart + i;
-    R h[6];
+    const KLaw<R> kle = elem_law<true>(a, kl, e);
+    R h[HW];
 #pragma unroll
-    for (int r = 0; r < 6; r++) h[r] = Hb[(int64_t)r * a.Eexp + e];
+    for (int r = 0; r < HW; r++) h[r] = Hb[(int64_t)r * a.Eexp + e];
     const EntT w = ent[e];
     uint32_t v[NE], loc[NE];
     Ent<NE>::unpack(w, v);
 #pragma unroll
     for (int n = 0; n < NE; n++) loc[n] = v[n] >> a.pb;
     const bool owner = a.eowner[e] != 0;
-    // s_e at the element mean of T^n (summed as in the forward load)
-    R se = s0;
+    // s_e and ds_e/dTbar at the element mean of T^n (summed as in the forward load)
+    R se = kle.s0, dse = (R)0;
     if (tdk) {
       R sum;
       if (NE == 8)
@@ -1047,24 +1297,22 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
               ((LT[loc[4]] + LT[loc[5]]) + (LT[loc[6]] + LT[loc[7]]));
       else
         sum = (LT[loc[0]] + LT[loc[1]]) + (LT[loc[2]] + LT[loc[3]]);
-      se = s0 + s1 * (sum * ((R)1 / (R)NE));
+      const R mean = sum * ((R)1 / (R)NE);
+      if (kle.n) {
+        se = table_eval(kle.tab, kle.n, mean, dse);
+      } else {
+        se = kle(mean);
+        dse = kle.s1;
+      }
     }
-    // mu_e . K0_e T_e = (S mu)^T Hhat (S T)
+    // mu_e . K0_e T_e
     R muKT = 0;
-    if (tdk || owner) {
-      R mx, my, mz, tx, ty, tz;
-      ElemAdj<R, NE>::u(Lmu, loc, mx, my, mz);
-      ElemAdj<R, NE>::u(LT, loc, tx, ty, tz);
-      const R qx = h[0] * tx + h[3] * ty + h[5] * tz;
-      const R qy = h[3] * tx + h[1] * ty + h[4] * tz;
-      const R qz = h[5] * tx + h[4] * ty + h[2] * tz;
-      muKT = mx * qx + my * qy + mz * qz;
-    }
+    if (tdk || owner) muKT = AdjDot<R, NE, OP>::dot(Lmu, LT, loc, h);
     // s_e K0_e mu_e (the forward element load with mu at factor s_e), plus the
     // k(Tbar) term spread evenly over the element's nodes
     R F[NE];
-    Elem<R, NE>::load(Lmu, loc, se, (R)0, false, h, F);
-    const R spread = tdk ? s1 * ((R)1 / (R)NE) * muKT : (R)0;
+    Op<R, NE, OP>::load(Lmu, loc, KLaw<R>{se, (R)0, nullptr, 0}, false, h, F);
+    const R spread = tdk ? dse * ((R)1 / (R)NE) * muKT : (R)0;
 #pragma unroll
     for (int n = 0; n < NE; n++)
       if (loc[n] < (uint32_t)nown) slot[(v[n] & pmask) * nown + loc[n]] = F[n] + spread;
@@ -1094,7 +1342,16 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
       a.S0[r] += (double)mu;
       a.S1[r] += (double)mu * (double)LT[j];
     }
-    if (tdc) d -= beta[k] * (Tn1[k] - LT[j]) * mu;
+    if (tdc) {
+      // d den / dT: beta, or alpha times the c table's slope
+      R dden = beta[k];
+      if (a.nct) {
+        R sl;
+        (void)table_eval(ctab, a.nct, LT[j], sl);
+        dden = alpha[k] * sl;
+      }
+      d -= dden * (Tn1[k] - LT[j]) * mu;
+    }
     const bool fixed = alpha[k] == (R)INFINITY;
     if (MODE == 1) {
       const float hi = (float)lam[k], lo = a.lamloin[k];
@@ -1264,7 +1521,7 @@ struct Words<double> {
   }
 };
 
-template <typename R, int NE, int MODE, bool TDK, bool TDC>
+template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN>
 __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   constexpr int EPT = ResCap<R, NE>::EPT, NPT = ResCap<R, NE>::NPT, HPT = ResCap<R, NE>::HPT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1330,7 +1587,8 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   }
   // slots past a node's incidence are never written and stay zero
   for (int j = tid; j < a.maxinc * nown; j += bs) slot[j] = (R)0;
-  const R s0 = (R)a.s0, s1 = (R)a.s1, Tz = (R)a.Tz;
+  const KLaw<R> kl = step_law<R, GEN>(a);
+  const R Tz = (R)a.Tz;
   const uint32_t pmask = (1u << a.pb) - 1u;
   for (int s = 0; s < r.nsteps; s++) {
     // ---- stage T: owned from registers, halo from the state or the exchange ----
@@ -1374,7 +1632,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     for (int q = 0; q < EPT; q++)
       if (tid + q * bs < nE) {
         keep_packed(ew[q]);
-        element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, s0, s1);
+        element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, kl);
       }
     __syncthreads();
     // ---- per node: ordered sum, surface loads, explicit update, export ----
@@ -1400,9 +1658,11 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
           d.bP = Lbnd[4 * nbnd + j];
         }
         float lo_new;
-        hi[q] = advance<R, MODE, TDC>(d, bnd, hi[q], F, Tz, lo_new);
+        hi[q] = advance<R, MODE, TDC>(d, bnd, hi[q], F, Tz, GEN ? (const R *)a.ctab : nullptr,
+                                      GEN ? a.nct : 0, lo_new);
         lo[q] = lo_new;
         if (ex[q]) Words<R>::put(Xw, th.nstart + j, tag, hi[q]);
+        if (r.seg) ((R *)r.seg)[(int64_t)(s + 1) * r.segN + th.nstart + j] = hi[q];
       }
     }
   }
@@ -1458,14 +1718,25 @@ hipError_t launch_node_arrays(const NodeArrArgs &a, hipStream_t s) {
   return hipSuccess;
 }
 
-hipError_t launch_expand_H(int prec, int64_t Eexp, int64_t E, const int32_t *eorig,
+hipError_t launch_expand_sk(int prec, int64_t Eexp, const int32_t *eorig, const MatDev *mats,
+                            const int32_t *emat, void *esk, hipStream_t s) {
+  if (prec == 1)
+    hipLaunchKernelGGL(k_expand_sk<double>, dim3(blocks_for(Eexp, 256)), dim3(256), 0, s, Eexp,
+                       eorig, mats, emat, (double *)esk);
+  else
+    hipLaunchKernelGGL(k_expand_sk<float>, dim3(blocks_for(Eexp, 256)), dim3(256), 0, s, Eexp,
+                       eorig, mats, emat, (float *)esk);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_H(int prec, int W, int from, int64_t Eexp, int64_t E, const int32_t *eorig,
                            const double *H0, const double *kscale, void *H, hipStream_t s) {
   if (prec == 1)
-    hipLaunchKernelGGL(k_expand_H<double>, dim3(blocks_for(Eexp, 256)), dim3(256), 0, s, Eexp, E,
-                       eorig, H0, kscale, (double *)H);
+    hipLaunchKernelGGL(k_expand_H<double>, dim3(blocks_for(Eexp, 256)), dim3(256), 0, s, W, from,
+                       Eexp, E, eorig, H0, kscale, (double *)H);
   else
-    hipLaunchKernelGGL(k_expand_H<float>, dim3(blocks_for(Eexp, 256)), dim3(256), 0, s, Eexp, E,
-                       eorig, H0, kscale, (float *)H);
+    hipLaunchKernelGGL(k_expand_H<float>, dim3(blocks_for(Eexp, 256)), dim3(256), 0, s, W, from,
+                       Eexp, E, eorig, H0, kscale, (float *)H);
   return hipGetLastError();
 }
 
@@ -1477,12 +1748,12 @@ hipError_t launch_step(const StepArgs &a, hipStream_t s) {
   return a.ne == 8 ? step_dispatch_tt<float, 8, 0>(a, s) : step_dispatch_tt<float, 4, 0>(a, s);
 }
 
-hipError_t step_set_lds_limit(int prec, int ne, int tdk, int tdc, int bytes) {
+hipError_t step_set_lds_limit(int prec, int ne, int tdk, int tdc, int gen, int op, int bytes) {
   if (prec == 1)
-    return ne == 8 ? attr_dispatch_tt<double, 8, 0>(tdk, tdc, bytes) : attr_dispatch_tt<double, 4, 0>(tdk, tdc, bytes);
+    return ne == 8 ? attr_dispatch_tt<double, 8, 0>(tdk, tdc, gen, op, bytes) : attr_dispatch_tt<double, 4, 0>(tdk, tdc, gen, op, bytes);
   if (prec == 0)
-    return ne == 8 ? attr_dispatch_tt<float, 8, 1>(tdk, tdc, bytes) : attr_dispatch_tt<float, 4, 1>(tdk, tdc, bytes);
-  return ne == 8 ? attr_dispatch_tt<float, 8, 0>(tdk, tdc, bytes) : attr_dispatch_tt<float, 4, 0>(tdk, tdc, bytes);
+    return ne == 8 ? attr_dispatch_tt<float, 8, 1>(tdk, tdc, gen, op, bytes) : attr_dispatch_tt<float, 4, 1>(tdk, tdc, gen, op, bytes);
+  return ne == 8 ? attr_dispatch_tt<float, 8, 0>(tdk, tdc, gen, op, bytes) : attr_dispatch_tt<float, 4, 0>(tdk, tdc, gen, op, bytes);
 }
 
 hipError_t launch_set_T(int prec, int64_t N, const double *Tuser, const int32_t *perm, void *T,
@@ -1537,21 +1808,27 @@ hipError_t launch_permute(int elem_bytes, int64_t N, const int32_t *perm, const 
 
 namespace fed {
 
-template <typename R, int NE, int MODE, bool TDK, bool TDC>
+template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN>
 const void *resident_fn() {
-  return (const void *)k_resident<R, NE, MODE, TDK, TDC>;
+  return (const void *)k_resident<R, NE, MODE, TDK, TDC, GEN>;
 }
 
+// tables run the general instance (per-element laws are not offered resident)
 template <typename R, int NE, int MODE>
-const void *resident_tt(int tdk, int tdc) {
-  if (tdk) return tdc ? resident_fn<R, NE, MODE, true, true>() : resident_fn<R, NE, MODE, true, false>();
-  return tdc ? resident_fn<R, NE, MODE, false, true>() : resident_fn<R, NE, MODE, false, false>();
+const void *resident_tt(int tdk, int tdc, bool gen) {
+  if (gen) return resident_fn<R, NE, MODE, true, true, true>();
+  if (tdk)
+    return tdc ? resident_fn<R, NE, MODE, true, true, false>() : resident_fn<R, NE, MODE, true, false, false>();
+  return tdc ? resident_fn<R, NE, MODE, false, true, false>() : resident_fn<R, NE, MODE, false, false, false>();
 }
 
 const void *resident_kernel(const StepArgs &a) {
-  if (a.prec == 1) return a.ne == 8 ? resident_tt<double, 8, 0>(a.tdk, a.tdc) : resident_tt<double, 4, 0>(a.tdk, a.tdc);
-  if (a.prec == 0) return a.ne == 8 ? resident_tt<float, 8, 1>(a.tdk, a.tdc) : resident_tt<float, 4, 1>(a.tdk, a.tdc);
-  return a.ne == 8 ? resident_tt<float, 8, 0>(a.tdk, a.tdc) : resident_tt<float, 4, 0>(a.tdk, a.tdc);
+  const bool g = a.ktab || a.ctab;
+  if (a.prec == 1)
+    return a.ne == 8 ? resident_tt<double, 8, 0>(a.tdk, a.tdc, g) : resident_tt<double, 4, 0>(a.tdk, a.tdc, g);
+  if (a.prec == 0)
+    return a.ne == 8 ? resident_tt<float, 8, 1>(a.tdk, a.tdc, g) : resident_tt<float, 4, 1>(a.tdk, a.tdc, g);
+  return a.ne == 8 ? resident_tt<float, 8, 0>(a.tdk, a.tdc, g) : resident_tt<float, 4, 0>(a.tdk, a.tdc, g);
 }
 
 ResCaps resident_caps(int prec, int ne) {
@@ -1579,6 +1856,12 @@ hipError_t launch_resident(const StepArgs &a, const ResArgs &r, hipStream_t s) {
 
 hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s) {
   dim3 g(8 * a.nper), b(a.block);
+  if (a.ne == 8 && a.op == 1) {
+    if (a.prec == 1) hipLaunchKernelGGL((k_adjoint1<double, 8, 0, 1>), g, b, a.lds, s, a);
+    else if (a.prec == 0) hipLaunchKernelGGL((k_adjoint1<float, 8, 1, 1>), g, b, a.lds, s, a);
+    else hipLaunchKernelGGL((k_adjoint1<float, 8, 0, 1>), g, b, a.lds, s, a);
+    return hipGetLastError();
+  }
   if (a.prec == 1) {
     if (a.ne == 8) hipLaunchKernelGGL((k_adjoint1<double, 8, 0>), g, b, a.lds, s, a);
     else hipLaunchKernelGGL((k_adjoint1<double, 4, 0>), g, b, a.lds, s, a);
@@ -1592,9 +1875,12 @@ hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t adjoint_set_lds_limit(int prec, int ne, int bytes) {
+hipError_t adjoint_set_lds_limit(int prec, int ne, int op, int bytes) {
   const void *f;
-  if (prec == 1) f = ne == 8 ? (const void *)k_adjoint1<double, 8, 0> : (const void *)k_adjoint1<double, 4, 0>;
+  if (ne == 8 && op == 1)
+    f = prec == 1 ? (const void *)k_adjoint1<double, 8, 0, 1>
+                  : (prec == 0 ? (const void *)k_adjoint1<float, 8, 1, 1> : (const void *)k_adjoint1<float, 8, 0, 1>);
+  else if (prec == 1) f = ne == 8 ? (const void *)k_adjoint1<double, 8, 0> : (const void *)k_adjoint1<double, 4, 0>;
   else if (prec == 0) f = ne == 8 ? (const void *)k_adjoint1<float, 8, 1> : (const void *)k_adjoint1<float, 4, 1>;
   else f = ne == 8 ? (const void *)k_adjoint1<float, 8, 0> : (const void *)k_adjoint1<float, 4, 0>;
   return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

@@ -58,7 +58,17 @@ class Simulation:
         ek = None if prob["elem_k"] is None else f64(prob["elem_k"])
         ks = None if prob["elem_kscale"] is None else f64(prob["elem_kscale"])
         keep += [emat, ek, ks]
-        mats = L.fed_materials(len(mats_in), arr, _ptr(emat, C.c_int32), _ptr(ek), _ptr(ks))
+        # optional multiplier tables (T points, values) of D and c
+        tabs = []
+        for key in ("k_table", "c_table"):
+            tb = prob.get(key)
+            tb = (None, None) if tb is None else (f64(tb[0]), f64(tb[1]))
+            keep += list(tb)
+            tabs.append(tb)
+        (kT, kf), (cT, cf) = tabs
+        mats = L.fed_materials(len(mats_in), arr, _ptr(emat, C.c_int32), _ptr(ek), _ptr(ks),
+                               0 if kT is None else kT.size, _ptr(kT), _ptr(kf),
+                               0 if cT is None else cT.size, _ptr(cT), _ptr(cf))
         dn, dT = i32(prob["dir_nodes"]), f64(prob["dir_T"])
         keep += [dn, dT]
         faces = prob["faces"]
@@ -81,7 +91,8 @@ class Simulation:
         opt = L.fed_options(PRECISIONS[prec], dt, float(prob["safety"]), float(prob["T_lo"]),
                             float(prob["T_hi"]), int(bool(allow_unstable)),
                             _ptr(inst, C.c_int32), int(tile_nodes), int(block_threads),
-                            int(fuse_steps), int(bool(resident)))
+                            int(fuse_steps), int(bool(resident)),
+                            1 if prob.get("hex_gradient", "centre") == "mean" else 0)
         self.stream = current_stream() if stream is None else stream
         ctx = C.c_void_p()
         L.check(lib.fed_create(C.byref(mesh), C.byref(mats), C.byref(bcs), C.byref(opt),

@@ -79,3 +79,37 @@ def nonlinear_adjoint_problem(elem):
     from oracle import Oracle
     p["dt"] = 0.5 * Oracle(p).dt_crit
     return p
+
+
+def two_material_problem(elem="hex8", n=6):
+    """Box of two materials with different k(T) laws (s0, s1), c(T) laws and
+    densities, split at x = side/2; convection, radiation on the top face, a
+    flux on the bottom, random T0."""
+    side = 0.1
+    m = M.box_hex(n, n, n, side, side, side) if elem == "hex8" else \
+        M.box_tet_kuhn(n, n, n, side, side, side)
+    p = P._base(m, f"two_material_{elem}")
+    p["materials"] = [P.material(2700.0, 880.0, [200.0, 180.0, 150.0], c1=0.4, s0=1.0, s1=-4e-4),
+                      P.material(7800.0, 460.0, [40.0], c1=0.25, s0=0.8, s1=2e-3)]
+    cx = m["x"][m["conn"]].mean(axis=0)
+    p["elem_material"] = (cx > side / 2).astype(np.int32)
+    faces = M.boundary_faces(m)
+    cz = m["z"][faces].mean(axis=1)
+    top, bottom = np.isclose(cz, side), np.isclose(cz, 0.0)
+    P.set_faces(p, faces, h=12.0, Ta=25.0, eps=np.where(top, 0.7, 0.0),
+                q=np.where(bottom, 4e4, 0.0))
+    p["T0"] = np.random.default_rng(31).uniform(20.0, 80.0, m["x"].size)
+    p["T_lo"], p["T_hi"] = 0.0, 400.0
+    return p
+
+
+def table_laws(p):
+    """The same problem with kinked multiplier tables for D and c instead of
+    linear laws (materials with s0 = 1, s1 = 0, c1 = 0)."""
+    q = dict(p)
+    q["materials"] = [dict(m, s0=1.0, s1=0.0, c1=0.0) for m in p["materials"]]
+    q["elem_material"] = p["elem_material"]
+    q["k_table"] = (np.array([0.0, 40.0, 55.0, 120.0, 400.0]),
+                    np.array([1.0, 1.3, 0.9, 1.6, 2.0]))
+    q["c_table"] = (np.array([10.0, 35.0, 60.0, 90.0]), np.array([0.8, 1.1, 1.4, 1.2]))
+    return q

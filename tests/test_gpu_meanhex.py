@@ -1,0 +1,104 @@
+"""The uniform-gradient (element-mean) hexahedron on the GPU against the
+oracle: distorted meshes with temperature-dependent properties and all
+boundary conditions (err_max <= 1e-12 FP64, <= 1e-5 compensated FP32), the
+distorted patch test of Sec. 4.1 (which the centre-point hexahedron fails),
+the adjoint (1e-10 / 1e-4), and equality with the centre point on affine
+grids."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from tests import helpers as H
+from workloads import mesh as M, problems as P
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32c": 1e-5}
+GTOL = {"fp64": 1e-10, "fp32c": 1e-4}
+
+
+def _sim(p, prec, **kw):
+    from paper_1909_03355_amd import Simulation
+    return Simulation(p, prec=prec, **kw)
+
+
+def _run(p, prec, nsteps, **kw):
+    with _sim(p, prec, **kw) as s:
+        s.set_temperature()
+        s.step(nsteps, graph_steps=10)
+        return s.temperature()
+
+
+def _distorted(n=7, seed=5):
+    """Nonlinear hexahedral cube (the 64^3 workload's laws and boundary
+    conditions at n^3) with its interior nodes jittered by up to 0.25 h."""
+    p = P.cube_nonlinear_hex(n, 100)
+    m = M.jitter_interior(dict(elem="hex8", x=p["x"], y=p["y"], z=p["z"], conn=p["conn"]),
+                          0.25, seed)
+    return dict(p, x=m["x"], y=m["y"], z=m["z"], hex_gradient="mean")
+
+
+def test_distorted_mesh_matches_oracle():
+    p = _distorted()
+    ref = Oracle(p).run(100)
+    centre = Oracle(dict(p, hex_gradient="centre")).run(100)
+    assert oracle.err_max(centre, ref) > 1e-6     # the formulations differ on this mesh
+    for prec in ("fp64", "fp32c"):
+        T = _run(p, prec, 100)
+        err = oracle.err_max(T, ref)
+        print(f"mean-gradient hex {prec}: err_max {err:.2e}", flush=True)
+        assert err <= TOL[prec]
+        assert np.array_equal(_run(p, prec, 100, tile_nodes=50, block_threads=128), T)
+
+
+def test_patch_test_on_gpu():
+    """Linear field on the 8 outer corners of the Fig. 2(c) patch: the
+    interior relaxes to the linear field (FP64)."""
+    x, y, z = M.patch_nodes(os.path.join(H.GOLDEN, "patch_nodes.txt"))
+    p = P._base(M.patch_hex(x, y, z), "patch_hex_mean")
+    p["materials"] = [P.material(1.0, 1.0, [1.0])]
+    p["hex_gradient"] = "mean"
+    lin = 200 * x + 100 * y + 200 * z
+    p["dir_nodes"], p["dir_T"] = np.arange(8, dtype=np.int32), lin[:8]
+    p["T0"] = np.zeros(16)
+    p["T_lo"], p["T_hi"] = 0.0, 500.0
+    nsteps = 120000                      # the slowest mode has decayed to ~1e-10
+    ref = Oracle(p).run(nsteps)
+    T = _run(p, "fp64", nsteps)
+    assert oracle.err_max(T, ref) <= 1e-12
+    assert np.max(np.abs(T - lin)) < 1e-9 * np.max(np.abs(lin))
+
+
+def test_mean_gradient_adjoint_matches_oracle():
+    p = _distorted(5, seed=9)
+    nsteps = 40
+    o = Oracle(p)
+    hist = o.run(nsteps, history=True)
+    sens = np.arange(0, o.N, 4)
+    lam = np.zeros(o.N)
+    lam[sens] = 2.0 * (hist[-1][sens] - 40.0) / sens.size
+    ref = o.adjoint(hist, lam)
+    rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    for prec in ("fp64", "fp32c"):
+        with _sim(p, prec) as s:
+            s.checkpoint_every(16)
+            s.set_temperature()
+            s.step(nsteps)
+            g = s.backward(lam)
+        errs = {"logk": rel(g["logk"], ref["g_logk"]), "c": rel(g["c"], ref["g_c"]),
+                "h": rel(g["h"], ref["g_h"]), "T0": rel(g["T0"], ref["lam0"])}
+        print("mean-gradient adjoint", prec, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        for k, v in errs.items():
+            assert v <= GTOL[prec], (prec, k, v)
+
+
+def test_mean_equals_centre_on_box():
+    p = P.cube_nonlinear_hex(8, 50)
+    a = _run(p, "fp64", 50)
+    b = _run(dict(p, hex_gradient="mean"), "fp64", 50)
+    assert oracle.err_max(a, b) < 1e-12

@@ -82,3 +82,16 @@ def test_validation_rejects_bad_inputs():
     inst[two["conn"][3, 0]] = 1 - inst[two["conn"][3, 0]]
     _expect(dict(two, node_instance=inst), L.FED_E_ARG)   # element spans instances
     _expect(p, L.FED_E_ARG, block_threads=100)
+    # multiplier tables: T must increase, a k table needs s0 = 1, s1 = 0, a c
+    # table c1 = 0
+    tab = (np.array([0.0, 50.0, 40.0]), np.array([1.0, 2.0, 3.0]))
+    _expect(dict(p, k_table=tab), L.FED_E_ARG)
+    ok_tab = (np.array([0.0, 50.0]), np.array([1.0, 2.0]))
+    mats = [dict(p["materials"][0], s1=0.01)]
+    _expect(dict(p, materials=mats, k_table=ok_tab), L.FED_E_ARG)
+    mats = [dict(p["materials"][0], c1=0.5)]
+    _expect(dict(p, materials=mats, c_table=ok_tab), L.FED_E_ARG)
+    _expect(dict(p, c_table=(ok_tab[0], np.array([1.0, -1.0]))), L.FED_E_ARG)
+    # the uniform-gradient hexahedron runs one step per launch
+    _expect(dict(p, hex_gradient="mean"), L.FED_E_ARG, fuse_steps=2)
+    _expect(dict(p, hex_gradient="mean"), L.FED_E_ARG, resident=True)

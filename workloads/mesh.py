@@ -150,6 +150,21 @@ def boundary_nodes(mesh):
     return np.unique(boundary_faces(mesh))
 
 
+def jitter_interior(mesh, amp, seed):
+    """Copy of a box mesh with every node off the boundary moved by a seeded
+    uniform offset of up to amp times the local spacing in each direction (a
+    distorted, still valid hexahedral or tetrahedral mesh for amp well below
+    1/2)."""
+    g = np.random.default_rng(seed)
+    x, y, z = mesh["x"].copy(), mesh["y"].copy(), mesh["z"].copy()
+    inner = np.ones(x.size, bool)
+    inner[boundary_nodes(mesh)] = False
+    for c in (x, y, z):
+        h = np.diff(np.unique(np.round(c, 12))).min()
+        c[inner] += amp * h * g.uniform(-1.0, 1.0, inner.sum())
+    return dict(mesh, x=x, y=y, z=z)
+
+
 # Patch-test geometry (Sec. 4.1, Fig. 2(c)): eight unit-cube corners and
 # eight interior nodes, loaded from the text fixture that transcribes the
 # printed coordinates.
