@@ -144,6 +144,8 @@ def main():
     for prec in precs:
         sim = Simulation(prob, prec=prec, **kw)
         if args.workload == "adjoint_hex48":
+            if args.warmup:
+                timed_adjoint(sim, steps, prob)  # first-use allocations and module loads
             tf, tb = timed_adjoint(sim, steps, prob)
             t = tf + tb
             log(f"{prec}: forward {tf * 1e3:.1f} ms + adjoint {tb * 1e3:.1f} ms for {steps} steps")

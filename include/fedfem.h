@@ -164,6 +164,9 @@ typedef struct {
   double exchange_bytes_per_step;      /* resident stepping: bytes one step moves through
                                           memory (tagged halo reads and export writes); 0
                                           else */
+  int32_t resident_adjoint;            /* 1 if fed_backward runs each checkpoint segment's
+                                          adjoint steps in one resident launch */
+  int32_t reserved_;
 } fed_info;
 
 /*
@@ -252,6 +255,20 @@ int fed_set_params(fed_ctx *ctx, const double *kscale, const double *elem_c,
 int fed_set_bc(fed_ctx *ctx, const double *face_Ta, const double *face_q, const double *pt_W,
                int32_t on_device, void *stream);
 
+/* Smallest and largest current temperature (FP64; NaN if any is not finite).
+ * The stability bound (Sec. 3.4) is derived for [T_lo, T_hi]; a run whose
+ * temperatures leave that range should re-derive it with fed_set_range.
+ * Synchronises `stream`.  FED_E_STATE before fed_set_temperature. */
+int fed_temperature_range(fed_ctx *ctx, double *tmin, double *tmax, void *stream);
+
+/* Re-derives dt_crit (Sec. 3.4, Eq. 29) for the temperature range [T_lo, T_hi]
+ * and re-checks the time step in use against it; the health check window
+ * follows the new range.  The time step itself is unchanged.  Errors:
+ * FED_E_ARG (bad range, c(T) or D(T) not positive on it), FED_E_UNSTABLE (the
+ * time step exceeds the new bound and allow_unstable is off; the new bound
+ * and range are kept), FED_E_HIP.  Synchronises `stream`. */
+int fed_set_range(fed_ctx *ctx, double T_lo, double T_hi, void *stream);
+
 /* Discrete adjoint of the steps taken since fed_set_temperature (not in the
  * paper; it differentiates the explicit recursion of Sec. 3.1 exactly).  For a
  * loss L with gradient dL_dT with respect to the current temperatures (FP64,
@@ -259,10 +276,15 @@ int fed_set_bc(fed_ctx *ctx, const double *face_Ta, const double *face_q, const 
  * checkpoint segment, and returns dL/dlog k_e (g_logk, n_elems), dL/dc_e (g_c,
  * n_elems), dL/dh_f (g_h, n_faces) and dL/dT0 (n_nodes; zero on Dirichlet
  * nodes); any output may be NULL.  Pointers are host memory if on_device == 0,
- * else device.  Requires a problem linear in T (s1 = 0, c1 = 0, no radiation)
- * and checkpointing on (FED_E_STATE otherwise); FED_E_MESH if a tile needs more
- * LDS than the adjoint kernel can take.  Synchronises `stream`; the forward
- * state is left unchanged. */
+ * else device.  Temperature-dependent k and c (laws or tables) and radiation
+ * are differentiated through; derivatives are taken at the parameters of the
+ * context.  A resident context recomputes each segment in one launch and, for
+ * hexahedra with the centre-point operator when the tiles fit
+ * (fed_info.resident_adjoint), runs the segment's adjoint steps in one launch
+ * too; results are bitwise identical either way.  Requires checkpointing on
+ * (FED_E_STATE otherwise); FED_E_MESH if a tile needs more LDS than the
+ * adjoint kernel can take; FED_E_HIP also if a resident wait gave up.
+ * Synchronises `stream`; the forward state is left unchanged. */
 int fed_backward(fed_ctx *ctx, const double *dL_dT, double *g_logk, double *g_c, double *g_h,
                  double *dL_dT0, int32_t on_device, void *stream);
 

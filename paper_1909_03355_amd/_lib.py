@@ -64,7 +64,8 @@ class fed_info(C.Structure):
                 ("lds_bytes", C.c_int32), ("fuse_steps", C.c_int32), ("resident", C.c_int32),
                 ("algorithmic_bytes_per_launch", C.c_double),
                 ("moved_bytes_per_launch", C.c_double),
-                ("exchange_bytes_per_step", C.c_double)]
+                ("exchange_bytes_per_step", C.c_double),
+                ("resident_adjoint", C.c_int32), ("reserved_", C.c_int32)]
 
 
 # name -> (restype, argtypes) of every symbol the header declares
@@ -86,6 +87,8 @@ SIGNATURES = {
                                  C.c_void_p]),
     "fed_set_bc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                              C.c_void_p]),
+    "fed_temperature_range": (C.c_int, [C.c_void_p, _d, _d, C.c_void_p]),
+    "fed_set_range": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
     "fed_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_int32, C.c_void_p]),
     "fed_destroy": (None, [C.c_void_p]),

@@ -87,6 +87,9 @@ struct fed_ctx {
   unsigned xtag = 1;
   int *d_rerr = nullptr;
   int res_lds = 0;
+  // resident adjoint (hexahedra, folded operator, tiles within the LDS)
+  bool adjres = false;
+  int adjres_lds = 0;
   // kept FP64 pre-computation (re-derived by fed_set_params, used by the adjoint)
   double *d_H0 = nullptr, *d_kscale = nullptr, *d_V = nullptr;
   double *d_M0 = nullptr, *d_M1 = nullptr, *d_Cmin = nullptr, *d_lamgeo = nullptr;
@@ -123,6 +126,11 @@ struct fed_ctx {
   // element operator: 0 the folded 3x3 (6 values), 1 the uniform-gradient
   // hexahedron (27 values)
   int op = 0, hw = 6;
+  // host copies for re-deriving the stability bound over a new range
+  std::vector<fed_material> h_mats;
+  std::vector<double> h_ktab_T, h_ktab_f, h_ctab_T, h_ctab_f;
+  unsigned long long *d_rkeys = nullptr;  // temperature-range keys and a non-finite flag
+  int *d_rnan = nullptr;
   // scalars
   double s0 = 1, s1 = 0, Tz = -273.15, T_lo = 0, T_hi = 0;
   int tdk = 0, tdc = 0, block = 256, nper = 1, K = 1;
@@ -346,12 +354,16 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   }
   HIPCHK(P.alloc((void **)&c->d_rerr, sizeof(int)));
   HIPCHK(hipMemset(c->d_rerr, 0, sizeof(int)));
-  // LDS of the resident kernel: T of the touched nodes, the slots of the owned
-  // nodes and the 5 boundary coefficients of the owned boundary nodes
+  // LDS of the resident kernel: T of the touched nodes, the slots of the
+  // touched nodes (hexahedra: 2^pb + 1 each) or of the owned nodes
+  // (tetrahedra: maxinc each) and the 5 boundary coefficients of the owned
+  // boundary nodes
   int64_t lds = 0;
-  for (const fed::TileHdr &th : T.tiles)
-    lds = std::max<int64_t>(lds, (int64_t)c->rb * (th.cum_n[1] + (int64_t)T.maxinc * th.nown +
-                                                    5LL * th.nbnd) + 16);
+  for (const fed::TileHdr &th : T.tiles) {
+    const int64_t ns = c->ne == FED_HEX8 ? (int64_t)th.cum_n[1] * ((1 << T.pb) + 1)
+                                         : (int64_t)T.maxinc * th.nown;
+    lds = std::max<int64_t>(lds, (int64_t)c->rb * (th.cum_n[1] + ns + 5LL * th.nbnd) + 16);
+  }
   if (lds > c->max_lds)
     return fail(FED_E_MESH, "resident stepping: a tile needs %lld bytes of LDS (the GPU has %d)",
                 (long long)lds, c->max_lds);
@@ -369,6 +381,27 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   int64_t nexp = 0;
   for (uint8_t v : exported) nexp += v;
   *exch = 8.0 * words * (double)(halo_total + nexp);  // tagged words read and written
+  // resident adjoint: the FP64 boundary sums (and, in FP64, the elements'
+  // derivative sums and rho V / n_e); mu, w, T^n, T^{n+1}, alpha, 1/dt (and beta) of the
+  // touched nodes, the slots of the owned nodes, hA and sigma eps A of the
+  // owned boundary nodes; offered where it fits, else fed_backward runs one
+  // adjoint step per launch
+  if (c->ne == FED_HEX8 && c->op == 0) {
+    int64_t alds = 0;
+    for (const fed::TileHdr &th : T.tiles)
+      alds = std::max<int64_t>(alds, 16LL * th.nbnd + (c->prec == FED_FP64 ? 24LL * th.cum_e[0] : 0) +
+                                         (int64_t)c->rb * ((6 + (c->tdc ? 1 : 0)) * (int64_t)th.cum_n[1] +
+                                                           (int64_t)T.maxinc * th.nown + 2LL * th.nbnd) + 16);
+    int aper = 0;
+    if (alds <= c->max_lds) {
+      HIPCHK(fed::adjres_prepare(c->prec == FED_FP64 ? 1 : (c->prec == FED_FP32C ? 0 : 2), c->block,
+                                 (int)alds, &aper));
+      if (aper >= 1 && grid <= (int64_t)aper * n_cu) {
+        c->adjres = true;
+        c->adjres_lds = (int)alds;
+      }
+    }
+  }
   return FED_OK;
 }
 
@@ -426,6 +459,15 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   };
   if (c->nkt) c->fk_max = table_extreme(c->nkt, mt->ktab_T, mt->ktab_f, true);
   if (c->nct) c->fc_min = table_extreme(c->nct, mt->ctab_T, mt->ctab_f, false);
+  c->h_mats.assign(mt->materials, mt->materials + mt->n_materials);
+  if (c->nkt) {
+    c->h_ktab_T.assign(mt->ktab_T, mt->ktab_T + c->nkt);
+    c->h_ktab_f.assign(mt->ktab_f, mt->ktab_f + c->nkt);
+  }
+  if (c->nct) {
+    c->h_ctab_T.assign(mt->ctab_T, mt->ctab_T + c->nct);
+    c->h_ctab_f.assign(mt->ctab_f, mt->ctab_f + c->nct);
+  }
   if (mixed_k && o->resident)
     return fail(FED_E_ARG, "resident stepping needs materials that share s0 and s1");
   c->resident = o->resident == 1;
@@ -760,6 +802,8 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
     HIPCHK(upload(P, &c->d_dir_T, bc->dir_T, (size_t)c->ndir));
   }
   HIPCHK(P.alloc((void **)&c->d_flag, sizeof(int)));
+  HIPCHK(P.alloc((void **)&c->d_rkeys, 2 * sizeof(unsigned long long)));
+  HIPCHK(P.alloc((void **)&c->d_rnan, sizeof(int)));
   HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
   HIPCHK(P.alloc((void **)&c->d_Tuser, sizeof(double) * N));
   if (T.lds_bytes > max_lds)
@@ -803,6 +847,7 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   I.fuse_steps = T.depth;
   I.resident = c->resident ? 1 : 0;
   I.exchange_bytes_per_step = exch_bytes;
+  I.resident_adjoint = c->adjres ? 1 : 0;
   double elem_b = 2.0 * ne + c->hw * rb + (c->d_esk ? 2.0 * rb : 0.0);
   double lo_b = c->prec == FED_FP32C ? 4.0 : 0.0;
   double coef_b = rb + (c->tdc ? rb : 0.0);
@@ -1187,6 +1232,88 @@ int fed_set_bc(fed_ctx *c, const double *face_Ta, const double *face_q, const do
   return FED_OK;
 }
 
+int fed_temperature_range(fed_ctx *c, double *tmin, double *tmax, void *stream) {
+  if (!c || !tmin || !tmax) return fail(FED_E_ARG, "null argument");
+  if (!c->have_T) return fail(FED_E_STATE, "no temperature set");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long init[2] = {~0ull, 0ull}, keys[2];
+  int nan = 0;
+  HIPCHK(hipMemcpyAsync(c->d_rkeys, init, sizeof(init), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(c->d_rnan, 0, sizeof(int), s));
+  HIPCHK(fed::launch_range(c->prec, c->N, c->d_T[c->cur], c->d_lo[c->cur], c->d_rkeys, c->d_rnan, s));
+  HIPCHK(hipMemcpyAsync(keys, c->d_rkeys, sizeof(keys), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&nan, c->d_rnan, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  auto value = [](unsigned long long k) {
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    double v;
+    std::memcpy(&v, &b, 8);
+    return v;
+  };
+  *tmin = nan ? NAN : value(keys[0]);
+  *tmax = nan ? NAN : value(keys[1]);
+  return FED_OK;
+}
+
+int fed_set_range(fed_ctx *c, double T_lo, double T_hi, void *stream) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  if (!std::isfinite(T_lo) || !std::isfinite(T_hi) || !(T_hi > T_lo))
+    return fail(FED_E_ARG, "need finite T_lo < T_hi");
+  for (size_t i = 0; i < c->h_mats.size(); i++) {
+    const fed_material &q = c->h_mats[i];
+    if (!(q.c0 + q.c1 * T_lo > 0 && q.c0 + q.c1 * T_hi > 0) ||
+        !(q.s0 + q.s1 * T_lo > 0 && q.s0 + q.s1 * T_hi > 0))
+      return fail(FED_E_ARG, "material %d: c(T) or D(T) not positive on [%g, %g]", (int)i, T_lo, T_hi);
+  }
+  // table extremes on the new range: at its ends or at breakpoints inside it
+  auto extreme = [&](const std::vector<double> &tT, const std::vector<double> &tf, bool want_max) {
+    const int n = (int)tT.size();
+    auto at = [&](double T) {
+      if (T <= tT[0]) return tf[0];
+      if (T >= tT[n - 1]) return tf[n - 1];
+      int i = 1;
+      while (T > tT[i]) i++;
+      return tf[i - 1] + (T - tT[i - 1]) / (tT[i] - tT[i - 1]) * (tf[i] - tf[i - 1]);
+    };
+    double r = want_max ? std::max(at(T_lo), at(T_hi)) : std::min(at(T_lo), at(T_hi));
+    for (int i = 0; i < n; i++)
+      if (tT[i] > T_lo && tT[i] < T_hi) r = want_max ? std::max(r, tf[i]) : std::min(r, tf[i]);
+    return r;
+  };
+  const double fk_max = c->nkt ? extreme(c->h_ktab_T, c->h_ktab_f, true) : 1.0;
+  const double fc_min = c->nct ? extreme(c->h_ctab_T, c->h_ctab_f, false) : 1.0;
+  hipStream_t s = (hipStream_t)stream;
+  fed::MassArgs ma{c->N, c->ne, c->d_incp, c->d_ince, c->d_mats, c->d_emat, c->d_ec0, c->d_V,
+                   T_lo, T_hi, c->d_M0, c->d_M1, c->d_Cmin, fc_min};
+  HIPCHK(fed::launch_mass(ma, s));
+  HIPCHK(hipMemsetAsync(c->d_lam, 0, sizeof(unsigned long long) * 2 * c->ninst, s));
+  fed::DtArgs da{c->ne, c->E, c->nrec, c->d_lamgeo, c->d_kscale, c->d_mats, c->d_emat, c->d_ec0,
+                 c->d_einst, c->d_recnode, c->d_ninst, c->d_b64[0], c->d_b64[2], c->d_Cmin,
+                 T_lo, T_hi, c->Tz, c->d_lam, c->d_lam + c->ninst, fk_max, fc_min};
+  HIPCHK(fed::launch_dt(da, s));
+  std::vector<unsigned long long> lam(2 * c->ninst);
+  HIPCHK(hipMemcpyAsync(lam.data(), c->d_lam, lam.size() * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<double> dtc(c->ninst);
+  for (int64_t i = 0; i < c->ninst; i++) {
+    double le, lb;
+    std::memcpy(&le, &lam[i], 8);
+    std::memcpy(&lb, &lam[c->ninst + i], 8);
+    dtc[i] = le + lb > 0 ? 2.0 / (le + lb) : INFINITY;
+  }
+  c->dt_crit = dtc;
+  c->T_lo = T_lo;
+  c->T_hi = T_hi;
+  c->fk_max = fk_max;
+  c->fc_min = fc_min;
+  for (int64_t i = 0; i < c->ninst; i++)
+    if (c->dt_used[i] > c->dt_crit[i] && !c->allow_unstable)
+      return fail(FED_E_UNSTABLE, "dt %.6g exceeds dt_crit %.6g on [%g, %g] (instance %lld)",
+                  c->dt_used[i], c->dt_crit[i], T_lo, T_hi, (long long)i);
+  return FED_OK;
+}
+
 int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, double *g_h,
                  double *dL_dT0, int32_t on_device, void *stream) {
   if (!c || !dL_dT) return fail(FED_E_ARG, "null argument");
@@ -1267,50 +1394,65 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       }
     }
     // adjoint steps n1-1 .. n0
+    fed::AdjArgs a{};
+    a.prec = c->prec;
+    a.ne = c->ne;
+    a.nt = c->til.nt;
+    a.nper = c->nper;
+    a.block = c->block;
+    a.lds = c->adj_lds;
+    a.pb = c->til.pb;
+    a.maxinc = c->til.maxinc;
+    a.Eexp = c->Eexp;
+    a.tiles = c->d_tiles;
+    a.ent = c->d_ent;
+    a.halo = c->d_halo;
+    a.eorig = c->d_eorig;
+    a.eowner = c->d_eowner;
+    a.H = c->d_H;
+    a.alpha = c->d_alpha;
+    a.rdt = c->d_rdt;
+    a.mV = c->d_mV;
+    a.rA = c->d_rA;
+    a.g_logk = c->d_gk;
+    a.g_c = c->d_gc;
+    a.S0 = c->d_S0;
+    a.S1 = c->d_S1;
+    a.s0 = c->s0;
+    a.tdk = c->tdk;
+    a.tdc = c->tdc;
+    a.s1 = c->s1;
+    a.Tz = c->Tz;
+    a.beta = c->d_beta;
+    a.reA = c->d_reA;
+    a.esk = c->d_esk;
+    a.ktab = c->d_ktab;
+    a.ctab = c->d_ctab;
+    a.nkt = c->nkt;
+    a.nct = c->nct;
+    a.op = c->op;
+    if (c->adjres && n1 > n0) {
+      // one resident launch for the segment
+      const int k = (int)(n1 - n0);
+      a.lds = c->adjres_lds;
+      a.lamin = c->d_lamb[lc];
+      a.lamloin = c->d_lamlo[lc];
+      a.lamout = c->d_lamb[1 - lc];
+      a.lamloout = c->d_lamlo[1 - lc];
+      fed::AdjResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
+                        c->d_seg, N};
+      HIPCHK(fed::launch_adjres(a, r, s));
+      c->xtag += (unsigned)k + 1u;
+      lc ^= 1;
+      continue;
+    }
     for (int64_t n = n1 - 1; n >= n0; n--) {
-      fed::AdjArgs a{};
-      a.prec = c->prec;
-      a.ne = c->ne;
-      a.nt = c->til.nt;
-      a.nper = c->nper;
-      a.block = c->block;
-      a.lds = c->adj_lds;
-      a.pb = c->til.pb;
-      a.maxinc = c->til.maxinc;
-      a.Eexp = c->Eexp;
-      a.tiles = c->d_tiles;
-      a.ent = c->d_ent;
-      a.halo = c->d_halo;
-      a.eorig = c->d_eorig;
-      a.eowner = c->d_eowner;
-      a.H = c->d_H;
-      a.alpha = c->d_alpha;
-      a.rdt = c->d_rdt;
-      a.mV = c->d_mV;
-      a.rA = c->d_rA;
       a.lamin = c->d_lamb[lc];
       a.lamloin = c->d_lamlo[lc];
       a.lamout = c->d_lamb[1 - lc];
       a.lamloout = c->d_lamlo[1 - lc];
       a.Tn = seg(n - n0);
       a.Tn1 = seg(n - n0 + 1);
-      a.g_logk = c->d_gk;
-      a.g_c = c->d_gc;
-      a.S0 = c->d_S0;
-      a.S1 = c->d_S1;
-      a.s0 = c->s0;
-      a.tdk = c->tdk;
-      a.tdc = c->tdc;
-      a.s1 = c->s1;
-      a.Tz = c->Tz;
-      a.beta = c->d_beta;
-      a.reA = c->d_reA;
-      a.esk = c->d_esk;
-      a.ktab = c->d_ktab;
-      a.ctab = c->d_ctab;
-      a.nkt = c->nkt;
-      a.nct = c->nct;
-      a.op = c->op;
       HIPCHK(fed::launch_adjoint(a, s));
       lc ^= 1;
     }
@@ -1328,7 +1470,12 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
     if (!on_device)
       HIPCHK(hipMemcpyAsync(dL_dT0, c->d_Tuser, sizeof(double) * N, hipMemcpyDeviceToHost, s));
   }
+  int rerr = 0;
+  if (c->resident) HIPCHK(hipMemcpyAsync(&rerr, c->d_rerr, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (rerr)
+    return fail(FED_E_HIP, "resident stepping: a tile gave up waiting for a neighbouring tile; "
+                           "the derivatives are invalid");
   return FED_OK;
 }
 

@@ -117,8 +117,7 @@ struct StepArgs {
   int op;                     // element operator: 0 folded 3x3, 1 uniform-gradient hexahedron
 };
 
-// One step of the discrete adjoint of the explicit update, for problems that are
-// linear in T (constant D and c, no radiation).
+// One step of the discrete adjoint of the explicit update.
 struct AdjArgs {
   int prec, ne;
   int nt, nper, block, lds;
@@ -185,6 +184,20 @@ struct ResArgs {
   int64_t segN;
 };
 
+// Resident adjoint of one checkpoint segment (hexahedra, folded operator):
+// nsteps adjoint steps over the stored states T^{n0 + i} at seg + i * segN,
+// i = 0..nsteps, with the exchange of ResArgs.
+struct AdjResArgs {
+  int nsteps;
+  int spin_limit;
+  unsigned tag0;
+  const uint8_t *exported;
+  unsigned long long *X[2];
+  int *err;
+  const void *seg;
+  int64_t segN;
+};
+
 // register capacity of the resident kernel per thread (elements, nodes, halo ids)
 struct ResCaps {
   int ept, npt, hpt;
@@ -197,6 +210,8 @@ hipError_t launch_resident(const StepArgs &a, const ResArgs &r, hipStream_t s);
 hipError_t resident_prepare(const StepArgs &a, int *blocks_per_cu);
 hipError_t step_set_lds_limit(int prec, int ne, int tdk, int tdc, int gen, int op, int bytes);
 hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s);
+hipError_t adjres_prepare(int prec, int block, int lds, int *blocks_per_cu);
+hipError_t launch_adjres(const AdjArgs &a, const AdjResArgs &r, hipStream_t s);
 hipError_t adjoint_set_lds_limit(int prec, int ne, int op, int bytes);
 // g_h[f] = -|f|/n_f * sum over the face's nodes of (S1 - Ta_f S0)
 hipError_t launch_face_grad(int64_t nf, int nfn, const int32_t *faces, const int32_t *perm,
@@ -217,6 +232,10 @@ hipError_t launch_get_T(int prec, int64_t N, const int32_t *perm, const void *T,
 hipError_t launch_check(int prec, int64_t N, const void *T, const float *lo, double lo_b,
                         double hi_b, int *flag, hipStream_t s);
 // gather/scatter of raw working arrays between caller and internal order
+// smallest / largest temperature as order keys (keys[0] must start at ~0,
+// keys[1] at 0); *nan |= 1 if a temperature is not finite
+hipError_t launch_range(int prec, int64_t N, const void *T, const float *lo,
+                        unsigned long long *keys, int *nan, hipStream_t s);
 hipError_t launch_permute(int elem_bytes, int64_t N, const int32_t *perm, const void *src,
                           void *dst, int to_internal, hipStream_t s);
 

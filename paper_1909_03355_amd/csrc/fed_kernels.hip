@@ -529,19 +529,25 @@ struct Elem<R, 8> {
   // differences (each a difference of nearby values, so exact or nearly so).
   __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
                               const R h[6], R F[8]) {
+    R T[8];
+#pragma unroll
+    for (int n = 0; n < 8; n++) T[n] = Tl[loc[n]];
+    load_vals(T, kl, tdk, h, F);
+  }
+  __device__ static void load_vals(const R *T, const KLaw<R> &kl, bool tdk, const R h[6], R F[8]) {
     // rounding fixed by the source in every kernel that inlines this (no
-    // FMA contraction), so all step kernels agree bit for bit
+    // FMA contraction; the FMAs are written out), so all step kernels agree
+    // bit for bit
     #pragma clang fp contract(off)
-    R T0 = Tl[loc[0]], T1 = Tl[loc[1]], T2 = Tl[loc[2]], T3 = Tl[loc[3]];
-    R T4 = Tl[loc[4]], T5 = Tl[loc[5]], T6 = Tl[loc[6]], T7 = Tl[loc[7]];
+    const R T0 = T[0], T1 = T[1], T2 = T[2], T3 = T[3], T4 = T[4], T5 = T[5], T6 = T[6], T7 = T[7];
     R ux = ((T1 - T0) + (T2 - T3)) + ((T5 - T4) + (T6 - T7));
     R uy = ((T3 - T0) + (T2 - T1)) + ((T7 - T4) + (T6 - T5));
     R uz = ((T4 - T0) + (T5 - T1)) + ((T6 - T2) + (T7 - T3));
     R s = kl.s0;
     if (tdk) s = kl((((T0 + T1) + (T2 + T3)) + ((T4 + T5) + (T6 + T7))) * (R)0.125);
-    R qx = s * (h[0] * ux + h[3] * uy + h[5] * uz);
-    R qy = s * (h[3] * ux + h[1] * uy + h[4] * uz);
-    R qz = s * (h[5] * ux + h[4] * uy + h[2] * uz);
+    R qx = s * fma(h[5], uz, fma(h[3], uy, h[0] * ux));
+    R qy = s * fma(h[4], uz, fma(h[1], uy, h[3] * ux));
+    R qz = s * fma(h[2], uz, fma(h[4], uy, h[5] * ux));
     R a = qx + qy, b = qx - qy;
     F[0] = -a - qz;
     F[1] = b - qz;
@@ -563,9 +569,9 @@ struct Elem<R, 4> {
     R d1 = T1 - T0, d2 = T2 - T0, d3 = T3 - T0;
     R s = kl.s0;
     if (tdk) s = kl(((T0 + T1) + (T2 + T3)) * (R)0.25);
-    F[1] = s * (h[0] * d1 + h[3] * d2 + h[5] * d3);
-    F[2] = s * (h[3] * d1 + h[1] * d2 + h[4] * d3);
-    F[3] = s * (h[5] * d1 + h[4] * d2 + h[2] * d3);
+    F[1] = s * fma(h[5], d3, fma(h[3], d2, h[0] * d1));
+    F[2] = s * fma(h[4], d3, fma(h[1], d2, h[3] * d1));
+    F[3] = s * fma(h[2], d3, fma(h[4], d2, h[5] * d1));
     F[0] = -((F[1] + F[2]) + F[3]);
   }
 };
@@ -648,7 +654,11 @@ struct Ent<4> {
 // element loads of one expanded element into the LDS slots of the nodes that
 // this sub-step updates (local index < nupd); slot (node j, position p) lives at
 // p * stride + j
-template <typename R, int NE, bool TDK, int OP = 0>
+// NM: node-major slots, every touched node's (node j, position p) at
+// j * (2^pb + 1) + p, which is the packed entry plus the local index: no
+// multiply, no test (the halo nodes' slots take the values no owned node
+// needs), and an odd stride keeps the LDS banks of neighbouring nodes apart.
+template <typename R, int NE, bool TDK, int OP = 0, bool NM = false>
 __device__ inline void element_to_slots(const typename Ent<NE>::T &w, const R *h, const R *Tl,
                                         R *slot, int stride, int nupd, int pb, uint32_t pmask,
                                         const KLaw<R> &kl) {
@@ -660,7 +670,8 @@ __device__ inline void element_to_slots(const typename Ent<NE>::T &w, const R *h
   Op<R, NE, OP>::load(Tl, loc, kl, TDK, h, F);
 #pragma unroll
   for (int n = 0; n < NE; n++)
-    if (loc[n] < (uint32_t)nupd) slot[(v[n] & pmask) * stride + loc[n]] = F[n];
+    if (NM) slot[v[n] + loc[n]] = F[n];
+    else if (loc[n] < (uint32_t)nupd) slot[(v[n] & pmask) * stride + loc[n]] = F[n];
 }
 
 // law of expanded element e: the shared one, or the element's material's
@@ -1198,19 +1209,21 @@ struct ElemAdj<R, 4> {
 template <typename R, int NE, int OP>
 struct AdjDot {
   __device__ static R dot(const R *Lmu, const R *LT, const uint32_t *loc, const R *h) {
+#pragma clang fp contract(off)
     // (S mu)^T Hhat (S T)
     R mx, my, mz, tx, ty, tz;
     ElemAdj<R, NE>::u(Lmu, loc, mx, my, mz);
     ElemAdj<R, NE>::u(LT, loc, tx, ty, tz);
-    const R qx = h[0] * tx + h[3] * ty + h[5] * tz;
-    const R qy = h[3] * tx + h[1] * ty + h[4] * tz;
-    const R qz = h[5] * tx + h[4] * ty + h[2] * tz;
-    return mx * qx + my * qy + mz * qz;
+    const R qx = fma(h[5], tz, fma(h[3], ty, h[0] * tx));
+    const R qy = fma(h[4], tz, fma(h[1], ty, h[3] * tx));
+    const R qz = fma(h[2], tz, fma(h[4], ty, h[5] * tx));
+    return fma(mz, qz, fma(my, qy, mx * qx));
   }
 };
 template <typename R>
 struct AdjDot<R, 8, 1> {
   __device__ static R dot(const R *Lmu, const R *LT, const uint32_t *loc, const R *h) {
+#pragma clang fp contract(off)
     // (Bbar mu)^T (V D) (Bbar T)
     R g[2][3] = {};
     const R *V2[2] = {Lmu, LT};
@@ -1233,6 +1246,115 @@ struct AdjDot<R, 8, 1> {
   }
 };
 
+// The arithmetic of the adjoint step, shared by the one-step and the resident
+// kernels so that both round alike (no FMA contraction: the source fixes it).
+
+// Per touched node at step n: mu = lambda^{n+1} / den(T^n) (0 on Dirichlet
+// nodes, den = +inf), and w = mu (T^{n+1} - T^n) / dt dc/dc0 (dc/dc0 = 1, or the
+// c table's value at T^n), the node's term of the capacity derivative.
+template <typename R>
+__device__ inline void adj_stage(R lam, R alpha, R beta, R tn, R tn1, R rdt, bool tdc,
+                                 const R *ctab, int nct, R &mu, R &w) {
+#pragma clang fp contract(off)
+  const R den = tdc ? cap_den(alpha, beta, tn, ctab, nct) : alpha;
+  mu = lam / den;
+  R dcdc0 = (R)1, sl;
+  if (nct) dcdc0 = table_eval(ctab, nct, tn, sl);
+  w = mu * ((tn1 - tn) * rdt * dcdc0);
+}
+
+// Element part: F = s_e K0_e mu_e plus the k(Tbar) term spread evenly over the
+// nodes, s_e, mu_e . K0_e T_e (when needed) and the sum of w over the nodes.
+template <typename R, int NE, int OP>
+__device__ inline void adj_elem(const uint32_t *loc, const R *h, const KLaw<R> &kle, bool tdk,
+                                bool owner, const R *Lmu, const R *LT, const R *Lw, R F[NE],
+                                R &se, R &muKT, R &gsum) {
+#pragma clang fp contract(off)
+  // s_e and ds_e/dTbar at the element mean of T^n (summed as in the forward load)
+  se = kle.s0;
+  R dse = (R)0;
+  if (tdk) {
+    R sum;
+    if (NE == 8)
+      sum = ((LT[loc[0]] + LT[loc[1]]) + (LT[loc[2]] + LT[loc[3]])) +
+            ((LT[loc[4]] + LT[loc[5]]) + (LT[loc[6]] + LT[loc[7]]));
+    else
+      sum = (LT[loc[0]] + LT[loc[1]]) + (LT[loc[2]] + LT[loc[3]]);
+    const R mean = sum * ((R)1 / (R)NE);
+    if (kle.n) {
+      se = table_eval(kle.tab, kle.n, mean, dse);
+    } else {
+      se = kle(mean);
+      dse = kle.s1;
+    }
+  }
+  muKT = (R)0;
+  if (tdk || owner) muKT = AdjDot<R, NE, OP>::dot(Lmu, LT, loc, h);
+  // the forward element load applied to mu at factor s_e
+  Op<R, NE, OP>::load(Lmu, loc, KLaw<R>{se, (R)0, nullptr, 0}, false, h, F);
+  const R spread = tdk ? dse * ((R)1 / (R)NE) * muKT : (R)0;
+#pragma unroll
+  for (int n = 0; n < NE; n++) F[n] = F[n] + spread;
+  gsum = (R)0;
+  if (owner) {
+#pragma unroll
+    for (int n = 0; n < NE; n++) gsum = gsum + Lw[loc[n]];
+  }
+}
+
+// Per-step parameter derivatives of an owner element, accumulated in FP64.
+template <typename R>
+__device__ inline void adj_grad(double &gk, double &gc, R se, R muKT, R mV, R gsum) {
+#pragma clang fp contract(off)
+  gk = gk + -(double)se * (double)muKT;
+  gc = gc + -(double)mV * (double)gsum;
+}
+
+// Node part: lambda^n - lambda^{n+1} of an owned node before the Dirichlet mask.
+template <typename R>
+__device__ inline R adj_node(R F, R mu, bool bnd, R rA, R reA, R tn, R tn1, R Tz, bool tdc,
+                             R dden) {
+#pragma clang fp contract(off)
+  R d = -F;
+  if (bnd) {
+    const R x = tn - Tz;
+    d = d - (rA + (R)4 * reA * (x * x * x)) * mu;
+  }
+  if (tdc) d = d - dden * (tn1 - tn) * mu;
+  return d;
+}
+
+// Sums of mu and mu T^n of a boundary node (for the face derivatives).
+template <typename R>
+__device__ inline void adj_bnd(double &S0, double &S1, R mu, R tn) {
+#pragma clang fp contract(off)
+  S0 = S0 + (double)mu;
+  S1 = S1 + (double)mu * (double)tn;
+}
+
+// lambda^n from lambda^{n+1} = (hi, lo) and d, zero on Dirichlet nodes.
+template <typename R, int MODE>
+__device__ inline R adj_lambda(R hi, float lo, R d, bool fixed, float &lo_new) {
+#pragma clang fp contract(off)
+  if (MODE == 1) {
+    const float yv = (float)d + lo;
+    const float tv = (float)hi + yv;
+    lo_new = fixed ? 0.0f : yv - (tv - (float)hi);
+    return fixed ? (R)0 : (R)tv;
+  }
+  lo_new = 0.0f;
+  return fixed ? (R)0 : hi + d;
+}
+
+// d den / dT: beta, or alpha times the c table's slope at T^n
+template <typename R>
+__device__ inline R adj_dden(R alpha, R beta, R tn, const R *ctab, int nct) {
+  if (!nct) return beta;
+  R sl;
+  (void)table_eval(ctab, nct, tn, sl);
+  return alpha * sl;
+}
+
 template <typename R, int NE, int MODE, int OP = 0>
 __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   constexpr int HW = Op<R, NE, OP>::W;
@@ -1245,11 +1367,11 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   const int nhalo = a.tiles[t].cum_n[1] - th.nown;
   const int tid = threadIdx.x, bs = blockDim.x;
   const int nown = th.nown, ntouch = nown + nhalo;
-  // LDS: mu, T^n and (T^{n+1} - T^n) / dt of touched nodes, slots of owned nodes
+  // LDS: mu, T^n and w of touched nodes, slots of owned nodes
   R *Lmu = reinterpret_cast<R *>(smem_raw);
   R *LT = Lmu + ntouch;
-  R *Ld = LT + ntouch;
-  R *slot = Ld + ntouch;
+  R *Lw = LT + ntouch;
+  R *slot = Lw + ntouch;
   const R *lam = (const R *)a.lamin, *alpha = (const R *)a.alpha, *rdt = (const R *)a.rdt;
   const R *beta = (const R *)a.beta;
   const R *Tn = (const R *)a.Tn, *Tn1 = (const R *)a.Tn1;
@@ -1258,14 +1380,9 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   for (int j = tid; j < ntouch; j += bs) {
     const int g = j < nown ? th.nstart + j : a.halo[th.hstart + j - nown];
     const R tn = Tn[g];
-    R den = alpha[g];
-    if (tdc) den = cap_den(alpha[g], beta[g], tn, ctab, a.nct);
-    Lmu[j] = lam[g] / den;  // 0 on Dirichlet nodes (alpha = +inf)
+    adj_stage<R>(lam[g], alpha[g], tdc ? beta[g] : (R)0, tn, Tn1[g], rdt[g], tdc, ctab, a.nct,
+                 Lmu[j], Lw[j]);
     LT[j] = tn;
-    // increment per time step, times dc/dc0 (1, or the c table's value)
-    R dcdc0 = (R)1, sl;
-    if (a.nct) dcdc0 = table_eval(ctab, a.nct, tn, sl);
-    Ld[j] = (Tn1[g] - tn) * rdt[g] * dcdc0;
   }
   const int nslot = a.maxinc * nown;
   for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
@@ -1278,7 +1395,6 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   const uint32_t pmask = (1u << a.pb) - 1u;
   for (int i = tid; i < nE; i += bs) {
     const int64_t e = (int64_t)th.estart + i;
-    const KLaw<R> kle = elem_law<true>(a, kl, e);
     R h[HW];
 #pragma unroll
     for (int r = 0; r < HW; r++) h[r] = Hb[(int64_t)r * a.Eexp + e];
@@ -1288,41 +1404,18 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
 #pragma unroll
     for (int n = 0; n < NE; n++) loc[n] = v[n] >> a.pb;
     const bool owner = a.eowner[e] != 0;
-    // s_e and ds_e/dTbar at the element mean of T^n (summed as in the forward load)
-    R se = kle.s0, dse = (R)0;
-    if (tdk) {
-      R sum;
-      if (NE == 8)
-        sum = ((LT[loc[0]] + LT[loc[1]]) + (LT[loc[2]] + LT[loc[3]])) +
-              ((LT[loc[4]] + LT[loc[5]]) + (LT[loc[6]] + LT[loc[7]]));
-      else
-        sum = (LT[loc[0]] + LT[loc[1]]) + (LT[loc[2]] + LT[loc[3]]);
-      const R mean = sum * ((R)1 / (R)NE);
-      if (kle.n) {
-        se = table_eval(kle.tab, kle.n, mean, dse);
-      } else {
-        se = kle(mean);
-        dse = kle.s1;
-      }
-    }
-    // mu_e . K0_e T_e
-    R muKT = 0;
-    if (tdk || owner) muKT = AdjDot<R, NE, OP>::dot(Lmu, LT, loc, h);
-    // s_e K0_e mu_e (the forward element load with mu at factor s_e), plus the
-    // k(Tbar) term spread evenly over the element's nodes
-    R F[NE];
-    Op<R, NE, OP>::load(Lmu, loc, KLaw<R>{se, (R)0, nullptr, 0}, false, h, F);
-    const R spread = tdk ? dse * ((R)1 / (R)NE) * muKT : (R)0;
+    R F[NE], se, muKT, gsum;
+    adj_elem<R, NE, OP>(loc, h, elem_law<true>(a, kl, e), tdk, owner, Lmu, LT, Lw, F, se, muKT,
+                        gsum);
 #pragma unroll
     for (int n = 0; n < NE; n++)
-      if (loc[n] < (uint32_t)nown) slot[(v[n] & pmask) * nown + loc[n]] = F[n] + spread;
+      if (loc[n] < (uint32_t)nown) slot[(v[n] & pmask) * nown + loc[n]] = F[n];
     if (owner) {
-      R gc = 0;
-#pragma unroll
-      for (int n = 0; n < NE; n++) gc += Lmu[loc[n]] * Ld[loc[n]];
       const int32_t eo = a.eorig[e];
-      a.g_logk[eo] += -(double)se * (double)muKT;
-      a.g_c[eo] += -(double)mV[eo] * (double)gc;
+      double gk = a.g_logk[eo], gc = a.g_c[eo];
+      adj_grad<R>(gk, gc, se, muKT, mV[eo], gsum);
+      a.g_logk[eo] = gk;
+      a.g_c[eo] = gc;
     }
   }
   __syncthreads();
@@ -1331,37 +1424,23 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   R *lout = (R *)a.lamout;
   for (int j = tid; j < nown; j += bs) {
     const int k = th.nstart + j;
-    R F = slot[j];
-    for (int p = 1; p < a.maxinc; p++) F += slot[p * nown + j];
-    const R mu = Lmu[j];
-    R d = -F;
-    if (j < th.nbnd) {
-      const int r = th.bstart + j;
-      const R x = LT[j] - Tz;
-      d -= (rA[r] + (R)4 * reA[r] * (x * x * x)) * mu;
-      a.S0[r] += (double)mu;
-      a.S1[r] += (double)mu * (double)LT[j];
+    const R F = slot_sum(slot, j, nown, a.maxinc);
+    const R mu = Lmu[j], tn = LT[j], tn1 = Tn1[k];
+    const bool bnd = j < th.nbnd;
+    const int r = th.bstart + j;
+    const R dden = tdc ? adj_dden<R>(alpha[k], beta[k], tn, ctab, a.nct) : (R)0;
+    const R d = adj_node<R>(F, mu, bnd, bnd ? rA[r] : (R)0, bnd ? reA[r] : (R)0, tn, tn1, Tz, tdc,
+                            dden);
+    if (bnd) {
+      double S0 = a.S0[r], S1 = a.S1[r];
+      adj_bnd<R>(S0, S1, mu, tn);
+      a.S0[r] = S0;
+      a.S1[r] = S1;
     }
-    if (tdc) {
-      // d den / dT: beta, or alpha times the c table's slope
-      R dden = beta[k];
-      if (a.nct) {
-        R sl;
-        (void)table_eval(ctab, a.nct, LT[j], sl);
-        dden = alpha[k] * sl;
-      }
-      d -= dden * (Tn1[k] - LT[j]) * mu;
-    }
-    const bool fixed = alpha[k] == (R)INFINITY;
-    if (MODE == 1) {
-      const float hi = (float)lam[k], lo = a.lamloin[k];
-      const float yv = (float)d + lo;
-      const float tv = hi + yv;
-      lout[k] = fixed ? (R)0 : (R)tv;
-      a.lamloout[k] = fixed ? 0.0f : yv - (tv - hi);
-    } else {
-      lout[k] = fixed ? (R)0 : lam[k] + d;
-    }
+    float lo_new;
+    lout[k] = adj_lambda<R, MODE>(lam[k], MODE == 1 ? a.lamloin[k] : 0.0f, d,
+                                  alpha[k] == (R)INFINITY, lo_new);
+    if (MODE == 1) a.lamloout[k] = lo_new;
   }
 }
 
@@ -1428,6 +1507,46 @@ __global__ void k_check(int64_t N, const R *T, const float *lo, double lo_b, dou
   if (!(v >= lo_b && v <= hi_b)) atomicOr(flag, 1);  // also catches NaN
 }
 
+// Order-preserving unsigned key of a double (larger key, larger value).
+__device__ inline unsigned long long order_key(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// Smallest and largest temperature (hi + lo) as order keys in keys[0], keys[1]
+// (block reduction, then one atomic per block); *nan set if any is not finite.
+template <typename R, int MODE>
+__global__ void k_range(int64_t N, const R *T, const float *lo, unsigned long long *keys, int *nan) {
+  __shared__ unsigned long long smin[1024 / 64], smax[1024 / 64];
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  unsigned long long kmin = ~0ull, kmax = 0ull;
+  if (k < N) {
+    double v = (double)T[k];
+    if (MODE == 1) v += (double)lo[k];
+    if (!isfinite(v)) atomicOr(nan, 1);
+    kmin = kmax = order_key(v);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long a = __shfl_down(kmin, off, 64), b = __shfl_down(kmax, off, 64);
+    kmin = a < kmin ? a : kmin;
+    kmax = b > kmax ? b : kmax;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    smin[w] = kmin;
+    smax[w] = kmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); i++) {
+      kmin = smin[i] < kmin ? smin[i] : kmin;
+      kmax = smax[i] > kmax ? smax[i] : kmax;
+    }
+    atomicMin(&keys[0], kmin);
+    atomicMax(&keys[1], kmax);
+  }
+}
+
 __global__ void k_permute(int eb, int64_t N, const int32_t *perm, const unsigned char *src,
                           unsigned char *dst, int to_internal) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1478,6 +1597,23 @@ __device__ inline void keep_packed(uint2 &w) {
   w = make_uint2(x, y);
 }
 
+// LDS addresses as 32-bit integers (the local address space), so a kernel can
+// keep precomputed addresses in registers and access LDS with no arithmetic
+template <typename R>
+using LdsPtr = __attribute__((address_space(3))) R *;
+template <typename R>
+__device__ inline uint32_t lds_addr(R *p) {
+  return (uint32_t)(uintptr_t)(LdsPtr<R>)p;
+}
+template <typename R>
+__device__ inline R lds_ld(uint32_t a) {
+  return *(LdsPtr<R>)(uintptr_t)a;
+}
+template <typename R>
+__device__ inline void lds_st(uint32_t a, R v) {
+  *(LdsPtr<R>)(uintptr_t)a = v;
+}
+
 // 64-bit loads and stores, single-copy atomic and coherent across the XCDs'
 // L2 caches
 __device__ inline unsigned long long ld_word(const unsigned long long *p) {
@@ -1493,33 +1629,73 @@ __device__ inline unsigned long long tagged(unsigned tag, uint32_t bits) {
 // tagged words of one value: 1 for float, 2 (low, high half) for double
 template <typename R>
 struct Words;
+// (ld: the raw words; ok: they carry `tag`; val: the value they hold)
 template <>
 struct Words<float> {
   static constexpr int W = 1;
+  struct Raw {
+    unsigned long long w;
+  };
   __device__ static void put(unsigned long long *X, int k, unsigned tag, float v) {
     st_word(X + k, tagged(tag, __float_as_uint(v)));
   }
-  // true once the word carries `tag`; then v holds the value
-  __device__ static bool get(const unsigned long long *X, int k, unsigned tag, float &v) {
-    const unsigned long long w = ld_word(X + k);
-    v = __uint_as_float((uint32_t)w);
-    return (unsigned)(w >> 32) == tag;
-  }
+  __device__ static Raw ld(const unsigned long long *X, int k) { return Raw{ld_word(X + k)}; }
+  __device__ static bool ok(const Raw &r, unsigned tag) { return (unsigned)(r.w >> 32) == tag; }
+  __device__ static float val(const Raw &r) { return __uint_as_float((uint32_t)r.w); }
 };
 template <>
 struct Words<double> {
   static constexpr int W = 2;
+  struct Raw {
+    unsigned long long w0, w1;
+  };
   __device__ static void put(unsigned long long *X, int k, unsigned tag, double v) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
     st_word(X + 2 * (int64_t)k, tagged(tag, (uint32_t)b));
     st_word(X + 2 * (int64_t)k + 1, tagged(tag, (uint32_t)(b >> 32)));
   }
-  __device__ static bool get(const unsigned long long *X, int k, unsigned tag, double &v) {
-    const unsigned long long w0 = ld_word(X + 2 * (int64_t)k), w1 = ld_word(X + 2 * (int64_t)k + 1);
-    v = __longlong_as_double((long long)(((w1 & 0xffffffffull) << 32) | (w0 & 0xffffffffull)));
-    return (unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag;
+  __device__ static Raw ld(const unsigned long long *X, int k) {
+    return Raw{ld_word(X + 2 * (int64_t)k), ld_word(X + 2 * (int64_t)k + 1)};
+  }
+  __device__ static bool ok(const Raw &r, unsigned tag) {
+    return (unsigned)(r.w0 >> 32) == tag && (unsigned)(r.w1 >> 32) == tag;
+  }
+  __device__ static double val(const Raw &r) {
+    return __longlong_as_double((long long)(((r.w1 & 0xffffffffull) << 32) | (r.w0 & 0xffffffffull)));
   }
 };
+
+// Polls a thread's halo words until each carries `want`, the values into hv.
+// A poll issues the loads of all the thread's missing words before it looks
+// at any, so it costs one memory round trip.  Gives up after spin_limit
+// polls, or soon after another wave gave up, and sets *err.
+template <typename R, int HPT>
+__device__ inline void wait_halo(const unsigned long long *X, const int *hid, int nleft, int bs,
+                                 unsigned want, R *hv, int spin_limit, int *err) {
+  unsigned missing = 0;
+#pragma unroll
+  for (int q = 0; q < HPT; q++)
+    if (q * bs < nleft) missing |= 1u << q;
+  for (int it = 0; missing; it++) {
+    typename Words<R>::Raw w[HPT];
+#pragma unroll
+    for (int q = 0; q < HPT; q++)
+      if ((missing >> q) & 1u) w[q] = Words<R>::ld(X, hid[q]);
+#pragma unroll
+    for (int q = 0; q < HPT; q++)
+      if (((missing >> q) & 1u) && Words<R>::ok(w[q], want)) {
+        hv[q] = Words<R>::val(w[q]);
+        missing &= ~(1u << q);
+      }
+    if (!missing) return;
+    if (it >= spin_limit ||
+        ((it & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
 
 template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN>
 __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
@@ -1548,6 +1724,34 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       for (int c = 0; c < 6; c++) eh[q][c] = Hb[(int64_t)c * a.Eexp + e];
     }
   }
+  // hexahedra use node-major slots (below).  FP32 hexahedra keep precomputed
+  // LDS addresses instead of the packed entries: the node temperatures' as
+  // 16-bit halves (4 registers an element) and the slots' as words (8), so
+  // the element phase spends no instructions on addressing
+  constexpr bool NM = NE == 8;
+  constexpr bool PRE = NM && sizeof(R) == 4;
+  const int nslot = NM ? ntouch * ((1 << a.pb) + 1) : a.maxinc * nown;
+  R *Tl = reinterpret_cast<R *>(smem_raw);
+  R *slot = Tl + ntouch;
+  R *Lbnd = slot + nslot;  // [5][nbnd]: hA, hA Ta, sigma eps A, radiation Ta, power
+  uint4 ta[PRE ? EPT : 1];
+  uint32_t sa[PRE ? EPT : 1][8];
+  if constexpr (PRE) {
+    const uint32_t tb = lds_addr(Tl), sb = lds_addr(slot);
+#pragma unroll
+    for (int q = 0; q < EPT; q++) {
+      uint32_t v[8], u[8];
+      Ent<8>::unpack(*reinterpret_cast<const uint4 *>(&ew[q]), v);
+#pragma unroll
+      for (int n = 0; n < 8; n++) {
+        const uint32_t loc = v[n] >> a.pb;
+        u[n] = tb + loc * (uint32_t)sizeof(R);
+        sa[q][n] = sb + (v[n] + loc) * (uint32_t)sizeof(R);
+      }
+      ta[q] = make_uint4(u[0] | (u[1] << 16), u[2] | (u[3] << 16), u[4] | (u[5] << 16),
+                         u[6] | (u[7] << 16));
+    }
+  }
   const R *Tin = (const R *)a.Tin;
   // per owned node in registers: alpha, beta, lo, hi, exported; the boundary
   // records (5 coefficients of the first nbnd nodes) live in LDS
@@ -1573,9 +1777,8 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     const int j = tid + q * bs;
     hid[q] = j < nhalo ? a.halo[th.hstart + j] : 0;
   }
-  R *Tl = reinterpret_cast<R *>(smem_raw);
-  R *slot = Tl + ntouch;
-  R *Lbnd = slot + a.maxinc * nown;  // [5][nbnd]: hA, hA Ta, sigma eps A, radiation Ta, power
+  // hexahedra: node-major slots of every touched node (element phase without
+  // tests); tetrahedra (24 slots a node): position-major, owned nodes only
   const int nbnd = th.nbnd;
   for (int j = tid; j < nbnd; j += bs) {
     const int rr = th.bstart + j;
@@ -1586,11 +1789,14 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     Lbnd[4 * nbnd + j] = ((const R *)a.rP)[rr];
   }
   // slots past a node's incidence are never written and stay zero
-  for (int j = tid; j < a.maxinc * nown; j += bs) slot[j] = (R)0;
+  for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
   const KLaw<R> kl = step_law<R, GEN>(a);
   const R Tz = (R)a.Tz;
   const uint32_t pmask = (1u << a.pb) - 1u;
   for (int s = 0; s < r.nsteps; s++) {
+    // the previous step's stores (exports) complete before the halo poll
+    // starts: polling while they drain is slower (s_waitcnt vmcnt(0))
+    __builtin_amdgcn_s_waitcnt(0x0f70);
     // ---- stage T: owned from registers, halo from the state or the exchange ----
 #pragma unroll
     for (int q = 0; q < NPT; q++) {
@@ -1604,22 +1810,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     } else {
       const unsigned long long *X = r.X[s & 1];
       const unsigned want = r.tag0 + (unsigned)s;
-      unsigned pending = 0;
-#pragma unroll
-      for (int q = 0; q < HPT; q++)
-        if (tid + q * bs < nhalo) pending |= 1u << q;
-      for (int it = 0; pending; it++) {
-#pragma unroll
-        for (int q = 0; q < HPT; q++)
-          if ((pending >> q) & 1u)
-            if (Words<R>::get(X, hid[q], want, hv[q])) pending &= ~(1u << q);
-        if (!pending) break;
-        if (it >= r.spin_limit || __hip_atomic_load(r.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          __hip_atomic_store(r.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
+      wait_halo<R, HPT>(X, hid, nhalo - tid, bs, want, hv, r.spin_limit, r.err);
     }
 #pragma unroll
     for (int q = 0; q < HPT; q++) {
@@ -1631,8 +1822,20 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
 #pragma unroll
     for (int q = 0; q < EPT; q++)
       if (tid + q * bs < nE) {
-        keep_packed(ew[q]);
-        element_to_slots<R, NE, TDK>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, kl);
+        if constexpr (PRE) {
+          keep_packed(ta[q]);
+          uint32_t u[8];
+          Ent<8>::unpack(ta[q], u);
+          R T[8], F[8];
+#pragma unroll
+          for (int n = 0; n < 8; n++) T[n] = lds_ld<R>(u[n]);
+          Elem<R, 8>::load_vals(T, kl, TDK, eh[q], F);
+#pragma unroll
+          for (int n = 0; n < 8; n++) lds_st<R>(sa[q][n], F[n]);
+        } else {
+          keep_packed(ew[q]);
+          element_to_slots<R, NE, TDK, 0, NM>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, kl);
+        }
       }
     __syncthreads();
     // ---- per node: ordered sum, surface loads, explicit update, export ----
@@ -1644,7 +1847,8 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     for (int q = 0; q < NPT; q++) {
       const int j = tid + q * bs;
       if (j < nown) {
-        const R F = slot_sum(slot, j, nown, a.maxinc);
+        const R F = NM ? slot_sum(slot + j * ((1 << a.pb) + 1), 0, 1, a.maxinc)
+                       : slot_sum(slot, j, nown, a.maxinc);
         Node1<R> d;
         d.alpha = al[q];
         d.beta = be[q];
@@ -1676,6 +1880,241 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       if (MODE == 1) r.lofin[th.nstart + j] = lo[q];
     }
   }
+}
+
+// Resident adjoint: one cooperative launch runs the adjoint steps n1-1 .. n0
+// of a checkpoint segment on the tiles of the resident forward kernel.  A tile
+// keeps its elements (entries, operator) and its owned nodes' lambda in
+// registers, the FP64 derivative sums of the elements it owns in registers
+// (FP32) or LDS (FP64), and the boundary sums and per touched node alpha, beta,
+// 1/dt and T^{n+1} in LDS; T^n of every node comes from the segment's stored
+// states.  The halo's lambda^{n+1} travels as
+// in the forward kernel: from the input at the first step, then through the
+// tagged exchange words (the tiles and their neighbour relation are the
+// forward's).  The arithmetic is that of k_adjoint1, so both give
+// bitwise-identical multipliers and derivatives.
+template <typename R, int MODE>
+__global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
+  constexpr int NE = 8;
+  constexpr int EPT = ResCap<R, NE>::EPT, NPT = ResCap<R, NE>::NPT, HPT = ResCap<R, NE>::HPT;
+  constexpr bool GREG = sizeof(R) == 4;  // derivative sums in registers, else LDS
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const int t = (b & 7) * a.nper + (b >> 3);
+  if (t >= a.nt) return;  // no tile: nobody reads from it
+  const TileHdr th = a.tiles[t];
+  const int nE = a.tiles[t].cum_e[0];
+  const int nhalo = a.tiles[t].cum_n[1] - th.nown;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int nown = th.nown, ntouch = nown + nhalo, nbnd = th.nbnd;
+  const bool tdk = a.tdk != 0, tdc = a.tdc != 0;
+  // LDS: FP64 boundary sums S0, S1 of the owned boundary nodes and (FP64
+  // steps) the owners' derivative sums and rho V / n_e; then mu, w, T^n and T^{n+1} (two
+  // buffers that swap every step), alpha, 1/dt (and beta) of the touched
+  // nodes; the slots of the owned nodes; hA and sigma eps A of the owned
+  // boundary nodes
+  double *LS0 = reinterpret_cast<double *>(smem_raw);
+  double *LS1 = LS0 + nbnd;
+  double *Lgk = LS1 + nbnd;
+  double *Lgc = Lgk + (GREG ? 0 : nE);
+  R *Lmv = reinterpret_cast<R *>(Lgc + (GREG ? 0 : nE));  // FP64: rho V / n_e of the owners
+  R *Lmu = Lmv + (GREG ? 0 : nE);
+  R *Lw = Lmu + ntouch;
+  R *LTa = Lw + ntouch;
+  R *LTb = LTa + ntouch;
+  R *Lal = LTb + ntouch;
+  R *Lrdt = Lal + ntouch;
+  R *Lbe = Lrdt + ntouch;  // tdc only
+  R *slot = Lbe + (tdc ? ntouch : 0);
+  R *LrA = slot + a.maxinc * nown;
+  R *LreA = LrA + nbnd;
+  const R *ctab = (const R *)a.ctab;
+  using EntT = typename Ent<NE>::T;
+  const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
+  const R *Hb = (const R *)a.H;
+  EntT ew[EPT];
+  R eh[EPT][6], emv[GREG ? EPT : 1];
+  double gk[GREG ? EPT : 1], gc[GREG ? EPT : 1];
+  uint32_t own = 0;
+#pragma unroll
+  for (int q = 0; q < EPT; q++) {
+    const int i = tid + q * bs;
+    if (GREG) {
+      gk[q] = gc[q] = 0.0;
+      emv[q] = (R)0;
+    }
+    if (i < nE) {
+      const int64_t e = (int64_t)th.estart + i;
+      ew[q] = ent[e];
+#pragma unroll
+      for (int c = 0; c < 6; c++) eh[q][c] = Hb[(int64_t)c * a.Eexp + e];
+      if (a.eowner[e]) {
+        const int32_t eo = a.eorig[e];
+        own |= 1u << q;
+        if (GREG) {
+          gk[q] = a.g_logk[eo];
+          gc[q] = a.g_c[eo];
+          emv[q] = ((const R *)a.mV)[eo];
+        } else {
+          Lgk[i] = a.g_logk[eo];
+          Lgc[i] = a.g_c[eo];
+          Lmv[i] = ((const R *)a.mV)[eo];
+        }
+      }
+    }
+  }
+  const R *lamin = (const R *)a.lamin;
+  R lam[NPT];
+  float llo[NPT];
+  bool ex[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; q++) {
+    const int j = tid + q * bs;
+    ex[q] = false;
+    if (j < nown) {
+      const int k = th.nstart + j;
+      lam[q] = lamin[k];
+      llo[q] = MODE == 1 ? a.lamloin[k] : 0.0f;
+      ex[q] = r.exported[k] != 0;
+    }
+  }
+  int hid[HPT];
+#pragma unroll
+  for (int q = 0; q < HPT; q++) {
+    const int j = tid + q * bs;
+    hid[q] = j < nhalo ? a.halo[th.hstart + j] : 0;
+  }
+  const R *segT = (const R *)r.seg;
+  {
+    const R *Tlast = segT + (int64_t)r.nsteps * r.segN;  // T^{n1}
+    for (int j = tid; j < ntouch; j += bs) {
+      const int g = j < nown ? th.nstart + j : a.halo[th.hstart + j - nown];
+      Lal[j] = ((const R *)a.alpha)[g];
+      Lrdt[j] = ((const R *)a.rdt)[g];
+      if (tdc) Lbe[j] = ((const R *)a.beta)[g];
+      LTb[j] = Tlast[g];
+    }
+    for (int j = tid; j < nbnd; j += bs) {
+      LrA[j] = ((const R *)a.rA)[th.bstart + j];
+      LreA[j] = ((const R *)a.reA)[th.bstart + j];
+      LS0[j] = a.S0[th.bstart + j];
+      LS1[j] = a.S1[th.bstart + j];
+    }
+    // slots past a node's incidence are never written and stay zero
+    for (int j = tid; j < a.maxinc * nown; j += bs) slot[j] = (R)0;
+  }
+  __syncthreads();
+  const KLaw<R> kl = KLaw<R>{(R)a.s0, (R)a.s1, (const R *)a.ktab, a.nkt};
+  const R Tz = (R)a.Tz;
+  const uint32_t pmask = (1u << a.pb) - 1u;
+  R *LT = LTa, *LTp = LTb;  // T^n, T^{n+1}
+  for (int s = 0; s < r.nsteps; s++) {
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // as in k_resident
+    const R *Ti = segT + (int64_t)(r.nsteps - 1 - s) * r.segN;  // T^n, n = n1 - 1 - s
+    // ---- T^n of the touched nodes (stored states) ----
+    R tno[NPT], tnh[HPT];
+#pragma unroll
+    for (int q = 0; q < NPT; q++) tno[q] = tid + q * bs < nown ? Ti[th.nstart + tid + q * bs] : (R)0;
+#pragma unroll
+    for (int q = 0; q < HPT; q++) tnh[q] = tid + q * bs < nhalo ? Ti[hid[q]] : (R)0;
+    // ---- lambda^{n+1} of the halo: the input, or the exchange ----
+    R hv[HPT];
+    if (s == 0) {
+#pragma unroll
+      for (int q = 0; q < HPT; q++) hv[q] = tid + q * bs < nhalo ? lamin[hid[q]] : (R)0;
+    } else {
+      const unsigned long long *X = r.X[s & 1];
+      const unsigned want = r.tag0 + (unsigned)s;
+      wait_halo<R, HPT>(X, hid, nhalo - tid, bs, want, hv, r.spin_limit, r.err);
+    }
+    // ---- stage mu, w, T^n (owned by their node's thread, halo by the halo thread) ----
+#pragma unroll
+    for (int q = 0; q < NPT; q++) {
+      const int j = tid + q * bs;
+      if (j < nown) {
+        adj_stage<R>(lam[q], Lal[j], tdc ? Lbe[j] : (R)0, tno[q], LTp[j], Lrdt[j], tdc, ctab, a.nct,
+                     Lmu[j], Lw[j]);
+        LT[j] = tno[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < HPT; q++) {
+      const int j = nown + tid + q * bs;
+      if (j < ntouch) {
+        adj_stage<R>(hv[q], Lal[j], tdc ? Lbe[j] : (R)0, tnh[q], LTp[j], Lrdt[j], tdc, ctab, a.nct,
+                     Lmu[j], Lw[j]);
+        LT[j] = tnh[q];
+      }
+    }
+    __syncthreads();
+    // ---- elements: slots, and the owners' derivative sums ----
+#pragma unroll
+    for (int q = 0; q < EPT; q++)
+      if (tid + q * bs < nE) {
+        keep_packed(ew[q]);
+        uint32_t v[NE], loc[NE];
+        Ent<NE>::unpack(ew[q], v);
+#pragma unroll
+        for (int n = 0; n < NE; n++) loc[n] = v[n] >> a.pb;
+        const bool owner = (own >> q) & 1u;
+        R F[NE], se, muKT, gsum;
+        adj_elem<R, NE, 0>(loc, eh[q], kl, tdk, owner, Lmu, LT, Lw, F, se, muKT, gsum);
+#pragma unroll
+        for (int n = 0; n < NE; n++)
+          if (loc[n] < (uint32_t)nown) slot[(v[n] & pmask) * nown + loc[n]] = F[n];
+        if (owner) {
+          if (GREG) adj_grad<R>(gk[q], gc[q], se, muKT, emv[q], gsum);
+          else adj_grad<R>(Lgk[tid + q * bs], Lgc[tid + q * bs], se, muKT, Lmv[tid + q * bs], gsum);
+        }
+      }
+    __syncthreads();
+    // ---- owned nodes: lambda^n, boundary sums, export ----
+    // (the next staging rewrites only entries its own thread reads here)
+    unsigned long long *Xw = r.X[(s + 1) & 1];
+    const unsigned tag = r.tag0 + (unsigned)s + 1u;
+#pragma unroll
+    for (int q = 0; q < NPT; q++) {
+      const int j = tid + q * bs;
+      if (j < nown) {
+        const R F = slot_sum(slot, j, nown, a.maxinc);
+        const R mu = Lmu[j], tn = LT[j], tn1 = LTp[j], al = Lal[j];
+        const bool bnd = j < nbnd;
+        const R dden = tdc ? adj_dden<R>(al, Lbe[j], tn, ctab, a.nct) : (R)0;
+        const R d = adj_node<R>(F, mu, bnd, bnd ? LrA[j] : (R)0, bnd ? LreA[j] : (R)0, tn, tn1, Tz,
+                                tdc, dden);
+        if (bnd) adj_bnd<R>(LS0[j], LS1[j], mu, tn);
+        float lo_new;
+        lam[q] = adj_lambda<R, MODE>(lam[q], llo[q], d, al == (R)INFINITY, lo_new);
+        llo[q] = lo_new;
+        if (ex[q]) Words<R>::put(Xw, th.nstart + j, tag, lam[q]);
+      }
+    }
+    R *tmp = LT;
+    LT = LTp;
+    LTp = tmp;
+  }
+  // ---- results: lambda^{n0}, the boundary sums, the owners' derivative sums ----
+  R *lout = (R *)a.lamout;
+#pragma unroll
+  for (int q = 0; q < NPT; q++) {
+    const int j = tid + q * bs;
+    if (j < nown) {
+      lout[th.nstart + j] = lam[q];
+      if (MODE == 1) a.lamloout[th.nstart + j] = llo[q];
+      if (j < nbnd) {
+        a.S0[th.bstart + j] = LS0[j];
+        a.S1[th.bstart + j] = LS1[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < EPT; q++)
+    if ((own >> q) & 1u) {
+      const int i = tid + q * bs;
+      const int32_t eo = a.eorig[(int64_t)th.estart + i];
+      a.g_logk[eo] = GREG ? gk[q] : Lgk[i];
+      a.g_c[eo] = GREG ? gc[q] : Lgc[i];
+    }
 }
 
 }  // namespace
@@ -1797,6 +2236,18 @@ hipError_t launch_check(int prec, int64_t N, const void *T, const float *lo, dou
   return hipGetLastError();
 }
 
+hipError_t launch_range(int prec, int64_t N, const void *T, const float *lo,
+                        unsigned long long *keys, int *nan, hipStream_t s) {
+  dim3 g(blocks_for(N, 256)), b(256);
+  if (prec == 1)
+    hipLaunchKernelGGL((k_range<double, 0>), g, b, 0, s, N, (const double *)T, lo, keys, nan);
+  else if (prec == 0)
+    hipLaunchKernelGGL((k_range<float, 1>), g, b, 0, s, N, (const float *)T, lo, keys, nan);
+  else
+    hipLaunchKernelGGL((k_range<float, 0>), g, b, 0, s, N, (const float *)T, lo, keys, nan);
+  return hipGetLastError();
+}
+
 hipError_t launch_permute(int elem_bytes, int64_t N, const int32_t *perm, const void *src,
                           void *dst, int to_internal, hipStream_t s) {
   hipLaunchKernelGGL(k_permute, dim3(blocks_for(N, 256)), dim3(256), 0, s, elem_bytes, N, perm,
@@ -1851,6 +2302,27 @@ hipError_t launch_resident(const StepArgs &a, const ResArgs &r, hipStream_t s) {
   ResArgs rr = r;
   void *args[] = {(void *)&aa, (void *)&rr};
   return hipLaunchCooperativeKernel(resident_kernel(a), dim3(8 * a.nper), dim3(a.block), args,
+                                    (unsigned)a.lds, s);
+}
+
+const void *adjres_kernel(int prec) {
+  if (prec == 1) return (const void *)k_adjres<double, 0>;
+  if (prec == 0) return (const void *)k_adjres<float, 1>;
+  return (const void *)k_adjres<float, 0>;
+}
+
+hipError_t adjres_prepare(int prec, int block, int lds, int *blocks_per_cu) {
+  const void *f = adjres_kernel(prec);
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds);
+}
+
+hipError_t launch_adjres(const AdjArgs &a, const AdjResArgs &r, hipStream_t s) {
+  AdjArgs aa = a;
+  AdjResArgs rr = r;
+  void *args[] = {(void *)&aa, (void *)&rr};
+  return hipLaunchCooperativeKernel(adjres_kernel(a.prec), dim3(8 * a.nper), dim3(a.block), args,
                                     (unsigned)a.lds, s);
 }
 

@@ -207,6 +207,24 @@ class Simulation:
                                    self.stream))
         self._keep_bc = args  # device tensors stay alive until the copies have run
 
+    def temperature_range(self):
+        """(min, max) of the current temperatures (synchronises)."""
+        lo, hi = C.c_double(), C.c_double()
+        L.check(L.lib().fed_temperature_range(self._c(), C.byref(lo), C.byref(hi), self.stream))
+        return lo.value, hi.value
+
+    def set_range(self, T_lo, T_hi):
+        """Re-derive the stability bound for [T_lo, T_hi] (raises FedError with
+        FED_E_UNSTABLE if the time step in use exceeds it)."""
+        try:
+            L.check(L.lib().fed_set_range(self._c(), float(T_lo), float(T_hi), self.stream))
+        finally:
+            self._refresh_dt()
+
+    def _refresh_dt(self):
+        n = self.info["n_instances"]
+        L.check(L.lib().fed_dt(self._c(), _ptr(self.dt_crit), _ptr(self.dt), n))
+
     def backward(self, dL_dT):
         """Discrete adjoint of the steps taken: returns dict(logk, c, h, T0) of
         dL/dlog k_e, dL/dc_e, dL/dh_f and dL/dT0 (numpy, or CUDA tensors when

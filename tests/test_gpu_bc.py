@@ -116,3 +116,28 @@ def test_set_bc_errors():
         with pytest.raises(FedError) as ei:
             s.set_bc(face_q=q)
         assert ei.value.code == L.FED_E_ARG
+
+
+def test_temperature_range_and_rederived_bound():
+    """fed_temperature_range against the read-back temperatures, and
+    fed_set_range: the re-derived dt_crit equals the oracle's for the new
+    range; widening it past the time step in use reports FED_E_UNSTABLE."""
+    from paper_1909_03355_amd import FedError
+    from paper_1909_03355_amd import _lib as L
+    # the heated face reaches ~710 and the Dirichlet step undershoots to ~-20
+    p = dict(P.cube_nonlinear_hex(8, 30), T_lo=-20.0, T_hi=800.0)
+    for prec in ("fp64", "fp32c"):
+        with _sim(p, prec) as s:
+            s.set_temperature()
+            s.step(30)
+            T = s.temperature()
+            lo, hi = s.temperature_range()
+            assert lo == T.min() and hi == T.max(), (lo, hi, T.min(), T.max())
+            s.set_range(-20.0, 750.0)         # narrower: a larger bound, still stable
+            o = Oracle(dict(p, T_lo=-20.0, T_hi=750.0))
+            assert abs(s.dt_crit[0] / o.dt_crit - 1) < 1e-12
+            with pytest.raises(FedError) as ei:
+                s.set_range(0.0, 2000.0)      # D grows with T: the bound shrinks 3x
+            assert ei.value.code == L.FED_E_UNSTABLE
+            o = Oracle(dict(p, T_lo=0.0, T_hi=2000.0))
+            assert abs(s.dt_crit[0] / o.dt_crit - 1) < 1e-12

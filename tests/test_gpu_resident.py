@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from oracle import Oracle
+from tests import helpers as H
 from workloads import problems as P
 
 pytestmark = pytest.mark.gpu
@@ -72,24 +73,52 @@ def test_resident_split_calls_graph_and_resume():
         assert np.array_equal(s.temperature(), base)
 
 
-def test_resident_adjoint_bitwise():
-    """fed_backward on a resident context (checkpoints break the resident
-    launches; the segments are recomputed one step per launch)."""
-    p = P.adjoint_hex(8, 40, n_sensors=16)
-    sens = p["meta"]["sensors"]
-    out = []
-    for res in (False, True):
-        with _sim(p, "fp32c", resident=res) as s:
-            s.checkpoint_every(15)
-            s.set_temperature()
-            s.step(40)
-            T = s.temperature()
-            lam = np.zeros(T.size)
-            lam[sens] = 2.0 * (T[sens] - 60.0) / sens.size
-            out.append((T, s.backward(lam)))
-    assert np.array_equal(out[0][0], out[1][0])
-    for k in out[0][1]:
-        assert np.array_equal(out[0][1][k], out[1][1][k]), k
+ADJ_CASES = {
+    "adjoint_hex8": lambda: P.adjoint_hex(8, 40, n_sensors=16),
+    "nonlinear_hex8": lambda: P.cube_nonlinear_hex(8, 40),
+    "nonlinear_radiation_dirichlet": lambda: H.nonlinear_adjoint_problem("hex8"),
+    "tables_two_materials": lambda: H.table_laws(H.two_material_problem("hex8", 6)),
+}
+
+
+def _backward(p, prec, res, nsteps=40, ck=15, **kw):
+    with _sim(p, prec, resident=res, **kw) as s:
+        s.checkpoint_every(ck)
+        s.set_temperature()
+        s.step(nsteps)
+        T = s.temperature()
+        g = np.random.default_rng(5).standard_normal(T.size) * 1e-3
+        return T, s.backward(g), dict(s.info)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64", "fp32"])
+@pytest.mark.parametrize("case", sorted(ADJ_CASES))
+def test_resident_adjoint_bitwise(case, prec):
+    """fed_backward on a resident context (each segment recomputed in one
+    launch and its adjoint steps run in one resident launch) against the
+    one-step-per-launch adjoint on the same tiles: bitwise equal multipliers
+    and derivatives; segments of 15, 15 and 10 steps."""
+    p = ADJ_CASES[case]()
+    print(f"resident adjoint {case} {prec}", flush=True)
+    for kw in (dict(), dict(tile_nodes=40, block_threads=256)):
+        T0, g0, _ = _backward(p, prec, False, **kw)
+        T1, g1, info = _backward(p, prec, True, **kw)
+        assert info["resident_adjoint"] == 1, kw
+        assert np.array_equal(T0, T1)
+        for k in g0:
+            assert np.array_equal(g0[k], g1[k]), (kw, k)
+
+
+def test_resident_adjoint_not_offered_for_tetrahedra():
+    """Tetrahedral resident contexts recompute resident and run the adjoint
+    one step per launch; still bitwise equal."""
+    p = P.cube_aniso_tet(4, 20)
+    T0, g0, _ = _backward(p, "fp32c", False, nsteps=20, ck=8)
+    T1, g1, info = _backward(p, "fp32c", True, nsteps=20, ck=8)
+    assert info["resident"] == 1 and info["resident_adjoint"] == 0
+    assert np.array_equal(T0, T1)
+    for k in g0:
+        assert np.array_equal(g0[k], g1[k]), k
 
 
 def test_resident_rejects_meshes_that_do_not_fit():
