@@ -382,16 +382,16 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   for (uint8_t v : exported) nexp += v;
   *exch = 8.0 * words * (double)(halo_total + nexp);  // tagged words read and written
   // resident adjoint: the FP64 boundary sums (and, in FP64, the elements'
-  // derivative sums and rho V / n_e); mu, w, T^n, T^{n+1}, alpha, 1/dt (and beta) of the
-  // touched nodes, the slots of the owned nodes, hA and sigma eps A of the
+  // derivative sums and rho V / n_e); mu, w, T^n, T^{n+1}, alpha, 1/dt (and beta) and
+  // the node-major slots of the touched nodes, hA and sigma eps A of the
   // owned boundary nodes; offered where it fits, else fed_backward runs one
   // adjoint step per launch
   if (c->ne == FED_HEX8 && c->op == 0) {
     int64_t alds = 0;
     for (const fed::TileHdr &th : T.tiles)
       alds = std::max<int64_t>(alds, 16LL * th.nbnd + (c->prec == FED_FP64 ? 24LL * th.cum_e[0] : 0) +
-                                         (int64_t)c->rb * ((6 + (c->tdc ? 1 : 0)) * (int64_t)th.cum_n[1] +
-                                                           (int64_t)T.maxinc * th.nown + 2LL * th.nbnd) + 16);
+                                         (int64_t)c->rb * ((6 + (c->tdc ? 1 : 0) + (1 << T.pb) + 1) *
+                                                               (int64_t)th.cum_n[1] + 2LL * th.nbnd) + 16);
     int aper = 0;
     if (alds <= c->max_lds) {
       HIPCHK(fed::adjres_prepare(c->prec == FED_FP64 ? 1 : (c->prec == FED_FP32C ? 0 : 2), c->block,

@@ -545,6 +545,11 @@ struct Elem<R, 8> {
     R uz = ((T4 - T0) + (T5 - T1)) + ((T6 - T2) + (T7 - T3));
     R s = kl.s0;
     if (tdk) s = kl((((T0 + T1) + (T2 + T3)) + ((T4 + T5) + (T6 + T7))) * (R)0.125);
+    apply(s, h, ux, uy, uz, F);
+  }
+  // F from the gradient sums u and the factor s
+  __device__ static void apply(R s, const R h[6], R ux, R uy, R uz, R F[8]) {
+    #pragma clang fp contract(off)
     R qx = s * fma(h[5], uz, fma(h[3], uy, h[0] * ux));
     R qy = s * fma(h[4], uz, fma(h[1], uy, h[3] * ux));
     R qz = s * fma(h[2], uz, fma(h[4], uy, h[5] * ux));
@@ -569,6 +574,10 @@ struct Elem<R, 4> {
     R d1 = T1 - T0, d2 = T2 - T0, d3 = T3 - T0;
     R s = kl.s0;
     if (tdk) s = kl(((T0 + T1) + (T2 + T3)) * (R)0.25);
+    apply(s, h, d1, d2, d3, F);
+  }
+  __device__ static void apply(R s, const R h[6], R d1, R d2, R d3, R F[4]) {
+    #pragma clang fp contract(off)
     F[1] = s * fma(h[5], d3, fma(h[3], d2, h[0] * d1));
     F[2] = s * fma(h[4], d3, fma(h[1], d2, h[3] * d1));
     F[3] = s * fma(h[2], d3, fma(h[4], d2, h[5] * d1));
@@ -1205,21 +1214,10 @@ struct ElemAdj<R, 4> {
   }
 };
 
-// mu_e . K0_e T_e for the element operator kinds (K0_e at s = 1)
+// mu_e . K0_e T_e of the uniform-gradient hexahedron (K0_e at s = 1); the
+// folded operator computes it inline from the gradient sums
 template <typename R, int NE, int OP>
-struct AdjDot {
-  __device__ static R dot(const R *Lmu, const R *LT, const uint32_t *loc, const R *h) {
-#pragma clang fp contract(off)
-    // (S mu)^T Hhat (S T)
-    R mx, my, mz, tx, ty, tz;
-    ElemAdj<R, NE>::u(Lmu, loc, mx, my, mz);
-    ElemAdj<R, NE>::u(LT, loc, tx, ty, tz);
-    const R qx = fma(h[5], tz, fma(h[3], ty, h[0] * tx));
-    const R qy = fma(h[4], tz, fma(h[1], ty, h[3] * tx));
-    const R qz = fma(h[2], tz, fma(h[4], ty, h[5] * tx));
-    return fma(mz, qz, fma(my, qy, mx * qx));
-  }
-};
+struct AdjDot;
 template <typename R>
 struct AdjDot<R, 8, 1> {
   __device__ static R dot(const R *Lmu, const R *LT, const uint32_t *loc, const R *h) {
@@ -1289,9 +1287,24 @@ __device__ inline void adj_elem(const uint32_t *loc, const R *h, const KLaw<R> &
     }
   }
   muKT = (R)0;
-  if (tdk || owner) muKT = AdjDot<R, NE, OP>::dot(Lmu, LT, loc, h);
-  // the forward element load applied to mu at factor s_e
-  Op<R, NE, OP>::load(Lmu, loc, KLaw<R>{se, (R)0, nullptr, 0}, false, h, F);
+  if constexpr (OP == 0) {
+    // the gradient sums of mu serve both mu . K0 T and the load K0 mu
+    R mx, my, mz;
+    ElemAdj<R, NE>::u(Lmu, loc, mx, my, mz);
+    if (tdk || owner) {
+      R tx, ty, tz;
+      ElemAdj<R, NE>::u(LT, loc, tx, ty, tz);
+      const R qx = fma(h[5], tz, fma(h[3], ty, h[0] * tx));
+      const R qy = fma(h[4], tz, fma(h[1], ty, h[3] * tx));
+      const R qz = fma(h[2], tz, fma(h[4], ty, h[5] * tx));
+      muKT = fma(mz, qz, fma(my, qy, mx * qx));
+    }
+    // the forward element load applied to mu at factor s_e
+    Elem<R, NE>::apply(se, h, mx, my, mz, F);
+  } else {
+    if (tdk || owner) muKT = AdjDot<R, NE, OP>::dot(Lmu, LT, loc, h);
+    Op<R, NE, OP>::load(Lmu, loc, KLaw<R>{se, (R)0, nullptr, 0}, false, h, F);
+  }
   const R spread = tdk ? dse * ((R)1 / (R)NE) * muKT : (R)0;
 #pragma unroll
   for (int n = 0; n < NE; n++) F[n] = F[n] + spread;
@@ -1925,8 +1938,9 @@ __global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
   R *Lal = LTb + ntouch;
   R *Lrdt = Lal + ntouch;
   R *Lbe = Lrdt + ntouch;  // tdc only
-  R *slot = Lbe + (tdc ? ntouch : 0);
-  R *LrA = slot + a.maxinc * nown;
+  R *slot = Lbe + (tdc ? ntouch : 0);  // node-major, every touched node (as in k_resident)
+  const int sstride = (1 << a.pb) + 1, nslot = ntouch * sstride;
+  R *LrA = slot + nslot;
   R *LreA = LrA + nbnd;
   const R *ctab = (const R *)a.ctab;
   using EntT = typename Ent<NE>::T;
@@ -2001,7 +2015,7 @@ __global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
       LS1[j] = a.S1[th.bstart + j];
     }
     // slots past a node's incidence are never written and stay zero
-    for (int j = tid; j < a.maxinc * nown; j += bs) slot[j] = (R)0;
+    for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
   }
   __syncthreads();
   const KLaw<R> kl = KLaw<R>{(R)a.s0, (R)a.s1, (const R *)a.ktab, a.nkt};
@@ -2060,8 +2074,7 @@ __global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
         R F[NE], se, muKT, gsum;
         adj_elem<R, NE, 0>(loc, eh[q], kl, tdk, owner, Lmu, LT, Lw, F, se, muKT, gsum);
 #pragma unroll
-        for (int n = 0; n < NE; n++)
-          if (loc[n] < (uint32_t)nown) slot[(v[n] & pmask) * nown + loc[n]] = F[n];
+        for (int n = 0; n < NE; n++) slot[v[n] + loc[n]] = F[n];
         if (owner) {
           if (GREG) adj_grad<R>(gk[q], gc[q], se, muKT, emv[q], gsum);
           else adj_grad<R>(Lgk[tid + q * bs], Lgc[tid + q * bs], se, muKT, Lmv[tid + q * bs], gsum);
@@ -2076,7 +2089,7 @@ __global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
     for (int q = 0; q < NPT; q++) {
       const int j = tid + q * bs;
       if (j < nown) {
-        const R F = slot_sum(slot, j, nown, a.maxinc);
+        const R F = slot_sum(slot + j * sstride, 0, 1, a.maxinc);
         const R mu = Lmu[j], tn = LT[j], tn1 = LTp[j], al = Lal[j];
         const bool bnd = j < nbnd;
         const R dden = tdc ? adj_dden<R>(al, Lbe[j], tn, ctab, a.nct) : (R)0;
