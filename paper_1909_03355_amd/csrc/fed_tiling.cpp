@@ -9,6 +9,7 @@
 // element's contribution into that slot and sums slots in position order, so
 // every nodal sum runs in ascending element order whatever the tiling.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <numeric>
 
@@ -154,17 +155,33 @@ struct Builder {
       if (!rcb(ids, gstart[g], gstart[g + 1], leaves))
         return "a single node touches more nodes or LDS than one tile can hold "
                "(node incidence too high)";
-    // internal order: tile by tile, boundary-record nodes first, caller id inside
+    // internal order: tile by tile; inside a tile the boundary-record nodes
+    // first, then nodes that another tile reads (grouped by the lowest such
+    // tile), then caller id, so the nodes a tile exports, and the nodes a
+    // neighbour reads from it, sit in few contiguous runs
     out.nt = (int32_t)leaves.size();
     out.tiles.resize(out.nt);
     out.perm.assign(N, -1);
     out.iperm.resize(N);
+    std::vector<int32_t> tile_of(N, -1), reader(N, INT32_MAX);
+    for (int32_t t = 0; t < out.nt; t++)
+      for (size_t i = leaves[t].first; i < leaves[t].second; i++) tile_of[ids[i]] = t;
+    for (int64_t el = 0; el < E; el++)
+      for (int a = 0; a < ne; a++) {
+        const int32_t k = node(el, a);
+        for (int b2 = 0; b2 < ne; b2++) {
+          const int32_t tb = tile_of[node(el, b2)];
+          if (tb != tile_of[k]) reader[k] = std::min(reader[k], tb);
+        }
+      }
     int32_t next = 0, bnext = 0;
     for (int32_t t = 0; t < out.nt; t++) {
       auto [b, e] = leaves[t];
       std::sort(ids.begin() + b, ids.begin() + e, [&](int32_t p, int32_t q) {
         bool bp = in.has_bnd && in.has_bnd[p], bq = in.has_bnd && in.has_bnd[q];
-        return bp != bq ? bp : p < q;
+        if (bp != bq) return bp;
+        if (reader[p] != reader[q]) return reader[p] < reader[q];
+        return p < q;
       });
       TileHdr &th = out.tiles[t];
       th.nstart = next;
