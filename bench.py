@@ -26,14 +26,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
-KERNEL_SRC = os.path.join(ROOT, "paper_1909_03355_amd", "csrc", "fed_kernels.hip")
+# sources that decide a kernel's memory traffic: the kernels, the tiler, the launches
+TRAFFIC_SRC = [os.path.join(ROOT, "paper_1909_03355_amd", "csrc", f)
+               for f in ("fed_kernels.hip", "fed_tiling.cpp", "fed_api.cpp")]
 # Memory traffic of the dominant kernel in the default launch shape, from
 # rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
 # scaled by what the counter reads for a copy kernel of known size
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0): bytes per launch for a one-step kernel;
 # for resident stepping (one launch for all steps) bytes once per launch plus
-# bytes per step, from runs of two step counts.  Valid only for the kernel
-# source with this SHA-1; any other source reports null.
+# bytes per step, from runs of two step counts.  Valid only for the sources
+# (TRAFFIC_SRC, concatenated) with this SHA-1; any other source reports null.
 #   workload -> (sha1, kernel, bytes per launch or once, bytes per step)
 TRAFFIC = {}
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
@@ -174,7 +176,7 @@ def main():
         log(f"oracle {osteps} steps {tc:.2f} s; err_max {errs}")
 
     import hashlib
-    src_sha = hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
+    src_sha = hashlib.sha1(b"".join(open(f, "rb").read() for f in TRAFFIC_SRC)).hexdigest()
     default_shape = not (args.tile_nodes or args.block or args.fuse or args.autotune
                          or args.resident != "default")
     r32 = res["fp32c"]

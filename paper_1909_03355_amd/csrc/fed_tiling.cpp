@@ -156,31 +156,42 @@ struct Builder {
         return "a single node touches more nodes or LDS than one tile can hold "
                "(node incidence too high)";
     // internal order: tile by tile; inside a tile the boundary-record nodes
-    // first, then nodes that another tile reads (grouped by the lowest such
-    // tile), then caller id, so the nodes a tile exports, and the nodes a
-    // neighbour reads from it, sit in few contiguous runs
+    // first, then by the sorted list of other tiles that read the node (nodes
+    // no other tile reads last), then caller id, so the nodes a tile exports,
+    // and the nodes a neighbour reads from it, sit in few contiguous runs
     out.nt = (int32_t)leaves.size();
     out.tiles.resize(out.nt);
     out.perm.assign(N, -1);
     out.iperm.resize(N);
-    std::vector<int32_t> tile_of(N, -1), reader(N, INT32_MAX);
+    std::vector<int32_t> tile_of(N, -1);
     for (int32_t t = 0; t < out.nt; t++)
       for (size_t i = leaves[t].first; i < leaves[t].second; i++) tile_of[ids[i]] = t;
-    for (int64_t el = 0; el < E; el++)
-      for (int a = 0; a < ne; a++) {
-        const int32_t k = node(el, a);
-        for (int b2 = 0; b2 < ne; b2++) {
-          const int32_t tb = tile_of[node(el, b2)];
-          if (tb != tile_of[k]) reader[k] = std::min(reader[k], tb);
+    // readers of node k: rd[rptr[k] .. rptr[k + 1]), ascending ({INT32_MAX} if none)
+    std::vector<int64_t> rptr(N + 1, 0);
+    std::vector<int32_t> rd, buf;
+    for (int64_t k = 0; k < N; k++) {
+      buf.clear();
+      for (int64_t p = cptr[k]; p < cptr[k + 1]; p++)
+        for (int a = 0; a < ne; a++) {
+          const int32_t tb = tile_of[node(celem[p], a)];
+          if (tb != tile_of[k]) buf.push_back(tb);
         }
-      }
+      std::sort(buf.begin(), buf.end());
+      buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+      if (buf.empty()) buf.push_back(INT32_MAX);
+      rd.insert(rd.end(), buf.begin(), buf.end());
+      rptr[k + 1] = (int64_t)rd.size();
+    }
     int32_t next = 0, bnext = 0;
     for (int32_t t = 0; t < out.nt; t++) {
       auto [b, e] = leaves[t];
       std::sort(ids.begin() + b, ids.begin() + e, [&](int32_t p, int32_t q) {
         bool bp = in.has_bnd && in.has_bnd[p], bq = in.has_bnd && in.has_bnd[q];
         if (bp != bq) return bp;
-        if (reader[p] != reader[q]) return reader[p] < reader[q];
+        const int32_t *r0 = rd.data() + rptr[p], *r1 = rd.data() + rptr[p + 1];
+        const int32_t *s0 = rd.data() + rptr[q], *s1 = rd.data() + rptr[q + 1];
+        if (std::lexicographical_compare(r0, r1, s0, s1)) return true;
+        if (std::lexicographical_compare(s0, s1, r0, r1)) return false;
         return p < q;
       });
       TileHdr &th = out.tiles[t];
