@@ -37,7 +37,11 @@ TRAFFIC_SRC = [os.path.join(ROOT, "paper_1909_03355_amd", "csrc", f)
 # bytes per step, from runs of two step counts.  Valid only for the sources
 # (TRAFFIC_SRC, concatenated) with this SHA-1; any other source reports null.
 #   workload -> (sha1, kernel, bytes per launch or once, bytes per step)
-TRAFFIC = {}
+TRAFFIC = {
+    "nonlinear_hex64": ("c41eeb5c8da71cb74f95533f611d93f78113cb25", "k_resident", 20750641.8, 2418622.8),
+    "aniso_tet128": ("c41eeb5c8da71cb74f95533f611d93f78113cb25", "k_step1", 620727504.0, 0.0),
+    "batched_hex256": ("c41eeb5c8da71cb74f95533f611d93f78113cb25", "k_step1", 463479744.0, 0.0),
+}
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
 
 WORKLOADS = {
