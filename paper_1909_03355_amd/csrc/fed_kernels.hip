@@ -1639,7 +1639,8 @@ __device__ inline unsigned long long tagged(unsigned tag, uint32_t bits) {
   return ((unsigned long long)tag << 32) | bits;
 }
 
-// tagged words of one value: 1 for float, 2 (low, high half) for double
+// tagged words of one value: one 64-bit (tag, value) word for float; one
+// 16-byte word for double (below)
 template <typename R>
 struct Words;
 // (ld: the raw words; ok: they carry `tag`; val: the value they hold)
@@ -1656,25 +1657,33 @@ struct Words<float> {
   __device__ static bool ok(const Raw &r, unsigned tag) { return (unsigned)(r.w >> 32) == tag; }
   __device__ static float val(const Raw &r) { return __uint_as_float((uint32_t)r.w); }
 };
+// FP64: one 16-byte word per value, (tag, low half, high half, tag), loaded
+// and stored with one 128-bit access (half the memory requests of two 64-bit
+// words).  Accesses are device-coherent (sc1); the load is volatile so every
+// poll reads memory.  A reader accepts a word only when both tags match, so a
+// store seen in part (its first or its last bytes only) is never taken.
 template <>
 struct Words<double> {
   static constexpr int W = 2;
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   struct Raw {
-    unsigned long long w0, w1;
+    u32x4 v;
   };
+  __device__ static __amdgpu_buffer_rsrc_t rsrc(const unsigned long long *X) {
+    // raw buffer over X (dword 3: the gfx9 buffer format); offsets stay below 2^31
+    return __builtin_amdgcn_make_buffer_rsrc((void *)X, 0, 0x7fffffff, 0x00020000);
+  }
   __device__ static void put(unsigned long long *X, int k, unsigned tag, double v) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    st_word(X + 2 * (int64_t)k, tagged(tag, (uint32_t)b));
-    st_word(X + 2 * (int64_t)k + 1, tagged(tag, (uint32_t)(b >> 32)));
+    const u32x4 d = {tag, (unsigned)b, (unsigned)(b >> 32), tag};
+    __builtin_amdgcn_raw_buffer_store_b128(d, rsrc(X), k * 16, 0, /*sc1*/ 16);
   }
   __device__ static Raw ld(const unsigned long long *X, int k) {
-    return Raw{ld_word(X + 2 * (int64_t)k), ld_word(X + 2 * (int64_t)k + 1)};
+    return Raw{__builtin_amdgcn_raw_buffer_load_b128(rsrc(X), k * 16, 0, /*sc1, volatile*/ 16 | (1u << 31))};
   }
-  __device__ static bool ok(const Raw &r, unsigned tag) {
-    return (unsigned)(r.w0 >> 32) == tag && (unsigned)(r.w1 >> 32) == tag;
-  }
+  __device__ static bool ok(const Raw &r, unsigned tag) { return r.v[0] == tag && r.v[3] == tag; }
   __device__ static double val(const Raw &r) {
-    return __longlong_as_double((long long)(((r.w1 & 0xffffffffull) << 32) | (r.w0 & 0xffffffffull)));
+    return __longlong_as_double((long long)(((unsigned long long)r.v[2] << 32) | r.v[1]));
   }
 };
 
