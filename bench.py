@@ -38,9 +38,9 @@ TRAFFIC_SRC = [os.path.join(ROOT, "paper_1909_03355_amd", "csrc", f)
 # (TRAFFIC_SRC, concatenated) with this SHA-1; any other source reports null.
 #   workload -> (sha1, kernel, bytes per launch or once, bytes per step)
 TRAFFIC = {
-    "nonlinear_hex64": ("c41eeb5c8da71cb74f95533f611d93f78113cb25", "k_resident", 20750641.8, 2418622.8),
-    "aniso_tet128": ("c41eeb5c8da71cb74f95533f611d93f78113cb25", "k_step1", 620727504.0, 0.0),
-    "batched_hex256": ("c41eeb5c8da71cb74f95533f611d93f78113cb25", "k_step1", 463479744.0, 0.0),
+    "nonlinear_hex64": ("4572db36821411bc77c6dea9c0296d8ae0114061", "k_resident", 21275384.9, 2415737.3),
+    "aniso_tet128": ("4572db36821411bc77c6dea9c0296d8ae0114061", "k_step1", 620713056.0, 0.0),
+    "batched_hex256": ("4572db36821411bc77c6dea9c0296d8ae0114061", "k_step1", 463481536.0, 0.0),
 }
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
 
