@@ -167,15 +167,15 @@ hipError_t launch_expand_H(int prec, int W, int from, int64_t Eexp, int64_t E, c
 // Resident stepping: one cooperative launch advances nsteps steps.  Every tile
 // keeps its element operators and node coefficients in registers for the whole
 // launch.  The temperatures of exported nodes (those in another tile's halo)
-// are passed through two exchange buffers of tagged words: 64 bits holding the
-// step number and the value (FP32) or half of it (FP64, two words), so a
-// reader polls the data itself until it carries the step it needs.
+// are passed through two exchange buffers of tagged words (FP32: 64 bits, the
+// step number and the value; FP64: 16 bytes, step, value, step), so a reader
+// polls the data itself until it carries the step it needs.
 struct ResArgs {
   int nsteps;
   int spin_limit;             // polls of a halo word before the wait gives up
   unsigned tag0;              // words written at step s carry tag0 + s + 1
   const uint8_t *exported;    // per internal node: 1 if in another tile's halo
-  unsigned long long *X[2];   // exchange buffers, N (FP32) or 2 N (FP64) words each
+  unsigned long long *X[2];   // exchange buffers, N (FP32) or 2 N (FP64) 64-bit words each
   int *err;                   // set to 1 when a wait gives up
   void *Tfin;                 // final hi (the T buffer of parity cur ^ (nsteps & 1))
   float *lofin;               // final lo (FP32C)
