@@ -228,6 +228,24 @@ int main(int argc, char **argv) {
     }
   }
   for (const auto &pr : rel) REQUIRE(rel.count({pr.second, pr.first}));
+  // inside a tile's boundary-record and other nodes, the nodes another tile
+  // reads (in some first halo ring) come first, grouped by the sorted list
+  // of their readers
+  std::vector<std::vector<int32_t>> readers(N);
+  for (int t = 0; t < T.nt; t++) {
+    const fed::TileHdr &th = T.tiles[t];
+    for (int h = 0; h < th.cum_n[1] - th.nown; h++) readers[T.halo[th.hstart + h]].push_back(t);
+  }
+  for (auto &v : readers) std::sort(v.begin(), v.end());
+  for (int t = 0; t < T.nt; t++) {
+    const fed::TileHdr &th = T.tiles[t];
+    for (int j = 1; j < th.nown; j++) {
+      if (j == th.nbnd) continue;  // a new group starts
+      const auto &a = readers[th.nstart + j - 1], &b = readers[th.nstart + j];
+      if (a.empty()) REQUIRE(b.empty());
+      if (!a.empty() && !b.empty()) REQUIRE(!(b < a));
+    }
+  }
   std::printf("OK %d tiles, %zu expanded elements, maxinc %d, pb %d\n", T.nt, T.eorig.size(),
               T.maxinc, T.pb);
   return 0;
