@@ -7,7 +7,11 @@ all faces, radiation on the top face and a flux patch on the bottom, seeded
 random T0 - in compensated FP32, with the same steps in FP64 timed for the
 speed ratio.  A step is one pass of the whole hot path (element loads, nodal
 sums, surface loads, explicit update).  Other workloads (--workload):
-aniso_tet128, batched_hex256, adjoint_hex48 (forward + adjoint).
+aniso_tet128, batched_hex256, adjoint_hex48 (forward + adjoint), and the
+follow-up features at the 64^3 size: tables_hex64 (tabulated D(T), c(T)),
+meanhex_hex64 (uniform-gradient hexahedron on a distorted mesh),
+nladjoint_hex64 (adjoint through D(T), c(T) and radiation) and
+moving_source_hex64 (point powers replaced before every step).
 
 Prints one JSON line.  `value` is element-updates/s (elements x steps / s)
 with all inputs resident on the GPU when the timed region starts.
@@ -45,19 +49,36 @@ TRAFFIC = {
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
 
 WORKLOADS = {
-    # name: (builder, default steps, oracle sample steps, description, default launch shape)
+    # name: (builder, default steps, oracle sample steps, description, default launch
+    #        shape, kind: "steps" | "adjoint" (forward + adjoint) | "moving" (a point
+    #        source moved every step))
     "nonlinear_hex64": ("cube_nonlinear_hex", 10000, 200,
                         "0.1 m cube, 64^3 hex8, orthotropic D(T), c(T), convection+radiation+flux",
-                        dict(resident=True)),
+                        dict(resident=True), "steps"),
     "aniso_tet128": ("cube_aniso_tet", 2000, 4,
                      "0.1 m cube, 128^3 x 6 Kuhn tet4, per-element SPD conductivity, c(T), "
-                     "convection", dict(tile_nodes=1024, block_threads=512)),
+                     "convection", dict(tile_nodes=1024, block_threads=512), "steps"),
     "batched_hex256": ("batched_hex", 5000, 10,
                        "256 hex8 boxes with 8..48 cells per axis, per-instance k, c, h, eps, T0, dt",
-                       dict(tile_nodes=1024, block_threads=512)),
+                       dict(tile_nodes=1024, block_threads=512), "steps"),
     "adjoint_hex48": ("adjoint_hex", 2000, 100,
                       "48^3 hex8, log-normal k field, convection; forward + adjoint with "
-                      "checkpoints every 100 steps", dict(resident=True)),
+                      "checkpoints every 100 steps", dict(resident=True), "adjoint"),
+    # the follow-up features at the size of nonlinear_hex64
+    "tables_hex64": ("cube_nonlinear_hex_tables", 10000, 200,
+                     "nonlinear_hex64 with D(T) and c(T) as piecewise-linear multiplier tables",
+                     dict(resident=True), "steps"),
+    "meanhex_hex64": ("cube_nonlinear_hex_mean", 2000, 100,
+                      "nonlinear_hex64 on a distorted mesh (interior nodes moved up to 0.25 h) "
+                      "with the uniform-gradient hexahedron", dict(), "steps"),
+    "nladjoint_hex64": ("nonlinear_adjoint_hex", 2000, 100,
+                        "nonlinear_hex64 (D(T), c(T), radiation) as the forward model of a sensor "
+                        "loss; forward + adjoint with checkpoints every 100 steps",
+                        dict(resident=True), "adjoint"),
+    "moving_source_hex64": ("moving_source_hex", 2000, 200,
+                            "nonlinear_hex64 with a 50 W point source moved one node along the "
+                            "top face every step (fed_set_bc between steps)",
+                            dict(resident=True), "moving"),
 }
 
 
@@ -112,6 +133,28 @@ def timed_adjoint(sim, steps, prob):
     return t1 - t0, t2 - t1
 
 
+def timed_moving(sim, steps, prob, warmup):
+    """One step at a time, the point source moved to the next node of its line
+    before each (device-side powers, no host transfer in the loop)."""
+    import torch
+    n = prob["pt_nodes"].size
+    W = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    W.fill_diagonal_(prob["meta"]["source_power"])
+    sim.set_temperature()
+    for i in range(warmup):
+        sim.set_bc(pt_W=W[i % n])
+        sim.step(1)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(steps):
+        sim.set_bc(pt_W=W[i % n])
+        sim.step(1)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -125,7 +168,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    builder, dsteps, osteps, desc, shape = WORKLOADS[args.workload]
+    builder, dsteps, osteps, desc, shape, kind = WORKLOADS[args.workload]
     steps = args.steps or dsteps
     osteps = args.oracle_steps or osteps
     prob = getattr(P, builder)(nsteps=steps)
@@ -149,12 +192,16 @@ def main():
     precs = ["fp32c"] if args.no_fp64 else ["fp32c", "fp64"]
     for prec in precs:
         sim = Simulation(prob, prec=prec, **kw)
-        if args.workload == "adjoint_hex48":
+        if kind == "adjoint":
             if args.warmup:
                 timed_adjoint(sim, steps, prob)  # first-use allocations and module loads
             tf, tb = timed_adjoint(sim, steps, prob)
             t = tf + tb
             log(f"{prec}: forward {tf * 1e3:.1f} ms + adjoint {tb * 1e3:.1f} ms for {steps} steps")
+        elif kind == "moving":
+            t = timed_moving(sim, steps, prob, min(args.warmup, 200))
+            log(f"{prec}: {steps} steps, source moved before each, in {t * 1e3:.2f} ms "
+                f"({t / steps * 1e6:.2f} us/step)")
         else:
             t = timed_steps(sim, steps, args.warmup, args.graph_steps)
             log(f"{prec}: {steps} steps in {t * 1e3:.2f} ms ({t / steps * 1e6:.2f} us/step)")
@@ -188,7 +235,13 @@ def main():
     info = r32["info"]
     K = info["fuse_steps"]
     resident = bool(info["resident"])
-    if resident:
+    if resident and kind == "moving":
+        # one resident launch a step
+        launches = steps
+        alg = info["algorithmic_bytes_per_launch"] + info["exchange_bytes_per_step"]
+        moved = info["moved_bytes_per_launch"] + info["exchange_bytes_per_step"]
+        kernel = "k_resident"
+    elif resident:
         # one launch runs all the timed steps: the tile data is loaded once, then
         # every step moves only the tagged halo exchange
         launches = 1
@@ -228,7 +281,7 @@ def main():
                      "bytes_per_launch_moved": moved},
         "cpu_baseline": cpu,
     }
-    if resident and args.workload != "adjoint_hex48":
+    if resident and kind == "steps":
         # the per-step working set of the method (every element operator and
         # node state, once) processed per step, for comparison with the
         # streaming kernel that moves it from memory every step
@@ -247,13 +300,19 @@ def main():
                                     "roofline_frac": a1 / PEAK_HBM_GBS,
                                     "resident_speedup": (t1 / n1) / (t / steps)}
         log(f"streaming k_step1: {t1 / n1 * 1e6:.2f} us/step")
-    if args.workload == "adjoint_hex48":
+    if kind == "adjoint":
         line["roofline"] = None   # forward + adjoint mix, no single dominant kernel rate
         line["note"] = "value counts forward steps; time includes the adjoint pass"
+    if kind == "moving":
+        line["note"] = ("one resident launch a step, the point powers replaced on the device "
+                        "before each; time includes the host calls")
     if "fp64" in res:
         t64 = res["fp64"]["t"]
         i64 = res["fp64"]["info"]
-        if i64["resident"]:
+        if i64["resident"] and kind == "moving":
+            b64 = i64["algorithmic_bytes_per_launch"] + i64["exchange_bytes_per_step"]
+            l64 = steps
+        elif i64["resident"]:
             b64 = i64["algorithmic_bytes_per_launch"] + steps * i64["exchange_bytes_per_step"]
             l64 = 1
         else:

@@ -1222,7 +1222,8 @@ int fed_set_bc(fed_ctx *c, const double *face_Ta, const double *face_q, const do
                     c->d_feps, c->d_fq, c->d_farea, c->nrec, c->d_recptr, c->d_recitem,
                     c->d_ptW, c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[3], c->d_b64[4]};
     HIPCHK(fed::launch_bnd(ba, s));
-    fed::NodeArrArgs na{c->prec, c->N, c->nrec, c->d_M0, c->d_M1, c->d_dtinst, c->d_ninst,
+    // the boundary records only (N = 0): alpha and beta do not depend on the loads
+    fed::NodeArrArgs na{c->prec, 0, c->nrec, c->d_M0, c->d_M1, c->d_dtinst, c->d_ninst,
                         c->d_isdir, c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[4],
                         c->d_b64[3], c->d_alpha, c->d_beta, c->d_rA, c->d_rAT, c->d_reA,
                         c->d_rTa, c->d_rP};

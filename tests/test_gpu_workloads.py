@@ -88,3 +88,58 @@ def test_autotuner(tmp_path):
     T1, _, _ = _run(p, "fp32c", 60, **launch_kwargs(best))
     T2, _, _ = _run(p, "fp32c", 60, **launch_kwargs(cands[0]))
     assert np.array_equal(T1, T2)
+
+
+def test_tables_hex64_full_size():
+    """The tabulated-D(T), c(T) workload at 64^3, resident, 200 steps: against
+    the oracle, and bitwise against one step per launch."""
+    p = P.cube_nonlinear_hex_tables(64, 200)
+    ref = Oracle(p).run(200)
+    for prec in ("fp64", "fp32c"):
+        T, _, _ = _run(p, prec, 200, resident=True)
+        err = oracle.err_max(T, ref)
+        print(f"tables_hex64 {prec}: err_max {err:.2e}", flush=True)
+        assert err <= TOL[prec]
+        assert np.array_equal(T, _run(p, prec, 200)[0])
+
+
+def test_meanhex_hex64_full_size():
+    """The uniform-gradient hexahedron on the distorted 64^3 mesh, 100 steps,
+    in the launch shape bench.py times, against the oracle."""
+    p = P.cube_nonlinear_hex_mean(64, 100)
+    ref = Oracle(p).run(100)
+    for prec in ("fp64", "fp32c"):
+        T, dtc, _ = _run(p, prec, 100)
+        err = oracle.err_max(T, ref)
+        print(f"meanhex_hex64 {prec}: err_max {err:.2e}", flush=True)
+        assert err <= TOL[prec]
+
+
+def test_nonlinear_adjoint_hex64():
+    """The adjoint through D(T), c(T) and radiation at 64^3 (200 steps,
+    checkpoints every 50, resident forward and adjoint): FP32C gradients
+    against the FP64 oracle adjoint (max error / max |g| <= 1e-4)."""
+    from paper_1909_03355_amd import Simulation
+    p = P.nonlinear_adjoint_hex(64, 200, ckpt_every=50)
+    sens = p["meta"]["sensors"]
+    o = Oracle(p)
+    hist = o.run(200, history=True)
+    lam = np.zeros(hist[-1].size)
+    lam[sens] = 2.0 * (hist[-1][sens] - 60.0) / sens.size
+    ref = o.adjoint(hist, lam)
+    del hist
+    with Simulation(p, prec="fp32c", resident=True) as s:
+        s.checkpoint_every(50)
+        s.set_temperature()
+        s.step(200)
+        T = s.temperature()
+        lam_gpu = np.zeros(T.size)
+        lam_gpu[sens] = 2.0 * (T[sens] - 60.0) / sens.size
+        g = s.backward(lam_gpu)
+        assert s.info["resident_adjoint"] == 1
+    rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    errs = {"logk": rel(g["logk"], ref["g_logk"]), "c": rel(g["c"], ref["g_c"]),
+            "h": rel(g["h"], ref["g_h"]), "T0": rel(g["T0"], ref["lam0"])}
+    print("nladjoint_hex64 fp32c", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= 1e-4, (k, v)

@@ -124,6 +124,62 @@ def cube_nonlinear_hex(n=64, nsteps=10000, seed=1909_0002):
 
 
 # --------------------------------------------------------------------------
+# Variants of workload 2 that exercise the follow-up features at full size:
+# the temperature dependence of D and c as piecewise-linear tables, the
+# uniform-gradient hexahedron on a distorted mesh, the forward model of a
+# sensor loss for the nonlinear adjoint, and a point source that moves
+# across the top face one node per step.
+def cube_nonlinear_hex_tables(n=64, nsteps=10000):
+    """Workload 2 with D and c scaled by tabulated multipliers of T (clamped
+    beyond the ends): D rises 0.5% per C up to 400 C and flattens above; c
+    has a latent-heat-like bump around 500 C."""
+    p = cube_nonlinear_hex(n, nsteps)
+    p["name"] = f"nonlinear_hex_tables_{n}"
+    p["materials"] = [dict(m, s0=1.0, s1=0.0, c1=0.0) for m in p["materials"]]
+    p["k_table"] = (np.array([0.0, 400.0, 700.0, 1000.0]), np.array([1.0, 3.0, 3.6, 4.0]))
+    p["c_table"] = (np.array([0.0, 400.0, 500.0, 600.0, 1000.0]),
+                    np.array([1.0, 1.8, 2.6, 2.2, 3.0]))
+    return p
+
+
+def cube_nonlinear_hex_mean(n=64, nsteps=10000, amp=0.25, seed=1909_0006):
+    """Workload 2 on a distorted mesh (interior nodes moved by up to amp times
+    the spacing) with the uniform-gradient hexahedron."""
+    p = cube_nonlinear_hex(n, nsteps)
+    mj = M.jitter_interior(dict(elem=p["elem"], x=p["x"], y=p["y"], z=p["z"], conn=p["conn"]),
+                           amp, seed)
+    p.update(x=mj["x"], y=mj["y"], z=mj["z"], name=f"nonlinear_hex_mean_{n}")
+    p["hex_gradient"] = "mean"
+    p["meta"].update(jitter=amp, jitter_seed=seed)
+    return p
+
+
+def nonlinear_adjoint_hex(n=64, nsteps=2000, n_sensors=512, ckpt_every=100, seed=1909_0007):
+    """Workload 2 as the forward model of a mean-square sensor loss (seeded
+    sensor nodes), for the adjoint through k(T), c(T) and radiation."""
+    p = cube_nonlinear_hex(n, nsteps)
+    g = fields.rng(seed)
+    p["name"] = f"nonlinear_adjoint_hex_{n}"
+    p["meta"].update(sensors=np.sort(g.choice(p["x"].size, n_sensors, replace=False)),
+                     ckpt_every=ckpt_every)
+    return p
+
+
+def moving_source_hex(n=64, nsteps=2000, power=50.0):
+    """Workload 2 with a point source of the given power on the line y = side/2
+    of the top face, listed node by node; the source moves one node a step."""
+    p = cube_nonlinear_hex(n, nsteps)
+    top = np.isclose(p["z"], p["z"].max())
+    mid = np.isclose(p["y"], 0.5 * (p["y"].min() + p["y"].max()))
+    line = np.nonzero(top & mid)[0]
+    line = line[np.argsort(p["x"][line])].astype(np.int32)
+    p["name"] = f"moving_source_hex_{n}"
+    p["pt_nodes"], p["pt_W"] = line, np.zeros(line.size)
+    p["meta"].update(source_power=power)
+    return p
+
+
+# --------------------------------------------------------------------------
 # Workload 3: large anisotropic tetrahedral mesh.  n^3 grid on a 0.1 m cube,
 # every cell split into 6 Kuhn tetrahedra; per-element SPD conductivity
 # R diag(lam) R^T with Haar-random R and lam log-uniform in [0.5, 5];
