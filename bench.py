@@ -11,7 +11,8 @@ aniso_tet128, batched_hex256, adjoint_hex48 (forward + adjoint), and the
 follow-up features at the 64^3 size: tables_hex64 (tabulated D(T), c(T)),
 meanhex_hex64 (uniform-gradient hexahedron on a distorted mesh),
 nladjoint_hex64 (adjoint through D(T), c(T) and radiation) and
-moving_source_hex64 (point powers replaced before every step).
+moving_source_hex64 (a point source moved one node every step by a point-load
+schedule).
 
 Prints one JSON line.  `value` is element-updates/s (elements x steps / s)
 with all inputs resident on the GPU when the timed region starts.
@@ -76,8 +77,8 @@ WORKLOADS = {
                         "loss; forward + adjoint with checkpoints every 100 steps",
                         dict(resident=True), "adjoint"),
     "moving_source_hex64": ("moving_source_hex", 2000, 200,
-                            "nonlinear_hex64 with a 50 W point source moved one node along the "
-                            "top face every step (fed_set_bc between steps)",
+                            "nonlinear_hex64 with a 2 W point source moved one node along the "
+                            "top face every step (a point-load schedule)",
                             dict(resident=True), "moving"),
 }
 
@@ -133,13 +134,19 @@ def timed_adjoint(sim, steps, prob):
     return t1 - t0, t2 - t1
 
 
-def timed_moving(sim, steps, prob, warmup):
-    """One step at a time, the point source moved to the next node of its line
-    before each (device-side powers, no host transfer in the loop)."""
-    import torch
+def moving_rows(prob):
+    """The source's path as a point-load schedule: row i loads the i-th node of
+    the line with the source power, the other listed nodes with nothing."""
     n = prob["pt_nodes"].size
-    W = torch.zeros((n, n), dtype=torch.float64, device="cuda")
-    W.fill_diagonal_(prob["meta"]["source_power"])
+    return np.diag(np.full(n, prob["meta"]["source_power"]))
+
+
+def timed_moving_host(sim, steps, prob, warmup):
+    """The same path driven from the host: the loads replaced (device-side rows,
+    no host transfer) before every one-step call."""
+    import torch
+    W = torch.tensor(moving_rows(prob), device="cuda")
+    n = W.shape[0]
     sim.set_temperature()
     for i in range(warmup):
         sim.set_bc(pt_W=W[i % n])
@@ -199,9 +206,10 @@ def main():
             t = tf + tb
             log(f"{prec}: forward {tf * 1e3:.1f} ms + adjoint {tb * 1e3:.1f} ms for {steps} steps")
         elif kind == "moving":
-            t = timed_moving(sim, steps, prob, min(args.warmup, 200))
-            log(f"{prec}: {steps} steps, source moved before each, in {t * 1e3:.2f} ms "
-                f"({t / steps * 1e6:.2f} us/step)")
+            sim.set_point_schedule(moving_rows(prob))
+            t = timed_steps(sim, steps, args.warmup, args.graph_steps)
+            log(f"{prec}: {steps} scheduled steps, the source one node further each step, "
+                f"in {t * 1e3:.2f} ms ({t / steps * 1e6:.2f} us/step)")
         else:
             t = timed_steps(sim, steps, args.warmup, args.graph_steps)
             log(f"{prec}: {steps} steps in {t * 1e3:.2f} ms ({t / steps * 1e6:.2f} us/step)")
@@ -214,13 +222,16 @@ def main():
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         o = oracle.Oracle(prob)
         t0 = time.perf_counter()
-        ref = o.run(osteps)
+        sched = moving_rows(prob) if kind == "moving" else None
+        ref = o.run(osteps, pt_schedule=sched)
         tc = time.perf_counter() - t0
         cpu = dict(value=E * osteps / tc, unit="element-updates/s", cores=threads, kind="oracle",
                    sample=f"{osteps} steps of the same workload ({args.workload}), FP64 C "
                           f"oracle with an OpenMP element loop, {tc:.2f} s")
         for prec in res:
             with Simulation(prob, prec=prec, **kw) as sim:
+                if sched is not None:
+                    sim.set_point_schedule(sched)
                 sim.set_temperature()
                 sim.step(osteps)
                 errs[prec] = oracle.err_max(sim.temperature(), ref)
@@ -235,18 +246,16 @@ def main():
     info = r32["info"]
     K = info["fuse_steps"]
     resident = bool(info["resident"])
-    if resident and kind == "moving":
-        # one resident launch a step
-        launches = steps
-        alg = info["algorithmic_bytes_per_launch"] + info["exchange_bytes_per_step"]
-        moved = info["moved_bytes_per_launch"] + info["exchange_bytes_per_step"]
-        kernel = "k_resident"
-    elif resident:
+    # a point-load schedule adds one row of record powers a step
+    sched_b = info["n_bnd_nodes"] * 4 if kind == "moving" else 0
+    if resident:
         # one launch runs all the timed steps: the tile data is loaded once, then
         # every step moves only the tagged halo exchange
         launches = 1
-        alg = info["algorithmic_bytes_per_launch"] + steps * info["exchange_bytes_per_step"]
-        moved = info["moved_bytes_per_launch"] + steps * info["exchange_bytes_per_step"]
+        alg = info["algorithmic_bytes_per_launch"] + steps * (info["exchange_bytes_per_step"]
+                                                              + sched_b)
+        moved = info["moved_bytes_per_launch"] + steps * (info["exchange_bytes_per_step"]
+                                                          + sched_b)
         kernel = "k_resident"
     else:
         launches = -(-steps // K)
@@ -281,7 +290,16 @@ def main():
                      "bytes_per_launch_moved": moved},
         "cpu_baseline": cpu,
     }
-    if resident and kind == "steps":
+    if kind == "moving":
+        sim = Simulation(prob, prec="fp32c", **kw)
+        n1 = min(steps, 1000)
+        t1 = timed_moving_host(sim, n1, prob, min(args.warmup, 200))
+        sim.close()
+        line["host_driven"] = {"us_per_step": t1 / n1 * 1e6, "steps": n1,
+                               "how": "fed_set_bc from device rows, then one step, per call",
+                               "schedule_speedup": (t1 / n1) / (t / steps)}
+        log(f"host-driven moving source: {t1 / n1 * 1e6:.2f} us/step")
+    if resident and kind in ("steps", "moving"):
         # the per-step working set of the method (every element operator and
         # node state, once) processed per step, for comparison with the
         # streaming kernel that moves it from memory every step
@@ -289,6 +307,8 @@ def main():
         # the one-step-per-launch kernel on the same problem, same run
         kw1 = {k: v for k, v in kw.items() if k != "resident"}
         sim = Simulation(prob, prec="fp32c", **kw1)
+        if kind == "moving":
+            sim.set_point_schedule(moving_rows(prob))
         n1 = min(steps, 2000)
         t1 = timed_steps(sim, n1, min(args.warmup, 200), args.graph_steps)
         i1 = sim.info
@@ -303,17 +323,12 @@ def main():
     if kind == "adjoint":
         line["roofline"] = None   # forward + adjoint mix, no single dominant kernel rate
         line["note"] = "value counts forward steps; time includes the adjoint pass"
-    if kind == "moving":
-        line["note"] = ("one resident launch a step, the point powers replaced on the device "
-                        "before each; time includes the host calls")
     if "fp64" in res:
         t64 = res["fp64"]["t"]
         i64 = res["fp64"]["info"]
-        if i64["resident"] and kind == "moving":
-            b64 = i64["algorithmic_bytes_per_launch"] + i64["exchange_bytes_per_step"]
-            l64 = steps
-        elif i64["resident"]:
-            b64 = i64["algorithmic_bytes_per_launch"] + steps * i64["exchange_bytes_per_step"]
+        if i64["resident"]:
+            b64 = i64["algorithmic_bytes_per_launch"] + steps * (i64["exchange_bytes_per_step"]
+                                                                 + 2 * sched_b)
             l64 = 1
         else:
             b64 = i64["algorithmic_bytes_per_launch"]

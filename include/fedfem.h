@@ -255,6 +255,31 @@ int fed_set_params(fed_ctx *ctx, const double *kscale, const double *elem_c,
 int fed_set_bc(fed_ctx *ctx, const double *face_Ta, const double *face_q, const double *pt_W,
                int32_t on_device, void *stream);
 
+/* Point-load schedule (the moving and time-varying sources of the paper's
+ * real-time use, Sec. 1 and 5, with the loads taken at the start of every
+ * step as in the explicit scheme of Sec. 3.1): W holds n_rows rows of n_pt
+ * concentrated loads (FP64, row-major, the order of the point loads given at
+ * fed_create); step n, counted from fed_set_temperature (or from the step
+ * given to fed_set_state), applies row n mod n_rows in place of the loads of
+ * fed_create / fed_set_bc.  The GPU derives every row's boundary-record powers
+ * once (n_rows x n_bnd_nodes values of the working precision), so the steps
+ * read them by index: a resident launch runs any number of scheduled steps,
+ * other contexts launch one step at a time (fuse_steps is not used and
+ * fed_step_graph runs as fed_step).  The results equal those of calling
+ * fed_set_bc(pt_W = row) before every single step, bit for bit, and
+ * fed_backward recomputes its segments with the rows of their steps (a run
+ * whose loads changed through fed_set_bc between steps is recomputed with the
+ * loads in effect when fed_backward is called).  A later fed_set_bc with
+ * face_q re-derives the rows; one with pt_W is refused while a schedule is
+ * set.  n_rows = 0 removes the schedule (W may then be NULL).  W is host
+ * memory (validated; `stream` synchronised before returning) if on_device ==
+ * 0, else device memory (not validated, copied in order on `stream`).
+ * Allocates device memory when n_rows changes, after synchronising the
+ * device.  Errors: FED_E_ARG (no point loads in the problem, n_rows < 0 or
+ * above 2^31 - 1, NULL W, non-finite values), FED_E_NOMEM / FED_E_HIP. */
+int fed_set_point_schedule(fed_ctx *ctx, const double *W, int64_t n_rows, int32_t on_device,
+                           void *stream);
+
 /* Smallest and largest current temperature (FP64; NaN if any is not finite).
  * The stability bound (Sec. 3.4) is derived for [T_lo, T_hi]; a run whose
  * temperatures leave that range should re-derive it with fed_set_range.

@@ -58,6 +58,8 @@ def lib():
         L.orc_loads.argtypes = [P, _d, _d, _d, _d]
         L.orc_surface.argtypes = [P, _d, _d]
         L.orc_run.argtypes = [P, _d, C.c_int64, _d, _d, _d, _d, _d, _d]
+        L.orc_run_sched.argtypes = [P, _d, C.c_int64, C.c_int64, C.c_int64, _d, _d, _d, _d, _d,
+                                    _d, _d]
         L.orc_adjoint.restype = C.c_int
         L.orc_adjoint.argtypes = [P, _d, C.c_int64, _i8, _d, _d, _d, _d]
         _LIB = L
@@ -274,14 +276,26 @@ class Oracle:
         lib().orc_surface(C.byref(self._s), _p(T), _p(Q))
         return Q
 
-    def run(self, nsteps=None, T0=None, history=False, apply_initial=True):
-        """T after nsteps explicit steps (or the (nsteps+1, N) history)."""
+    def run(self, nsteps=None, T0=None, history=False, apply_initial=True, pt_schedule=None,
+            step0=0):
+        """T after nsteps explicit steps (or the (nsteps+1, N) history).
+
+        With ``pt_schedule`` (n_rows x n_pt) step n of the run takes the
+        concentrated loads of row (step0 + n) mod n_rows instead of pt_W."""
         nsteps = self.prob["nsteps"] if nsteps is None else int(nsteps)
         T = self.initial(T0) if apply_initial else _f64(T0).copy()
         w = self._buffers()
         hist = np.zeros((nsteps + 1, self.N)) if history else None
-        lib().orc_run(C.byref(self._s), _p(T), nsteps, _p(w["Fe"]), _p(w["F"]),
-                      _p(w["C"]), _p(w["Q"]), _p(w["Tn"]), _p(hist))
+        if pt_schedule is None:
+            lib().orc_run(C.byref(self._s), _p(T), nsteps, _p(w["Fe"]), _p(w["F"]),
+                          _p(w["C"]), _p(w["Q"]), _p(w["Tn"]), _p(hist))
+        else:
+            Ws = _f64(pt_schedule)
+            if Ws.ndim != 2 or Ws.shape[1] != self.pt_nodes.size or Ws.shape[0] < 1:
+                raise ValueError("pt_schedule must be (n_rows >= 1, n_pt)")
+            lib().orc_run_sched(C.byref(self._s), _p(T), nsteps, int(step0), Ws.shape[0],
+                                _p(Ws), _p(w["Fe"]), _p(w["F"]), _p(w["C"]), _p(w["Q"]),
+                                _p(w["Tn"]), _p(hist))
         return hist if history else T
 
     def adjoint(self, hist, lam_final):

@@ -431,6 +431,22 @@ void orc_run(const orc_problem *P, double *T, int64_t nsteps, double *Fe, double
   }
 }
 
+/* orc_run with concentrated loads that change from step to step (a moving or
+ * time-varying source; the explicit scheme of Sec. 3.1 evaluates the loads at
+ * the start of each step): step n, counted from step0, takes its loads from row
+ * (step0 + n) mod nrows of Wrows (nrows x npt, row-major) instead of pt_W. */
+void orc_run_sched(const orc_problem *P, double *T, int64_t nsteps, int64_t step0, int64_t nrows,
+                   const double *Wrows, double *Fe, double *F, double *C, double *Q, double *Tn,
+                   double *hist) {
+  orc_problem Pn = *P;
+  if (hist) memcpy(hist, T, sizeof(double) * P->N);
+  for (int64_t n = 0; n < nsteps; n++) {
+    Pn.pt_W = Wrows + ((step0 + n) % nrows) * P->npt;
+    orc_run(&Pn, T, 1, Fe, F, C, Q, Tn, NULL);
+    if (hist) memcpy(hist + (n + 1) * P->N, T, sizeof(double) * P->N);
+  }
+}
+
 /* s K0_e v_e = W B^T (s Dk) B v_e: the element operator at a given factor s
  * applied to the nodal values v (the adjoint needs it with s taken from T^n
  * while v is the adjoint field). */

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -101,6 +102,11 @@ struct fed_ctx {
   int64_t *d_recptr = nullptr;
   double *d_fh = nullptr, *d_fTa = nullptr, *d_feps = nullptr, *d_fq = nullptr, *d_farea = nullptr;
   double *d_ptW = nullptr, *d_b64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // point-load schedule: its rows of concentrated loads (FP64, npt each) and
+  // the record powers of every row (step precision, nrec each)
+  double *d_psW = nullptr;
+  void *d_psP = nullptr;
+  int64_t ps_rows = 0;
   double *d_dtinst = nullptr;
   uint8_t *d_isdir = nullptr;
   unsigned long long *d_lam = nullptr;
@@ -185,6 +191,11 @@ struct fed_ctx {
     a.nct = nct;
     a.op = op;
     return a;
+  }
+
+  // record powers of step n (counted from fed_set_temperature) under the schedule
+  const void *ps_row(int64_t n) const {
+    return (const char *)d_psP + (size_t)rb * nrec * (size_t)(n % ps_rows);
   }
 
   void drop_graph() {
@@ -920,6 +931,12 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
       const int fin = c->cur ^ (k & 1);
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
                      c->d_T[fin], c->d_lo[fin], nullptr, 0};
+      if (c->ps_rows > 0) {
+        r.pts = c->d_psP;
+        r.pts_nrec = c->nrec;
+        r.pts_row = (int)((c->steps + nsteps - n) % c->ps_rows);
+        r.pts_nrows = (int)c->ps_rows;
+      }
       HIPCHK(fed::launch_resident(a, r, s));
       // the launch wrote tags up to xtag + k: the next one starts beyond them
       c->xtag += (unsigned)k + 1u;
@@ -930,8 +947,11 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
     return FED_OK;
   }
   for (int64_t n = nsteps; n > 0;) {
-    int k = (int)std::min<int64_t>(c->K, n);
+    // under a point-load schedule every step takes its own record powers: one
+    // step per launch
+    int k = c->ps_rows > 0 ? 1 : (int)std::min<int64_t>(c->K, n);
     fed::StepArgs a = c->step_args(c->cur, k);
+    if (c->ps_rows > 0) a.rP = c->ps_row(c->steps + nsteps - n);
     HIPCHK(fed::launch_step(a, s));
     c->cur ^= 1;
     n -= k;
@@ -985,8 +1005,9 @@ int fed_step_graph(fed_ctx *c, int64_t nsteps, int32_t graph_steps, void *stream
   if (!c) return fail(FED_E_ARG, "null ctx");
   if (!c->have_T) return fail(FED_E_STATE, "fed_set_temperature must come first");
   if (nsteps < 0 || graph_steps < 0) return fail(FED_E_ARG, "negative count");
-  // checkpoints break launches; a resident launch already runs all the steps
-  if (c->ckpt_every > 0 || c->resident) return fed_step(c, nsteps, stream);
+  // checkpoints break launches; a resident launch already runs all the steps; a
+  // point-load schedule gives every step its own launch arguments
+  if (c->ckpt_every > 0 || c->resident || c->ps_rows > 0) return fed_step(c, nsteps, stream);
   hipStream_t s = (hipStream_t)stream;
   // an even number of K-step launches, so every replay starts on the same buffer
   int64_t want = graph_steps ? graph_steps : 100;
@@ -1188,6 +1209,8 @@ int fed_set_bc(fed_ctx *c, const double *face_Ta, const double *face_q, const do
   if (!c) return fail(FED_E_ARG, "null ctx");
   if ((face_Ta || face_q) && c->nf == 0) return fail(FED_E_ARG, "the problem has no faces");
   if (pt_W && c->npt == 0) return fail(FED_E_ARG, "the problem has no point loads");
+  if (pt_W && c->ps_rows > 0)
+    return fail(FED_E_STATE, "a point-load schedule is set (fed_set_point_schedule)");
   hipStream_t s = (hipStream_t)stream;
   const int64_t nf = c->nf;
   if (!on_device) {
@@ -1228,8 +1251,48 @@ int fed_set_bc(fed_ctx *c, const double *face_Ta, const double *face_q, const do
                         c->d_b64[3], c->d_alpha, c->d_beta, c->d_rA, c->d_rAT, c->d_reA,
                         c->d_rTa, c->d_rP};
     HIPCHK(fed::launch_node_arrays(na, s));
+    // the schedule's rows hold the face fluxes too
+    if (face_q && c->ps_rows > 0)
+      HIPCHK(fed::launch_point_rows(c->prec == FED_FP64 ? 1 : 0, ba, c->ps_rows, c->npt,
+                                    c->d_psW, c->d_psP, s));
   }
   if (!on_device) HIPCHK(hipStreamSynchronize(s));  // the host arrays may be reused
+  return FED_OK;
+}
+
+int fed_set_point_schedule(fed_ctx *c, const double *W, int64_t n_rows, int32_t on_device,
+                           void *stream) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  if (n_rows < 0 || n_rows > INT32_MAX) return fail(FED_E_ARG, "n_rows %lld out of range", (long long)n_rows);
+  if (n_rows > 0 && !W) return fail(FED_E_ARG, "null W");
+  if (n_rows > 0 && c->npt == 0) return fail(FED_E_ARG, "the problem has no point loads");
+  hipStream_t s = (hipStream_t)stream;
+  if (n_rows > 0 && !on_device)
+    for (int64_t i = 0; i < n_rows * c->npt; i++)
+      if (!std::isfinite(W[i])) return fail(FED_E_ARG, "W[%lld] invalid", (long long)i);
+  if (c->ps_rows != n_rows) {
+    // launches already queued may still read the old tables
+    HIPCHK(hipDeviceSynchronize());
+    c->pool.release(c->d_psW);
+    c->pool.release(c->d_psP);
+    c->d_psW = nullptr;
+    c->d_psP = nullptr;
+    c->ps_rows = 0;
+    if (n_rows == 0) return FED_OK;
+    HIPCHK(c->pool.alloc((void **)&c->d_psW, sizeof(double) * n_rows * c->npt));
+    HIPCHK(c->pool.alloc(&c->d_psP, (size_t)c->rb * n_rows * c->nrec));
+  } else if (n_rows == 0) {
+    return FED_OK;
+  }
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIPCHK(hipMemcpyAsync(c->d_psW, W, sizeof(double) * n_rows * c->npt, kind, s));
+  fed::BndArgs ba{0, c->nfn, c->d_faces, nullptr, nullptr, nullptr, c->d_fh, c->d_fTa,
+                  c->d_feps, c->d_fq, c->d_farea, c->nrec, c->d_recptr, c->d_recitem,
+                  c->d_ptW, c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[3], c->d_b64[4]};
+  HIPCHK(fed::launch_point_rows(c->prec == FED_FP64 ? 1 : 0, ba, n_rows, c->npt, c->d_psW,
+                                c->d_psP, s));
+  c->ps_rows = n_rows;
+  if (!on_device) HIPCHK(hipStreamSynchronize(s));  // the host array may be reused
   return FED_OK;
 }
 
@@ -1382,6 +1445,12 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       a.Tout = seg(1);  // not used by the resident kernel
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
                      seg(k), c->d_seglo[k & 1], c->d_seg, N};
+      if (c->ps_rows > 0) {
+        r.pts = c->d_psP;
+        r.pts_nrec = c->nrec;
+        r.pts_row = (int)(n0 % c->ps_rows);
+        r.pts_nrows = (int)c->ps_rows;
+      }
       HIPCHK(fed::launch_resident(a, r, s));
       c->xtag += (unsigned)k + 1u;
     } else {
@@ -1391,6 +1460,7 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
         a.Tout = seg(i + 1);
         a.loin = c->d_seglo[i & 1];
         a.loout = c->d_seglo[(i + 1) & 1];
+        if (c->ps_rows > 0) a.rP = c->ps_row(n0 + i);
         HIPCHK(fed::launch_step(a, s));
       }
     }

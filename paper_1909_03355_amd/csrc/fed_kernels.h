@@ -155,6 +155,11 @@ struct AdjArgs {
 hipError_t launch_geom(const GeomArgs &a, hipStream_t s);
 hipError_t launch_mass(const MassArgs &a, hipStream_t s);
 hipError_t launch_bnd(const BndArgs &a, hipStream_t s);
+// record powers (face fluxes and concentrated loads, the P of the records that
+// launch_bnd derives) for each of nrows rows of point-load values W[nrows][npt],
+// cast to the working precision: out[row * nrec + r]
+hipError_t launch_point_rows(int prec, const BndArgs &a, int64_t nrows, int64_t npt,
+                             const double *W, void *out, hipStream_t s);
 hipError_t launch_dt(const DtArgs &a, hipStream_t s);
 hipError_t launch_node_arrays(const NodeArrArgs &a, hipStream_t s);
 // (s0, s1) of the material of every expanded element, in the step precision
@@ -182,6 +187,11 @@ struct ResArgs {
   void *seg;                  // nullable: hi after step s goes to seg + (s + 1) * N (the
                               // adjoint's segment recompute)
   int64_t segN;
+  // nullable: per-step record powers R[pts_nrows][pts_nrec]; step s of the launch
+  // takes row (pts_row + s) mod pts_nrows in place of rP
+  const void *pts;
+  int64_t pts_nrec;
+  int pts_row, pts_nrows;
 };
 
 // Resident adjoint of one checkpoint segment (hexahedra, folded operator):

@@ -323,36 +323,61 @@ __global__ void k_face_area(BndArgs a) {
   a.farea[f] = area;
 }
 
+// Applied power of boundary record r: flux q A of its faces (|f| / n_f each)
+// plus the concentrated loads W of its point items, in item order.  Shared by
+// the record refresh and the per-step rows of a point-load schedule, so a row
+// equals the record a refresh with the same loads derives, bit for bit.
+__device__ inline double rec_power(const BndArgs &a, int64_t r, const double *W) {
+#pragma clang fp contract(off)
+  double P = 0;
+  for (int64_t p = a.rec_ptr[r]; p < a.rec_ptr[r + 1]; p++) {
+    const int32_t it = a.rec_item[p];
+    if (it >= 0) {
+      const double s = a.farea[it] / a.nfn, q = a.fq ? a.fq[it] : 0.0;
+      P += q * s;
+    } else {
+      P += W[-(it + 1)];
+    }
+  }
+  return P;
+}
+
 // Per boundary node: lumped convection h A, h A Ta, radiation sigma eps A and the
 // applied power (flux q A plus concentrated loads), each face giving |f| / n_f.
 __global__ void k_bnd_rec(BndArgs a) {
   int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= a.nrec) return;
-  double hA = 0, hAT = 0, eA = 0, P = 0, rTa = 0;
+  double hA = 0, hAT = 0, eA = 0, rTa = 0;
   bool rad = false;
   for (int64_t p = a.rec_ptr[r]; p < a.rec_ptr[r + 1]; p++) {
     int32_t it = a.rec_item[p];
     if (it >= 0) {
       double s = a.farea[it] / a.nfn;
       double h = a.fh ? a.fh[it] : 0.0, Ta = a.fTa ? a.fTa[it] : 0.0;
-      double eps = a.feps ? a.feps[it] : 0.0, q = a.fq ? a.fq[it] : 0.0;
+      double eps = a.feps ? a.feps[it] : 0.0;
       hA += h * s;
       hAT += h * s * Ta;
       eA += kSigma * eps * s;
-      P += q * s;
       if (eps > 0 && !rad) {
         rad = true;
         rTa = Ta;
       }
-    } else {
-      P += a.pt_W[-(it + 1)];
     }
   }
   a.bhA[r] = hA;
   a.bhAT[r] = hAT;
   a.beA[r] = eA;
-  a.bP[r] = P;
+  a.bP[r] = rec_power(a, r, a.pt_W);
   if (a.bTa) a.bTa[r] = rTa;
+}
+
+// Rows of a point-load schedule: out[row][r] = (R) rec_power(r, W[row])
+template <typename R>
+__global__ void k_point_rows(BndArgs a, int64_t nrows, int64_t npt, const double *W, R *out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nrows * a.nrec) return;
+  const int64_t row = i / a.nrec, r = i - row * a.nrec;
+  out[i] = (R)rec_power(a, r, W + row * npt);
 }
 
 // Stability bound (Sec. 3.4): per element lambda_e = lambda_max(K_e(T)) / (rho c V /
@@ -1815,10 +1840,24 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   const KLaw<R> kl = step_law<R, GEN>(a);
   const R Tz = (R)a.Tz;
   const uint32_t pmask = (1u << a.pb) - 1u;
+  int prow = r.pts_row;
   for (int s = 0; s < r.nsteps; s++) {
     // the previous step's stores (exports) complete before the halo poll
     // starts: polling while they drain is slower (s_waitcnt vmcnt(0))
     __builtin_amdgcn_s_waitcnt(0x0f70);
+    // a point-load schedule's row for this step: loaded now, its latency
+    // hidden behind the halo wait, and put where the node phase reads the
+    // record's power (each thread writes only the entries it reads itself)
+    R pn[NPT];
+    if (r.pts) {
+      const R *rp = (const R *)r.pts + (int64_t)prow * r.pts_nrec + th.bstart;
+#pragma unroll
+      for (int q = 0; q < NPT; q++) {
+        const int j = tid + q * bs;
+        pn[q] = j < nbnd ? rp[j] : (R)0;
+      }
+      prow = prow + 1 == r.pts_nrows ? 0 : prow + 1;
+    }
     // ---- stage T: owned from registers, halo from the state or the exchange ----
 #pragma unroll
     for (int q = 0; q < NPT; q++) {
@@ -1838,6 +1877,13 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     for (int q = 0; q < HPT; q++) {
       const int j = tid + q * bs;
       if (j < nhalo) Tl[nown + j] = hv[q];
+    }
+    if (r.pts) {
+#pragma unroll
+      for (int q = 0; q < NPT; q++) {
+        const int j = tid + q * bs;
+        if (j < nbnd) Lbnd[4 * nbnd + j] = pn[q];
+      }
     }
     __syncthreads();
     // ---- element loads into the node-local slots ----
@@ -2157,6 +2203,19 @@ hipError_t launch_bnd(const BndArgs &a, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.nrec > 0) hipLaunchKernelGGL(k_bnd_rec, dim3(blocks_for(a.nrec, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_point_rows(int prec, const BndArgs &a, int64_t nrows, int64_t npt,
+                             const double *W, void *out, hipStream_t s) {
+  const int64_t n = nrows * a.nrec;
+  if (n == 0) return hipSuccess;
+  if (prec == 1)
+    hipLaunchKernelGGL(k_point_rows<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, nrows,
+                       npt, W, (double *)out);
+  else
+    hipLaunchKernelGGL(k_point_rows<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, nrows,
+                       npt, W, (float *)out);
   return hipGetLastError();
 }
 

@@ -207,6 +207,21 @@ class Simulation:
                                    self.stream))
         self._keep_bc = args  # device tensors stay alive until the copies have run
 
+    def set_point_schedule(self, W):
+        """Per-step concentrated loads: W is (n_rows, n_pt) (numpy, validated,
+        or a CUDA tensor); step n since set_temperature applies row n mod
+        n_rows.  None removes the schedule."""
+        if W is None:
+            L.check(L.lib().fed_set_point_schedule(self._c(), None, 0, 0, self.stream))
+            self._keep_sched = None
+            return
+        if len(W.shape) != 2:
+            raise ValueError("W must be (n_rows, n_pt)")
+        ptr, on_dev, keep = self._arg(W)
+        L.check(L.lib().fed_set_point_schedule(self._c(), ptr, int(W.shape[0]), on_dev,
+                                               self.stream))
+        self._keep_sched = keep  # a device tensor stays alive until the copy has run
+
     def temperature_range(self):
         """(min, max) of the current temperatures (synchronises)."""
         lo, hi = C.c_double(), C.c_double()

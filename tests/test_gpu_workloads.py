@@ -143,3 +143,27 @@ def test_nonlinear_adjoint_hex64():
     print("nladjoint_hex64 fp32c", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     for k, v in errs.items():
         assert v <= 1e-4, (k, v)
+
+
+def test_moving_source_hex64_full_size():
+    """The moving-source workload at 64^3 in the launch shape bench.py times
+    (resident, a point-load schedule moving a 2 W source one node a step),
+    200 steps (the 65-row path wraps three times): against the oracle, and
+    bitwise against one step per launch."""
+    from paper_1909_03355_amd import Simulation
+    p = P.moving_source_hex(64, 200)
+    n = p["pt_nodes"].size
+    W = np.diag(np.full(n, p["meta"]["source_power"]))
+    ref = Oracle(p).run(200, pt_schedule=W)
+    for prec in ("fp64", "fp32c"):
+        out = []
+        for kw in (dict(resident=True), dict()):
+            with Simulation(p, prec=prec, **kw) as s:
+                s.set_point_schedule(W)
+                s.set_temperature()
+                s.step(200)
+                out.append(s.temperature())
+        err = oracle.err_max(out[0], ref)
+        print(f"moving_source_hex64 {prec}: err_max {err:.2e}", flush=True)
+        assert err <= TOL[prec]
+        assert np.array_equal(out[0], out[1])

@@ -375,6 +375,43 @@ def test_energy_balance_nonlinear():
         assert abs(stored - o.dt[0] * 3.5) < 1e-10 * abs(stored)
 
 
+def test_point_schedule_energy_and_location():
+    """Scheduled point loads (row (step0 + n) mod n_rows at step n), insulated
+    box with nonlinear c(T) and D(T): every step stores dt times the total of
+    its own row (rows with distinct totals, the table wrapping twice, two
+    values of step0), and the first two steps from a uniform field raise only
+    the nodes their rows load, by dt W / C (the second row's node is not a
+    neighbour of the first's, so no conduction reaches it yet)."""
+    mat = P.material(rho=1000.0, c0=1000.0, c1=2.0, k=[1.0, 2.0, 0.5], s0=1.0, s1=0.005)
+    p, m = H.box_problem("hex8", 4, side=0.1, mat=mat)
+    nodes = np.array([3, 17, 40, 77], np.int32)      # (3,0,0) (2,3,0) (0,3,1) (2,0,3)
+    p["pt_nodes"], p["pt_W"] = nodes, np.zeros(4)
+    p["T_lo"], p["T_hi"] = 0.0, 200.0
+    W = np.array([[2.0, 0.0, 0.0, 0.0], [0.0, 3.0, 0.0, 0.0], [0.0, 0.0, 1.0, 3.0]])
+    n_inc = np.bincount(m["conn"].ravel(), minlength=m["x"].size)
+    cap = 1000.0 * 0.1 ** 3 / m["conn"].shape[1] / 8 * n_inc
+    for step0 in (0, 2):
+        p["T0"] = np.random.default_rng(6).uniform(20, 80, m["x"].size)
+        o = Oracle(p)
+        hist = o.run(7, history=True, pt_schedule=W, step0=step0)
+        for n in range(7):
+            stored = np.sum(cap * (1000.0 + 2.0 * hist[n]) * (hist[n + 1] - hist[n]))
+            total = W[(step0 + n) % 3].sum()
+            assert abs(stored - o.dt[0] * total) < 1e-10 * abs(stored)
+    p["T0"] = np.full(m["x"].size, 30.0)
+    o = Oracle(p)
+    hist = o.run(2, history=True, pt_schedule=W)
+    C30 = cap * (1000.0 + 2.0 * 30.0)
+    d1 = hist[1] - hist[0]
+    assert np.max(np.abs(np.delete(d1, 3))) < 1e-12
+    assert abs(d1[3] - o.dt[0] * 2.0 / C30[3]) < 1e-12 * d1[3]
+    d2 = hist[2] - hist[1]
+    assert abs(d2[17] - o.dt[0] * 3.0 / C30[17]) < 1e-12 * d2[17]
+    # a one-row schedule is the fixed loads of that row
+    p["pt_W"] = W[2]
+    assert np.array_equal(Oracle(p).run(3), Oracle(p).run(3, pt_schedule=W[2:]))
+
+
 def test_constant_field_is_fixed_point():
     mat = P.material(rho=1000.0, c0=1000.0, c1=2.0, k=[1.0, 2.0, 0.5], s0=1.0, s1=0.005)
     for elem in ("hex8", "tet4"):
