@@ -26,6 +26,7 @@ struct TileHdr {
   int32_t nhalo;   // halo nodes (levels 1..K)
   int32_t estart;  // first expanded element of the tile
   int32_t ecount;  // expanded elements of the tile (= cum_e[K-1])
+  int32_t nint;    // elements whose nodes are all owned: the first nint of the list
   int32_t cum_n[kMaxDepth + 1];  // local nodes of level <= l
   int32_t cum_e[kMaxDepth];      // elements of lowest level <= l
 };

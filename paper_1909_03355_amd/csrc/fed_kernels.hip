@@ -1841,9 +1841,44 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   const R Tz = (R)a.Tz;
   const uint32_t pmask = (1u << a.pb) - 1u;
   int prow = r.pts_row;
+  // element loads into the node-local slots
+  auto element = [&](int q) {
+    if constexpr (PRE) {
+      keep_packed(ta[q]);
+      uint32_t u[8];
+      Ent<8>::unpack(ta[q], u);
+      R T[8], F[8];
+#pragma unroll
+      for (int n = 0; n < 8; n++) T[n] = lds_ld<R>(u[n]);
+      Elem<R, 8>::load_vals(T, kl, TDK, eh[q], F);
+#pragma unroll
+      for (int n = 0; n < 8; n++) lds_st<R>(sa[q][n], F[n]);
+    } else {
+      keep_packed(ew[q]);
+      element_to_slots<R, NE, TDK, 0, NM>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, kl);
+    }
+  };
+  // the elements with every node owned come first in the tile's list
+  const int nint = r.split ? th.nint : 0;
   for (int s = 0; s < r.nsteps; s++) {
-    // the previous step's stores (exports) complete before the halo poll
-    // starts: polling while they drain is slower (s_waitcnt vmcnt(0))
+    // ---- stage the owned T from registers ----
+#pragma unroll
+    for (int q = 0; q < NPT; q++) {
+      const int j = tid + q * bs;
+      if (j < nown) Tl[j] = hi[q];
+    }
+    // ---- elements with every node owned need no halo value: they run while
+    // the neighbours' exports of the previous step arrive (the barrier orders
+    // them after the staging and after the previous step's slot sums) ----
+    if (r.split) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < EPT; q++)
+        if (tid + q * bs < nint) element(q);
+    }
+    // ---- halo from the state or the exchange, once the previous step's
+    // export stores have completed (polling while they drain is slower;
+    // s_waitcnt vmcnt(0)) ----
     __builtin_amdgcn_s_waitcnt(0x0f70);
     // a point-load schedule's row for this step: loaded now, its latency
     // hidden behind the halo wait, and put where the node phase reads the
@@ -1857,12 +1892,6 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
         pn[q] = j < nbnd ? rp[j] : (R)0;
       }
       prow = prow + 1 == r.pts_nrows ? 0 : prow + 1;
-    }
-    // ---- stage T: owned from registers, halo from the state or the exchange ----
-#pragma unroll
-    for (int q = 0; q < NPT; q++) {
-      const int j = tid + q * bs;
-      if (j < nown) Tl[j] = hi[q];
     }
     R hv[HPT];
     if (s == 0) {
@@ -1886,29 +1915,17 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       }
     }
     __syncthreads();
-    // ---- element loads into the node-local slots ----
+    // ---- the elements that touch the halo ----
 #pragma unroll
-    for (int q = 0; q < EPT; q++)
-      if (tid + q * bs < nE) {
-        if constexpr (PRE) {
-          keep_packed(ta[q]);
-          uint32_t u[8];
-          Ent<8>::unpack(ta[q], u);
-          R T[8], F[8];
-#pragma unroll
-          for (int n = 0; n < 8; n++) T[n] = lds_ld<R>(u[n]);
-          Elem<R, 8>::load_vals(T, kl, TDK, eh[q], F);
-#pragma unroll
-          for (int n = 0; n < 8; n++) lds_st<R>(sa[q][n], F[n]);
-        } else {
-          keep_packed(ew[q]);
-          element_to_slots<R, NE, TDK, 0, NM>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, kl);
-        }
-      }
+    for (int q = 0; q < EPT; q++) {
+      const int i = tid + q * bs;
+      if (i >= nint && i < nE) element(q);
+    }
     __syncthreads();
     // ---- per node: ordered sum, surface loads, explicit update, export ----
-    // (the next staging writes only Tl, which nothing reads after the barrier
-    // above; the next slot writes come after the next staging's barrier)
+    // (the next step's owned staging writes only Tl, which nothing reads after
+    // the barrier above; its slot writes come after a barrier, its halo writes
+    // after the elements with every node owned, which read only owned T)
     unsigned long long *Xw = r.X[(s + 1) & 1];
     const unsigned tag = r.tag0 + (unsigned)s + 1u;
 #pragma unroll

@@ -211,7 +211,7 @@ struct Builder {
     // per tile: node levels, elements within K - 1 rings, halo, packed entries
     const int K = in.depth;
     out.depth = K;
-    std::vector<int32_t> loc(N, -1), estamp(E, -1), minlev(E, 0);
+    std::vector<int32_t> loc(N, -1), estamp(E, -1), minlev(E, 0), maxlev(E, 0);
     std::vector<int32_t> telems;
     out.halo.clear();
     out.ent.clear();
@@ -252,18 +252,29 @@ struct Builder {
               telems.push_back(el);
             }
           }
+      // sorted by lowest node level (a K-step launch drops the outer levels
+      // step by step), then elements with every node owned first (they need no
+      // halo value, so a resident step can run them while it waits for the
+      // halo), then id; the order changes no result: every nodal sum runs over
+      // the node's elements in ascending element id
+      th.nint = 0;
       for (int32_t el : telems) {
-        int32_t m = kMaxDepth + 1;
+        int32_t m = kMaxDepth + 1, mx = 0;
         for (int a = 0; a < ne; a++) {
           int32_t lc = loc[node(el, a)];
           int32_t lv = 0;
           while (lc >= th.cum_n[lv]) lv++;
           m = std::min(m, lv);
+          mx = std::max(mx, lv);
         }
         minlev[el] = m;
+        maxlev[el] = mx;
+        th.nint += mx == 0;
       }
       std::sort(telems.begin(), telems.end(), [&](int32_t p, int32_t q) {
-        return minlev[p] != minlev[q] ? minlev[p] < minlev[q] : p < q;
+        if (minlev[p] != minlev[q]) return minlev[p] < minlev[q];
+        if ((maxlev[p] == 0) != (maxlev[q] == 0)) return maxlev[p] == 0;
+        return p < q;
       });
       th.estart = (int32_t)out.eorig.size();
       th.ecount = (int32_t)telems.size();

@@ -165,17 +165,26 @@ int main(int argc, char **argv) {
         for (int64_t p = T.inc_ptr[ki]; p < T.inc_ptr[ki + 1]; p++) want.insert(T.inc_elem[p]);
     REQUIRE((int)want.size() == th.ecount && th.cum_e[K - 1] == th.ecount);
     std::vector<std::vector<std::pair<int32_t, int>>> got(th.cum_n[K - 1]);  // (elem, pos)
-    int prevlev = 0;
+    // order: lowest node level, then all nodes owned first, then id; the
+    // first nint elements are exactly those with every node owned
+    int prevlev = 0, prevout = 0;
     int32_t prev = -1;
     for (int i = 0; i < th.ecount; i++) {
       int64_t ie = th.estart + i;
       int32_t e = T.eorig[ie];
       REQUIRE(want.count(e));
-      int ml = 99;
-      for (int a = 0; a < ne; a++) ml = std::min(ml, lvl[T.perm[conn[a * E + e]]]);
-      REQUIRE(ml >= prevlev && (ml > prevlev || e > prev));
+      int ml = 99, mx = 0;
+      for (int a = 0; a < ne; a++) {
+        ml = std::min(ml, lvl[T.perm[conn[a * E + e]]]);
+        mx = std::max(mx, lvl[T.perm[conn[a * E + e]]]);
+      }
+      const int out = mx > 0;
+      REQUIRE(ml >= prevlev);
+      if (ml == prevlev) REQUIRE(out >= prevout && (out > prevout || e > prev));
+      REQUIRE((i < th.nint) == (mx == 0));
       for (int l = 0; l < K; l++) REQUIRE((i < th.cum_e[l]) == (ml <= l));
       prevlev = ml;
+      prevout = out;
       prev = e;
       owners[e] += T.eowner[ie];
       for (int a = 0; a < ne; a++) {
