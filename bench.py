@@ -280,7 +280,6 @@ def main():
                    "elements": E, "nodes": N, "precision": "fp32c",
                    "graph_steps": args.graph_steps,
                    "steps_per_launch": steps if resident else K, "resident": resident,
-                   "resident_overlap": bool(info["resident_overlap"]),
                    "tiles": info["n_tiles"], "block_threads": info["block_threads"],
                    "autotuned": tuned is not None},
         "hbm_gbs_algorithmic": achieved,

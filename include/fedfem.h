@@ -166,8 +166,7 @@ typedef struct {
                                           else */
   int32_t resident_adjoint;            /* 1 if fed_backward runs each checkpoint segment's
                                           adjoint steps in one resident launch */
-  int32_t resident_overlap;            /* 1 if a resident step runs the elements whose nodes
-                                          the tile owns while it waits for the halo */
+  int32_t reserved_;
 } fed_info;
 
 /*

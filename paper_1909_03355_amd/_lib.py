@@ -65,7 +65,7 @@ class fed_info(C.Structure):
                 ("algorithmic_bytes_per_launch", C.c_double),
                 ("moved_bytes_per_launch", C.c_double),
                 ("exchange_bytes_per_step", C.c_double),
-                ("resident_adjoint", C.c_int32), ("resident_overlap", C.c_int32)]
+                ("resident_adjoint", C.c_int32), ("reserved_", C.c_int32)]
 
 
 # name -> (restype, argtypes) of every symbol the header declares

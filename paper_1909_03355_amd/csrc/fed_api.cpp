@@ -88,7 +88,6 @@ struct fed_ctx {
   unsigned xtag = 1;
   int *d_rerr = nullptr;
   int res_lds = 0;
-  int res_split = 0;  // resident steps run the tile-interior elements before the halo wait
   // resident adjoint (hexahedra, folded operator, tiles within the LDS)
   bool adjres = false;
   int adjres_lds = 0;
@@ -349,14 +348,6 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
                   "%d threads' registers (%d / %d / %d per thread); use more tiles or resident = 0",
                   t, th.nown, nE, nhalo, c->block, cap.npt, cap.ept, cap.hpt);
   }
-  // Overlapping the tile-interior elements with the halo wait costs a third
-  // workgroup barrier a step.  It pays where the exchange dominates the step:
-  // tiles with at most one element a thread, and FP64 (64^3 hexahedra: 3.14
-  // against 3.37 us FP64, 2.71 against 2.67 us FP32C; 48^3: 2.25 against 2.61
-  // and 2.09 against 2.27 us)
-  int maxe = 0;
-  for (const fed::TileHdr &th : T.tiles) maxe = std::max(maxe, th.cum_e[0]);
-  c->res_split = (c->prec == FED_FP64 || maxe <= c->block) ? 1 : 0;
   std::vector<uint8_t> exported(N, 0);
   int64_t halo_total = 0;
   for (int32_t t = 0; t < T.nt; t++) {
@@ -868,7 +859,6 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   I.resident = c->resident ? 1 : 0;
   I.exchange_bytes_per_step = exch_bytes;
   I.resident_adjoint = c->adjres ? 1 : 0;
-  I.resident_overlap = c->resident && c->res_split ? 1 : 0;
   double elem_b = 2.0 * ne + c->hw * rb + (c->d_esk ? 2.0 * rb : 0.0);
   double lo_b = c->prec == FED_FP32C ? 4.0 : 0.0;
   double coef_b = rb + (c->tdc ? rb : 0.0);
@@ -941,7 +931,6 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
       const int fin = c->cur ^ (k & 1);
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
                      c->d_T[fin], c->d_lo[fin], nullptr, 0};
-      r.split = c->res_split;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
         r.pts_nrec = c->nrec;
@@ -1456,7 +1445,6 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       a.Tout = seg(1);  // not used by the resident kernel
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
                      seg(k), c->d_seglo[k & 1], c->d_seg, N};
-      r.split = c->res_split;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
         r.pts_nrec = c->nrec;

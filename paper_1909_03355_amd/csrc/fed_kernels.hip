@@ -1772,31 +1772,31 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     }
   }
   // hexahedra use node-major slots (below).  FP32 hexahedra keep precomputed
-  // LDS addresses instead of the packed entries: the node temperatures' as
-  // 16-bit halves (4 registers an element) and the slots' as words (8), so
-  // the element phase spends no instructions on addressing
+  // LDS addresses instead of the packed entries, the node temperatures' and
+  // the slots' (16 registers an element), so the element phase spends no
+  // instructions on addressing
   constexpr bool NM = NE == 8;
   constexpr bool PRE = NM && sizeof(R) == 4;
   const int nslot = NM ? ntouch * ((1 << a.pb) + 1) : a.maxinc * nown;
   R *Tl = reinterpret_cast<R *>(smem_raw);
   R *slot = Tl + ntouch;
   R *Lbnd = slot + nslot;  // [5][nbnd]: hA, hA Ta, sigma eps A, radiation Ta, power
-  uint4 ta[PRE ? EPT : 1];
-  uint32_t sa[PRE ? EPT : 1][8];
+  uint32_t ta[PRE ? EPT : 1][8], sa[PRE ? EPT : 1][8];
   if constexpr (PRE) {
     const uint32_t tb = lds_addr(Tl), sb = lds_addr(slot);
 #pragma unroll
     for (int q = 0; q < EPT; q++) {
-      uint32_t v[8], u[8];
+      uint32_t v[8];
       Ent<8>::unpack(*reinterpret_cast<const uint4 *>(&ew[q]), v);
 #pragma unroll
       for (int n = 0; n < 8; n++) {
         const uint32_t loc = v[n] >> a.pb;
-        u[n] = tb + loc * (uint32_t)sizeof(R);
+        ta[q][n] = tb + loc * (uint32_t)sizeof(R);
         sa[q][n] = sb + (v[n] + loc) * (uint32_t)sizeof(R);
+        // opaque from here on: the loop uses the whole addresses as they are
+        // instead of re-adding the LDS bases at every access
+        asm volatile("" : "+v"(ta[q][n]), "+v"(sa[q][n]));
       }
-      ta[q] = make_uint4(u[0] | (u[1] << 16), u[2] | (u[3] << 16), u[4] | (u[5] << 16),
-                         u[6] | (u[7] << 16));
     }
   }
   const R *Tin = (const R *)a.Tin;
@@ -1844,12 +1844,9 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   // element loads into the node-local slots
   auto element = [&](int q) {
     if constexpr (PRE) {
-      keep_packed(ta[q]);
-      uint32_t u[8];
-      Ent<8>::unpack(ta[q], u);
       R T[8], F[8];
 #pragma unroll
-      for (int n = 0; n < 8; n++) T[n] = lds_ld<R>(u[n]);
+      for (int n = 0; n < 8; n++) T[n] = lds_ld<R>(ta[q][n]);
       Elem<R, 8>::load_vals(T, kl, TDK, eh[q], F);
 #pragma unroll
       for (int n = 0; n < 8; n++) lds_st<R>(sa[q][n], F[n]);
@@ -1859,7 +1856,12 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     }
   };
   // the elements with every node owned come first in the tile's list
-  const int nint = r.split ? th.nint : 0;
+  const int nint = th.nint;
+  // every load above completes here, once: otherwise the compiler waits for
+  // them at their first use inside the loop, on every step, and such a wait
+  // (vmcnt counts stores too) would also hold the interior elements until the
+  // previous step's exports have completed
+  __builtin_amdgcn_s_waitcnt(0x0f70);
   for (int s = 0; s < r.nsteps; s++) {
     // ---- stage the owned T from registers ----
 #pragma unroll
@@ -1867,15 +1869,13 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       const int j = tid + q * bs;
       if (j < nown) Tl[j] = hi[q];
     }
+    __syncthreads();
     // ---- elements with every node owned need no halo value: they run while
     // the neighbours' exports of the previous step arrive (the barrier orders
     // them after the staging and after the previous step's slot sums) ----
-    if (r.split) {
-      __syncthreads();
 #pragma unroll
-      for (int q = 0; q < EPT; q++)
-        if (tid + q * bs < nint) element(q);
-    }
+    for (int q = 0; q < EPT; q++)
+      if (tid + q * bs < nint) element(q);
     // ---- halo from the state or the exchange, once the previous step's
     // export stores have completed (polling while they drain is slower;
     // s_waitcnt vmcnt(0)) ----
