@@ -88,6 +88,7 @@ struct fed_ctx {
   unsigned xtag = 1;
   int *d_rerr = nullptr;
   int res_lds = 0;
+  int res_split = 1;  // resident steps run the tile-interior elements during the halo wait
   // resident adjoint (hexahedra, folded operator, tiles within the LDS)
   bool adjres = false;
   int adjres_lds = 0;
@@ -348,6 +349,12 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
                   "%d threads' registers (%d / %d / %d per thread); use more tiles or resident = 0",
                   t, th.nown, nE, nhalo, c->block, cap.npt, cap.ept, cap.hpt);
   }
+  // Overlapping the tile-interior elements with the halo wait costs a third
+  // workgroup barrier a step; it pays unless the element work is long enough
+  // to cover the exchange anyway: tables or per-element laws (64^3 hexahedra:
+  // 2.37 against 2.67 us FP32C, 3.15 against 3.36 us FP64 with the linear
+  // laws; see the design notes for the table-driven case)
+  c->res_split = (c->d_esk || c->d_ktab || c->d_ctab) ? 0 : 1;
   std::vector<uint8_t> exported(N, 0);
   int64_t halo_total = 0;
   for (int32_t t = 0; t < T.nt; t++) {
@@ -931,6 +938,7 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
       const int fin = c->cur ^ (k & 1);
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
                      c->d_T[fin], c->d_lo[fin], nullptr, 0};
+      r.split = c->res_split;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
         r.pts_nrec = c->nrec;
@@ -1445,6 +1453,7 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       a.Tout = seg(1);  // not used by the resident kernel
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
                      seg(k), c->d_seglo[k & 1], c->d_seg, N};
+      r.split = c->res_split;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
         r.pts_nrec = c->nrec;

@@ -192,6 +192,9 @@ struct ResArgs {
   const void *pts;
   int64_t pts_nrec;
   int pts_row, pts_nrows;
+  // 1: each step runs the elements whose nodes the tile owns before it waits
+  // for the halo (one more workgroup barrier a step); 0: all elements after it
+  int split;
 };
 
 // Resident adjoint of one checkpoint segment (hexahedra, folded operator):

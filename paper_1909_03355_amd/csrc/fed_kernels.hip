@@ -1856,7 +1856,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     }
   };
   // the elements with every node owned come first in the tile's list
-  const int nint = th.nint;
+  const int nint = r.split ? th.nint : 0;
   // every load above completes here, once: otherwise the compiler waits for
   // them at their first use inside the loop, on every step, and such a wait
   // (vmcnt counts stores too) would also hold the interior elements until the
@@ -1869,13 +1869,15 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       const int j = tid + q * bs;
       if (j < nown) Tl[j] = hi[q];
     }
-    __syncthreads();
     // ---- elements with every node owned need no halo value: they run while
     // the neighbours' exports of the previous step arrive (the barrier orders
     // them after the staging and after the previous step's slot sums) ----
+    if (r.split) {
+      __syncthreads();
 #pragma unroll
-    for (int q = 0; q < EPT; q++)
-      if (tid + q * bs < nint) element(q);
+      for (int q = 0; q < EPT; q++)
+        if (tid + q * bs < nint) element(q);
+    }
     // ---- halo from the state or the exchange, once the previous step's
     // export stores have completed (polling while they drain is slower;
     // s_waitcnt vmcnt(0)) ----
