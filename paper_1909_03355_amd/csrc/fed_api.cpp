@@ -351,9 +351,10 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   }
   // Overlapping the tile-interior elements with the halo wait costs a third
   // workgroup barrier a step; it pays unless the element work is long enough
-  // to cover the exchange anyway: tables or per-element laws (64^3 hexahedra:
-  // 2.37 against 2.67 us FP32C, 3.15 against 3.36 us FP64 with the linear
-  // laws; see the design notes for the table-driven case)
+  // to cover the exchange anyway, as with tables or per-element laws (64^3
+  // hexahedra with the linear laws: 2.37 against 2.67 us FP32C, 3.15 against
+  // 3.36 us FP64; with tables: 4.08 against 3.89 us FP32C, 4.91 against 4.76
+  // us FP64)
   c->res_split = (c->d_esk || c->d_ktab || c->d_ctab) ? 0 : 1;
   std::vector<uint8_t> exported(N, 0);
   int64_t halo_total = 0;
