@@ -43,9 +43,9 @@ TRAFFIC_SRC = [os.path.join(ROOT, "paper_1909_03355_amd", "csrc", f)
 # (TRAFFIC_SRC, concatenated) with this SHA-1; any other source reports null.
 #   workload -> (sha1, kernel, bytes per launch or once, bytes per step)
 TRAFFIC = {
-    "nonlinear_hex64": ("4572db36821411bc77c6dea9c0296d8ae0114061", "k_resident", 21275384.9, 2415737.3),
-    "aniso_tet128": ("4572db36821411bc77c6dea9c0296d8ae0114061", "k_step1", 620713056.0, 0.0),
-    "batched_hex256": ("4572db36821411bc77c6dea9c0296d8ae0114061", "k_step1", 463481536.0, 0.0),
+    "nonlinear_hex64": ("71f8cd06285168d18eba0b9c39828ba143a94fa8", "k_resident", 20445048.9, 2361433.3),
+    "aniso_tet128": ("71f8cd06285168d18eba0b9c39828ba143a94fa8", "k_step1", 620835568.0, 0.0),
+    "batched_hex256": ("71f8cd06285168d18eba0b9c39828ba143a94fa8", "k_step1", 463505648.0, 0.0),
 }
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
 
