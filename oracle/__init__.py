@@ -37,7 +37,8 @@ class _Problem(C.Structure):
                 ("dir_nodes", _i32), ("dir_T", _d), ("dt", _d),
                 ("Tz", C.c_double), ("sigma", C.c_double),
                 ("nkt", C.c_int32), ("nct", C.c_int32),
-                ("kt_T", _d), ("kt_f", _d), ("ct_T", _d), ("ct_f", _d)]
+                ("kt_T", _d), ("kt_f", _d), ("ct_T", _d), ("ct_f", _d),
+                ("hg_G", _d), ("hg_k", _d)]
 
 
 def lib():
@@ -52,6 +53,7 @@ def lib():
         L.orc_geometry.argtypes = [C.c_int, C.c_int64, _d, _d, _d, _i32, _d, _d, _d, _d]
         L.orc_geometry_mean.restype = C.c_int64
         L.orc_geometry_mean.argtypes = [C.c_int64, _d, _d, _d, _i32, _d, _d, _d, _d]
+        L.orc_hourglass.argtypes = [C.c_int64, _d, _d, _d, _i32, _d, _d, _d, C.c_double, _d, _d]
         L.orc_face_areas.restype = None
         L.orc_face_areas.argtypes = [C.c_int, C.c_int64, _d, _d, _d, _i32, _d]
         P = C.POINTER(_Problem)
@@ -112,6 +114,16 @@ class Oracle:
         if prob["elem_kscale"] is not None:
             Dk = Dk * _f64(prob["elem_kscale"])[None, :]
         self.Dk = np.ascontiguousarray(Dk)
+        # optional hourglass control of the uniform-gradient hexahedron
+        # ("hourglass": eps > 0; the term is described at orc_hourglass)
+        self.hourglass = float(prob.get("hourglass", 0.0) or 0.0)
+        self.hg_G = self.hg_k = None
+        if self.hourglass > 0:
+            if not (self.ne == 8 and self.hex_gradient == "mean"):
+                raise ValueError("hourglass control needs the uniform-gradient hexahedron")
+            self.hg_G, self.hg_k = np.zeros(self.E * 32), np.zeros(self.E)
+            L.orc_hourglass(self.E, _p(x), _p(y), _p(z), _p(conn, _i32), _p(self.B), _p(self.V),
+                            _p(self.Dk), self.hourglass, _p(self.hg_G), _p(self.hg_k))
         # optional shared multiplier tables: D(T) = Dk fk(Tbar), c(T) = c0 fc(T)
         kt, ct = prob.get("k_table"), prob.get("c_table")
         self.kt = None if kt is None else (_f64(kt[0]), _f64(kt[1]))
@@ -175,6 +187,8 @@ class Oracle:
             s.kt_T, s.kt_f = _p(self.kt[0]), _p(self.kt[1])
         if self.ct is not None:
             s.ct_T, s.ct_f = _p(self.ct[0]), _p(self.ct[1])
+        if self.hg_k is not None:
+            s.hg_G, s.hg_k = _p(self.hg_G), _p(self.hg_k)
         self._s = s
 
     def _buffers(self):
@@ -186,7 +200,7 @@ class Oracle:
     # ------------------------------------------------------------------
     def element_matrices(self, scale=None, lo=0, hi=None):
         """K_e = W B^T D B for elements [lo, hi) with D = Dk * scale
-        (scale defaults to s0 + s1 * 0)."""
+        (scale defaults to s0 + s1 * 0), plus the hourglass term when on."""
         hi = self.E if hi is None else hi
         ne = self.ne
         B = self.B.reshape(self.E, 3, ne)[lo:hi]
@@ -196,7 +210,11 @@ class Oracle:
         for (i, j), r in zip([(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)], range(6)):
             D[:, i, j] = Dk[r] * sc
             D[:, j, i] = Dk[r] * sc
-        return self.W[lo:hi, None, None] * np.einsum("eia,eij,ejb->eab", B, D, B)
+        K = self.W[lo:hi, None, None] * np.einsum("eia,eij,ejb->eab", B, D, B)
+        if self.hg_k is not None:
+            G = self.hg_G.reshape(self.E, 4, 8)[lo:hi]
+            K = K + (sc * self.hg_k[lo:hi])[:, None, None] * np.einsum("eqa,eqb->eab", G, G)
+        return K
 
     def critical_dt(self):
         """Stability bound dt_crit = 2 / lambda_max (Eq. 29), with lambda_max

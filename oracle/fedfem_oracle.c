@@ -305,6 +305,9 @@ typedef struct {
    * c_e(T) = c0_e * fc(T) replaces c0 + c1 T */
   int32_t nkt, nct;
   const double *kt_T, *kt_f, *ct_T, *ct_f;
+  /* optional hourglass control of the uniform-gradient hexahedron: per element
+   * the four vectors gamma (4 x 8) and kappa (see orc_hourglass); NULL = off */
+  const double *hg_G, *hg_k;
 } orc_problem;
 
 /* Piecewise-linear interpolation in a table, constant beyond its ends;
@@ -376,6 +379,56 @@ static void element_load(const orc_problem *P, int64_t e, const double *T, doubl
     double s2 = 0;
     for (int i = 0; i < 3; i++) s2 += P->W[e] * Be[i * ne + a] * q[i];
     Fe[a] = s2;
+  }
+  if (P->hg_k) {
+    /* s kappa sum_alpha (gamma_alpha . T_e) gamma_alpha */
+    const double *G = P->hg_G + e * 32;
+    for (int al = 0; al < 4; al++) {
+      double c = 0;
+      for (int a = 0; a < 8; a++) c += G[al * 8 + a] * Te[a];
+      for (int a = 0; a < 8; a++) Fe[a] += s * P->hg_k[e] * c * G[al * 8 + a];
+    }
+  }
+}
+
+/* Hourglass control of the uniform-gradient hexahedron (not in the paper: the
+ * scalar-field form of Flanagan and Belytschko's orthogonal hourglass control,
+ * 1981).  With the hourglass patterns h_1 = eta zeta, h_2 = zeta xi,
+ * h_3 = xi eta, h_4 = xi eta zeta of the nodes' natural signs, b_i the rows of
+ * the mean gradient operator (B, 3 x 8) and x_i the nodal coordinates,
+ *   gamma_alpha = (h_alpha - sum_i (h_alpha . x_i) b_i) / 8
+ * vanishes on every linear field (b reproduces its gradient), and the element
+ * adds K_hg = kappa sum_alpha gamma_alpha gamma_alpha^T to its conductance,
+ *   kappa = eps (tr Dk / 3) V sum_a |b_a|^2,
+ * scaled by the conductivity factor s(Tbar) like the rest of the element.  On
+ * a cube of side h, gamma_alpha = h_alpha / 8 and kappa = 1.5 eps k h.
+ * G receives gamma (E x 4 x 8), kap kappa (E). */
+void orc_hourglass(int64_t E, const double *x, const double *y, const double *z,
+                   const int32_t *conn, const double *B, const double *V, const double *Dk,
+                   double eps, double *G, double *kap) {
+  for (int64_t e = 0; e < E; e++) {
+    double X[8][3];
+    for (int a = 0; a < 8; a++) {
+      const int32_t k = conn[(int64_t)a * E + e];
+      X[a][0] = x[k];
+      X[a][1] = y[k];
+      X[a][2] = z[k];
+    }
+    const double *Be = B + e * 24;
+    double bb = 0;
+    for (int i = 0; i < 24; i++) bb += Be[i] * Be[i];
+    kap[e] = eps * (Dk[0 * E + e] + Dk[1 * E + e] + Dk[2 * E + e]) / 3.0 * V[e] * bb;
+    for (int al = 0; al < 4; al++) {
+      double h[8], hx[3] = {0, 0, 0};
+      for (int a = 0; a < 8; a++) {
+        const double sx = HEX_S[a][0], sy = HEX_S[a][1], sz = HEX_S[a][2];
+        h[a] = al == 0 ? sy * sz : al == 1 ? sz * sx : al == 2 ? sx * sy : sx * sy * sz;
+        for (int i = 0; i < 3; i++) hx[i] += h[a] * X[a][i];
+      }
+      for (int a = 0; a < 8; a++)
+        G[e * 32 + al * 8 + a] =
+            (h[a] - (hx[0] * Be[0 * 8 + a] + hx[1] * Be[1 * 8 + a] + hx[2] * Be[2 * 8 + a])) / 8.0;
+    }
   }
 }
 
@@ -475,6 +528,14 @@ static void element_apply(const orc_problem *P, int64_t e, const double *v, doub
     double s2 = 0;
     for (int i = 0; i < 3; i++) s2 += P->W[e] * Be[i * ne + a] * q[i];
     out[a] = s2;
+  }
+  if (P->hg_k) {
+    const double *G = P->hg_G + e * 32;
+    for (int al = 0; al < 4; al++) {
+      double c = 0;
+      for (int a = 0; a < 8; a++) c += G[al * 8 + a] * ve[a];
+      for (int a = 0; a < 8; a++) out[a] += s * P->hg_k[e] * c * G[al * 8 + a];
+    }
   }
 }
 

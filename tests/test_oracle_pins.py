@@ -303,6 +303,75 @@ def test_patch_distorted_hex_mean_gradient():
     assert np.max(np.abs(T - lin)) < 1e-9
 
 
+def _hg_cube(eps, h=0.5, k=2.0):
+    X = (M.HEX_SIGNS.astype(float) + 1.0) / 2.0 * h
+    p = H.single_element("hex8", X, P.material(rho=3.0, c0=5.0, k=[k]))
+    p["hex_gradient"] = "mean"
+    p["hourglass"] = eps
+    return p
+
+
+def test_hourglass_cube_closed_form():
+    """Hourglass control on a cube of side h: gamma_alpha = h_alpha / 8 and
+    kappa = 1.5 eps k h, so a pure hourglass field h_alpha gets the load
+    kappa h_alpha / 8, a linear field gets nothing from the term, and the
+    element's largest eigenvalue is max(k h / 2, kappa / 8) (the ranges of
+    the mean-gradient and hourglass parts are orthogonal on a cube), which
+    fixes the critical step 2 (rho c V / 8) / lambda."""
+    h, k = 0.5, 2.0
+    S = M.HEX_SIGNS.astype(float)
+    pats = [S[:, 1] * S[:, 2], S[:, 2] * S[:, 0], S[:, 0] * S[:, 1], S[:, 0] * S[:, 1] * S[:, 2]]
+    X = (S + 1.0) / 2.0 * h
+    lin = 3.0 * X[:, 0] - 2.0 * X[:, 1] + X[:, 2]
+    F0, _ = Oracle(_hg_cube(0.0, h, k)).loads(lin)
+    for eps in (0.5, 4.0):
+        o = Oracle(_hg_cube(eps, h, k))
+        kap = 1.5 * eps * k * h
+        for hp in pats:
+            F, _ = o.loads(hp)
+            assert np.max(np.abs(F - kap * hp / 8.0)) < 1e-12 * kap
+        F, _ = o.loads(lin)
+        assert np.max(np.abs(F - F0)) < 1e-12 * np.max(np.abs(F0))
+        lam = max(k * h / 2.0, kap / 8.0)
+        dt = 2.0 * (3.0 * 5.0 * h ** 3 / 8.0) / lam
+        assert abs(o.dt_crit - dt) < 1e-12 * dt
+
+
+def test_hourglass_mode_decays_only_with_control():
+    """The checkerboard (-1)^(i+j+k) is a pure hourglass field in every
+    hexahedron of a box grid: the uniform-gradient element leaves it fixed,
+    the hourglass term damps it (every step lowers its amplitude)."""
+    n = 4
+    k, j, i = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    for eps in (0.0, 0.3):
+        p, m = H.box_problem("hex8", n, side=1.0)
+        p["hex_gradient"] = "mean"
+        p["hourglass"] = eps
+        p["T0"] = ((-1.0) ** (i + j + k)).ravel() * 5.0
+        hist = Oracle(p).run(20, history=True)
+        amp = np.max(np.abs(hist), axis=1)
+        if eps == 0.0:
+            assert np.max(np.abs(hist[-1] - p["T0"])) < 1e-12
+        else:
+            assert np.all(np.diff(amp) < 0) and amp[-1] < 0.9 * amp[0]
+
+
+def test_hourglass_keeps_the_distorted_patch_test():
+    """gamma vanishes on linear fields on any hexahedron: with the hourglass
+    term on, the distorted patch of Fig. 2(c) still reproduces the linear
+    field exactly."""
+    x, y, z = M.patch_nodes(os.path.join(H.GOLDEN, "patch_nodes.txt"))
+    p = P._base(M.patch_hex(x, y, z), "patch_hex_hg")
+    p["materials"] = [P.material(1.0, 1.0, [1.0])]
+    p["hex_gradient"] = "mean"
+    p["hourglass"] = 0.5
+    lin = 200 * x + 100 * y + 200 * z
+    F, _ = Oracle(p).loads(lin)
+    assert np.max(np.abs(F[8:])) < 1e-10
+    o, T = _linear_patch(p, np.arange(8), lin)
+    assert np.max(np.abs(T - lin)) < 1e-9
+
+
 # ----------------------------------------------------------------------------
 # workload 1 reduces to 1-D FTCS at every step (exact identity)
 def test_cube_plain_equals_ftcs():
@@ -662,6 +731,41 @@ def test_adjoint_matches_finite_differences():
         Ls.append(_loss(dict(p, face_h=hh), sens, target, nsteps)[0])
     fd_h = (Ls[0] - Ls[1]) / (2 * eps * 15.0)
     assert abs(fd_h - g["g_h"][f]) <= 1e-6 * abs(fd_h)
+
+
+def test_hourglass_adjoint_matches_finite_differences():
+    """The hourglass term enters the adjoint (its load, and log k through
+    kappa): central differences of the oracle's forward run on the nonlinear
+    problem with the uniform-gradient hexahedron and hourglass control."""
+    p = dict(H.nonlinear_adjoint_problem("hex8"), hex_gradient="mean", hourglass=0.5)
+    p["dt"] = 0.5 * Oracle(dict(p, dt=None)).dt_crit
+    nsteps = 30
+    o = Oracle(p)
+    sens = np.arange(1, o.N, 3)
+    sens = sens[~np.isin(sens, o.dir_nodes)]
+    target = np.full(sens.size, 100.0)
+    hist = o.run(nsteps, history=True)
+    lam = np.zeros(o.N)
+    lam[sens] = hist[-1][sens] - target
+    g = o.adjoint(hist, lam)
+    theta = np.log(p["elem_kscale"])
+    for e in (0, o.E - 1, int(np.argmax(np.abs(g["g_logk"])))):
+        Ls = []
+        for d in (1e-4, -1e-4):
+            th = theta.copy()
+            th[e] += d
+            Ls.append(_loss(dict(p, elem_kscale=np.exp(th)), sens, target, nsteps)[0])
+        fd = (Ls[0] - Ls[1]) / 2e-4
+        assert abs(fd - g["g_logk"][e]) <= 2e-6 * max(abs(fd), 1e-3 * np.abs(g["g_logk"]).max())
+    k = o.N // 2 + 1
+    assert k not in set(o.dir_nodes)
+    Ls = []
+    for d in (1e-3, -1e-3):
+        T0 = o.initial().copy()
+        T0[k] += d
+        Ls.append(0.5 * np.sum((o.run(nsteps, T0=T0, apply_initial=False)[sens] - target) ** 2))
+    fd = (Ls[0] - Ls[1]) / 2e-3
+    assert abs(fd - g["lam0"][k]) <= 2e-6 * max(abs(fd), 1e-3 * np.abs(g["lam0"]).max())
 
 
 def test_adjoint_transpose_identity():
