@@ -9,7 +9,8 @@ speed ratio.  A step is one pass of the whole hot path (element loads, nodal
 sums, surface loads, explicit update).  Other workloads (--workload):
 aniso_tet128, batched_hex256, adjoint_hex48 (forward + adjoint), and the
 follow-up features at the 64^3 size: tables_hex64 (tabulated D(T), c(T)),
-meanhex_hex64 (uniform-gradient hexahedron on a distorted mesh),
+meanhex_hex64 (uniform-gradient hexahedron on a distorted mesh), meanhg_hex64
+(the same with hourglass control),
 nladjoint_hex64 (adjoint through D(T), c(T) and radiation) and
 moving_source_hex64 (a point source moved one node every step by a point-load
 schedule).
@@ -72,6 +73,9 @@ WORKLOADS = {
     "meanhex_hex64": ("cube_nonlinear_hex_mean", 2000, 100,
                       "nonlinear_hex64 on a distorted mesh (interior nodes moved up to 0.25 h) "
                       "with the uniform-gradient hexahedron", dict(), "steps"),
+    "meanhg_hex64": ("cube_nonlinear_hex_mean_hg", 2000, 100,
+                     "meanhex_hex64 with hourglass control (eps 0.3, 40 values per element)",
+                     dict(), "steps"),
     "nladjoint_hex64": ("nonlinear_adjoint_hex", 2000, 100,
                         "nonlinear_hex64 (D(T), c(T), radiation) as the forward model of a sensor "
                         "loss; forward + adjoint with checkpoints every 100 steps",

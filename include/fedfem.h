@@ -148,6 +148,19 @@ typedef struct {
                                 on distorted hexahedra (the patch test of Sec. 4.1); 27
                                 values per element instead of 6, one step per launch
                                 (fuse_steps <= 1, resident = 0).  Ignored for tetrahedra. */
+  double hourglass;          /* eps >= 0 (0 = off): hourglass control of the uniform-
+                                gradient hexahedron (not in the paper; the scalar-field form
+                                of Flanagan and Belytschko's orthogonal hourglass control).
+                                With h_1..h_4 the hourglass patterns of the nodes' natural
+                                signs (eta zeta, zeta xi, xi eta, xi eta zeta), b_a the mean
+                                gradients and x_a the nodes, gamma_alpha = (h_alpha -
+                                sum_i (h_alpha . x_i) b_i) / 8 vanishes on linear fields and
+                                the element adds s(Tbar) kappa sum_alpha gamma_alpha
+                                gamma_alpha^T to its conductance, kappa = eps (tr D / 3) V
+                                sum_a |b_a|^2 (1.5 eps k h on a cube of side h).  Damps the
+                                four hourglass modes, keeps the patch test, and enters the
+                                stability bound and the adjoint; 40 values per element.
+                                Needs hex_gradient = 1 (FED_E_ARG otherwise). */
 } fed_options;
 
 typedef struct fed_ctx fed_ctx;

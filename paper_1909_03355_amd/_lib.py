@@ -53,7 +53,8 @@ class fed_options(C.Structure):
                 ("T_lo", C.c_double), ("T_hi", C.c_double), ("allow_unstable", C.c_int32),
                 ("node_instance", _i32), ("tile_nodes", C.c_int32),
                 ("block_threads", C.c_int32), ("fuse_steps", C.c_int32),
-                ("resident", C.c_int32), ("hex_gradient", C.c_int32)]
+                ("resident", C.c_int32), ("hex_gradient", C.c_int32),
+                ("hourglass", C.c_double)]
 
 
 class fed_info(C.Structure):

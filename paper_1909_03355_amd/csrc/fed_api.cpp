@@ -133,6 +133,10 @@ struct fed_ctx {
   // element operator: 0 the folded 3x3 (6 values), 1 the uniform-gradient
   // hexahedron (27 values)
   int op = 0, hw = 6;
+  double hg_eps = 0;  // hourglass control of the uniform-gradient hexahedron (op 2)
+  // rows of H that take the per-element conductivity factor: V D, and kappa
+  int hs_from() const { return op ? 21 : 0; }
+  int hs_to() const { return op == 2 ? 28 : hw; }
   // host copies for re-deriving the stability bound over a new range
   std::vector<fed_material> h_mats;
   std::vector<double> h_ktab_T, h_ktab_f, h_ctab_T, h_ctab_f;
@@ -330,6 +334,10 @@ int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, cons
   if (o->hex_gradient == 1 && m->elem == FED_HEX8 && (o->fuse_steps > 1 || o->resident))
     return fail(FED_E_ARG, "the uniform-gradient hexahedron runs one step per launch "
                            "(fuse_steps <= 1, resident = 0)");
+  if (!(o->hourglass >= 0) || !std::isfinite(o->hourglass))
+    return fail(FED_E_ARG, "hourglass must be a finite number >= 0");
+  if (o->hourglass > 0 && !(m->elem == FED_HEX8 && o->hex_gradient == 1))
+    return fail(FED_E_ARG, "hourglass control needs hexahedra with hex_gradient = 1");
   return FED_OK;
 }
 
@@ -490,8 +498,9 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   if (mixed_k && o->resident)
     return fail(FED_E_ARG, "resident stepping needs materials that share s0 and s1");
   c->resident = o->resident == 1;
-  c->op = (ne == FED_HEX8 && o->hex_gradient == 1) ? 1 : 0;
-  c->hw = c->op ? 27 : 6;
+  c->op = (ne == FED_HEX8 && o->hex_gradient == 1) ? (o->hourglass > 0 ? 2 : 1) : 0;
+  c->hw = c->op == 2 ? 40 : c->op ? 27 : 6;
+  c->hg_eps = c->op == 2 ? o->hourglass : 0.0;
   c->block = o->block_threads ? o->block_threads : (c->resident ? 1024 : 256);
 
   // ---- host index work: boundary records, instances, tiling ---------------
@@ -647,7 +656,7 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   HIPCHK(P.alloc((void **)&d_lamgeo, sizeof(double) * E));
   c->d_lamgeo = d_lamgeo;
   fed::GeomArgs ga{ne, E, d_x, d_y, d_z, d_conn, d_mats, d_emat, d_ek,
-                   c->d_H0, c->op, c->d_V, d_lamgeo, d_cnt, d_cnt + 1};
+                   c->d_H0, c->op, c->d_V, d_lamgeo, d_cnt, d_cnt + 1, c->hg_eps};
   HIPCHK(fed::launch_geom(ga, s));
   int cnt[2];
   HIPCHK(hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, s));
@@ -780,7 +789,7 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   HIPCHK(upload(P, &c->d_eorig, T.eorig.data(), T.eorig.size()));
   HIPCHK(upload(P, &c->d_eowner, T.eowner.data(), T.eowner.size()));
   HIPCHK(P.alloc(&c->d_H, (size_t)rb * c->hw * c->Eexp));
-  HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->hw, c->op ? 21 : 0, c->Eexp, E,
+  HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->hw, c->hs_from(), c->hs_to(), c->Eexp, E,
                               c->d_eorig, c->d_H0,
                               c->d_kscale, c->d_H, s));
   if (mixed_k) {
@@ -1206,7 +1215,7 @@ int fed_set_params(fed_ctx *c, const double *kscale, const double *elem_c, const
                       c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[4], c->d_b64[3],
                       c->d_alpha, c->d_beta, c->d_rA, c->d_rAT, c->d_reA, c->d_rTa, c->d_rP};
   HIPCHK(fed::launch_node_arrays(na, s));
-  HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->hw, c->op ? 21 : 0, c->Eexp, E,
+  HIPCHK(fed::launch_expand_H(c->prec == FED_FP64 ? 1 : 0, c->hw, c->hs_from(), c->hs_to(), c->Eexp, E,
                               c->d_eorig, c->d_H0,
                               c->d_kscale, c->d_H, s));
   HIPCHK(hipStreamSynchronize(s));

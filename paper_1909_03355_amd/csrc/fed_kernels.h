@@ -24,13 +24,15 @@ struct GeomArgs {
   const int32_t *emat;     // nullable
   const double *ek;        // nullable, [6 * E]
   double *H0;              // [W * E] element operator without per-element factor: W = 6
-                           // (folded 3x3), or 27 (uniform-gradient hexahedron: 21 mean
-                           // gradient values, then V D)
-  int hexmean;             // hexahedra: 1 = uniform gradient, 0 = centre point (Eq. 17)
+                           // (folded 3x3), 27 (uniform-gradient hexahedron: 21 mean
+                           // gradient values, then V D) or 40 (then also kappa and the
+                           // 12 values h_alpha . x_i of the hourglass control)
+  int hexmean;             // hexahedra: nonzero = uniform gradient, 0 = centre point (Eq. 17)
   double *V;               // [E] exact volume
-  double *lamgeo;          // [E] W / V * lambda_max(L^T B B^T L), k = L L^T
+  double *lamgeo;          // [E] lambda_max(K0_e) / V
   int *nbad;               // inverted / degenerate element count
   int *nnotspd;            // conductivity tensors that are not SPD
+  double hg_eps;           // > 0: hourglass control of the uniform-gradient hexahedron
 };
 
 struct MassArgs {
@@ -167,7 +169,8 @@ hipError_t launch_expand_sk(int prec, int64_t Eexp, const int32_t *eorig, const 
                             const int32_t *emat, void *esk, hipStream_t s);
 // H = H0 of each expanded element's original (W values), rows >= from scaled by
 // the element's conductivity factor
-hipError_t launch_expand_H(int prec, int W, int from, int64_t Eexp, int64_t E, const int32_t *eorig,
+// rows [from, to) of H0 take the per-element conductivity factor
+hipError_t launch_expand_H(int prec, int W, int from, int to, int64_t Eexp, int64_t E, const int32_t *eorig,
                            const double *H0, const double *kscale, void *H, hipStream_t s);
 // Resident stepping: one cooperative launch advances nsteps steps.  Every tile
 // keeps its element operators and node coefficients in registers for the whole

@@ -90,6 +90,56 @@ __device__ double det3(const double J[3][3]) {
 // for the linear tetrahedron, with d_i = T_i - T_0 and J = [x_i - x_0],
 //   F_{1..3} = Hhat d,  F_0 = -(F_1 + F_2 + F_3),  Hhat = V J^{-1} D J^{-T}.
 // Hhat (6 numbers, symmetric) is the precomputed "G D B" of Eq. 19-22.
+// Natural signs (xi, eta, zeta) of the hexahedron's nodes in the local order
+// of kHexS, and the hourglass patterns of Flanagan and Belytschko's orthogonal
+// hourglass control (not in the paper): h_0 = eta zeta, h_1 = zeta xi,
+// h_2 = xi eta, h_3 = xi eta zeta.
+__host__ __device__ constexpr int hex_xi(int n) { return (n == 1 || n == 2 || n == 5 || n == 6) ? 1 : -1; }
+__host__ __device__ constexpr int hex_eta(int n) { return (n >> 1 & 1) ? 1 : -1; }
+__host__ __device__ constexpr int hex_zeta(int n) { return n >= 4 ? 1 : -1; }
+__host__ __device__ constexpr int hg_sign(int al, int n) {
+  return al == 0   ? hex_eta(n) * hex_zeta(n)
+         : al == 1 ? hex_zeta(n) * hex_xi(n)
+         : al == 2 ? hex_xi(n) * hex_eta(n)
+                   : hex_xi(n) * hex_eta(n) * hex_zeta(n);
+}
+static_assert(hex_xi(0) == -1 && hex_xi(2) == 1 && hex_eta(3) == 1 && hex_eta(5) == -1 &&
+                  hex_zeta(3) == -1 && hex_zeta(7) == 1,
+              "node signs follow kHexS");
+
+// Largest eigenvalue of a symmetric 8x8 matrix by the cyclic Jacobi method
+// (rotations until the off-diagonal part is negligible; A is overwritten).
+__device__ double sym8_lmax(double A[8][8]) {
+  for (int sweep = 0; sweep < 50; sweep++) {
+    double off = 0, diag = 0;
+    for (int p = 0; p < 8; p++) {
+      diag += A[p][p] * A[p][p];
+      for (int q = p + 1; q < 8; q++) off += A[p][q] * A[p][q];
+    }
+    if (off <= 1e-32 * diag) break;
+    for (int p = 0; p < 7; p++)
+      for (int q = p + 1; q < 8; q++) {
+        if (A[p][q] == 0.0) continue;
+        const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 8; k++) {
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 8; k++) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  double m = A[0][0];
+  for (int p = 1; p < 8; p++) m = fmax(m, A[p][p]);
+  return m;
+}
+
 __global__ void k_geom(GeomArgs a) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= a.E) return;
@@ -106,6 +156,7 @@ __global__ void k_geom(GeomArgs a) {
   for (int r = 0; r < 6; r++) dk[r] = a.ek ? a.ek[(int64_t)r * a.E + e] : a.mats[m].k[r];
   double J[3][3], Ji[3][3], W, V, det;
   double M3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // B B^T
+  double bm[8][3];  // uniform-gradient hexahedron: the mean gradient of every shape function
   if (ne == 8) {
     for (int i = 0; i < 3; i++)
       for (int j = 0; j < 3; j++) {
@@ -171,7 +222,7 @@ __global__ void k_geom(GeomArgs a) {
       }
       W = V;
       for (int n = 0; n < 8; n++) {
-        double b[3];
+        double *b = bm[n];
         for (int i = 0; i < 3; i++) b[i] = S[n][i] / V;
         if (n < 7)
           for (int i = 0; i < 3; i++) a.H0[(int64_t)(3 * n + i) * a.E + e] = b[i];
@@ -213,6 +264,7 @@ __global__ void k_geom(GeomArgs a) {
   }
   // Hhat = c * Ji D Ji^T,  c = W/64 (hex) or V (tet)
   double D[3][3] = {{dk[0], dk[3], dk[5]}, {dk[3], dk[1], dk[4]}, {dk[5], dk[4], dk[2]}};
+  double lam_hg = -1.0;  // set by the hourglass-controlled hexahedron
   double c = ne == 8 ? W / 64.0 : V;
   double T1[3][3];
   for (int i = 0; i < 3; i++)
@@ -224,6 +276,35 @@ __global__ void k_geom(GeomArgs a) {
       Hm[i][j] = c * (T1[i][0] * Ji[j][0] + T1[i][1] * Ji[j][1] + T1[i][2] * Ji[j][2]);
   if (ne == 8 && a.hexmean) {
     for (int r = 0; r < 6; r++) a.H0[(int64_t)(21 + r) * a.E + e] = V * dk[r];
+    if (a.hg_eps > 0) {
+      // hourglass control: kappa = eps (tr D / 3) V sum_a |b_a|^2 (row 27, takes
+      // the per-element factor) and h_alpha . x_i (rows 28 + 3 alpha + i)
+      double bb = 0;
+      for (int n = 0; n < 8; n++) bb += bm[n][0] * bm[n][0] + bm[n][1] * bm[n][1] + bm[n][2] * bm[n][2];
+      const double kap = a.hg_eps * (dk[0] + dk[1] + dk[2]) / 3.0 * V * bb;
+      a.H0[(int64_t)27 * a.E + e] = kap;
+      double gam[4][8];
+      for (int al = 0; al < 4; al++) {
+        double hx[3] = {0, 0, 0};
+        for (int n = 0; n < 8; n++)
+          for (int i = 0; i < 3; i++) hx[i] += hg_sign(al, n) * X[n][i];
+        for (int i = 0; i < 3; i++) a.H0[(int64_t)(28 + 3 * al + i) * a.E + e] = hx[i];
+        for (int n = 0; n < 8; n++)
+          gam[al][n] = (hg_sign(al, n) - (hx[0] * bm[n][0] + hx[1] * bm[n][1] + hx[2] * bm[n][2])) / 8.0;
+      }
+      // stability: lambda_max of the whole element matrix V b D b^T + kappa G^T G
+      double K8[8][8];
+      for (int p = 0; p < 8; p++)
+        for (int q = 0; q < 8; q++) {
+          double t = 0;
+          for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) t += bm[p][i] * D[i][j] * bm[q][j];
+          double g2 = 0;
+          for (int al = 0; al < 4; al++) g2 += gam[al][p] * gam[al][q];
+          K8[p][q] = V * t + kap * g2;
+        }
+      lam_hg = sym8_lmax(K8) / V;
+    }
   } else {
     a.H0[0 * a.E + e] = Hm[0][0];
     a.H0[1 * a.E + e] = Hm[1][1];
@@ -255,7 +336,7 @@ __global__ void k_geom(GeomArgs a) {
     for (int j = 0; j < 3; j++) A[i][j] = L[0][i] * ML[0][j] + L[1][i] * ML[1][j] + L[2][i] * ML[2][j];
   double lm = sym3_lmax(A[0][0], A[1][1], A[2][2], 0.5 * (A[0][1] + A[1][0]),
                         0.5 * (A[1][2] + A[2][1]), 0.5 * (A[0][2] + A[2][0]));
-  a.lamgeo[e] = (V > 0 ? W / V : 0.0) * lm;
+  a.lamgeo[e] = lam_hg >= 0 ? lam_hg : (V > 0 ? W / V : 0.0) * lm;
 }
 
 // Lumped (diagonal) heat capacity (Sec. 3.1, Eq. 13-14): every element gives
@@ -493,14 +574,15 @@ __global__ void k_expand_sk(int64_t Eexp, const int32_t *eorig, const MatDev *ma
 }
 
 template <typename R>
-__global__ void k_expand_H(int W, int from, int64_t Eexp, int64_t E, const int32_t *eorig,
+__global__ void k_expand_H(int W, int from, int to, int64_t Eexp, int64_t E, const int32_t *eorig,
                            const double *H0, const double *kscale, R *H) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= Eexp) return;
   int32_t e = eorig[i];
   double ks = kscale ? kscale[e] : 1.0;
   for (int r = 0; r < W; r++)
-    H[(int64_t)r * Eexp + i] = (R)(r >= from ? H0[(int64_t)r * E + e] * ks : H0[(int64_t)r * E + e]);
+    H[(int64_t)r * Eexp + i] =
+        (R)(r >= from && r < to ? H0[(int64_t)r * E + e] * ks : H0[(int64_t)r * E + e]);
 }
 
 // ---------------------------------------------------------------------------
@@ -647,8 +729,75 @@ struct ElemMean {
   }
 };
 
+// Uniform-gradient hexahedron with hourglass control (not in the paper: the
+// scalar-field form of Flanagan and Belytschko's orthogonal hourglass
+// control).  The load of ElemMean plus s kappa sum_alpha c_alpha gamma_alpha,
+// where gamma_alpha,n = (h_alpha,n - hx_alpha . b_n) / 8 vanishes on linear
+// fields and c_alpha = gamma_alpha . T = (h_alpha . T - hx_alpha . g) / 8.
+// hb as for ElemMean, then hb[27] = kappa (with the per-element factor) and
+// hb[28 + 3 alpha + i] = hx_alpha,i = h_alpha . x_i.
+template <typename R>
+struct ElemMeanHg {
+  // hourglass amplitudes c_alpha from the differences d_n = T_n - T_7 (the
+  // patterns sum to zero) and the mean gradient g
+  __device__ static void amps(const R d[7], R gx, R gy, R gz, const R *hb, R c[4]) {
+    #pragma clang fp contract(off)
+#pragma unroll
+    for (int al = 0; al < 4; al++) {
+      R ht = 0;
+#pragma unroll
+      for (int n = 0; n < 7; n++) ht = hg_sign(al, n) > 0 ? ht + d[n] : ht - d[n];
+      const R *hx = hb + 28 + 3 * al;
+      c[al] = (ht - ((hx[0] * gx + hx[1] * gy) + hx[2] * gz)) * (R)0.125;
+    }
+  }
+  __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
+                              const R hb[40], R F[8]) {
+    #pragma clang fp contract(off)
+    R T[8], d[7];
+#pragma unroll
+    for (int n = 0; n < 8; n++) T[n] = Tl[loc[n]];
+    R gx = 0, gy = 0, gz = 0;
+#pragma unroll
+    for (int n = 0; n < 7; n++) {
+      d[n] = T[n] - T[7];
+      gx += hb[3 * n] * d[n];
+      gy += hb[3 * n + 1] * d[n];
+      gz += hb[3 * n + 2] * d[n];
+    }
+    R s = kl.s0;
+    if (tdk) s = kl((((T[0] + T[1]) + (T[2] + T[3])) + ((T[4] + T[5]) + (T[6] + T[7]))) * (R)0.125);
+    const R *vd = hb + 21;
+    const R qx = s * (vd[0] * gx + vd[3] * gy + vd[5] * gz);
+    const R qy = s * (vd[3] * gx + vd[1] * gy + vd[4] * gz);
+    const R qz = s * (vd[5] * gx + vd[4] * gy + vd[2] * gz);
+    R c[4];
+    amps(d, gx, gy, gz, hb, c);
+    R w0 = 0, w1 = 0, w2 = 0;
+#pragma unroll
+    for (int al = 0; al < 4; al++) {
+      w0 += c[al] * hb[28 + 3 * al];
+      w1 += c[al] * hb[29 + 3 * al];
+      w2 += c[al] * hb[30 + 3 * al];
+    }
+    const R sk = s * hb[27] * (R)0.125;
+    R sum = 0;
+#pragma unroll
+    for (int n = 0; n < 7; n++) {
+      R hc = 0;
+#pragma unroll
+      for (int al = 0; al < 4; al++) hc = hg_sign(al, n) > 0 ? hc + c[al] : hc - c[al];
+      const R wb = (w0 * hb[3 * n] + w1 * hb[3 * n + 1]) + w2 * hb[3 * n + 2];
+      F[n] = ((hb[3 * n] * qx + hb[3 * n + 1] * qy) + hb[3 * n + 2] * qz) + sk * (hc - wb);
+      sum += F[n];
+    }
+    F[7] = -sum;
+  }
+};
+
 // element operator by kind: OP 0 the folded 3x3 operator of Eq. 17-22 (6
-// values), OP 1 the uniform-gradient hexahedron (27 values)
+// values), OP 1 the uniform-gradient hexahedron (27 values), OP 2 the same with
+// hourglass control (40 values)
 template <typename R, int NE, int OP>
 struct Op {
   static constexpr int W = 6;
@@ -663,6 +812,14 @@ struct Op<R, 8, 1> {
   __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
                               const R *h, R *F) {
     ElemMean<R>::load(Tl, loc, kl, tdk, h, F);
+  }
+};
+template <typename R>
+struct Op<R, 8, 2> {
+  static constexpr int W = 40;
+  __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
+                              const R *h, R *F) {
+    ElemMeanHg<R>::load(Tl, loc, kl, tdk, h, F);
   }
 };
 
@@ -1084,9 +1241,9 @@ __device__ inline void update1(const StepArgs &a, const TileHdr &th, int j, cons
 template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN, int OP = 0>
 __global__ __launch_bounds__(1024) void k_step1(StepArgs a) {
   constexpr int HW = Op<R, NE, OP>::W;  // operator values per element
-  constexpr int EPT = OP == 1 ? 1
+  constexpr int EPT = OP >= 1 ? 1
                       : NE == 8 ? (sizeof(R) == 4 ? 4 : 2) : (sizeof(R) == 4 ? (TDK ? 6 : 8) : 3);
-  constexpr int NPT = OP == 1 ? (sizeof(R) == 4 ? 2 : 1) : (sizeof(R) == 4 ? 4 : 2);
+  constexpr int NPT = OP >= 1 ? (sizeof(R) == 4 ? 2 : 1) : (sizeof(R) == 4 ? 4 : 2);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int t = (b & 7) * a.nper + (b >> 3);
@@ -1184,6 +1341,7 @@ hipError_t step_attr(int bytes) {
 template <typename R, int NE, int MODE>
 hipError_t step_dispatch_tt(const StepArgs &a, hipStream_t s) {
   if (NE == 8 && a.op == 1) return step_t<R, 8, MODE, true, true, true, 1>(a, s);
+  if (NE == 8 && a.op == 2) return step_t<R, 8, MODE, true, true, true, 2>(a, s);
   if (a.esk || a.ktab || a.ctab) return step_t<R, NE, MODE, true, true, true>(a, s);
   if (a.tdk)
     return a.tdc ? step_t<R, NE, MODE, true, true, false>(a, s) : step_t<R, NE, MODE, true, false, false>(a, s);
@@ -1193,6 +1351,7 @@ hipError_t step_dispatch_tt(const StepArgs &a, hipStream_t s) {
 template <typename R, int NE, int MODE>
 hipError_t attr_dispatch_tt(int tdk, int tdc, int gen, int op, int bytes) {
   if (NE == 8 && op == 1) return step_attr<R, 8, MODE, true, true, true, 1>(bytes);
+  if (NE == 8 && op == 2) return step_attr<R, 8, MODE, true, true, true, 2>(bytes);
   if (gen) return step_attr<R, NE, MODE, true, true, true>(bytes);
   if (tdk)
     return tdc ? step_attr<R, NE, MODE, true, true, false>(bytes) : step_attr<R, NE, MODE, true, false, false>(bytes);
@@ -1266,6 +1425,38 @@ struct AdjDot<R, 8, 1> {
     const R qy = vd[3] * g[1][0] + vd[1] * g[1][1] + vd[4] * g[1][2];
     const R qz = vd[5] * g[1][0] + vd[4] * g[1][1] + vd[2] * g[1][2];
     return g[0][0] * qx + g[0][1] * qy + g[0][2] * qz;
+  }
+};
+
+// with hourglass control: the mean-gradient part plus kappa sum_alpha
+// c_alpha(mu) c_alpha(T)
+template <typename R>
+struct AdjDot<R, 8, 2> {
+  __device__ static R dot(const R *Lmu, const R *LT, const uint32_t *loc, const R *h) {
+#pragma clang fp contract(off)
+    R g[2][3] = {}, c[2][4];
+    const R *V2[2] = {Lmu, LT};
+#pragma unroll
+    for (int w = 0; w < 2; w++) {
+      const R t7 = V2[w][loc[7]];
+      R d[7];
+#pragma unroll
+      for (int n = 0; n < 7; n++) {
+        d[n] = V2[w][loc[n]] - t7;
+        g[w][0] += h[3 * n] * d[n];
+        g[w][1] += h[3 * n + 1] * d[n];
+        g[w][2] += h[3 * n + 2] * d[n];
+      }
+      ElemMeanHg<R>::amps(d, g[w][0], g[w][1], g[w][2], h, c[w]);
+    }
+    const R *vd = h + 21;
+    const R qx = vd[0] * g[1][0] + vd[3] * g[1][1] + vd[5] * g[1][2];
+    const R qy = vd[3] * g[1][0] + vd[1] * g[1][1] + vd[4] * g[1][2];
+    const R qz = vd[5] * g[1][0] + vd[4] * g[1][1] + vd[2] * g[1][2];
+    R hg = 0;
+#pragma unroll
+    for (int al = 0; al < 4; al++) hg += c[0][al] * c[1][al];
+    return (g[0][0] * qx + g[0][1] * qy + g[0][2] * qz) + h[27] * hg;
   }
 };
 
@@ -2268,14 +2459,14 @@ hipError_t launch_expand_sk(int prec, int64_t Eexp, const int32_t *eorig, const 
   return hipGetLastError();
 }
 
-hipError_t launch_expand_H(int prec, int W, int from, int64_t Eexp, int64_t E, const int32_t *eorig,
+hipError_t launch_expand_H(int prec, int W, int from, int to, int64_t Eexp, int64_t E, const int32_t *eorig,
                            const double *H0, const double *kscale, void *H, hipStream_t s) {
   if (prec == 1)
     hipLaunchKernelGGL(k_expand_H<double>, dim3(blocks_for(Eexp, 256)), dim3(256), 0, s, W, from,
-                       Eexp, E, eorig, H0, kscale, (double *)H);
+                       to, Eexp, E, eorig, H0, kscale, (double *)H);
   else
     hipLaunchKernelGGL(k_expand_H<float>, dim3(blocks_for(Eexp, 256)), dim3(256), 0, s, W, from,
-                       Eexp, E, eorig, H0, kscale, (float *)H);
+                       to, Eexp, E, eorig, H0, kscale, (float *)H);
   return hipGetLastError();
 }
 
@@ -2434,6 +2625,12 @@ hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s) {
     else hipLaunchKernelGGL((k_adjoint1<float, 8, 0, 1>), g, b, a.lds, s, a);
     return hipGetLastError();
   }
+  if (a.ne == 8 && a.op == 2) {
+    if (a.prec == 1) hipLaunchKernelGGL((k_adjoint1<double, 8, 0, 2>), g, b, a.lds, s, a);
+    else if (a.prec == 0) hipLaunchKernelGGL((k_adjoint1<float, 8, 1, 2>), g, b, a.lds, s, a);
+    else hipLaunchKernelGGL((k_adjoint1<float, 8, 0, 2>), g, b, a.lds, s, a);
+    return hipGetLastError();
+  }
   if (a.prec == 1) {
     if (a.ne == 8) hipLaunchKernelGGL((k_adjoint1<double, 8, 0>), g, b, a.lds, s, a);
     else hipLaunchKernelGGL((k_adjoint1<double, 4, 0>), g, b, a.lds, s, a);
@@ -2452,6 +2649,9 @@ hipError_t adjoint_set_lds_limit(int prec, int ne, int op, int bytes) {
   if (ne == 8 && op == 1)
     f = prec == 1 ? (const void *)k_adjoint1<double, 8, 0, 1>
                   : (prec == 0 ? (const void *)k_adjoint1<float, 8, 1, 1> : (const void *)k_adjoint1<float, 8, 0, 1>);
+  else if (ne == 8 && op == 2)
+    f = prec == 1 ? (const void *)k_adjoint1<double, 8, 0, 2>
+                  : (prec == 0 ? (const void *)k_adjoint1<float, 8, 1, 2> : (const void *)k_adjoint1<float, 8, 0, 2>);
   else if (prec == 1) f = ne == 8 ? (const void *)k_adjoint1<double, 8, 0> : (const void *)k_adjoint1<double, 4, 0>;
   else if (prec == 0) f = ne == 8 ? (const void *)k_adjoint1<float, 8, 1> : (const void *)k_adjoint1<float, 4, 1>;
   else f = ne == 8 ? (const void *)k_adjoint1<float, 8, 0> : (const void *)k_adjoint1<float, 4, 0>;

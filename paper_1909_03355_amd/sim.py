@@ -92,7 +92,8 @@ class Simulation:
                             float(prob["T_hi"]), int(bool(allow_unstable)),
                             _ptr(inst, C.c_int32), int(tile_nodes), int(block_threads),
                             int(fuse_steps), int(bool(resident)),
-                            1 if prob.get("hex_gradient", "centre") == "mean" else 0)
+                            1 if prob.get("hex_gradient", "centre") == "mean" else 0,
+                            float(prob.get("hourglass", 0.0) or 0.0))
         self.stream = current_stream() if stream is None else stream
         ctx = C.c_void_p()
         L.check(lib.fed_create(C.byref(mesh), C.byref(mats), C.byref(bcs), C.byref(opt),

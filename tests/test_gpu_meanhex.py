@@ -3,7 +3,8 @@ oracle: distorted meshes with temperature-dependent properties and all
 boundary conditions (err_max <= 1e-12 FP64, <= 1e-5 compensated FP32), the
 distorted patch test of Sec. 4.1 (which the centre-point hexahedron fails),
 the adjoint (1e-10 / 1e-4), and equality with the centre point on affine
-grids."""
+grids; with hourglass control: the critical step, the temperatures and the
+adjoint against the oracle, and the decay of the checkerboard mode."""
 from __future__ import annotations
 
 import os
@@ -102,3 +103,66 @@ def test_mean_equals_centre_on_box():
     a = _run(p, "fp64", 50)
     b = _run(dict(p, hex_gradient="mean"), "fp64", 50)
     assert oracle.err_max(a, b) < 1e-12
+
+
+# ---- hourglass control of the uniform-gradient hexahedron -------------------
+def test_hourglass_control_matches_oracle():
+    """Distorted mesh, hourglass control on: the critical step and the
+    temperatures against the oracle, bitwise across tilings."""
+    from paper_1909_03355_amd import Simulation
+    p = dict(_distorted(), hourglass=0.3)
+    o = Oracle(p)
+    assert o.dt_crit < Oracle(dict(p, hourglass=0.0)).dt_crit   # the term stiffens the step
+    ref = o.run(100)
+    for prec in ("fp64", "fp32c"):
+        with Simulation(p, prec=prec) as s:
+            assert abs(s.dt_crit[0] / o.dt_crit - 1) < 1e-12
+            s.set_temperature()
+            s.step(100, graph_steps=10)
+            T = s.temperature()
+        err = oracle.err_max(T, ref)
+        print(f"hourglass-controlled hex {prec}: err_max {err:.2e}", flush=True)
+        assert err <= TOL[prec]
+        assert np.array_equal(_run(p, prec, 100, tile_nodes=50, block_threads=128), T)
+
+
+def test_hourglass_mode_decays_on_gpu():
+    """The checkerboard is a fixed point of the uniform-gradient element and
+    decays under hourglass control, as in the oracle."""
+    n = 6
+    p, m = H.box_problem("hex8", n, side=0.1, mat=P.material(1000.0, 1000.0, [2.0]))
+    k, j, i = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    p["T0"] = 20.0 + 5.0 * ((-1.0) ** (i + j + k)).ravel()
+    p["T_lo"], p["T_hi"] = 0.0, 50.0
+    p["hex_gradient"] = "mean"
+    T0 = _run(dict(p, hourglass=0.0), "fp64", 200)
+    assert np.max(np.abs(T0 - p["T0"])) < 1e-10
+    q = dict(p, hourglass=0.5)
+    ref = Oracle(q).run(200)
+    assert np.max(np.abs(ref - 20.0)) < 0.5 * 5.0
+    for prec in ("fp64", "fp32c"):
+        T = _run(q, prec, 200)
+        assert oracle.err_max(T, ref) <= TOL[prec]
+
+
+def test_hourglass_adjoint_matches_oracle():
+    p = dict(_distorted(5, seed=9), hourglass=0.4)
+    nsteps = 40
+    o = Oracle(p)
+    hist = o.run(nsteps, history=True)
+    sens = np.arange(0, o.N, 4)
+    lam = np.zeros(o.N)
+    lam[sens] = 2.0 * (hist[-1][sens] - 40.0) / sens.size
+    ref = o.adjoint(hist, lam)
+    rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    for prec in ("fp64", "fp32c"):
+        with _sim(p, prec) as s:
+            s.checkpoint_every(16)
+            s.set_temperature()
+            s.step(nsteps)
+            g = s.backward(lam)
+        errs = {"logk": rel(g["logk"], ref["g_logk"]), "c": rel(g["c"], ref["g_c"]),
+                "h": rel(g["h"], ref["g_h"]), "T0": rel(g["T0"], ref["lam0"])}
+        print("hourglass adjoint", prec, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        for k, v in errs.items():
+            assert v <= GTOL[prec], (prec, k, v)

@@ -115,6 +115,21 @@ def test_meanhex_hex64_full_size():
         assert err <= TOL[prec]
 
 
+def test_meanhg_hex64_full_size():
+    """Hourglass control on the distorted 64^3 mesh, 100 steps, in the launch
+    shape bench.py times: the critical step and the temperatures against the
+    oracle."""
+    p = P.cube_nonlinear_hex_mean_hg(64, 100)
+    o = Oracle(p)
+    ref = o.run(100)
+    for prec in ("fp64", "fp32c"):
+        T, dtc, _ = _run(p, prec, 100)
+        assert abs(dtc[0] / o.dt_crit - 1) < 1e-12
+        err = oracle.err_max(T, ref)
+        print(f"meanhg_hex64 {prec}: err_max {err:.2e}", flush=True)
+        assert err <= TOL[prec]
+
+
 def test_nonlinear_adjoint_hex64():
     """The adjoint through D(T), c(T) and radiation at 64^3 (200 steps,
     checkpoints every 50, resident forward and adjoint): FP32C gradients

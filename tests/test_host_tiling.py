@@ -95,3 +95,5 @@ def test_validation_rejects_bad_inputs():
     # the uniform-gradient hexahedron runs one step per launch
     _expect(dict(p, hex_gradient="mean"), L.FED_E_ARG, fuse_steps=2)
     _expect(dict(p, hex_gradient="mean"), L.FED_E_ARG, resident=True)
+    _expect(dict(p, hourglass=0.5), L.FED_E_ARG)                      # needs the mean gradient
+    _expect(dict(p, hex_gradient="mean", hourglass=-1.0), L.FED_E_ARG)

@@ -29,6 +29,10 @@ dt              float or None.  None: dt = safety * dt_crit, with dt_crit the
 Tz              absolute zero in C (-273.15)
 node_instance   int32[N] or None: independent instances of a batched mesh
 nsteps          number of explicit steps
+hex_gradient    optional 'centre' (default) | 'mean': the hexahedron's gradient
+                at its centre or averaged over it (uniform gradient)
+hourglass       optional float >= 0 (default 0): hourglass control strength of
+                the uniform-gradient hexahedron
 """
 from __future__ import annotations
 
@@ -151,6 +155,16 @@ def cube_nonlinear_hex_mean(n=64, nsteps=10000, amp=0.25, seed=1909_0006):
     p.update(x=mj["x"], y=mj["y"], z=mj["z"], name=f"nonlinear_hex_mean_{n}")
     p["hex_gradient"] = "mean"
     p["meta"].update(jitter=amp, jitter_seed=seed)
+    return p
+
+
+def cube_nonlinear_hex_mean_hg(n=64, nsteps=10000, eps=0.3):
+    """The distorted uniform-gradient workload with hourglass control of
+    strength eps."""
+    p = cube_nonlinear_hex_mean(n, nsteps)
+    p["name"] = f"nonlinear_hex_mean_hg_{n}"
+    p["hourglass"] = eps
+    p["meta"].update(hourglass=eps)
     return p
 
 
