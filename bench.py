@@ -44,9 +44,9 @@ TRAFFIC_SRC = [os.path.join(ROOT, "paper_1909_03355_amd", "csrc", f)
 # (TRAFFIC_SRC, concatenated) with this SHA-1; any other source reports null.
 #   workload -> (sha1, kernel, bytes per launch or once, bytes per step)
 TRAFFIC = {
-    "nonlinear_hex64": ("71f8cd06285168d18eba0b9c39828ba143a94fa8", "k_resident", 20445048.9, 2361433.3),
-    "aniso_tet128": ("71f8cd06285168d18eba0b9c39828ba143a94fa8", "k_step1", 620835568.0, 0.0),
-    "batched_hex256": ("71f8cd06285168d18eba0b9c39828ba143a94fa8", "k_step1", 463505648.0, 0.0),
+    "nonlinear_hex64": ("e44f6f8252f3cdd63e3a71e1e8bbe00f65920080", "k_resident", 20609329.8, 2359800.4),
+    "aniso_tet128": ("e44f6f8252f3cdd63e3a71e1e8bbe00f65920080", "k_step1", 620867824.0, 0.0),
+    "batched_hex256": ("e44f6f8252f3cdd63e3a71e1e8bbe00f65920080", "k_step1", 463492896.0, 0.0),
 }
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
 
