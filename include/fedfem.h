@@ -293,6 +293,16 @@ int fed_set_bc(fed_ctx *ctx, const double *face_Ta, const double *face_q, const 
 int fed_set_point_schedule(fed_ctx *ctx, const double *W, int64_t n_rows, int32_t on_device,
                            void *stream);
 
+/* Test hook for the failure path of resident stepping (for tests only):
+ * spin_limit bounds every halo wait of the context's later fed_step launches
+ * (0 = the default, 2^22 polls), and never_match != 0 makes those waits look
+ * for a tag no exchange word carries, so each gives up after spin_limit polls.
+ * The launch still ends normally, its results are invalid, and the next
+ * fed_get_temperature returns FED_E_HIP.  fed_test_waits(ctx, 0, 0) restores
+ * normal waits and fed_set_temperature clears the error.  Errors: FED_E_ARG
+ * (spin_limit < 0), FED_E_STATE (not a resident context). */
+int fed_test_waits(fed_ctx *ctx, int32_t spin_limit, int32_t never_match);
+
 /* Smallest and largest current temperature (FP64; NaN if any is not finite).
  * The stability bound (Sec. 3.4) is derived for [T_lo, T_hi]; a run whose
  * temperatures leave that range should re-derive it with fed_set_range.

@@ -88,6 +88,10 @@ struct fed_ctx {
   unsigned xtag = 1;
   int *d_rerr = nullptr;
   int res_lds = 0;
+  // bounded halo waits of resident launches; tag_skew != 0 only in tests of
+  // the failure path (fed_test_waits)
+  int spin_limit = 1 << 22;
+  unsigned tag_skew = 0;
   int res_split = 1;  // resident steps run the tile-interior elements during the halo wait
   // resident adjoint (hexahedra, folded operator, tiles within the LDS)
   bool adjres = false;
@@ -946,9 +950,10 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
       fed::StepArgs a = c->step_args(c->cur, 1);
       a.lds = c->res_lds;
       const int fin = c->cur ^ (k & 1);
-      fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
+      fed::ResArgs r{k, c->spin_limit, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
                      c->d_T[fin], c->d_lo[fin], nullptr, 0};
       r.split = c->res_split;
+      r.tag_skew = c->tag_skew;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
         r.pts_nrec = c->nrec;
@@ -1311,6 +1316,15 @@ int fed_set_point_schedule(fed_ctx *c, const double *W, int64_t n_rows, int32_t 
                                 c->d_psP, s));
   c->ps_rows = n_rows;
   if (!on_device) HIPCHK(hipStreamSynchronize(s));  // the host array may be reused
+  return FED_OK;
+}
+
+int fed_test_waits(fed_ctx *c, int32_t spin_limit, int32_t never_match) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  if (spin_limit < 0) return fail(FED_E_ARG, "spin_limit < 0");
+  if (!c->resident) return fail(FED_E_STATE, "not a resident context");
+  c->spin_limit = spin_limit ? spin_limit : 1 << 22;
+  c->tag_skew = never_match ? 0x40000000u : 0u;
   return FED_OK;
 }
 

@@ -198,6 +198,8 @@ struct ResArgs {
   // 1: each step runs the elements whose nodes the tile owns before it waits
   // for the halo (one more workgroup barrier a step); 0: all elements after it
   int split;
+  unsigned tag_skew;          // added to the tag a wait looks for: 0, or (tests of the
+                              // failure path) a value no word carries
 };
 
 // Resident adjoint of one checkpoint segment (hexahedra, folded operator):

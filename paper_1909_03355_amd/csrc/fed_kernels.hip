@@ -2092,7 +2092,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       for (int q = 0; q < HPT; q++) hv[q] = tid + q * bs < nhalo ? Tin[hid[q]] : (R)0;
     } else {
       const unsigned long long *X = r.X[s & 1];
-      const unsigned want = r.tag0 + (unsigned)s;
+      const unsigned want = r.tag0 + (unsigned)s + r.tag_skew;
       wait_halo<R, HPT>(X, hid, nhalo - tid, bs, want, hv, r.spin_limit, r.err);
     }
 #pragma unroll

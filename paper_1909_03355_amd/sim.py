@@ -223,6 +223,10 @@ class Simulation:
                                                self.stream))
         self._keep_sched = keep  # a device tensor stays alive until the copy has run
 
+    def test_waits(self, spin_limit=0, never_match=False):
+        """Test hook of resident stepping's failure path (see fed_test_waits)."""
+        L.check(L.lib().fed_test_waits(self._c(), int(spin_limit), int(bool(never_match))))
+
     def temperature_range(self):
         """(min, max) of the current temperatures (synchronises)."""
         lo, hi = C.c_double(), C.c_double()

@@ -147,3 +147,29 @@ def test_resident_hex64_full_size():
         assert err <= TOL[prec]
         base, _ = _run(p, prec, 200, graph_steps=100)
         assert np.array_equal(T, base)
+
+
+def test_resident_wait_failure_is_reported():
+    """Failure path of the bounded halo waits: with every wait looking for a
+    tag no word carries, each gives up after 64 polls, the launch still ends,
+    and the readout reports FED_E_HIP; normal waits and a new initial state
+    then step exactly as a fresh context does."""
+    from paper_1909_03355_amd import FedError
+    p = P.cube_nonlinear_hex(8, 20)
+    with _sim(p, "fp32c", resident=True) as s:
+        s.test_waits(spin_limit=64, never_match=True)
+        s.set_temperature()
+        s.step(5)
+        with pytest.raises(FedError, match="FED_E_HIP"):
+            s.temperature()
+        s.test_waits(0, False)
+        s.set_temperature()
+        s.step(20)
+        T = s.temperature()
+    with _sim(p, "fp32c", resident=True) as s:
+        s.set_temperature()
+        s.step(20)
+        assert np.array_equal(s.temperature(), T)
+    with _sim(p, "fp32c") as s:
+        with pytest.raises(FedError, match="FED_E_STATE"):
+            s.test_waits(64, True)
