@@ -104,6 +104,8 @@ def parse():
                     help="steps of the CPU oracle sample (timed baseline and error reference)")
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-keep-states", action="store_true",
+                    help="adjoint workloads: recompute the checkpoint segments in the backward pass")
     return ap.parse_args()
 
 
@@ -120,11 +122,15 @@ def timed_steps(sim, steps, warmup, graph_steps):
     return start.elapsed_time(stop) / 1e3
 
 
-def timed_adjoint(sim, steps, prob):
-    """Forward with checkpoints plus the adjoint of an MSE sensor loss."""
+def timed_adjoint(sim, steps, prob, keep=True):
+    """Forward with checkpoints plus the adjoint of an MSE sensor loss; a
+    resident context keeps every forward state (unless keep is off), so the
+    backward pass does not recompute the checkpoint segments."""
     import torch
     sens = prob["meta"]["sensors"]
     sim.checkpoint_every(prob["meta"]["ckpt_every"])
+    if keep and sim.info["resident"]:
+        sim.keep_states()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.set_temperature()
@@ -204,9 +210,10 @@ def main():
     for prec in precs:
         sim = Simulation(prob, prec=prec, **kw)
         if kind == "adjoint":
+            keep = not args.no_keep_states
             if args.warmup:
-                timed_adjoint(sim, steps, prob)  # first-use allocations and module loads
-            tf, tb = timed_adjoint(sim, steps, prob)
+                timed_adjoint(sim, steps, prob, keep)  # first-use allocations and module loads
+            tf, tb = timed_adjoint(sim, steps, prob, keep)
             t = tf + tb
             log(f"{prec}: forward {tf * 1e3:.1f} ms + adjoint {tb * 1e3:.1f} ms for {steps} steps")
         elif kind == "moving":

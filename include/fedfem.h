@@ -239,8 +239,21 @@ int fed_set_state(fed_ctx *ctx, const void *hi, const void *lo, int64_t step, vo
 /* Checkpointing for the adjoint: with every > 0, the state at step 0 (the one
  * fed_set_temperature sets) and after every `every` steps is kept on the device
  * (2 state vectors each; fed_step breaks its launches at those steps).  0 turns
- * it off and frees the checkpoints.  Call before fed_set_temperature. */
+ * it off and frees the checkpoints (another interval frees them too; the same
+ * interval reuses them).  Call before fed_set_temperature. */
 int fed_checkpoint_every(fed_ctx *ctx, int64_t every);
+
+/* Kept states for the adjoint (resident contexts with checkpointing on): with
+ * on != 0 the forward launches also store every step's state (n_nodes values
+ * of the working precision a step, per checkpoint segment, allocated as the
+ * steps run: about steps x n_nodes x 4 bytes in FP32C), and fed_backward uses
+ * them instead of recomputing each segment from its checkpoint.  The
+ * derivatives are bit for bit those of the recomputing backward pass.  States
+ * count from fed_set_temperature; a fed_set_state in between, or on = 0,
+ * makes fed_backward recompute again.  Call after fed_checkpoint_every and
+ * before fed_set_temperature.  Errors: FED_E_STATE (not resident, or
+ * checkpointing off). */
+int fed_keep_states(fed_ctx *ctx, int32_t on);
 
 /* Replaces per-element conductivity factors (kscale, n_elems, > 0), per-element
  * heat capacities (elem_c, n_elems, > 0; the capacity c0 of each element, for

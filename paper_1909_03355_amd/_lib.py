@@ -91,6 +91,7 @@ SIGNATURES = {
     "fed_set_point_schedule": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                          C.c_void_p]),
     "fed_test_waits": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "fed_keep_states": (C.c_int, [C.c_void_p, C.c_int32]),
     "fed_temperature_range": (C.c_int, [C.c_void_p, _d, _d, C.c_void_p]),
     "fed_set_range": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
     "fed_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

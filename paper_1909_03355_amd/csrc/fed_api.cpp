@@ -125,6 +125,12 @@ struct fed_ctx {
   // checkpoints (state after every ckpt_every steps) and adjoint work arrays
   int64_t ckpt_every = 0;
   std::vector<void *> ck_hi, ck_lo;
+  // kept states (resident contexts, fed_keep_states): per checkpoint segment
+  // g the hi of steps g*ckpt_every .. (g+1)*ckpt_every, written by the forward
+  // launches, so fed_backward need not recompute them; kept_ok while every
+  // step since fed_set_temperature was stored
+  bool keep_states = false, kept_ok = false;
+  std::vector<void *> segbuf;
   void *d_seg = nullptr, *d_lamb[2] = {nullptr, nullptr}, *d_rdt = nullptr, *d_mV = nullptr;
   float *d_seglo[2] = {nullptr, nullptr}, *d_lamlo[2] = {nullptr, nullptr};
   double *d_S0 = nullptr, *d_S1 = nullptr, *d_gk = nullptr, *d_gc = nullptr, *d_gh = nullptr;
@@ -227,6 +233,7 @@ namespace {
 
 int save_checkpoint(fed_ctx *c, int64_t i, hipStream_t s);
 int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s);
+int seg_buffer(fed_ctx *c, int64_t g);
 
 template <typename T>
 hipError_t upload(DevPool &pool, T **d, const T *h, size_t n) {
@@ -928,6 +935,7 @@ int fed_set_temperature(fed_ctx *c, const double *T, int32_t on_device, void *st
                            c->d_dir_node, c->d_dir_T, s));
   c->steps = 0;
   c->have_T = true;
+  c->kept_ok = c->keep_states && c->resident && c->ckpt_every > 0;
   HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
   if (c->resident) HIPCHK(hipMemsetAsync(c->d_rerr, 0, sizeof(int), s));
   if (c->ckpt_every > 0) {
@@ -954,6 +962,14 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
                      c->d_T[fin], c->d_lo[fin], nullptr, 0};
       r.split = c->res_split;
       r.tag_skew = c->tag_skew;
+      if (c->keep_states && c->ckpt_every > 0) {
+        // fed_step breaks launches at checkpoints: this one stays inside segment g
+        const int64_t st = c->steps + nsteps - n, g = st / c->ckpt_every, i0 = st % c->ckpt_every;
+        int rc = seg_buffer(c, g);
+        if (rc) return rc;
+        r.seg = (char *)c->segbuf[g] + (size_t)c->rb * c->N * i0;
+        r.segN = c->N;
+      }
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
         r.pts_nrec = c->nrec;
@@ -969,6 +985,7 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
     c->steps += nsteps;
     return FED_OK;
   }
+  c->kept_ok = false;  // one-step launches keep no states
   for (int64_t n = nsteps; n > 0;) {
     // under a point-load schedule every step takes its own record powers: one
     // step per launch
@@ -983,6 +1000,15 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
   return FED_OK;
 }
 
+// the kept-states buffer of checkpoint segment g, (ckpt_every + 1) hi vectors
+// (allocated on first use)
+int seg_buffer(fed_ctx *c, int64_t g) {
+  if ((int64_t)c->segbuf.size() <= g) c->segbuf.resize(g + 1, nullptr);
+  if (!c->segbuf[g])
+    HIPCHK(c->pool.alloc(&c->segbuf[g], (size_t)c->rb * c->N * (c->ckpt_every + 1)));
+  return FED_OK;
+}
+
 // copies the current state into checkpoint slot i (allocating it on first use)
 int save_checkpoint(fed_ctx *c, int64_t i, hipStream_t s) {
   if ((int64_t)c->ck_hi.size() <= i) {
@@ -992,6 +1018,12 @@ int save_checkpoint(fed_ctx *c, int64_t i, hipStream_t s) {
   const size_t hb = (size_t)c->rb * c->N;
   if (!c->ck_hi[i]) HIPCHK(c->pool.alloc(&c->ck_hi[i], hb));
   HIPCHK(hipMemcpyAsync(c->ck_hi[i], c->d_T[c->cur], hb, hipMemcpyDeviceToDevice, s));
+  if (c->keep_states) {
+    // row 0 of the segment's kept states
+    int rc = seg_buffer(c, i);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(c->segbuf[i], c->d_T[c->cur], hb, hipMemcpyDeviceToDevice, s));
+  }
   if (c->prec == FED_FP32C) {
     if (!c->ck_lo[i]) HIPCHK(c->pool.alloc(&c->ck_lo[i], sizeof(float) * c->N));
     HIPCHK(hipMemcpyAsync(c->ck_lo[i], c->d_lo[c->cur], sizeof(float) * c->N,
@@ -1138,6 +1170,7 @@ int fed_set_state(fed_ctx *c, const void *hi, const void *lo, int64_t step, void
   if (c->resident) HIPCHK(hipMemsetAsync(c->d_rerr, 0, sizeof(int), s));
   HIPCHK(hipStreamSynchronize(s));
   c->steps = step;
+  c->kept_ok = false;
   c->have_T = true;
   return FED_OK;
 }
@@ -1145,10 +1178,15 @@ int fed_set_state(fed_ctx *c, const void *hi, const void *lo, int64_t step, void
 int fed_checkpoint_every(fed_ctx *c, int64_t every) {
   if (!c) return fail(FED_E_ARG, "null ctx");
   if (every < 0) return fail(FED_E_ARG, "every < 0");
-  for (void *p : c->ck_hi) c->pool.release(p);
-  for (void *p : c->ck_lo) c->pool.release(p);
-  c->ck_hi.clear();
-  c->ck_lo.clear();
+  if (every != c->ckpt_every || every == 0) {
+    // the buffers are reused (and overwritten) while the interval stays the same
+    for (void *p : c->ck_hi) c->pool.release(p);
+    for (void *p : c->ck_lo) c->pool.release(p);
+    c->ck_hi.clear();
+    c->ck_lo.clear();
+    for (void *p : c->segbuf) c->pool.release(p);
+    c->segbuf.clear();
+  }
   c->ckpt_every = every;
   c->have_T = false;  // the checkpoint of step 0 is taken by fed_set_temperature
   return FED_OK;
@@ -1319,6 +1357,20 @@ int fed_set_point_schedule(fed_ctx *c, const double *W, int64_t n_rows, int32_t 
   return FED_OK;
 }
 
+int fed_keep_states(fed_ctx *c, int32_t on) {
+  if (!c) return fail(FED_E_ARG, "null ctx");
+  if (on && !c->resident) return fail(FED_E_STATE, "kept states need a resident context");
+  if (on && c->ckpt_every <= 0) return fail(FED_E_STATE, "checkpointing is off (fed_checkpoint_every)");
+  c->keep_states = on != 0;
+  if (!c->keep_states) {
+    for (void *p : c->segbuf) c->pool.release(p);
+    c->segbuf.clear();
+  }
+  c->have_T = false;  // the states are kept from fed_set_temperature on
+  c->kept_ok = false;
+  return FED_OK;
+}
+
 int fed_test_waits(fed_ctx *c, int32_t spin_limit, int32_t never_match) {
   if (!c) return fail(FED_E_ARG, "null ctx");
   if (spin_limit < 0) return fail(FED_E_ARG, "spin_limit < 0");
@@ -1454,20 +1506,28 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
   HIPCHK(fed::launch_set_T(c->prec, N, src, c->d_perm, c->d_lamb[0], c->d_lamlo[0], 0, nullptr,
                            nullptr, s));
   int lc = 0;
+  void *segb = c->d_seg;  // the states of the segment at hand: kept or recomputed
   auto seg = [&](int64_t i) {
-    return (void *)((char *)c->d_seg + (size_t)rb * N * i);
+    return (void *)((char *)segb + (size_t)rb * N * i);
   };
   const int64_t nseg = (steps + ck - 1) / ck;
   for (int64_t g = nseg - 1; g >= 0; g--) {
     const int64_t n0 = g * ck, n1 = std::min(steps, n0 + ck);
     if (g >= (int64_t)c->ck_hi.size() || !c->ck_hi[g])
       return fail(FED_E_STATE, "checkpoint %lld missing", (long long)g);
-    // recompute the segment's states T^{n0..n1} from its checkpoint
-    HIPCHK(hipMemcpyAsync(seg(0), c->ck_hi[g], (size_t)rb * N, hipMemcpyDeviceToDevice, s));
-    if (c->prec == FED_FP32C)
-      HIPCHK(hipMemcpyAsync(c->d_seglo[0], c->ck_lo[g], sizeof(float) * N,
-                            hipMemcpyDeviceToDevice, s));
-    if (c->resident && n1 > n0) {
+    // the segment's states T^{n0..n1}: kept by the forward launches, or
+    // recomputed from its checkpoint
+    const bool kept = c->kept_ok && g < (int64_t)c->segbuf.size() && c->segbuf[g];
+    segb = kept ? c->segbuf[g] : c->d_seg;
+    if (!kept) {
+      HIPCHK(hipMemcpyAsync(seg(0), c->ck_hi[g], (size_t)rb * N, hipMemcpyDeviceToDevice, s));
+      if (c->prec == FED_FP32C)
+        HIPCHK(hipMemcpyAsync(c->d_seglo[0], c->ck_lo[g], sizeof(float) * N,
+                              hipMemcpyDeviceToDevice, s));
+    }
+    if (kept) {
+      // nothing to recompute
+    } else if (c->resident && n1 > n0) {
       // one resident launch recomputes the segment, storing every step's hi
       const int k = (int)(n1 - n0);
       fed::StepArgs a = c->step_args(0, 1);
@@ -1476,7 +1536,7 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       a.loin = c->d_seglo[0];
       a.Tout = seg(1);  // not used by the resident kernel
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
-                     seg(k), c->d_seglo[k & 1], c->d_seg, N};
+                     seg(k), c->d_seglo[k & 1], segb, N};
       r.split = c->res_split;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
@@ -1544,7 +1604,7 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       a.lamout = c->d_lamb[1 - lc];
       a.lamloout = c->d_lamlo[1 - lc];
       fed::AdjResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
-                        c->d_seg, N};
+                        segb, N};
       HIPCHK(fed::launch_adjres(a, r, s));
       c->xtag += (unsigned)k + 1u;
       lc ^= 1;

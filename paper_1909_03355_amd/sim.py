@@ -223,6 +223,11 @@ class Simulation:
                                                self.stream))
         self._keep_sched = keep  # a device tensor stays alive until the copy has run
 
+    def keep_states(self, on=True):
+        """Keep every forward state for the adjoint instead of recomputing the
+        checkpoint segments (resident contexts; after checkpoint_every)."""
+        L.check(L.lib().fed_keep_states(self._c(), int(bool(on))))
+
     def test_waits(self, spin_limit=0, never_match=False):
         """Test hook of resident stepping's failure path (see fed_test_waits)."""
         L.check(L.lib().fed_test_waits(self._c(), int(spin_limit), int(bool(never_match))))

@@ -173,3 +173,35 @@ def test_resident_wait_failure_is_reported():
     with _sim(p, "fp32c") as s:
         with pytest.raises(FedError, match="FED_E_STATE"):
             s.test_waits(64, True)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_kept_states_give_the_same_gradients(prec):
+    """fed_keep_states: the backward pass over the states the forward launches
+    kept equals, bit for bit, the one that recomputes every checkpoint
+    segment (also across a partial last segment and a split step call)."""
+    from paper_1909_03355_amd import FedError, Simulation
+    p = P.nonlinear_adjoint_hex(8, 45, n_sensors=30, ckpt_every=10)
+    sens = p["meta"]["sensors"]
+    out = []
+    for keep in (False, True):
+        with Simulation(p, prec=prec, resident=True) as s:
+            s.checkpoint_every(10)
+            if keep:
+                s.keep_states()
+            s.set_temperature()
+            s.step(17)
+            s.step(28)
+            T = s.temperature()
+            lam = np.zeros(T.size)
+            lam[sens] = 2.0 * (T[sens] - 60.0) / sens.size
+            g = s.backward(lam)
+            out.append((T, g))
+    (Ta, ga), (Tb, gb) = out
+    assert np.array_equal(Ta, Tb)
+    for k in ("logk", "c", "h", "T0"):
+        assert np.array_equal(ga[k], gb[k]), k
+    with Simulation(p, prec=prec) as s:
+        s.checkpoint_every(10)
+        with pytest.raises(FedError, match="FED_E_STATE"):
+            s.keep_states()
