@@ -44,9 +44,9 @@ TRAFFIC_SRC = [os.path.join(ROOT, "paper_1909_03355_amd", "csrc", f)
 # (TRAFFIC_SRC, concatenated) with this SHA-1; any other source reports null.
 #   workload -> (sha1, kernel, bytes per launch or once, bytes per step)
 TRAFFIC = {
-    "nonlinear_hex64": ("51441f290c1182f8df1cec2969f947fbc5d4b05f", "k_resident", 20317788.4, 2354383.9),
-    "aniso_tet128": ("51441f290c1182f8df1cec2969f947fbc5d4b05f", "k_step1", 620893968.0, 0.0),
-    "batched_hex256": ("51441f290c1182f8df1cec2969f947fbc5d4b05f", "k_step1", 463510640.0, 0.0),
+    "nonlinear_hex64": ("de64b5db9606d8bc557316424e90b8ec4b678c82", "k_resident", 20824839.1, 2357571.5),
+    "aniso_tet128": ("de64b5db9606d8bc557316424e90b8ec4b678c82", "k_step1", 620856944.0, 0.0),
+    "batched_hex256": ("de64b5db9606d8bc557316424e90b8ec4b678c82", "k_step1", 463512144.0, 0.0),
 }
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
 
