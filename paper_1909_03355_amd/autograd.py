@@ -5,10 +5,13 @@ explicit steps from T0 with per-element conductivity factors exp(log_k),
 per-element heat capacities elem_c and per-face convection coefficients
 face_h (each may be None to keep the problem's values) and returns the final
 temperatures as a CUDA float64 tensor.  Its backward is the library's
-hand-written discrete adjoint (fed_backward): checkpoints every
-``sim``'s checkpoint interval, segment recomputation, FP64 gradient
-accumulators.  The problem must be linear in T (constant D and c, no
-radiation).  Torch provides tensors and the stream only.
+hand-written discrete adjoint (fed_backward): checkpoints every ``sim``'s
+checkpoint interval (set with ``sim.checkpoint_every`` before the call),
+each segment recomputed from its checkpoint or, after ``sim.keep_states()``
+on a resident context, read from the states the forward kept; FP64 gradient
+accumulators.  The adjoint differentiates through D(T), c(T), radiation,
+property tables and the uniform-gradient hexahedron (with or without
+hourglass control).  Torch provides tensors and the stream only.
 """
 from __future__ import annotations
 
