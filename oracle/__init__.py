@@ -124,7 +124,7 @@ class Oracle:
             self.hg_G, self.hg_k = np.zeros(self.E * 32), np.zeros(self.E)
             L.orc_hourglass(self.E, _p(x), _p(y), _p(z), _p(conn, _i32), _p(self.B), _p(self.V),
                             _p(self.Dk), self.hourglass, _p(self.hg_G), _p(self.hg_k))
-        # optional shared multiplier tables: D(T) = Dk fk(Tbar), c(T) = c0 fc(T)
+        # optional shared multiplier tables: D_e = Dk mean_a fk(T_a), c(T) = c0 fc(T)
         kt, ct = prob.get("k_table"), prob.get("c_table")
         self.kt = None if kt is None else (_f64(kt[0]), _f64(kt[1]))
         self.ct = None if ct is None else (_f64(ct[0]), _f64(ct[1]))

@@ -20,7 +20,10 @@
  *     the update is T += dt (Q - K T) / C  (K = sum of B^T D B dV is PSD).
  *   - convection adds -h A (T - Ta) into a node (the physical sign, Eq. 7's).
  *   - surface loads are lumped to the face nodes with area |f| / n_f.
- *   - c(T) is evaluated at the node, D(T) at the element mean temperature.
+ *   - c(T) is evaluated at the node; the conductivity factor of D(T) is
+ *     evaluated at every node of the element and the nodal values averaged
+ *     (Sec. 4.2.2), which for a linear k(T) equals its value at the element's
+ *     mean temperature.
  *   - the lumped mass uses the exact element volume (2x2x2 Gauss for a
  *     trilinear hexahedron, which is exact), stiffness uses 8 det J(0).
  */
@@ -285,7 +288,8 @@ void orc_face_areas(int nfn, int64_t nf, const double *x, const double *y,
 /* Everything one explicit run needs; arrays are per element (E), per node
  * (N), per face (nf) as named.  Dk is the element conductivity tensor, 6 rows
  * (xx, yy, zz, xy, yz, xz) of length E, with any per-element factor folded in;
- * D(T) = Dk * (s0 + s1 * Tbar).  c(T) = c0 + c1 * T. */
+ * D_e(T) = Dk * s_e with s_e the mean over the element's nodes of s0 + s1 T_a.
+ * c(T) = c0 + c1 * T. */
 typedef struct {
   int32_t ne, nfn;
   int64_t N, E, nf, npt, ndir;
@@ -301,7 +305,7 @@ typedef struct {
   const double *dt; /* per node */
   double Tz, sigma;
   /* optional piecewise-linear multiplier tables (n points, T increasing):
-   * with nkt > 0, D_e(T) = Dk_e * fk(Tbar) replaces s0 + s1 Tbar; with nct > 0,
+   * with nkt > 0, the nodal values fk(T_a) replace s0 + s1 T_a; with nct > 0,
    * c_e(T) = c0_e * fc(T) replaces c0 + c1 T */
   int32_t nkt, nct;
   const double *kt_T, *kt_f, *ct_T, *ct_f;
@@ -329,11 +333,26 @@ static double table_eval(int32_t n, const double *Tt, const double *f, double T,
   return f[i - 1] + (T - Tt[i - 1]) / h * (f[i] - f[i - 1]);
 }
 
-/* conductivity factor s_e(Tbar) and its derivative */
-static double kfac(const orc_problem *P, int64_t e, double Tbar, double *ds) {
-  if (P->nkt > 0) return table_eval(P->nkt, P->kt_T, P->kt_f, Tbar, ds);
+/* conductivity factor of element e's material at one node temperature T
+ * (s0 + s1 T, or the k table) and its derivative */
+static double kfac_node(const orc_problem *P, int64_t e, double T, double *ds) {
+  if (P->nkt > 0) return table_eval(P->nkt, P->kt_T, P->kt_f, T, ds);
   *ds = P->s1[e];
-  return P->s0[e] + P->s1[e] * Tbar;
+  return P->s0[e] + P->s1[e] * T;
+}
+
+/* Element conductivity factor (Sec. 4.2.2): the property is evaluated at each
+ * node of the element from that node's temperature, and the nodal values are
+ * averaged for the element-level calculation.  ds[a] receives
+ * d s_e / d T_a = (d s / d T)(T_a) / n_e. */
+static double kfac(const orc_problem *P, int64_t e, const double *Te, double *ds) {
+  double s = 0;
+  for (int a = 0; a < P->ne; a++) {
+    double d;
+    s += kfac_node(P, e, Te[a], &d);
+    ds[a] = d / P->ne;
+  }
+  return s / P->ne;
 }
 
 /* specific heat c_e(T) and its derivative */
@@ -348,18 +367,14 @@ static double cfun(const orc_problem *P, int64_t e, double T, double *dc) {
   return P->c0[e] + P->c1[e] * T;
 }
 
-/* Element load F_e = G D(Tbar) B T_e with G = W B^T (Eq. 19-20). */
+/* Element load F_e = G D_e B T_e with G = W B^T (Eq. 19-20) and D_e from the
+ * nodal average of the conductivity factor (kfac). */
 static void element_load(const orc_problem *P, int64_t e, const double *T, double *Fe) {
   int ne = P->ne;
   int64_t E = P->E;
-  double Te[8], Tbar = 0;
-  for (int a = 0; a < ne; a++) {
-    Te[a] = T[P->conn[(int64_t)a * E + e]];
-    Tbar += Te[a];
-  }
-  Tbar /= ne;
-  double ds;
-  double s = kfac(P, e, Tbar, &ds);
+  double Te[8], ds[8];
+  for (int a = 0; a < ne; a++) Te[a] = T[P->conn[(int64_t)a * E + e]];
+  const double s = kfac(P, e, Te, ds);
   const double *Dk = P->Dk;
   double D[3][3];
   D[0][0] = Dk[0 * E + e] * s;
@@ -400,7 +415,7 @@ static void element_load(const orc_problem *P, int64_t e, const double *T, doubl
  * vanishes on every linear field (b reproduces its gradient), and the element
  * adds K_hg = kappa sum_alpha gamma_alpha gamma_alpha^T to its conductance,
  *   kappa = eps (tr Dk / 3) V sum_a |b_a|^2,
- * scaled by the conductivity factor s(Tbar) like the rest of the element.  On
+ * scaled by the conductivity factor s_e like the rest of the element.  On
  * a cube of side h, gamma_alpha = h_alpha / 8 and kappa = 1.5 eps k h.
  * G receives gamma (E x 4 x 8), kap kappa (E). */
 void orc_hourglass(int64_t E, const double *x, const double *y, const double *z,
@@ -543,7 +558,7 @@ static void element_apply(const orc_problem *P, int64_t e, const double *v, doub
  * Discrete adjoint of orc_run (not in the paper: the exact transpose of its
  * explicit recursion).  One step, for a node k that is not Dirichlet, is
  *   T'_k = T_k + dt_k r_k(T) / C_k(T_k),   r = Q(T) - F(T),
- * with F_e = s_e(Tbar_e) K0_e T_e (s_e = s0_e + s1_e Tbar_e or the k table;
+ * with F_e = s_e K0_e T_e (s_e = (1/n_e) sum_a s(T_a), s = s0_e + s1_e T or the k table;
  * K0_e the element matrix at s = 1, symmetric), C_k = sum_e m_e c_e(T_k)
  * (c_e = c0_e + c1_e T or c0_e times the c table), m_e = rho_e V_e / n_e,
  * and Q_k = sum_f share_f [-h_f (T_k - Ta_f) - sigma eps_f ((T_k - Tz)^4 -
@@ -551,7 +566,7 @@ static void element_apply(const orc_problem *P, int64_t e, const double *v, doub
  * their rows of the Jacobian vanish.  With lam = dL/dT', mu_k = dt_k lam_k / C_k
  * (0 on Dirichlet nodes) and dT = T' - T:
  *   dL/dT_j = lam_j (1 - dT_j C'_j / C_j)          C'_j = sum_{e owns j} m_e c_e'(T_j)
- *           - sum_{e owns j} [ s_e (K0_e mu_e)_j + s_e'(Tbar_e) / n_e (mu_e . K0_e T_e) ]
+ *           - sum_{e owns j} [ s_e (K0_e mu_e)_j + s'(T_j) / n_e (mu_e . K0_e T_e) ]
  *           - mu_j sum_{f owns j} share_f (h_f + 4 sigma eps_f (T_j - Tz)^3),
  * set to 0 on Dirichlet nodes (their values are data, not state), and the
  * parameter derivatives accumulated over the steps are
@@ -591,15 +606,13 @@ int orc_adjoint(const orc_problem *P, const double *hist, int64_t nsteps, const 
       out[k] = is_dir[k] ? 0.0 : lam[k] * (1.0 - (Tn1[k] - Tn[k]) * Cp[k] / C[k]);
     }
     for (int64_t e = 0; e < E; e++) {
-      double Tbar = 0, muF = 0, gc = 0, Kmu[8];
+      double muF = 0, gc = 0, Kmu[8], Te[8], dse[8];
       int32_t kk[8];
       for (int a = 0; a < ne; a++) {
         kk[a] = P->conn[(int64_t)a * E + e];
-        Tbar += Tn[kk[a]];
+        Te[a] = Tn[kk[a]];
       }
-      Tbar /= ne;
-      double dse;
-      const double se = kfac(P, e, Tbar, &dse);
+      const double se = kfac(P, e, Te, dse);
       element_apply(P, e, mu, se, Kmu); /* s_e K0_e mu_e */
       for (int a = 0; a < ne; a++) {
         muF += mu[kk[a]] * Fe[e * ne + a];
@@ -608,9 +621,9 @@ int orc_adjoint(const orc_problem *P, const double *hist, int64_t nsteps, const 
         if (P->nct > 0) dcdc0 = table_eval(P->nct, P->ct_T, P->ct_f, Tn[kk[a]], &sl);
         if (!is_dir[kk[a]]) gc += lam[kk[a]] * (Tn1[kk[a]] - Tn[kk[a]]) / C[kk[a]] * dcdc0;
       }
-      /* mu_e . K0_e T_e = mu_e . F_e / s_e */
-      const double spread = dse / ne * (muF / se);
-      for (int a = 0; a < ne; a++) out[kk[a]] -= Kmu[a] + spread;
+      /* mu_e . K0_e T_e = mu_e . F_e / s_e, times d s_e / d T_a per node */
+      const double muKT = muF / se;
+      for (int a = 0; a < ne; a++) out[kk[a]] -= Kmu[a] + dse[a] * muKT;
       g_logk[e] += -muF;
       g_c[e] += -P->rho[e] * P->V[e] / ne * gc;
     }

@@ -557,6 +557,71 @@ def test_single_hex_boundary_recursion():
     assert np.max(np.abs(o.run(50) - T)) < 1e-11 * T
 
 
+@pytest.mark.parametrize("s1,c1", [(0.004, 2.0), (-0.0006, -0.5), (-0.0006, 2.0), (0.004, -0.5)])
+def test_critical_step_closed_form_with_boundary_and_range(s1, c1):
+    """Eq. 29 with the element bound and the boundary rate of Sec. 2 (Eq. 4,
+    7), in closed form for one cube of side a, k(T) = k (s0 + s1 T),
+    c(T) = c0 + c1 T, convection and radiation on all six faces.  The
+    one-point hexahedron's K_e = (k a / 16) sum_i s_i s_i^T has largest
+    eigenvalue k a / 2; each node carries capacity rho c a^3 / 8 and area
+    3 a^2 / 4, so
+        lambda_e = 4 k s_max / (rho c_min a^2),
+        lambda_k = (h + 4 sigma eps (T_hi - Tz)^3) 6 / (rho c_min a),
+    with s_max and c_min the extremes over [T_lo, T_hi]: at T_hi or T_lo
+    depending on the signs of the slopes."""
+    a, k, rho, c0, h, eps, Ta = 0.02, 10.0, 2500.0, 700.0, 80.0, 0.9, 15.0
+    T_lo, T_hi, Tz = 10.0, 900.0, -273.15
+    m = M.box_hex(1, 1, 1, a, a, a)
+    p = P._base(m, "one_dt")
+    p["materials"] = [P.material(rho, c0, [k], c1=c1, s0=1.0, s1=s1)]
+    faces, _ = M.box_side_faces(m)
+    P.set_faces(p, faces, h=h, Ta=Ta, eps=eps)
+    p["T_lo"], p["T_hi"], p["Tz"] = T_lo, T_hi, Tz
+    s_max = max(1.0 + s1 * T_lo, 1.0 + s1 * T_hi)
+    c_min = min(c0 + c1 * T_lo, c0 + c1 * T_hi)
+    lam_e = 4.0 * k * s_max / (rho * c_min * a * a)
+    lam_k = (h + 4.0 * SIG * eps * (T_hi - Tz) ** 3) * 6.0 / (rho * c_min * a)
+    assert 0.1 * lam_e < lam_k < 10.0 * lam_e      # both terms matter
+    assert Oracle(p).dt_crit == pytest.approx(2.0 / (lam_e + lam_k), rel=1e-12)
+
+
+def test_twisted_quad_face_area():
+    """Face areas of bilinear quadrilaterals: on a hexahedron whose top face
+    is twisted (one corner lifted by 0.6 of the side), the 2x2 Gauss rule of
+    |x_u x x_v| is within 2e-4 of a 40x40 Gauss-Legendre reference (a rule
+    with misplaced points, or the centre point alone, misses by >= 2e-3); the
+    planar faces are exact against the diagonal cross-product area."""
+    m = M.box_hex(1, 1, 1, 1.0, 1.0, 1.0)
+    top = np.nonzero((m["x"] > 0.5) & (m["y"] > 0.5) & (m["z"] > 0.5))[0]
+    m["z"] = m["z"].copy()
+    m["z"][top] = 1.6
+    p = P._base(m, "twist")
+    p["materials"] = [P.material(1000.0, 1000.0, [1.0])]
+    faces, _ = M.box_side_faces(m)
+    P.set_faces(p, faces, h=1.0, Ta=0.0)
+    o = Oracle(p)
+    X = np.stack([m["x"], m["y"], m["z"]], 1)
+    su, sv = np.array([-1.0, 1.0, 1.0, -1.0]), np.array([-1.0, -1.0, 1.0, 1.0])
+    x, w = np.polynomial.legendre.leggauss(40)
+    n_twisted = 0
+    for f, fa in enumerate(faces):
+        Xf = X[fa]
+        planar = abs(np.dot(np.cross(Xf[1] - Xf[0], Xf[3] - Xf[0]), Xf[2] - Xf[0])) < 1e-14
+        if planar:
+            ref = 0.5 * np.linalg.norm(np.cross(Xf[2] - Xf[0], Xf[3] - Xf[1]))
+            assert o.farea[f] == pytest.approx(ref, rel=1e-13)
+            continue
+        n_twisted += 1
+        ref = 0.0
+        for u, wu in zip(x, w):
+            for v, wv in zip(x, w):
+                xu = (su * (1 + sv * v) / 4) @ Xf
+                xv = (sv * (1 + su * u) / 4) @ Xf
+                ref += wu * wv * np.linalg.norm(np.cross(xu, xv))
+        assert abs(o.farea[f] - ref) <= 2e-4 * ref
+    assert n_twisted == 1
+
+
 # ----------------------------------------------------------------------------
 # piecewise-linear property tables (shared multipliers of D and c)
 def _table_problem(elem="hex8"):
@@ -597,6 +662,59 @@ def test_table_segment_selection_and_clamping():
         const = dict(p, materials=[dict(p["materials"][0], s0=s, c0=p["materials"][0]["c0"] * s)])
         ref = Oracle(const).run(30)
         assert np.max(np.abs(got - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("elem", ["hex8", "tet4"])
+def test_k_table_nodal_average_on_an_element_straddling_a_kink(elem):
+    """Sec. 4.2.2: the conductivity of an element is the average of the table
+    evaluated at each of its nodes from the node's own temperature.  One
+    element whose nodes sit on both sides of a sharp kink: the oracle's load
+    equals s_e K0 T with s_e = mean(np.interp(T_a)) and K0 from the
+    brute-force quadratic form, and differs from the table read at the mean
+    temperature by far more than rounding (so the pin tells the rules apart)."""
+    mat = H.aniso_material()
+    X = H.distorted_hex(4) if elem == "hex8" else H.random_tet(4)
+    ne = X.shape[0]
+    p = H.single_element(elem, X, mat)
+    Tt, f = np.array([0.0, 50.0, 60.0, 200.0]), np.array([1.0, 1.2, 4.0, 4.5])
+    p["k_table"] = (Tt, f)
+    T = np.where(np.arange(ne) % 2 == 0, 20.0, 95.0) + np.arange(ne)
+    F, _ = Oracle(p).loads(T)
+    energy = hex_energy if elem == "hex8" else tet_energy
+    K0 = np.zeros((ne, ne))
+    for a in range(ne):
+        for b in range(ne):
+            ea, eb = np.eye(ne)[a], np.eye(ne)[b]
+            K0[a, b] = (energy(X, ea + eb, H.D_of(mat)) - energy(X, ea - eb, H.D_of(mat))) / 4.0
+    s_nodal = np.mean(np.interp(T, Tt, f))
+    s_mean = np.interp(T.mean(), Tt, f)
+    ref = s_nodal * (K0 @ T)
+    assert np.max(np.abs(F - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert abs(s_nodal - s_mean) > 0.2 * s_nodal
+
+
+def test_k_table_nodal_average_adjoint_on_a_kink():
+    """The derivative of the nodal average with respect to T_a is the table's
+    slope at T_a over n_e: one distorted hexahedron straddling a kink, dL/dT0
+    of a one-step run against central differences."""
+    mat = H.aniso_material(rho=1000.0, c0=1000.0)
+    X = H.distorted_hex(5)
+    p = H.single_element("hex8", X, mat)
+    p["k_table"] = (np.array([0.0, 50.0, 60.0, 200.0]), np.array([1.0, 1.2, 4.0, 4.5]))
+    p["T0"] = np.array([20.0, 95.0, 22.0, 93.0, 30.0, 85.0, 25.0, 90.0])
+    p["dt"] = 50.0
+    w = np.linspace(0.5, 1.5, 8)
+    o = Oracle(p)
+    hist = o.run(1, history=True)
+    g = o.adjoint(hist, w.copy())
+    for k in range(8):
+        Ls = []
+        for d in (1e-4, -1e-4):
+            T0 = p["T0"].copy()
+            T0[k] += d
+            Ls.append(w @ Oracle(dict(p, T0=T0)).run(1))
+        fd = (Ls[0] - Ls[1]) / 2e-4
+        assert abs(fd - g["lam0"][k]) <= 1e-7 * max(abs(fd), 1.0)
 
 
 def test_c_table_single_hex_recursion():
