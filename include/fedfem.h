@@ -71,8 +71,9 @@ typedef struct {
 /* Material (Sec. 2, Eq. 1): density rho, heat capacity c(T) = c0 + c1 T and
  * conductivity D(T) = k * (s0 + s1 T) with k the symmetric tensor
  * [xx, yy, zz, xy, yz, xz].  Orthotropic: zero off-diagonals; isotropic: equal
- * diagonals.  D is evaluated at the element's mean nodal temperature and c at the
- * node (Sec. 4.2.2).  Materials may differ in every field (different s0, s1
+ * diagonals.  The factor of D is evaluated at each node of the element and the
+ * nodal values averaged (for this linear law: its value at the element's mean
+ * nodal temperature); c is evaluated at the node (Sec. 4.2.2).  Materials may differ in every field (different s0, s1
  * cost 2 values per element and step, and rule out resident stepping). */
 typedef struct {
   double rho, c0, c1;
@@ -90,8 +91,10 @@ typedef struct {
   /* Optional piecewise-linear multiplier tables shared by all materials
    * (temperature-dependent properties given as tables, Sec. 4.2.2): n points
    * (2..16, T strictly increasing, f > 0), linear between points and constant
-   * beyond the ends.  With a k table, D_e(T) = k_e * fk(Tbar) and every material
-   * must have s0 = 1, s1 = 0; with a c table, c_e(T) = c0_e * fc(T) and every
+   * beyond the ends.  With a k table, D_e(T) = k_e * (1/n_e) sum_a fk(T_a): the
+   * table is evaluated at each node of the element from the node's temperature
+   * and the nodal values are averaged (Sec. 4.2.2); every material must have
+   * s0 = 1, s1 = 0; with a c table, c_e(T) = c0_e * fc(T) and every
    * material must have c1 = 0.  n = 0: no table. */
   int32_t n_ktab;
   const double *ktab_T, *ktab_f;   /* host, n_ktab each */
@@ -155,7 +158,7 @@ typedef struct {
                                 signs (eta zeta, zeta xi, xi eta, xi eta zeta), b_a the mean
                                 gradients and x_a the nodes, gamma_alpha = (h_alpha -
                                 sum_i (h_alpha . x_i) b_i) / 8 vanishes on linear fields and
-                                the element adds s(Tbar) kappa sum_alpha gamma_alpha
+                                the element adds s_e kappa sum_alpha gamma_alpha
                                 gamma_alpha^T to its conductance, kappa = eps (tr D / 3) V
                                 sum_a |b_a|^2 (1.5 eps k h on a cube of side h).  Damps the
                                 four hourglass modes, keeps the patch test, and enters the

@@ -143,7 +143,8 @@ struct AdjArgs {
   double *g_logk, *g_c;       // [E] caller element order
   double *S0, *S1;            // [nrec]: sum of mu and of mu T^n
   double s0;
-  // temperature dependence: D(T) = Dk (s0 + s1 Tbar) when tdk, capacity
+  // temperature dependence: D(T) = Dk s_e when tdk (s_e the element mean of the
+  // nodal s0 + s1 T_a, or of the k table's nodal values), capacity
   // alpha + beta T when tdc, radiation sigma eps A per boundary record
   int tdk, tdc;
   double s1, Tz;

@@ -611,19 +611,48 @@ __device__ inline R table_eval(const R *tab, int n, R T, R &slope) {
   return fma((T - tab[i - 1]) / h, df, tab[n + i - 1]);
 }
 
-// Conductivity factor s(Tbar) of an element: s0 + s1 Tbar, or the shared
-// multiplier table when n > 0 (Sec. 4.2.2's temperature-dependent k)
+// pairwise sums of an element's nodal values, in the order every kernel uses
+template <typename R, int NE>
+__device__ inline R node_sum(const R *v) {
+#pragma clang fp contract(off)
+  if constexpr (NE == 8) return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  else return (v[0] + v[1]) + (v[2] + v[3]);
+}
+
+// Conductivity factor s_e of an element (Sec. 4.2.2): the property is
+// evaluated at each node of the element from that node's temperature and the
+// nodal values are averaged for the element.  For the linear law s0 + s1 T
+// that average is s0 + s1 Tbar, which is how it is evaluated; the shared
+// multiplier table (n > 0) is evaluated at every node.  elem_d also returns
+// d s_e / d T_a times n_e (the law's slope at each node).
 template <typename R>
 struct KLaw {
   R s0, s1;
   const R *tab;
   int n;
-  __device__ R operator()(R Tbar) const {
+  template <int NE>
+  __device__ R elem(const R *T) const {
+#pragma clang fp contract(off)
     if (n) {
-      R sl;
-      return table_eval(tab, n, Tbar, sl);
+      R f[NE], sl;
+#pragma unroll
+      for (int a = 0; a < NE; a++) f[a] = table_eval(tab, n, T[a], sl);
+      return node_sum<R, NE>(f) * ((R)1 / (R)NE);
     }
-    return fma(s1, Tbar, s0);
+    return fma(s1, node_sum<R, NE>(T) * ((R)1 / (R)NE), s0);
+  }
+  template <int NE>
+  __device__ R elem_d(const R *T, R ds[NE]) const {
+#pragma clang fp contract(off)
+    if (n) {
+      R f[NE];
+#pragma unroll
+      for (int a = 0; a < NE; a++) f[a] = table_eval(tab, n, T[a], ds[a]);
+      return node_sum<R, NE>(f) * ((R)1 / (R)NE);
+    }
+#pragma unroll
+    for (int a = 0; a < NE; a++) ds[a] = s1;
+    return fma(s1, node_sum<R, NE>(T) * ((R)1 / (R)NE), s0);
   }
 };
 
@@ -651,7 +680,7 @@ struct Elem<R, 8> {
     R uy = ((T3 - T0) + (T2 - T1)) + ((T7 - T4) + (T6 - T5));
     R uz = ((T4 - T0) + (T5 - T1)) + ((T6 - T2) + (T7 - T3));
     R s = kl.s0;
-    if (tdk) s = kl((((T0 + T1) + (T2 + T3)) + ((T4 + T5) + (T6 + T7))) * (R)0.125);
+    if (tdk) s = kl.template elem<8>(T);
     apply(s, h, ux, uy, uz, F);
   }
   // F from the gradient sums u and the factor s
@@ -677,10 +706,10 @@ struct Elem<R, 4> {
   __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
                               const R h[6], R F[4]) {
     #pragma clang fp contract(off)
-    R T0 = Tl[loc[0]], T1 = Tl[loc[1]], T2 = Tl[loc[2]], T3 = Tl[loc[3]];
-    R d1 = T1 - T0, d2 = T2 - T0, d3 = T3 - T0;
+    const R T[4] = {Tl[loc[0]], Tl[loc[1]], Tl[loc[2]], Tl[loc[3]]};
+    R d1 = T[1] - T[0], d2 = T[2] - T[0], d3 = T[3] - T[0];
     R s = kl.s0;
-    if (tdk) s = kl(((T0 + T1) + (T2 + T3)) * (R)0.25);
+    if (tdk) s = kl.template elem<4>(T);
     apply(s, h, d1, d2, d3, F);
   }
   __device__ static void apply(R s, const R h[6], R d1, R d2, R d3, R F[4]) {
@@ -714,7 +743,7 @@ struct ElemMean {
       gz += hb[3 * n + 2] * d;
     }
     R s = kl.s0;
-    if (tdk) s = kl((((T[0] + T[1]) + (T[2] + T[3])) + ((T[4] + T[5]) + (T[6] + T[7]))) * (R)0.125);
+    if (tdk) s = kl.template elem<8>(T);
     const R *vd = hb + 21;
     const R qx = s * (vd[0] * gx + vd[3] * gy + vd[5] * gz);
     const R qy = s * (vd[3] * gx + vd[1] * gy + vd[4] * gz);
@@ -766,7 +795,7 @@ struct ElemMeanHg {
       gz += hb[3 * n + 2] * d[n];
     }
     R s = kl.s0;
-    if (tdk) s = kl((((T[0] + T[1]) + (T[2] + T[3])) + ((T[4] + T[5]) + (T[6] + T[7]))) * (R)0.125);
+    if (tdk) s = kl.template elem<8>(T);
     const R *vd = hb + 21;
     const R qx = s * (vd[0] * gx + vd[3] * gy + vd[5] * gz);
     const R qy = s * (vd[3] * gx + vd[1] * gy + vd[4] * gz);
@@ -1477,30 +1506,22 @@ __device__ inline void adj_stage(R lam, R alpha, R beta, R tn, R tn1, R rdt, boo
   w = mu * ((tn1 - tn) * rdt * dcdc0);
 }
 
-// Element part: F = s_e K0_e mu_e plus the k(Tbar) term spread evenly over the
-// nodes, s_e, mu_e . K0_e T_e (when needed) and the sum of w over the nodes.
+// Element part: F = s_e K0_e mu_e plus the conductivity-factor term
+// d s_e / d T_a (mu_e . K0_e T_e) at every node a, s_e, mu_e . K0_e T_e (when
+// needed) and the sum of w over the nodes.
 template <typename R, int NE, int OP>
 __device__ inline void adj_elem(const uint32_t *loc, const R *h, const KLaw<R> &kle, bool tdk,
                                 bool owner, const R *Lmu, const R *LT, const R *Lw, R F[NE],
                                 R &se, R &muKT, R &gsum) {
 #pragma clang fp contract(off)
-  // s_e and ds_e/dTbar at the element mean of T^n (summed as in the forward load)
+  // s_e and n_e d s_e / d T_a from T^n, as in the forward load
   se = kle.s0;
-  R dse = (R)0;
+  R dse[NE];
   if (tdk) {
-    R sum;
-    if (NE == 8)
-      sum = ((LT[loc[0]] + LT[loc[1]]) + (LT[loc[2]] + LT[loc[3]])) +
-            ((LT[loc[4]] + LT[loc[5]]) + (LT[loc[6]] + LT[loc[7]]));
-    else
-      sum = (LT[loc[0]] + LT[loc[1]]) + (LT[loc[2]] + LT[loc[3]]);
-    const R mean = sum * ((R)1 / (R)NE);
-    if (kle.n) {
-      se = table_eval(kle.tab, kle.n, mean, dse);
-    } else {
-      se = kle(mean);
-      dse = kle.s1;
-    }
+    R Te[NE];
+#pragma unroll
+    for (int n = 0; n < NE; n++) Te[n] = LT[loc[n]];
+    se = kle.template elem_d<NE>(Te, dse);
   }
   muKT = (R)0;
   if constexpr (OP == 0) {
@@ -1521,9 +1542,10 @@ __device__ inline void adj_elem(const uint32_t *loc, const R *h, const KLaw<R> &
     if (tdk || owner) muKT = AdjDot<R, NE, OP>::dot(Lmu, LT, loc, h);
     Op<R, NE, OP>::load(Lmu, loc, KLaw<R>{se, (R)0, nullptr, 0}, false, h, F);
   }
-  const R spread = tdk ? dse * ((R)1 / (R)NE) * muKT : (R)0;
+  if (tdk) {
 #pragma unroll
-  for (int n = 0; n < NE; n++) F[n] = F[n] + spread;
+    for (int n = 0; n < NE; n++) F[n] = F[n] + dse[n] * ((R)1 / (R)NE) * muKT;
+  }
   gsum = (R)0;
   if (owner) {
 #pragma unroll
