@@ -29,6 +29,7 @@
 #ifndef FEDFEM_H
 #define FEDFEM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -164,6 +165,19 @@ typedef struct {
                                 four hourglass modes, keeps the patch test, and enters the
                                 stability bound and the adjoint; 40 values per element.
                                 Needs hex_gradient = 1 (FED_E_ARG otherwise). */
+  /* Device memory.  Every device buffer of the context (the pre-computed arrays of
+   * Sec. 3.5 (i), the state, checkpoints and adjoint work arrays, and the
+   * temporaries of fed_create) comes from dev_alloc(bytes, alloc_ctx), which
+   * returns a device pointer of the current device or NULL when it cannot, and
+   * goes back through dev_free(ptr, alloc_ctx) once the library no longer uses
+   * it: at fed_destroy, or when a call replaces a buffer (the library
+   * synchronises the device before giving a buffer back, as hipFree would).
+   * Both are called on the thread that calls the library.  NULL for both:
+   * hipMalloc and hipFree.  Giving one without the other is FED_E_ARG; a NULL
+   * from dev_alloc makes the call fail with FED_E_HIP (out of memory). */
+  void *(*dev_alloc)(size_t bytes, void *alloc_ctx);
+  void (*dev_free)(void *ptr, void *alloc_ctx);
+  void *alloc_ctx;
 } fed_options;
 
 typedef struct fed_ctx fed_ctx;
@@ -183,6 +197,8 @@ typedef struct {
   int32_t resident_adjoint;            /* 1 if fed_backward runs each checkpoint segment's
                                           adjoint steps in one resident launch */
   int32_t reserved_;
+  int64_t device_bytes;                /* device memory the context holds now (from the
+                                          dev_alloc hook or hipMalloc) */
 } fed_info;
 
 /*
@@ -199,8 +215,11 @@ typedef struct {
 int fed_create(const fed_mesh *mesh, const fed_materials *mats, const fed_bcs *bcs,
                const fed_options *opt, void *stream, fed_ctx **out);
 
-/* Stability bound and the time step in use, per instance (n = number of entries
- * the arrays can hold; the count is fed_info.n_instances). */
+/* Stability bound of the explicit scheme (Sec. 3.4, Eq. 29: dt_crit = 2 /
+ * lambda_max, bounded by the element eigenvalues and the boundary terms over
+ * [T_lo, T_hi]) and the time step in use, per instance (n = number of entries
+ * the arrays can hold; the count is fed_info.n_instances).  Errors: FED_E_ARG
+ * (null ctx, n too small). */
 int fed_dt(const fed_ctx *ctx, double *dt_crit, double *dt_used, int64_t n);
 
 int fed_info_get(const fed_ctx *ctx, fed_info *out);

@@ -48,13 +48,20 @@ class fed_bcs(C.Structure):
                 ("n_pt", C.c_int64), ("pt_nodes", _i32), ("pt_W", _d), ("Tz", C.c_double)]
 
 
+# device-memory hooks of fed_options: dev_alloc(bytes, alloc_ctx) -> pointer or
+# NULL, dev_free(pointer, alloc_ctx)
+DEV_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class fed_options(C.Structure):
     _fields_ = [("prec", C.c_int32), ("dt", C.c_double), ("safety", C.c_double),
                 ("T_lo", C.c_double), ("T_hi", C.c_double), ("allow_unstable", C.c_int32),
                 ("node_instance", _i32), ("tile_nodes", C.c_int32),
                 ("block_threads", C.c_int32), ("fuse_steps", C.c_int32),
                 ("resident", C.c_int32), ("hex_gradient", C.c_int32),
-                ("hourglass", C.c_double)]
+                ("hourglass", C.c_double),
+                ("dev_alloc", DEV_ALLOC), ("dev_free", DEV_FREE), ("alloc_ctx", C.c_void_p)]
 
 
 class fed_info(C.Structure):
@@ -66,7 +73,8 @@ class fed_info(C.Structure):
                 ("algorithmic_bytes_per_launch", C.c_double),
                 ("moved_bytes_per_launch", C.c_double),
                 ("exchange_bytes_per_step", C.c_double),
-                ("resident_adjoint", C.c_int32), ("reserved_", C.c_int32)]
+                ("resident_adjoint", C.c_int32), ("reserved_", C.c_int32),
+                ("device_bytes", C.c_int64)]
 
 
 # name -> (restype, argtypes) of every symbol the header declares

@@ -37,26 +37,53 @@ int fail(int code, const char *fmt, ...) {
                   __FILE__, __LINE__);                                                \
   } while (0)
 
-// device allocations of a context, freed together
+// device allocations of a context, freed together: from the caller's
+// allocator hooks when given (fed_options.dev_alloc / dev_free), else
+// hipMalloc / hipFree
 struct DevPool {
+  void *(*af)(size_t, void *) = nullptr;
+  void (*ff)(void *, void *) = nullptr;
+  void *actx = nullptr;
   std::vector<void *> ptrs;
+  std::vector<size_t> sizes;
+  size_t total = 0;  // bytes held
   hipError_t alloc(void **p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) return hipSuccess;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e == hipSuccess) ptrs.push_back(*p);
-    return e;
+    if (af) {
+      *p = af(bytes, actx);
+      if (!*p) return hipErrorOutOfMemory;
+    } else {
+      hipError_t e = hipMalloc(p, bytes);
+      if (e != hipSuccess) return e;
+    }
+    ptrs.push_back(*p);
+    sizes.push_back(bytes);
+    total += bytes;
+    return hipSuccess;
   }
+  void give_back(void *p) {
+    if (ff) ff(p, actx);
+    else (void)hipFree(p);
+  }
+  // gives one buffer back; with the caller's hooks the device is synchronised
+  // first (hipFree does that itself), so no enqueued work still uses it
   void release(void *p) {
     auto it = std::find(ptrs.begin(), ptrs.end(), p);
     if (it != ptrs.end()) {
-      (void)hipFree(p);
+      if (af) (void)hipDeviceSynchronize();
+      give_back(p);
+      const size_t i = (size_t)(it - ptrs.begin());
+      total -= sizes[i];
+      sizes.erase(sizes.begin() + i);
       ptrs.erase(it);
     }
   }
   void free_all() {
-    for (void *p : ptrs) (void)hipFree(p);
+    for (void *p : ptrs) give_back(p);
     ptrs.clear();
+    sizes.clear();
+    total = 0;
   }
 };
 
@@ -347,6 +374,8 @@ int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, cons
                            "(fuse_steps <= 1, resident = 0)");
   if (!(o->hourglass >= 0) || !std::isfinite(o->hourglass))
     return fail(FED_E_ARG, "hourglass must be a finite number >= 0");
+  if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr))
+    return fail(FED_E_ARG, "dev_alloc and dev_free must be given together");
   if (o->hourglass > 0 && !(m->elem == FED_HEX8 && o->hex_gradient == 1))
     return fail(FED_E_ARG, "hourglass control needs hexahedra with hex_gradient = 1");
   return FED_OK;
@@ -461,6 +490,9 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   std::unique_ptr<fed_ctx> c(new (std::nothrow) fed_ctx());
   if (!c) return fail(FED_E_NOMEM, "host allocation failed");
   c->prec = o->prec;
+  c->pool.af = o->dev_alloc;
+  c->pool.ff = o->dev_free;
+  c->pool.actx = o->alloc_ctx;
   c->ne = ne;
   c->rb = o->prec == FED_FP64 ? 8 : 4;
   c->N = N;
@@ -632,6 +664,9 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
 
   // ---- device pre-computation in FP64 (Sec. 3.5 (i)) ------------------------
   DevPool tmp;
+  tmp.af = o->dev_alloc;
+  tmp.ff = o->dev_free;
+  tmp.actx = o->alloc_ctx;
   struct TmpGuard {
     DevPool &p;
     ~TmpGuard() { p.free_all(); }
@@ -919,6 +954,7 @@ int fed_dt(const fed_ctx *c, double *dt_crit, double *dt_used, int64_t n) {
 int fed_info_get(const fed_ctx *c, fed_info *out) {
   if (!c || !out) return fail(FED_E_ARG, "null argument");
   *out = c->info;
+  out->device_bytes = (int64_t)c->pool.total;
   return FED_OK;
 }
 
@@ -1137,15 +1173,14 @@ int fed_get_state(fed_ctx *c, void *hi, void *lo, int64_t *step, void *stream) {
   if (!c->have_T) return fail(FED_E_STATE, "no temperature set");
   hipStream_t s = (hipStream_t)stream;
   const int rb = c->rb;
-  void *tmp;
-  HIPCHK(hipMallocAsync(&tmp, (size_t)rb * c->N, s));
+  // staged in caller order through the FP64 readout buffer (8 bytes a node)
+  void *tmp = c->d_Tuser;
   HIPCHK(fed::launch_permute(rb, c->N, c->d_perm, c->d_T[c->cur], tmp, 0, s));
   HIPCHK(hipMemcpyAsync(hi, tmp, (size_t)rb * c->N, hipMemcpyDeviceToHost, s));
   if (lo && c->prec == FED_FP32C) {
     HIPCHK(fed::launch_permute(4, c->N, c->d_perm, c->d_lo[c->cur], tmp, 0, s));
     HIPCHK(hipMemcpyAsync(lo, tmp, sizeof(float) * c->N, hipMemcpyDeviceToHost, s));
   }
-  HIPCHK(hipFreeAsync(tmp, s));
   HIPCHK(hipStreamSynchronize(s));
   if (step) *step = c->steps;
   return FED_OK;
@@ -1156,8 +1191,7 @@ int fed_set_state(fed_ctx *c, const void *hi, const void *lo, int64_t step, void
   if (c->prec == FED_FP32C && !lo) return fail(FED_E_ARG, "FP32C state needs lo");
   hipStream_t s = (hipStream_t)stream;
   const int rb = c->rb;
-  void *tmp;
-  HIPCHK(hipMallocAsync(&tmp, (size_t)rb * c->N, s));
+  void *tmp = c->d_Tuser;  // caller-order staging, as in fed_get_state
   c->cur = 0;
   HIPCHK(hipMemcpyAsync(tmp, hi, (size_t)rb * c->N, hipMemcpyHostToDevice, s));
   HIPCHK(fed::launch_permute(rb, c->N, c->d_perm, tmp, c->d_T[0], 1, s));
@@ -1165,7 +1199,6 @@ int fed_set_state(fed_ctx *c, const void *hi, const void *lo, int64_t step, void
     HIPCHK(hipMemcpyAsync(tmp, lo, sizeof(float) * c->N, hipMemcpyHostToDevice, s));
     HIPCHK(fed::launch_permute(4, c->N, c->d_perm, tmp, c->d_lo[0], 1, s));
   }
-  HIPCHK(hipFreeAsync(tmp, s));
   HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
   if (c->resident) HIPCHK(hipMemsetAsync(c->d_rerr, 0, sizeof(int), s));
   HIPCHK(hipStreamSynchronize(s));

@@ -8,13 +8,48 @@ device memory and the current HIP stream.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 
 from . import _lib as L
 
 PRECISIONS = {"fp32c": L.FED_FP32C, "fp64": L.FED_FP64, "fp32": L.FED_FP32}
+
+# contexts still open; closed before the interpreter tears torch and the HIP
+# runtime down, so no context outlives the allocator that owns its memory
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for s in list(_LIVE):
+        try:
+            s.close()
+        except Exception:
+            pass
+
+
+def torch_allocator(stream):
+    """(dev_alloc, dev_free) hooks that take a context's device memory from
+    torch's caching allocator on `stream` (a raw hipStream_t or None for the
+    current stream), so torch owns and accounts for it."""
+    import torch
+    dev = torch.cuda.current_device()
+    st = None if stream is None else int(stream.value or 0)
+
+    def alloc(nbytes, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+        except RuntimeError:
+            return None  # the library reports FED_E_HIP (out of memory)
+
+    def free(ptr, _ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return L.DEV_ALLOC(alloc), L.DEV_FREE(free)
 
 
 def _ptr(a, t=C.c_double):
@@ -34,8 +69,12 @@ def current_stream():
 
 class Simulation:
     def __init__(self, prob, prec="fp32c", tile_nodes=0, block_threads=0, fuse_steps=0,
-                 allow_unstable=False, stream=None, resident=False):
+                 allow_unstable=False, stream=None, resident=False, allocator="torch"):
+        """allocator: "torch" takes the device memory from torch's caching
+        allocator (the default when torch sees a GPU), "hip" lets the library
+        call hipMalloc."""
         lib = L.lib()
+        self._ctx = None
         self.prec = prec
         self.prob = prob
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
@@ -95,10 +134,25 @@ class Simulation:
                             1 if prob.get("hex_gradient", "centre") == "mean" else 0,
                             float(prob.get("hourglass", 0.0) or 0.0))
         self.stream = current_stream() if stream is None else stream
+        if allocator not in ("torch", "hip"):
+            raise ValueError("allocator must be 'torch' or 'hip'")
+        self._hooks = None
+        if allocator == "torch":
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    self._hooks = torch_allocator(self.stream)
+            except ImportError:
+                pass
+        if self._hooks is not None:
+            # the callbacks live as long as the context (self._hooks)
+            opt.dev_alloc, opt.dev_free = self._hooks
+        self.allocator = "torch" if self._hooks is not None else "hip"
         ctx = C.c_void_p()
         L.check(lib.fed_create(C.byref(mesh), C.byref(mats), C.byref(bcs), C.byref(opt),
                                self.stream, C.byref(ctx)))
         self._ctx = ctx
+        _LIVE.add(self)
         info = L.fed_info()
         L.check(lib.fed_info_get(ctx, C.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in L.fed_info._fields_}
@@ -144,6 +198,13 @@ class Simulation:
         L.check(L.lib().fed_get_temperature(self._c(), T.ctypes.data_as(C.c_void_p), 0,
                                             self.stream))
         return T
+
+    @property
+    def device_bytes(self):
+        """Device memory the context holds now (bytes)."""
+        info = L.fed_info()
+        L.check(L.lib().fed_info_get(self._c(), C.byref(info)))
+        return info.device_bytes
 
     @property
     def steps_taken(self):
