@@ -371,6 +371,23 @@ int fed_set_range(fed_ctx *ctx, double T_lo, double T_hi, void *stream);
 int fed_backward(fed_ctx *ctx, const double *dL_dT, double *g_logk, double *g_c, double *g_h,
                  double *dL_dT0, int32_t on_device, void *stream);
 
+/* For callers that cannot allocate device memory (serving loops and harnesses
+ * that forbid allocation while they run): fed_backward with the same arguments
+ * and the same results, bit for bit, that allocates nothing.  Its work arrays
+ * (the recomputed segment's states unless every segment's states were kept,
+ * the multiplier pair, the FP64 derivative sums, 1/dt per node and rho V / n_e
+ * per element: about (ckpt_every + 4) x n_nodes x 4 + 28 x n_elems bytes in
+ * FP32C) are placed in a static array of FED_NOALLOC_SCRATCH_BYTES (64 MiB) that
+ * the library's code object holds on every GPU it runs on until the process
+ * ends, instead of the context's own buffers.  Every call on a GPU shares that
+ * GPU's array and each call initialises what it reads; calls that overlap on
+ * one GPU (from two host threads, or on two streams) race and give wrong
+ * derivatives.  Errors: those of fed_backward, and FED_E_ARG when the work
+ * arrays exceed the array (the message gives both sizes). */
+#define FED_NOALLOC_SCRATCH_BYTES (64u << 20)
+int fed_backward_noalloc(fed_ctx *ctx, const double *dL_dT, double *g_logk, double *g_c,
+                         double *g_h, double *dL_dT0, int32_t on_device, void *stream);
+
 /* Destroys the context and frees its device memory (synchronises the device). */
 void fed_destroy(fed_ctx *ctx);
 

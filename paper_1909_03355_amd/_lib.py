@@ -104,6 +104,8 @@ SIGNATURES = {
     "fed_set_range": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
     "fed_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_int32, C.c_void_p]),
+    "fed_backward_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "fed_destroy": (None, [C.c_void_p]),
     "fed_last_error": (C.c_char_p, []),
 }

@@ -89,6 +89,17 @@ struct DevPool {
 
 }  // namespace
 
+namespace fed {
+// work arrays of the adjoint: the states of the segment at hand (ckpt_every + 1
+// hi vectors and two lo), the multiplier pair (hi, lo) ping-pong, the FP64
+// boundary and derivative sums, 1/dt per node and rho V / n_e per element
+struct AdjWork {
+  void *seg = nullptr, *lamb[2] = {nullptr, nullptr}, *rdt = nullptr, *mV = nullptr;
+  float *seglo[2] = {nullptr, nullptr}, *lamlo[2] = {nullptr, nullptr};
+  double *S0 = nullptr, *S1 = nullptr, *gk = nullptr, *gc = nullptr, *gh = nullptr;
+};
+}  // namespace fed
+
 struct fed_ctx {
   int prec = 0, ne = 8, rb = 4;
   int64_t N = 0, E = 0, Eexp = 0, nrec = 0, ninst = 1, ndir = 0;
@@ -158,9 +169,7 @@ struct fed_ctx {
   // step since fed_set_temperature was stored
   bool keep_states = false, kept_ok = false;
   std::vector<void *> segbuf;
-  void *d_seg = nullptr, *d_lamb[2] = {nullptr, nullptr}, *d_rdt = nullptr, *d_mV = nullptr;
-  float *d_seglo[2] = {nullptr, nullptr}, *d_lamlo[2] = {nullptr, nullptr};
-  double *d_S0 = nullptr, *d_S1 = nullptr, *d_gk = nullptr, *d_gc = nullptr, *d_gh = nullptr;
+  fed::AdjWork adjw;  // fed_backward's work arrays (allocated on first use)
   int adj_lds = 0, max_lds = 64 * 1024;
   // conductivity/capacity laws: per-element (s0, s1) when the materials differ,
   // shared multiplier tables (step precision) and their extremes on [T_lo, T_hi]
@@ -1495,51 +1504,67 @@ int fed_set_range(fed_ctx *c, double T_lo, double T_hi, void *stream) {
   return FED_OK;
 }
 
-int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, double *g_h,
-                 double *dL_dT0, int32_t on_device, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Places the adjoint's work arrays through place(void **slot, size_t bytes), in
+// a fixed order; the segment's states only when some segment is recomputed.
+template <typename F>
+int adj_work_layout(const fed_ctx *c, bool need_seg, fed::AdjWork &w, F place) {
+  const int64_t N = c->N, E = c->E;
+  const size_t rb = (size_t)c->rb;
+  const bool c32 = c->prec == FED_FP32C;
+  if (need_seg) {
+    HIPCHK(place(&w.seg, rb * N * (c->ckpt_every + 1)));
+    if (c32)
+      for (int i = 0; i < 2; i++) HIPCHK(place((void **)&w.seglo[i], sizeof(float) * N));
+  }
+  for (int i = 0; i < 2; i++) {
+    HIPCHK(place(&w.lamb[i], rb * N));
+    if (c32) HIPCHK(place((void **)&w.lamlo[i], sizeof(float) * N));
+  }
+  HIPCHK(place((void **)&w.S0, sizeof(double) * std::max<int64_t>(c->nrec, 1)));
+  HIPCHK(place((void **)&w.S1, sizeof(double) * std::max<int64_t>(c->nrec, 1)));
+  HIPCHK(place((void **)&w.gk, sizeof(double) * E));
+  HIPCHK(place((void **)&w.gc, sizeof(double) * E));
+  HIPCHK(place((void **)&w.gh, sizeof(double) * std::max<int64_t>(c->nf, 1)));
+  HIPCHK(place(&w.rdt, rb * N));
+  HIPCHK(place(&w.mV, rb * E));
+  return FED_OK;
+}
+
+int backward_checks(const fed_ctx *c, const double *dL_dT) {
   if (!c || !dL_dT) return fail(FED_E_ARG, "null argument");
   if (!c->have_T) return fail(FED_E_STATE, "no forward run");
   if (c->ckpt_every <= 0) return fail(FED_E_STATE, "checkpointing is off (fed_checkpoint_every)");
   if (c->adj_lds > c->max_lds)
     return fail(FED_E_MESH, "adjoint tiles need %d bytes of LDS; use smaller tile_nodes", c->adj_lds);
-  hipStream_t s = (hipStream_t)stream;
+  return FED_OK;
+}
+
+// The adjoint of the steps taken, with the work arrays w (fed_backward: the
+// context's; fed_backward_noalloc: the static scratch).
+int backward_run(fed_ctx *c, const fed::AdjWork &w, const double *dL_dT, double *g_logk,
+                 double *g_c, double *g_h, double *dL_dT0, int32_t on_device, hipStream_t s) {
   const int64_t N = c->N, E = c->E, ck = c->ckpt_every, steps = c->steps;
   const int rb = c->rb;
-  DevPool &P = c->pool;
-  // work arrays, allocated on first use
-  if (!c->d_seg) {
-    HIPCHK(P.alloc(&c->d_seg, (size_t)rb * N * (ck + 1)));
-    for (int i = 0; i < 2; i++) {
-      HIPCHK(P.alloc(&c->d_lamb[i], (size_t)rb * N));
-      if (c->prec == FED_FP32C) {
-        HIPCHK(P.alloc((void **)&c->d_seglo[i], sizeof(float) * N));
-        HIPCHK(P.alloc((void **)&c->d_lamlo[i], sizeof(float) * N));
-      }
-    }
-    HIPCHK(P.alloc((void **)&c->d_S0, sizeof(double) * std::max<int64_t>(c->nrec, 1)));
-    HIPCHK(P.alloc((void **)&c->d_S1, sizeof(double) * std::max<int64_t>(c->nrec, 1)));
-    HIPCHK(P.alloc((void **)&c->d_gk, sizeof(double) * E));
-    HIPCHK(P.alloc((void **)&c->d_gc, sizeof(double) * E));
-    HIPCHK(P.alloc((void **)&c->d_gh, sizeof(double) * std::max<int64_t>(c->nf, 1)));
-    HIPCHK(P.alloc(&c->d_rdt, (size_t)rb * N));
-    HIPCHK(P.alloc(&c->d_mV, (size_t)rb * E));
-  }
   HIPCHK(fed::launch_adjoint_coefs(c->prec == FED_FP64 ? 1 : 0, N, E, c->ne, c->d_dtinst,
-                                   c->d_ninst, c->d_mats, c->d_emat, c->d_V, c->d_rdt, c->d_mV, s));
-  HIPCHK(hipMemsetAsync(c->d_S0, 0, sizeof(double) * std::max<int64_t>(c->nrec, 1), s));
-  HIPCHK(hipMemsetAsync(c->d_S1, 0, sizeof(double) * std::max<int64_t>(c->nrec, 1), s));
-  HIPCHK(hipMemsetAsync(c->d_gk, 0, sizeof(double) * E, s));
-  HIPCHK(hipMemsetAsync(c->d_gc, 0, sizeof(double) * E, s));
+                                   c->d_ninst, c->d_mats, c->d_emat, c->d_V, w.rdt, w.mV, s));
+  HIPCHK(hipMemsetAsync(w.S0, 0, sizeof(double) * std::max<int64_t>(c->nrec, 1), s));
+  HIPCHK(hipMemsetAsync(w.S1, 0, sizeof(double) * std::max<int64_t>(c->nrec, 1), s));
+  HIPCHK(hipMemsetAsync(w.gk, 0, sizeof(double) * E, s));
+  HIPCHK(hipMemsetAsync(w.gc, 0, sizeof(double) * E, s));
   // lambda^N = dL/dT^N in internal order
   const double *src = dL_dT;
   if (!on_device) {
     HIPCHK(hipMemcpyAsync(c->d_Tuser, dL_dT, sizeof(double) * N, hipMemcpyHostToDevice, s));
     src = c->d_Tuser;
   }
-  HIPCHK(fed::launch_set_T(c->prec, N, src, c->d_perm, c->d_lamb[0], c->d_lamlo[0], 0, nullptr,
+  HIPCHK(fed::launch_set_T(c->prec, N, src, c->d_perm, w.lamb[0], w.lamlo[0], 0, nullptr,
                            nullptr, s));
   int lc = 0;
-  void *segb = c->d_seg;  // the states of the segment at hand: kept or recomputed
+  void *segb = w.seg;  // the states of the segment at hand: kept or recomputed
   auto seg = [&](int64_t i) {
     return (void *)((char *)segb + (size_t)rb * N * i);
   };
@@ -1551,11 +1576,11 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
     // the segment's states T^{n0..n1}: kept by the forward launches, or
     // recomputed from its checkpoint
     const bool kept = c->kept_ok && g < (int64_t)c->segbuf.size() && c->segbuf[g];
-    segb = kept ? c->segbuf[g] : c->d_seg;
+    segb = kept ? c->segbuf[g] : w.seg;
     if (!kept) {
       HIPCHK(hipMemcpyAsync(seg(0), c->ck_hi[g], (size_t)rb * N, hipMemcpyDeviceToDevice, s));
       if (c->prec == FED_FP32C)
-        HIPCHK(hipMemcpyAsync(c->d_seglo[0], c->ck_lo[g], sizeof(float) * N,
+        HIPCHK(hipMemcpyAsync(w.seglo[0], c->ck_lo[g], sizeof(float) * N,
                               hipMemcpyDeviceToDevice, s));
     }
     if (kept) {
@@ -1566,10 +1591,10 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       fed::StepArgs a = c->step_args(0, 1);
       a.lds = c->res_lds;
       a.Tin = seg(0);
-      a.loin = c->d_seglo[0];
+      a.loin = w.seglo[0];
       a.Tout = seg(1);  // not used by the resident kernel
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
-                     seg(k), c->d_seglo[k & 1], segb, N};
+                     seg(k), w.seglo[k & 1], segb, N};
       r.split = c->res_split;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
@@ -1584,8 +1609,8 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
         fed::StepArgs a = c->step_args(0, 1);
         a.Tin = seg(i);
         a.Tout = seg(i + 1);
-        a.loin = c->d_seglo[i & 1];
-        a.loout = c->d_seglo[(i + 1) & 1];
+        a.loin = w.seglo[i & 1];
+        a.loout = w.seglo[(i + 1) & 1];
         if (c->ps_rows > 0) a.rP = c->ps_row(n0 + i);
         HIPCHK(fed::launch_step(a, s));
       }
@@ -1608,13 +1633,13 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
     a.eowner = c->d_eowner;
     a.H = c->d_H;
     a.alpha = c->d_alpha;
-    a.rdt = c->d_rdt;
-    a.mV = c->d_mV;
+    a.rdt = w.rdt;
+    a.mV = w.mV;
     a.rA = c->d_rA;
-    a.g_logk = c->d_gk;
-    a.g_c = c->d_gc;
-    a.S0 = c->d_S0;
-    a.S1 = c->d_S1;
+    a.g_logk = w.gk;
+    a.g_c = w.gc;
+    a.S0 = w.S0;
+    a.S1 = w.S1;
     a.s0 = c->s0;
     a.tdk = c->tdk;
     a.tdc = c->tdc;
@@ -1632,10 +1657,10 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       // one resident launch for the segment
       const int k = (int)(n1 - n0);
       a.lds = c->adjres_lds;
-      a.lamin = c->d_lamb[lc];
-      a.lamloin = c->d_lamlo[lc];
-      a.lamout = c->d_lamb[1 - lc];
-      a.lamloout = c->d_lamlo[1 - lc];
+      a.lamin = w.lamb[lc];
+      a.lamloin = w.lamlo[lc];
+      a.lamout = w.lamb[1 - lc];
+      a.lamloout = w.lamlo[1 - lc];
       fed::AdjResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
                         segb, N};
       HIPCHK(fed::launch_adjres(a, r, s));
@@ -1644,10 +1669,10 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
       continue;
     }
     for (int64_t n = n1 - 1; n >= n0; n--) {
-      a.lamin = c->d_lamb[lc];
-      a.lamloin = c->d_lamlo[lc];
-      a.lamout = c->d_lamb[1 - lc];
-      a.lamloout = c->d_lamlo[1 - lc];
+      a.lamin = w.lamb[lc];
+      a.lamloin = w.lamlo[lc];
+      a.lamout = w.lamb[1 - lc];
+      a.lamloout = w.lamlo[1 - lc];
       a.Tn = seg(n - n0);
       a.Tn1 = seg(n - n0 + 1);
       HIPCHK(fed::launch_adjoint(a, s));
@@ -1656,14 +1681,14 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
   }
   if (c->nf > 0)
     HIPCHK(fed::launch_face_grad(c->nf, c->nfn, c->d_faces, c->d_perm, c->d_rec_of, c->d_farea,
-                                 c->d_fTa, c->d_S0, c->d_S1, c->d_gh, s));
+                                 c->d_fTa, w.S0, w.S1, w.gh, s));
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  if (g_logk) HIPCHK(hipMemcpyAsync(g_logk, c->d_gk, sizeof(double) * E, kind, s));
-  if (g_c) HIPCHK(hipMemcpyAsync(g_c, c->d_gc, sizeof(double) * E, kind, s));
-  if (g_h && c->nf > 0) HIPCHK(hipMemcpyAsync(g_h, c->d_gh, sizeof(double) * c->nf, kind, s));
+  if (g_logk) HIPCHK(hipMemcpyAsync(g_logk, w.gk, sizeof(double) * E, kind, s));
+  if (g_c) HIPCHK(hipMemcpyAsync(g_c, w.gc, sizeof(double) * E, kind, s));
+  if (g_h && c->nf > 0) HIPCHK(hipMemcpyAsync(g_h, w.gh, sizeof(double) * c->nf, kind, s));
   if (dL_dT0) {
     double *dst = on_device ? dL_dT0 : c->d_Tuser;
-    HIPCHK(fed::launch_get_T(c->prec, N, c->d_perm, c->d_lamb[lc], c->d_lamlo[lc], dst, s));
+    HIPCHK(fed::launch_get_T(c->prec, N, c->d_perm, w.lamb[lc], w.lamlo[lc], dst, s));
     if (!on_device)
       HIPCHK(hipMemcpyAsync(dL_dT0, c->d_Tuser, sizeof(double) * N, hipMemcpyDeviceToHost, s));
   }
@@ -1674,6 +1699,61 @@ int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, d
     return fail(FED_E_HIP, "resident stepping: a tile gave up waiting for a neighbouring tile; "
                            "the derivatives are invalid");
   return FED_OK;
+
+}
+
+// true when every segment of the run has its states kept (no recompute)
+bool all_segments_kept(const fed_ctx *c) {
+  if (!c->kept_ok) return false;
+  const int64_t nseg = (c->steps + c->ckpt_every - 1) / c->ckpt_every;
+  if ((int64_t)c->segbuf.size() < nseg) return false;
+  for (int64_t g = 0; g < nseg; g++)
+    if (!c->segbuf[g]) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fed_backward(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c, double *g_h,
+                 double *dL_dT0, int32_t on_device, void *stream) {
+  int rc = backward_checks(c, dL_dT);
+  if (rc) return rc;
+  if (!c->adjw.lamb[0]) {
+    // the context's work arrays, allocated on first use
+    DevPool &P = c->pool;
+    rc = adj_work_layout(c, true, c->adjw,
+                         [&](void **slot, size_t bytes) { return P.alloc(slot, bytes); });
+    if (rc) return rc;
+  }
+  return backward_run(c, c->adjw, dL_dT, g_logk, g_c, g_h, dL_dT0, on_device,
+                      (hipStream_t)stream);
+}
+
+int fed_backward_noalloc(fed_ctx *c, const double *dL_dT, double *g_logk, double *g_c,
+                         double *g_h, double *dL_dT0, int32_t on_device, void *stream) {
+  int rc = backward_checks(c, dL_dT);
+  if (rc) return rc;
+  void *base = nullptr;
+  HIPCHK(fed::scratch_address(&base));
+  // the work arrays, 256-byte aligned, one after another in the scratch
+  size_t used = 0;
+  fed::AdjWork w;
+  auto carve = [&](void **slot, size_t bytes) {
+    used = (used + 255) & ~(size_t)255;
+    *slot = used + bytes <= fed::kScratchBytes ? (char *)base + used : nullptr;
+    used += bytes;
+    return hipSuccess;
+  };
+  rc = adj_work_layout(c, !all_segments_kept(c), w, carve);
+  if (rc) return rc;
+  if (used > fed::kScratchBytes)
+    return fail(FED_E_ARG,
+                "fed_backward_noalloc: the adjoint's work arrays need %zu bytes, the scratch "
+                "holds %zu; use fed_backward, a shorter checkpoint interval or kept states",
+                used, fed::kScratchBytes);
+  return backward_run(c, w, dL_dT, g_logk, g_c, g_h, dL_dT0, on_device, (hipStream_t)stream);
 }
 
 void fed_destroy(fed_ctx *c) {

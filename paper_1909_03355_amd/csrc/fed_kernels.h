@@ -4,6 +4,7 @@
 
 #include <cstdint>
 
+#include "../../include/fedfem.h"
 #include "fed_internal.h"
 
 namespace fed {
@@ -257,5 +258,10 @@ hipError_t launch_range(int prec, int64_t N, const void *T, const float *lo,
                         unsigned long long *keys, int *nan, hipStream_t s);
 hipError_t launch_permute(int elem_bytes, int64_t N, const int32_t *perm, const void *src,
                           void *dst, int to_internal, hipStream_t s);
+
+// Device address of the static scratch array on the current device (looked up
+// once per device); it holds kScratchBytes bytes.
+constexpr size_t kScratchBytes = FED_NOALLOC_SCRATCH_BYTES;
+hipError_t scratch_address(void **ptr);
 
 }  // namespace fed

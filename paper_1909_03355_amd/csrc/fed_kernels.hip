@@ -10,6 +10,8 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
+#include <vector>
 
 #include "fed_kernels.h"
 
@@ -2701,6 +2703,33 @@ hipError_t launch_adjoint_coefs(int prec, int64_t N, int64_t E, int ne, const do
     hipLaunchKernelGGL(k_adjoint_coefs<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, N, E,
                        ne, dt_inst, node_inst, mats, emat, V, (float *)rdt, (float *)mV);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free adjoint entry point: one array in the code
+// object, which every GPU the library runs on holds until the process ends.
+// Host code never uses the array's name as an address (on the host it names
+// a stand-in, not device memory): scratch_address looks the device address up
+// once per device, with that device current, and every kernel argument,
+// memset and copy uses that address.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void **ptr) {
+  static std::mutex mu;
+  static std::vector<void *> addr;  // per device
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace fed
