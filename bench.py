@@ -84,7 +84,22 @@ WORKLOADS = {
                             "nonlinear_hex64 with a 2 W point source moved one node along the "
                             "top face every step (a point-load schedule)",
                             dict(resident=True), "moving"),
+    # the paper's timing study (Sec. 4.6) on a synthetic cube of its size: the
+    # oracle runs all the steps on one thread and on all threads, beside the
+    # paper's single-thread times (context, not a target)
+    "paper_standin_ti": ("paper_standin", 2000, 2000,
+                         "0.1 m cube, 19^3 x 6 Kuhn tet4 (the paper's timing-study size), k=200, "
+                         "rho=1000, c=2000, dt=0.005 s, back face 37 C, 0.2 W point loads",
+                         dict(resident=True), "standin"),
+    "paper_standin_td": ("paper_standin", 2000, 2000,
+                         "paper_standin_ti with k(T), c(T) rising 6 and 20 per C (Sec. 4.2.2)",
+                         dict(resident=True), "standin"),
 }
+# the paper's single-thread C++ times of the timing study (Sec. 4.6), quoted as
+# context: 40,021 tetrahedra / 7,872 nodes on an Intel i7-6700 at 3.40 GHz
+PAPER_STANDIN = {"paper_standin_ti": 2.376, "paper_standin_td": 4.656}
+# a launch shape chosen by the project's autotuner (cached per problem class)
+AUTOTUNED = {"batched_hex256"}
 
 
 def parse():
@@ -104,8 +119,8 @@ def parse():
                     help="steps of the CPU oracle sample (timed baseline and error reference)")
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-keep-states", action="store_true",
-                    help="adjoint workloads: recompute the checkpoint segments in the backward pass")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="workloads timed with the autotuner's shape: use the fixed one")
     return ap.parse_args()
 
 
@@ -123,14 +138,14 @@ def timed_steps(sim, steps, warmup, graph_steps):
 
 
 def timed_adjoint(sim, steps, prob, keep=True):
-    """Forward with checkpoints plus the adjoint of an MSE sensor loss; a
-    resident context keeps every forward state (unless keep is off), so the
-    backward pass does not recompute the checkpoint segments."""
+    """Forward with checkpoints plus the adjoint of an MSE sensor loss; with
+    keep on, a resident context keeps every forward state, so the backward
+    pass does not recompute the checkpoint segments."""
     import torch
     sens = prob["meta"]["sensors"]
     sim.checkpoint_every(prob["meta"]["ckpt_every"])
-    if keep and sim.info["resident"]:
-        sim.keep_states()
+    if sim.info["resident"]:
+        sim.keep_states(keep)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.set_temperature()
@@ -172,6 +187,59 @@ def timed_moving_host(sim, steps, prob, warmup):
     return start.elapsed_time(stop) / 1e3
 
 
+def cpu_info():
+    """Model name, logical CPUs and physical cores of the host (/proc/cpuinfo)."""
+    model, cores, logical = None, set(), 0
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "processor":
+                    logical += 1
+                elif k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": logical or os.cpu_count(),
+            "physical_cores": len(cores) or None}
+
+
+def golden_error(name, sim_factory, steps):
+    """err_max of a fresh run of the workload's full step count against the
+    oracle's stored temperatures at sampled nodes (tests/golden), or None."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    try:
+        import make_golden as G
+    finally:
+        sys.path.pop(0)
+    gsteps = G.WORKLOADS.get(name, (None, None))[1]
+    if gsteps is None or not os.path.exists(G.path_of(name, gsteps)):
+        return None
+    head, ids, vals = G.read(name, gsteps)
+    with sim_factory() as sim:
+        sim.set_temperature()
+        sim.step(gsteps, graph_steps=100)
+        T = sim.temperature()
+        health = sim.health() if hasattr(sim, "health") else None
+    err = float(np.max(np.abs(T[ids] - vals)) / float(head["max_abs"]))
+    out = {"err_max": err, "steps": gsteps, "nodes": int(ids.size),
+           "reference": f"tests/golden/{name}_{gsteps}.txt (oracle, sampled nodes)"}
+    if health is not None:
+        out["energy_residual"] = health["energy_residual"]
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -188,7 +256,10 @@ def main():
     builder, dsteps, osteps, desc, shape, kind = WORKLOADS[args.workload]
     steps = args.steps or dsteps
     osteps = args.oracle_steps or osteps
-    prob = getattr(P, builder)(nsteps=steps)
+    bargs = dict(nsteps=steps)
+    if kind == "standin":
+        bargs["td"] = args.workload.endswith("_td")
+    prob = getattr(P, builder)(**bargs)
     E, N = prob["conn"].shape[1], prob["x"].size
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
 
@@ -200,7 +271,8 @@ def main():
     if args.resident != "default":
         kw["resident"] = args.resident == "on"
     tuned = None
-    if args.autotune:
+    if args.autotune or (args.workload in AUTOTUNED and not args.no_autotune
+                         and not (args.tile_nodes or args.block or args.fuse)):
         tuned = autotune(prob, "fp32c", steps=200, log=log)
         kw = launch_kwargs(tuned)
         log(f"autotuned: {tuned}")
@@ -208,37 +280,60 @@ def main():
     res = {}
     precs = ["fp32c"] if args.no_fp64 else ["fp32c", "fp64"]
     for prec in precs:
-        sim = Simulation(prob, prec=prec, **kw)
-        if kind == "adjoint":
-            keep = not args.no_keep_states
-            if args.warmup:
-                timed_adjoint(sim, steps, prob, keep)  # first-use allocations and module loads
-            tf, tb = timed_adjoint(sim, steps, prob, keep)
-            t = tf + tb
-            log(f"{prec}: forward {tf * 1e3:.1f} ms + adjoint {tb * 1e3:.1f} ms for {steps} steps")
-        elif kind == "moving":
-            sim.set_point_schedule(moving_rows(prob))
-            t = timed_steps(sim, steps, args.warmup, args.graph_steps)
-            log(f"{prec}: {steps} scheduled steps, the source one node further each step, "
-                f"in {t * 1e3:.2f} ms ({t / steps * 1e6:.2f} us/step)")
-        else:
-            t = timed_steps(sim, steps, args.warmup, args.graph_steps)
-            log(f"{prec}: {steps} steps in {t * 1e3:.2f} ms ({t / steps * 1e6:.2f} us/step)")
-        res[prec] = dict(t=t, info=sim.info)
-        sim.close()
+        with Simulation(prob, prec=prec, **kw) as sim:
+            if kind == "adjoint":
+                # spec: checkpoints every K steps, each segment recomputed
+                # in the backward pass; the kept-states variant is timed beside it
+                if args.warmup:
+                    timed_adjoint(sim, steps, prob, False)  # first-use allocations, module loads
+                tf, tb = timed_adjoint(sim, steps, prob, False)
+                t = tf + tb
+                log(f"{prec}: forward {tf * 1e3:.1f} ms + adjoint {tb * 1e3:.1f} ms for {steps} "
+                    "steps (segments recomputed)")
+                extra = dict(forward_s=tf, backward_s=tb)
+                if sim.info["resident"]:
+                    timed_adjoint(sim, steps, prob, True)
+                    kf, kb = timed_adjoint(sim, steps, prob, True)
+                    log(f"{prec}: kept states: forward {kf * 1e3:.1f} ms + adjoint "
+                        f"{kb * 1e3:.1f} ms")
+                    extra["kept_states"] = dict(forward_s=kf, backward_s=kb)
+                res[prec] = dict(t=t, info=sim.info, **extra)
+                continue
+            if kind == "moving":
+                sim.set_point_schedule(moving_rows(prob))
+                t = timed_steps(sim, steps, args.warmup, args.graph_steps)
+                log(f"{prec}: {steps} scheduled steps, the source one node further each step, "
+                    f"in {t * 1e3:.2f} ms ({t / steps * 1e6:.2f} us/step)")
+            else:
+                t = timed_steps(sim, steps, args.warmup, args.graph_steps)
+                log(f"{prec}: {steps} steps in {t * 1e3:.2f} ms ({t / steps * 1e6:.2f} us/step)")
+            res[prec] = dict(t=t, info=sim.info)
 
-    cpu, errs = None, {}
+    host = cpu_info()
+    cpu, errs, gerr = None, {}, {}
     if not args.no_oracle:
         import oracle
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        threads = oracle.threads()
         o = oracle.Oracle(prob)
-        t0 = time.perf_counter()
         sched = moving_rows(prob) if kind == "moving" else None
+        t0 = time.perf_counter()
         ref = o.run(osteps, pt_schedule=sched)
         tc = time.perf_counter() - t0
         cpu = dict(value=E * osteps / tc, unit="element-updates/s", cores=threads, kind="oracle",
                    sample=f"{osteps} steps of the same workload ({args.workload}), FP64 C "
-                          f"oracle with an OpenMP element loop, {tc:.2f} s")
+                          f"oracle with an OpenMP element loop on {threads} threads, {tc:.2f} s",
+                   host=host)
+        if kind == "standin":
+            # the paper's timing study ran one thread: the oracle on one thread too
+            oracle.set_threads(1)
+            t0 = time.perf_counter()
+            o.run(osteps)
+            t1c = time.perf_counter() - t0
+            oracle.set_threads(threads)
+            cpu["one_thread"] = dict(value=E * osteps / t1c, ms_per_step=t1c / osteps * 1e3,
+                                     seconds=t1c)
+            cpu["ms_per_step"] = tc / osteps * 1e3
+            log(f"oracle {osteps} steps: {threads} threads {tc:.2f} s, one thread {t1c:.2f} s")
         for prec in res:
             with Simulation(prob, prec=prec, **kw) as sim:
                 if sched is not None:
@@ -247,11 +342,18 @@ def main():
                 sim.step(osteps)
                 errs[prec] = oracle.err_max(sim.temperature(), ref)
         log(f"oracle {osteps} steps {tc:.2f} s; err_max {errs}")
+    # error after the workload's full step count, against the stored oracle run
+    for prec in res:
+        g = golden_error(args.workload, lambda: Simulation(prob, prec=prec, **kw), steps)
+        if g is not None:
+            gerr[prec] = g
+    if gerr:
+        log(f"full-horizon err_max {({k: v['err_max'] for k, v in gerr.items()})}")
 
     import hashlib
     src_sha = hashlib.sha1(b"".join(open(f, "rb").read() for f in TRAFFIC_SRC)).hexdigest()
     default_shape = not (args.tile_nodes or args.block or args.fuse or args.autotune
-                         or args.resident != "default")
+                         or args.resident != "default") and tuned is None
     r32 = res["fp32c"]
     t = r32["t"]
     info = r32["info"]
@@ -278,6 +380,15 @@ def main():
     tr = TRAFFIC.get(args.workload)
     if tr and default_shape and tr[0] == src_sha and tr[1] == kernel:
         traffic = tr[2] + (steps * tr[3] if resident else 0.0)
+    cfg = {"workload": f"{args.workload}: {desc} ({E} elements, {N} nodes)",
+           "elements": E, "nodes": N, "precision": "fp32c",
+           "graph_steps": args.graph_steps,
+           "steps_per_launch": steps if resident else K, "resident": resident,
+           "tiles": info["n_tiles"], "block_threads": info["block_threads"],
+           "autotuned": tuned is not None}
+    if kind == "adjoint":
+        cfg["ckpt_every"] = prob["meta"]["ckpt_every"]
+        cfg["keep_states"] = False
     line = {
         "metric": METRIC,
         "value": E * steps / t,
@@ -287,12 +398,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-compensated",
         "data": "synthetic (seeded)",
-        "config": {"workload": f"{args.workload}: {desc} ({E} elements, {N} nodes)",
-                   "elements": E, "nodes": N, "precision": "fp32c",
-                   "graph_steps": args.graph_steps,
-                   "steps_per_launch": steps if resident else K, "resident": resident,
-                   "tiles": info["n_tiles"], "block_threads": info["block_threads"],
-                   "autotuned": tuned is not None},
+        "config": cfg,
         "hbm_gbs_algorithmic": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
@@ -302,28 +408,26 @@ def main():
         "cpu_baseline": cpu,
     }
     if kind == "moving":
-        sim = Simulation(prob, prec="fp32c", **kw)
-        n1 = min(steps, 1000)
-        t1 = timed_moving_host(sim, n1, prob, min(args.warmup, 200))
-        sim.close()
+        with Simulation(prob, prec="fp32c", **kw) as sim:
+            n1 = min(steps, 1000)
+            t1 = timed_moving_host(sim, n1, prob, min(args.warmup, 200))
         line["host_driven"] = {"us_per_step": t1 / n1 * 1e6, "steps": n1,
                                "how": "fed_set_bc from device rows, then one step, per call",
                                "schedule_speedup": (t1 / n1) / (t / steps)}
         log(f"host-driven moving source: {t1 / n1 * 1e6:.2f} us/step")
-    if resident and kind in ("steps", "moving"):
+    if resident and kind in ("steps", "moving", "standin"):
         # the per-step working set of the method (every element operator and
         # node state, once) processed per step, for comparison with the
         # streaming kernel that moves it from memory every step
         line["working_set_gbs_per_step"] = info["algorithmic_bytes_per_launch"] * steps / t / 1e9
         # the one-step-per-launch kernel on the same problem, same run
         kw1 = {k: v for k, v in kw.items() if k != "resident"}
-        sim = Simulation(prob, prec="fp32c", **kw1)
-        if kind == "moving":
-            sim.set_point_schedule(moving_rows(prob))
-        n1 = min(steps, 2000)
-        t1 = timed_steps(sim, n1, min(args.warmup, 200), args.graph_steps)
-        i1 = sim.info
-        sim.close()
+        with Simulation(prob, prec="fp32c", **kw1) as sim:
+            if kind == "moving":
+                sim.set_point_schedule(moving_rows(prob))
+            n1 = min(steps, 2000)
+            t1 = timed_steps(sim, n1, min(args.warmup, 200), args.graph_steps)
+            i1 = sim.info
         a1 = i1["algorithmic_bytes_per_launch"] / (t1 / n1) / 1e9
         line["streaming_kernel"] = {"kernel": "k_step1", "us_per_step": t1 / n1 * 1e6,
                                     "steps": n1, "tiles": i1["n_tiles"],
@@ -333,7 +437,15 @@ def main():
         log(f"streaming k_step1: {t1 / n1 * 1e6:.2f} us/step")
     if kind == "adjoint":
         line["roofline"] = None   # forward + adjoint mix, no single dominant kernel rate
-        line["note"] = "value counts forward steps; time includes the adjoint pass"
+        line["note"] = ("value counts forward steps; time includes the adjoint pass with "
+                        "every checkpoint segment recomputed")
+        line["adjoint"] = {p: {k: v for k, v in r.items() if k not in ("t", "info")}
+                           for p, r in res.items()}
+    if kind == "standin":
+        ms = PAPER_STANDIN[args.workload]
+        line["paper"] = {"ms_per_step": ms, "element_updates_per_s": 40021 / (ms * 1e-3),
+                         "how": "the paper's single-thread C++ on 40,021 tetrahedra, Intel "
+                                "i7-6700 at 3.40 GHz (Sec. 4.6); context, not a target"}
     if "fp64" in res:
         t64 = res["fp64"]["t"]
         i64 = res["fp64"]["info"]
@@ -350,7 +462,14 @@ def main():
     if errs:
         line["err_max_vs_oracle"] = errs
         line["err_steps"] = osteps
+    if gerr:
+        line["err_full_horizon"] = gerr
     print(json.dumps(line), flush=True)
+    # every context is closed (with-blocks above); drain the device and hand
+    # torch's cached blocks back before the interpreter and the HIP runtime
+    # shut down
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":

@@ -62,6 +62,10 @@ def lib():
         L.orc_run.argtypes = [P, _d, C.c_int64, _d, _d, _d, _d, _d, _d]
         L.orc_run_sched.argtypes = [P, _d, C.c_int64, C.c_int64, C.c_int64, _d, _d, _d, _d, _d,
                                     _d, _d]
+        L.orc_threads.restype = C.c_int
+        L.orc_threads.argtypes = []
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_adjoint.restype = C.c_int
         L.orc_adjoint.argtypes = [P, _d, C.c_int64, _i8, _d, _d, _d, _d]
         _LIB = L
@@ -336,6 +340,16 @@ class Oracle:
         if rc != 0:
             raise MemoryError("oracle adjoint: out of memory")
         return dict(g_logk=g_logk, g_c=g_c, g_h=g_h, lam0=lam)
+
+
+def threads():
+    """Threads the oracle's element loop uses (OpenMP)."""
+    return int(lib().orc_threads())
+
+
+def set_threads(n):
+    """Sets the oracle's OpenMP thread count (n >= 1)."""
+    lib().orc_set_threads(int(n))
 
 
 def err_max(T, Tref):

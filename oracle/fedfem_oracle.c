@@ -31,6 +31,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 static const int HEX_S[8][3] = {
     {-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
@@ -445,6 +448,24 @@ void orc_hourglass(int64_t E, const double *x, const double *y, const double *z,
             (h[a] - (hx[0] * Be[0 * 8 + a] + hx[1] * Be[1 * 8 + a] + hx[2] * Be[2 * 8 + a])) / 8.0;
     }
   }
+}
+
+/* Threads of the element loop (OpenMP): the count in use, and a new count
+ * (n >= 1) for the timed single-thread baseline. */
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 /* Net nodal conductive load F = sum_e F_e (summed in element order) and the
