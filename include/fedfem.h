@@ -178,6 +178,33 @@ typedef struct {
   void *(*dev_alloc)(size_t bytes, void *alloc_ctx);
   void (*dev_free)(void *ptr, void *alloc_ctx);
   void *alloc_ctx;
+  /* In-run health check.  The stability bound (Sec. 3.4, Eq. 29) is derived
+   * for temperatures in [T_lo, T_hi]: every step checks every new temperature
+   * against a window (a value outside it or not finite latches the first such
+   * step, reported by the next fed_get_temperature as FED_E_UNSTABLE and by
+   * fed_health_get).  check_window 0: the window is [T_lo - m, T_hi + m] with
+   * m the largest margin for which the time step in use stays within the
+   * bound over the window (the step takes a safety factor below the bound, so
+   * it stays provably stable somewhat beyond the range; m = 0 if the step
+   * exceeds the bound, no limit where the bound does not depend on T);
+   * re-derived by fed_set_range and fed_set_params.  check_window 1: the window
+   * is [T_lo - check_margin, T_hi + check_margin].  With
+   * check_every > 0, the step that reaches every multiple of check_every
+   * (launches end there; with fed_step_graph and one-step launches, the last
+   * step of every replay instead) also takes the energy balance of the
+   * explicit update: summed over the nodes, C_k (T_k^{n+1} - T_k^n) / dt - Q_k
+   * over the nodes that are not Dirichlet minus the conductive load F_k of the
+   * Dirichlet nodes is zero (every element's loads sum to zero); the check
+   * records its magnitude over the sum of the terms' magnitudes.  The largest
+   * is reported by fed_health_get and, when energy_tol > 0 and it exceeds
+   * energy_tol, as FED_E_UNSTABLE.  The check step runs in the one-step kernel
+   * (same results, bit for bit), so on resident contexts each check ends a
+   * resident launch.  check_window 0 or 1; check_margin >= 0; check_every >= 0
+   * (0: no energy checks); energy_tol >= 0 (0: report only). */
+  int32_t check_window;
+  double check_margin;
+  int32_t check_every;
+  double energy_tol;
 } fed_options;
 
 typedef struct fed_ctx fed_ctx;
@@ -243,11 +270,27 @@ int fed_step(fed_ctx *ctx, int64_t nsteps, void *stream);
 int fed_step_graph(fed_ctx *ctx, int64_t nsteps, int32_t graph_steps, void *stream);
 
 /* Copies the current temperatures (FP64, caller order; FP32C returns hi + lo) to
- * T (host if on_device == 0).  Synchronises `stream`, then runs the health check
- * (all temperatures finite and within [T_lo - w, T_hi + w], w = T_hi - T_lo);
- * returns FED_E_UNSTABLE if it fired, and FED_E_HIP if a resident launch had to
- * give up waiting for a neighbouring tile (its results are then invalid). */
+ * T (host if on_device == 0).  Synchronises `stream` and reports the health
+ * check (see fed_options): FED_E_UNSTABLE if a temperature left the window or
+ * was not finite after any step since fed_set_temperature (or is now), or if
+ * the energy residual exceeded energy_tol; FED_E_HIP if a resident launch had
+ * to give up waiting for a neighbouring tile (its results are then invalid).
+ * The temperatures are copied in every case. */
 int fed_get_temperature(fed_ctx *ctx, double *T, int32_t on_device, void *stream);
+
+/* Health record of the steps since fed_set_temperature (or fed_set_state). */
+typedef struct {
+  int64_t steps;              /* steps taken */
+  int64_t first_bad_step;     /* first step after which a temperature was outside the
+                                 window or not finite; -1: none (fed_set_range clears it) */
+  double window_lo, window_hi;  /* the window in use (see fed_options) */
+  double energy_residual;     /* largest relative energy residual of the checks (0: none) */
+  int64_t energy_step;        /* the step of that check; -1: none */
+  int64_t energy_checks;      /* energy checks taken */
+} fed_health;
+
+/* Reads the health record (synchronises `stream`). */
+int fed_health_get(fed_ctx *ctx, fed_health *out, void *stream);
 
 /* Number of steps taken since fed_set_temperature. */
 int fed_steps_taken(const fed_ctx *ctx, int64_t *steps);
@@ -346,7 +389,7 @@ int fed_temperature_range(fed_ctx *ctx, double *tmin, double *tmax, void *stream
 
 /* Re-derives dt_crit (Sec. 3.4, Eq. 29) for the temperature range [T_lo, T_hi]
  * and re-checks the time step in use against it; the health check window
- * follows the new range.  The time step itself is unchanged.  Errors:
+ * follows the new range and its out-of-window record is cleared.  The time step itself is unchanged.  Errors:
  * FED_E_ARG (bad range, c(T) or D(T) not positive on it), FED_E_UNSTABLE (the
  * time step exceeds the new bound and allow_unstable is off; the new bound
  * and range are kept), FED_E_HIP.  Synchronises `stream`. */

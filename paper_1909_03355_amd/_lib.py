@@ -61,7 +61,17 @@ class fed_options(C.Structure):
                 ("block_threads", C.c_int32), ("fuse_steps", C.c_int32),
                 ("resident", C.c_int32), ("hex_gradient", C.c_int32),
                 ("hourglass", C.c_double),
-                ("dev_alloc", DEV_ALLOC), ("dev_free", DEV_FREE), ("alloc_ctx", C.c_void_p)]
+                ("dev_alloc", DEV_ALLOC), ("dev_free", DEV_FREE), ("alloc_ctx", C.c_void_p),
+                ("check_window", C.c_int32), ("check_margin", C.c_double),
+                ("check_every", C.c_int32),
+                ("energy_tol", C.c_double)]
+
+
+class fed_health(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("first_bad_step", C.c_int64),
+                ("window_lo", C.c_double), ("window_hi", C.c_double),
+                ("energy_residual", C.c_double), ("energy_step", C.c_int64),
+                ("energy_checks", C.c_int64)]
 
 
 class fed_info(C.Structure):
@@ -88,6 +98,7 @@ SIGNATURES = {
     "fed_step_graph": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
     "fed_get_temperature": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "fed_steps_taken": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "fed_health_get": (C.c_int, [C.c_void_p, C.POINTER(fed_health), C.c_void_p]),
     "fed_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
                                 C.c_void_p]),
     "fed_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),

@@ -19,6 +19,10 @@ namespace {
 
 thread_local std::string g_err;
 
+// static LDS of the step kernels' energy check (block sums and a flag),
+// reserved out of the LDS a tile may take
+constexpr int kStaticLds = 512;
+
 int fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -186,6 +190,15 @@ struct fed_ctx {
   // host copies for re-deriving the stability bound over a new range
   std::vector<fed_material> h_mats;
   std::vector<double> h_ktab_T, h_ktab_f, h_ctab_T, h_ctab_f;
+  // in-run health check: the record the step kernels write, per-tile partial
+  // sums of the energy checks, the window margin, the energy-check interval
+  // (0: the last step of every fed_step call) and the energy tolerance (0: report only)
+  fed::Health *d_health = nullptr;
+  double *d_hpart = nullptr;
+  double check_margin = 0, energy_tol = 0;
+  int check_window = 0;             // 0: derived from the stability bound, 1: the margin
+  double win_lo = 0, win_hi = 0;    // the window in use
+  int64_t check_every = 0;
   unsigned long long *d_rkeys = nullptr;  // temperature-range keys and a non-finite flag
   int *d_rnan = nullptr;
   // scalars
@@ -242,6 +255,23 @@ struct fed_ctx {
     a.nct = nct;
     a.op = op;
     return a;
+  }
+
+  // the health check of a launch whose first step follows step count step0
+  void health_args(fed::StepArgs &a, long long step0, bool energy) const {
+    a.hl = d_health;
+    a.hpart = d_hpart;
+    a.win_lo = win_lo;
+    a.win_hi = win_hi;
+    // FP32 kernels compare in FP32: the window rounded outward, so no
+    // temperature inside the FP64 window is flagged
+    a.win_lo_f = (float)a.win_lo;
+    a.win_hi_f = (float)a.win_hi;
+    if ((double)a.win_lo_f > a.win_lo) a.win_lo_f = std::nextafter(a.win_lo_f, -INFINITY);
+    if ((double)a.win_hi_f < a.win_hi) a.win_hi_f = std::nextafter(a.win_hi_f, INFINITY);
+    a.step0 = step0;
+    a.hbase = 0;
+    a.energy = energy ? 1 : 0;
   }
 
   // record powers of step n (counted from fed_set_temperature) under the schedule
@@ -383,10 +413,126 @@ int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, cons
                            "(fuse_steps <= 1, resident = 0)");
   if (!(o->hourglass >= 0) || !std::isfinite(o->hourglass))
     return fail(FED_E_ARG, "hourglass must be a finite number >= 0");
+  if (!(o->check_margin >= 0) || !std::isfinite(o->check_margin))
+    return fail(FED_E_ARG, "check_margin must be a finite number >= 0");
+  if (o->check_window != 0 && o->check_window != 1)
+    return fail(FED_E_ARG, "check_window must be 0 or 1");
+  if (o->check_every < 0) return fail(FED_E_ARG, "check_every must be >= 0");
+  if (!(o->energy_tol >= 0) || !std::isfinite(o->energy_tol))
+    return fail(FED_E_ARG, "energy_tol must be a finite number >= 0");
   if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr))
     return fail(FED_E_ARG, "dev_alloc and dev_free must be given together");
   if (o->hourglass > 0 && !(m->elem == FED_HEX8 && o->hex_gradient == 1))
     return fail(FED_E_ARG, "hourglass control needs hexahedra with hex_gradient = 1");
+  return FED_OK;
+}
+
+// Extreme of a piecewise-linear table (constant beyond its ends) on [lo, hi]:
+// at the ends or at a breakpoint inside.
+double table_extreme(const std::vector<double> &tT, const std::vector<double> &tf, double lo,
+                     double hi, bool want_max) {
+  const int n = (int)tT.size();
+  auto at = [&](double T) {
+    if (T <= tT[0]) return tf[0];
+    if (T >= tT[n - 1]) return tf[n - 1];
+    int i = 1;
+    while (T > tT[i]) i++;
+    return tf[i - 1] + (T - tT[i - 1]) / (tT[i] - tT[i - 1]) * (tf[i] - tf[i - 1]);
+  };
+  double r = want_max ? std::max(at(lo), at(hi)) : std::min(at(lo), at(hi));
+  for (int i = 0; i < n; i++)
+    if (tT[i] > lo && tT[i] < hi) r = want_max ? std::max(r, tf[i]) : std::min(r, tf[i]);
+  return r;
+}
+
+// The stability bound (Sec. 3.4, Eq. 29) per instance for temperatures in
+// [lo, hi], from the context's pre-computation (leaves the per-node minimum
+// capacity of [lo, hi] in d_Cmin).
+int bound_dt(fed_ctx *c, double lo, double hi, std::vector<double> &dtc, hipStream_t s) {
+  const double fk = c->nkt ? table_extreme(c->h_ktab_T, c->h_ktab_f, lo, hi, true) : 1.0;
+  const double fc = c->nct ? table_extreme(c->h_ctab_T, c->h_ctab_f, lo, hi, false) : 1.0;
+  fed::MassArgs ma{c->N, c->ne, c->d_incp, c->d_ince, c->d_mats, c->d_emat, c->d_ec0, c->d_V,
+                   lo, hi, c->d_M0, c->d_M1, c->d_Cmin, fc};
+  HIPCHK(fed::launch_mass(ma, s));
+  HIPCHK(hipMemsetAsync(c->d_lam, 0, sizeof(unsigned long long) * 2 * c->ninst, s));
+  fed::DtArgs da{c->ne, c->E, c->nrec, c->d_lamgeo, c->d_kscale, c->d_mats, c->d_emat, c->d_ec0,
+                 c->d_einst, c->d_recnode, c->d_ninst, c->d_b64[0], c->d_b64[2], c->d_Cmin,
+                 lo, hi, c->Tz, c->d_lam, c->d_lam + c->ninst, fk, fc};
+  HIPCHK(fed::launch_dt(da, s));
+  std::vector<unsigned long long> lam(2 * c->ninst);
+  HIPCHK(hipMemcpyAsync(lam.data(), c->d_lam, lam.size() * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  dtc.resize(c->ninst);
+  for (int64_t i = 0; i < c->ninst; i++) {
+    double le, lb;
+    std::memcpy(&le, &lam[i], 8);
+    std::memcpy(&lb, &lam[c->ninst + i], 8);
+    dtc[i] = le + lb > 0 ? 2.0 / (le + lb) : INFINITY;
+  }
+  return FED_OK;
+}
+
+// The health window.  check_window 1: [T_lo - check_margin, T_hi +
+// check_margin].  0: [T_lo - m, T_hi + m] with m the largest margin for which
+// the time step in use stays within the stability bound over the window (the
+// bound is derived for [T_lo, T_hi] and the step takes a safety factor below
+// it, so the step stays provably stable a little beyond the range; m = 0 if
+// the step exceeds the bound, unbounded where the bound does not depend on
+// T).  Leaves d_Cmin as [T_lo, T_hi] gives it.
+int derive_window(fed_ctx *c, hipStream_t s) {
+  const double wlo0 = c->win_lo, whi0 = c->win_hi;
+  if (c->check_window == 1) {
+    c->win_lo = c->T_lo - c->check_margin;
+    c->win_hi = c->T_hi + c->check_margin;
+  } else {
+    // margins that keep every law positive (c(T) > 0, s(T) > 0) on the window
+    double cap = 1e6 * (1.0 + c->T_hi - c->T_lo);
+    auto limit = [&](double a0, double a1) {  // a0 + a1 T > 0 on [T_lo - m, T_hi + m]
+      if (a1 > 0) cap = std::min(cap, c->T_lo + a0 / a1);
+      if (a1 < 0) cap = std::min(cap, -a0 / a1 - c->T_hi);
+    };
+    for (const fed_material &q : c->h_mats) {
+      limit(q.c0, q.c1);
+      limit(q.s0, q.s1);
+    }
+    cap = std::max(0.0, cap * (1.0 - 1e-9));
+    std::vector<double> dtc;
+    auto stable = [&](double m, bool &ok) -> int {
+      int rc = bound_dt(c, c->T_lo - m, c->T_hi + m, dtc, s);
+      if (rc) return rc;
+      ok = true;
+      for (int64_t i = 0; i < c->ninst; i++) ok &= c->dt_used[i] <= dtc[i];
+      return FED_OK;
+    };
+    bool ok = false;
+    int rc = stable(0.0, ok);
+    if (rc) return rc;
+    double m = 0.0;
+    if (ok) {
+      rc = stable(cap, ok);
+      if (rc) return rc;
+      if (ok) {
+        m = cap >= 1e6 * (1.0 + c->T_hi - c->T_lo) * (1.0 - 1e-6) ? INFINITY : cap;
+      } else {
+        double a = 0.0, b = cap;  // stable at a, not at b
+        for (int it = 0; it < 48 && b - a > 1e-9 * (1.0 + a); it++) {
+          const double mid = 0.5 * (a + b);
+          rc = stable(mid, ok);
+          if (rc) return rc;
+          (ok ? a : b) = mid;
+        }
+        m = a;
+      }
+    }
+    c->win_lo = c->T_lo - m;
+    c->win_hi = c->T_hi + m;
+    std::vector<double> keep;
+    rc = bound_dt(c, c->T_lo, c->T_hi, keep, s);  // d_Cmin of the range itself
+    if (rc) return rc;
+  }
+  // captured graph launches carry the window
+  if (c->win_lo != wlo0 || c->win_hi != whi0) c->drop_graph();
   return FED_OK;
 }
 
@@ -440,9 +586,10 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
                                          : (int64_t)T.maxinc * th.nown;
     lds = std::max<int64_t>(lds, (int64_t)c->rb * (th.cum_n[1] + ns + 5LL * th.nbnd) + 16);
   }
-  if (lds > c->max_lds)
-    return fail(FED_E_MESH, "resident stepping: a tile needs %lld bytes of LDS (the GPU has %d)",
-                (long long)lds, c->max_lds);
+  if (lds > c->max_lds - kStaticLds)
+    return fail(FED_E_MESH, "resident stepping: a tile needs %lld bytes of LDS (the GPU has %d, "
+                "%d of them taken by the health check)",
+                (long long)lds, c->max_lds, kStaticLds);
   c->res_lds = (int)lds;
   int per_cu = 0;
   fed::StepArgs a0 = c->step_args(0, 1);
@@ -470,7 +617,8 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
                                                                (int64_t)th.cum_n[1] + 2LL * th.nbnd) + 16);
     int aper = 0;
     if (alds <= c->max_lds) {
-      HIPCHK(fed::adjres_prepare(c->prec == FED_FP64 ? 1 : (c->prec == FED_FP32C ? 0 : 2), c->block,
+      HIPCHK(fed::adjres_prepare(c->prec == FED_FP64 ? 1 : (c->prec == FED_FP32C ? 0 : 2),
+                                 c->d_ktab || c->d_ctab || c->d_esk, c->block,
                                  (int)alds, &aper));
       if (aper >= 1 && grid <= (int64_t)aper * n_cu) {
         c->adjres = true;
@@ -521,31 +669,16 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   c->tdc |= mt->n_ctab > 0;
   c->nkt = mt->n_ktab;
   c->nct = mt->n_ctab;
-  // a table's extremes on [T_lo, T_hi] are at the ends or at breakpoints inside
-  auto table_extreme = [&](int n, const double *tT, const double *tf, bool want_max) {
-    auto at = [&](double T) {
-      if (T <= tT[0]) return tf[0];
-      if (T >= tT[n - 1]) return tf[n - 1];
-      int i = 1;
-      while (T > tT[i]) i++;
-      return tf[i - 1] + (T - tT[i - 1]) / (tT[i] - tT[i - 1]) * (tf[i] - tf[i - 1]);
-    };
-    double v = at(o->T_lo), w = at(o->T_hi);
-    double r = want_max ? std::max(v, w) : std::min(v, w);
-    for (int i = 0; i < n; i++)
-      if (tT[i] > o->T_lo && tT[i] < o->T_hi) r = want_max ? std::max(r, tf[i]) : std::min(r, tf[i]);
-    return r;
-  };
-  if (c->nkt) c->fk_max = table_extreme(c->nkt, mt->ktab_T, mt->ktab_f, true);
-  if (c->nct) c->fc_min = table_extreme(c->nct, mt->ctab_T, mt->ctab_f, false);
   c->h_mats.assign(mt->materials, mt->materials + mt->n_materials);
   if (c->nkt) {
     c->h_ktab_T.assign(mt->ktab_T, mt->ktab_T + c->nkt);
     c->h_ktab_f.assign(mt->ktab_f, mt->ktab_f + c->nkt);
+    c->fk_max = table_extreme(c->h_ktab_T, c->h_ktab_f, o->T_lo, o->T_hi, true);
   }
   if (c->nct) {
     c->h_ctab_T.assign(mt->ctab_T, mt->ctab_T + c->nct);
     c->h_ctab_f.assign(mt->ctab_f, mt->ctab_f + c->nct);
+    c->fc_min = table_extreme(c->h_ctab_T, c->h_ctab_f, o->T_lo, o->T_hi, false);
   }
   if (mixed_k && o->resident)
     return fail(FED_E_ARG, "resident stepping needs materials that share s0 and s1");
@@ -613,7 +746,7 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
     const int64_t wgs = (int64_t)n_cu * res_per_cu;
     if (!o->tile_nodes) ti.target_nodes = (int32_t)std::max<int64_t>(1, (N + wgs - 1) / wgs);
     ti.depth = 1;
-    ti.lds_budget = max_lds;
+    ti.lds_budget = max_lds - kStaticLds;
     ti.upd_bytes = 0;
   }
   std::string terr;
@@ -822,6 +955,10 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
       c->dt_used[i] = o->safety * c->dt_crit[i];
     }
   }
+  c->check_margin = o->check_margin;
+  c->check_window = o->check_window;
+  rc = derive_window(c.get(), s);
+  if (rc) return rc;
   // ---- working arrays in the step precision ---------------------------------
   const int rb = c->rb;
   double *d_dtinst;
@@ -884,6 +1021,11 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
     HIPCHK(upload(P, &c->d_dir_node, dir_node.data(), dir_node.size()));
     HIPCHK(upload(P, &c->d_dir_T, bc->dir_T, (size_t)c->ndir));
   }
+  HIPCHK(P.alloc((void **)&c->d_health, sizeof(fed::Health)));
+  HIPCHK(P.alloc((void **)&c->d_hpart, sizeof(double) * 2 * std::max(T.nt, 1)));
+  HIPCHK(fed::launch_health(c->d_health, 0, 0, s));
+  c->check_every = o->check_every;
+  c->energy_tol = o->energy_tol;
   HIPCHK(P.alloc((void **)&c->d_flag, sizeof(int)));
   HIPCHK(P.alloc((void **)&c->d_rkeys, 2 * sizeof(unsigned long long)));
   HIPCHK(P.alloc((void **)&c->d_rnan, sizeof(int)));
@@ -982,6 +1124,7 @@ int fed_set_temperature(fed_ctx *c, const double *T, int32_t on_device, void *st
   c->have_T = true;
   c->kept_ok = c->keep_states && c->resident && c->ckpt_every > 0;
   HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  HIPCHK(fed::launch_health(c->d_health, 0, 0, s));
   if (c->resident) HIPCHK(hipMemsetAsync(c->d_rerr, 0, sizeof(int), s));
   if (c->ckpt_every > 0) {
     int rc = save_checkpoint(c, 0, s);
@@ -996,36 +1139,78 @@ int fed_set_temperature(fed_ctx *c, const double *T, int32_t on_device, void *st
 namespace {
 
 // nsteps steps in launches of up to K steps, no checkpoint handling
+// With check_every > 0, launches end at its multiples and the step that
+// reaches one checks the energy balance; that step runs in the one-step
+// kernel (whose results are bitwise those of the others), the only one that
+// takes the check.
+int64_t check_cut(const fed_ctx *c, int64_t done, int64_t k) {
+  if (c->check_every <= 0) return k;
+  return std::min<int64_t>(k, c->check_every - done % c->check_every);
+}
+bool energy_at(const fed_ctx *c, int64_t end) {
+  return c->check_every > 0 && end % c->check_every == 0;
+}
+
+// one step in the one-step kernel from step count st, with the energy check
+int energy_step(fed_ctx *c, int64_t st, hipStream_t s) {
+  fed::StepArgs a = c->step_args(c->cur, 1);
+  c->health_args(a, st, true);
+  if (c->ps_rows > 0) a.rP = c->ps_row(st);
+  HIPCHK(fed::launch_step(a, s));
+  c->cur ^= 1;
+  if (c->resident && c->keep_states && c->ckpt_every > 0) {
+    // the step's state into the kept states, as a resident launch stores it
+    const int64_t g = st / c->ckpt_every, i = st % c->ckpt_every + 1;
+    int rc = seg_buffer(c, g);
+    if (rc) return rc;
+    const size_t hb = (size_t)c->rb * c->N;
+    HIPCHK(hipMemcpyAsync((char *)c->segbuf[g] + hb * i, c->d_T[c->cur], hb,
+                          hipMemcpyDeviceToDevice, s));
+  }
+  return FED_OK;
+}
+
 int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
   if (c->resident) {
     for (int64_t n = nsteps; n > 0;) {
-      const int k = (int)std::min<int64_t>(n, 1 << 30);
-      fed::StepArgs a = c->step_args(c->cur, 1);
-      a.lds = c->res_lds;
-      const int fin = c->cur ^ (k & 1);
-      fed::ResArgs r{k, c->spin_limit, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
-                     c->d_T[fin], c->d_lo[fin], nullptr, 0};
-      r.split = c->res_split;
-      r.tag_skew = c->tag_skew;
-      if (c->keep_states && c->ckpt_every > 0) {
-        // fed_step breaks launches at checkpoints: this one stays inside segment g
-        const int64_t st = c->steps + nsteps - n, g = st / c->ckpt_every, i0 = st % c->ckpt_every;
-        int rc = seg_buffer(c, g);
+      const int64_t st = c->steps + nsteps - n;
+      const int kc = (int)check_cut(c, st, std::min<int64_t>(n, 1 << 30));
+      const bool chk = energy_at(c, st + kc);
+      // the check step itself runs in the one-step kernel
+      const int k = chk ? kc - 1 : kc;
+      if (k > 0) {
+        fed::StepArgs a = c->step_args(c->cur, 1);
+        a.lds = c->res_lds;
+        c->health_args(a, st, false);
+        const int fin = c->cur ^ (k & 1);
+        fed::ResArgs r{k, c->spin_limit, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
+                       c->d_T[fin], c->d_lo[fin], nullptr, 0};
+        r.split = c->res_split;
+        r.tag_skew = c->tag_skew;
+        if (c->keep_states && c->ckpt_every > 0) {
+          // fed_step breaks launches at checkpoints: this one stays inside segment g
+          const int64_t g = st / c->ckpt_every, i0 = st % c->ckpt_every;
+          int rc = seg_buffer(c, g);
+          if (rc) return rc;
+          r.seg = (char *)c->segbuf[g] + (size_t)c->rb * c->N * i0;
+          r.segN = c->N;
+        }
+        if (c->ps_rows > 0) {
+          r.pts = c->d_psP;
+          r.pts_nrec = c->nrec;
+          r.pts_row = (int)(st % c->ps_rows);
+          r.pts_nrows = (int)c->ps_rows;
+        }
+        HIPCHK(fed::launch_resident(a, r, s));
+        // the launch wrote tags up to xtag + k: the next one starts beyond them
+        c->xtag += (unsigned)k + 1u;
+        c->cur = fin;
+      }
+      if (chk) {
+        int rc = energy_step(c, st + k, s);
         if (rc) return rc;
-        r.seg = (char *)c->segbuf[g] + (size_t)c->rb * c->N * i0;
-        r.segN = c->N;
       }
-      if (c->ps_rows > 0) {
-        r.pts = c->d_psP;
-        r.pts_nrec = c->nrec;
-        r.pts_row = (int)((c->steps + nsteps - n) % c->ps_rows);
-        r.pts_nrows = (int)c->ps_rows;
-      }
-      HIPCHK(fed::launch_resident(a, r, s));
-      // the launch wrote tags up to xtag + k: the next one starts beyond them
-      c->xtag += (unsigned)k + 1u;
-      c->cur = fin;
-      n -= k;
+      n -= kc;
     }
     c->steps += nsteps;
     return FED_OK;
@@ -1034,12 +1219,22 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
   for (int64_t n = nsteps; n > 0;) {
     // under a point-load schedule every step takes its own record powers: one
     // step per launch
-    int k = c->ps_rows > 0 ? 1 : (int)std::min<int64_t>(c->K, n);
-    fed::StepArgs a = c->step_args(c->cur, k);
-    if (c->ps_rows > 0) a.rP = c->ps_row(c->steps + nsteps - n);
-    HIPCHK(fed::launch_step(a, s));
-    c->cur ^= 1;
-    n -= k;
+    const int64_t st = c->steps + nsteps - n;
+    const int kc = c->ps_rows > 0 ? 1 : (int)check_cut(c, st, std::min<int64_t>(c->K, n));
+    const bool chk = energy_at(c, st + kc);
+    const int k = chk ? kc - 1 : kc;
+    if (k > 0) {
+      fed::StepArgs a = c->step_args(c->cur, k);
+      c->health_args(a, st, false);
+      if (c->ps_rows > 0) a.rP = c->ps_row(st);
+      HIPCHK(fed::launch_step(a, s));
+      c->cur ^= 1;
+    }
+    if (chk) {
+      int rc = energy_step(c, st + k, s);
+      if (rc) return rc;
+    }
+    n -= kc;
   }
   c->steps += nsteps;
   return FED_OK;
@@ -1106,8 +1301,11 @@ int fed_step_graph(fed_ctx *c, int64_t nsteps, int32_t graph_steps, void *stream
   if (!c->have_T) return fail(FED_E_STATE, "fed_set_temperature must come first");
   if (nsteps < 0 || graph_steps < 0) return fail(FED_E_ARG, "negative count");
   // checkpoints break launches; a resident launch already runs all the steps; a
-  // point-load schedule gives every step its own launch arguments
-  if (c->ckpt_every > 0 || c->resident || c->ps_rows > 0) return fed_step(c, nsteps, stream);
+  // point-load schedule gives every step its own launch arguments; energy checks
+  // with K-step launches split launches (replays check at their last step only
+  // with one-step launches)
+  if (c->ckpt_every > 0 || c->resident || c->ps_rows > 0 || (c->check_every > 0 && c->K > 1))
+    return fed_step(c, nsteps, stream);
   hipStream_t s = (hipStream_t)stream;
   // an even number of K-step launches, so every replay starts on the same buffer
   int64_t want = graph_steps ? graph_steps : 100;
@@ -1123,9 +1321,18 @@ int fed_step_graph(fed_ctx *c, int64_t nsteps, int32_t graph_steps, void *stream
     hipStream_t cs = c->cap_stream;
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int par = c->cur;
-    for (int i = 0; i < launches; i++) {
-      fed::StepArgs a = c->step_args(par, c->K);
-      hipError_t e = fed::launch_step(a, cs);
+    for (int i = 0; i <= launches; i++) {
+      hipError_t e;
+      if (i < launches) {
+        // health: steps counted from the replay's base; the replay's last
+        // launch checks the energy balance
+        fed::StepArgs a = c->step_args(par, c->K);
+        c->health_args(a, (long long)i * c->K, c->check_every > 0 && i == launches - 1);
+        a.hbase = 1;
+        e = fed::launch_step(a, cs);
+      } else {
+        e = fed::launch_health(c->d_health, 2, gs, cs);  // the next replay's base
+      }
       if (e != hipSuccess) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(cs, &g);
@@ -1140,6 +1347,7 @@ int fed_step_graph(fed_ctx *c, int64_t nsteps, int32_t graph_steps, void *stream
     c->gparity = c->cur;
   }
   int64_t reps = nsteps / gs;
+  HIPCHK(fed::launch_health(c->d_health, 1, c->steps, s));
   for (int64_t r = 0; r < reps; r++) HIPCHK(hipGraphLaunch(c->gexec, s));
   c->steps += reps * gs;
   return run_steps(c, nsteps - reps * gs, s);
@@ -1149,25 +1357,53 @@ int fed_get_temperature(fed_ctx *c, double *T, int32_t on_device, void *stream) 
   if (!c || !T) return fail(FED_E_ARG, "null argument");
   if (!c->have_T) return fail(FED_E_STATE, "no temperature set");
   hipStream_t s = (hipStream_t)stream;
-  double w = c->T_hi - c->T_lo;
-  HIPCHK(fed::launch_check(c->prec, c->N, c->d_T[c->cur], c->d_lo[c->cur], c->T_lo - w,
-                           c->T_hi + w, c->d_flag, s));
+  const double wlo = c->win_lo, whi = c->win_hi;
+  // the readout check covers the current state only
+  HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  HIPCHK(fed::launch_check(c->prec, c->N, c->d_T[c->cur], c->d_lo[c->cur], wlo, whi, c->d_flag, s));
   double *dst = on_device ? T : c->d_Tuser;
   HIPCHK(fed::launch_get_T(c->prec, c->N, c->d_perm, c->d_T[c->cur], c->d_lo[c->cur], dst, s));
   int flag = 0;
   if (!on_device)
     HIPCHK(hipMemcpyAsync(T, c->d_Tuser, sizeof(double) * c->N, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  fed::Health h{};
+  HIPCHK(hipMemcpyAsync(&h, c->d_health, sizeof(h), hipMemcpyDeviceToHost, s));
   int rerr = 0;
   if (c->resident) HIPCHK(hipMemcpyAsync(&rerr, c->d_rerr, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (rerr)
     return fail(FED_E_HIP, "resident stepping: a tile gave up waiting for a neighbouring tile; "
                            "the temperatures are invalid");
+  if (h.first_bad != ~0ull)
+    return fail(FED_E_UNSTABLE,
+                "health check: a temperature left [%g, %g] or was not finite after step %llu "
+                "(the stability bound holds for [T_lo, T_hi]; %lld steps taken)",
+                wlo, whi, h.first_bad, (long long)c->steps);
   if (flag)
     return fail(FED_E_UNSTABLE,
                 "health check: a temperature is non-finite or outside [%g, %g] after %lld steps",
-                c->T_lo - w, c->T_hi + w, (long long)c->steps);
+                wlo, whi, (long long)c->steps);
+  if (c->energy_tol > 0 && !(h.energy_max <= c->energy_tol))
+    return fail(FED_E_UNSTABLE,
+                "health check: energy residual %.3g at step %lld exceeds energy_tol %.3g",
+                h.energy_max, h.energy_step, c->energy_tol);
+  return FED_OK;
+}
+
+int fed_health_get(fed_ctx *c, fed_health *out, void *stream) {
+  if (!c || !out) return fail(FED_E_ARG, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  fed::Health h{};
+  HIPCHK(hipMemcpyAsync(&h, c->d_health, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  out->steps = c->steps;
+  out->first_bad_step = h.first_bad == ~0ull ? -1 : (int64_t)h.first_bad;
+  out->window_lo = c->win_lo;
+  out->window_hi = c->win_hi;
+  out->energy_residual = h.energy_max;
+  out->energy_step = h.energy_step;
+  out->energy_checks = h.checks;
   return FED_OK;
 }
 
@@ -1209,6 +1445,7 @@ int fed_set_state(fed_ctx *c, const void *hi, const void *lo, int64_t step, void
     HIPCHK(fed::launch_permute(4, c->N, c->d_perm, tmp, c->d_lo[0], 1, s));
   }
   HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  HIPCHK(fed::launch_health(c->d_health, 0, 0, s));
   if (c->resident) HIPCHK(hipMemsetAsync(c->d_rerr, 0, sizeof(int), s));
   HIPCHK(hipStreamSynchronize(s));
   c->steps = step;
@@ -1296,6 +1533,8 @@ int fed_set_params(fed_ctx *c, const double *kscale, const double *elem_c, const
       return fail(FED_E_UNSTABLE, "dt %.6g exceeds the new dt_crit %.6g (instance %lld)",
                   c->dt_used[i], c->dt_crit[i], (long long)i);
   }
+  int rc = derive_window(c, s);  // the bound moved: so does the window it allows
+  if (rc) return rc;
   fed::NodeArrArgs na{c->prec, N, c->nrec, c->d_M0, c->d_M1, c->d_dtinst, c->d_ninst, c->d_isdir,
                       c->d_b64[0], c->d_b64[1], c->d_b64[2], c->d_b64[4], c->d_b64[3],
                       c->d_alpha, c->d_beta, c->d_rA, c->d_rAT, c->d_reA, c->d_rTa, c->d_rP};
@@ -1455,48 +1694,21 @@ int fed_set_range(fed_ctx *c, double T_lo, double T_hi, void *stream) {
         !(q.s0 + q.s1 * T_lo > 0 && q.s0 + q.s1 * T_hi > 0))
       return fail(FED_E_ARG, "material %d: c(T) or D(T) not positive on [%g, %g]", (int)i, T_lo, T_hi);
   }
-  // table extremes on the new range: at its ends or at breakpoints inside it
-  auto extreme = [&](const std::vector<double> &tT, const std::vector<double> &tf, bool want_max) {
-    const int n = (int)tT.size();
-    auto at = [&](double T) {
-      if (T <= tT[0]) return tf[0];
-      if (T >= tT[n - 1]) return tf[n - 1];
-      int i = 1;
-      while (T > tT[i]) i++;
-      return tf[i - 1] + (T - tT[i - 1]) / (tT[i] - tT[i - 1]) * (tf[i] - tf[i - 1]);
-    };
-    double r = want_max ? std::max(at(T_lo), at(T_hi)) : std::min(at(T_lo), at(T_hi));
-    for (int i = 0; i < n; i++)
-      if (tT[i] > T_lo && tT[i] < T_hi) r = want_max ? std::max(r, tf[i]) : std::min(r, tf[i]);
-    return r;
-  };
-  const double fk_max = c->nkt ? extreme(c->h_ktab_T, c->h_ktab_f, true) : 1.0;
-  const double fc_min = c->nct ? extreme(c->h_ctab_T, c->h_ctab_f, false) : 1.0;
   hipStream_t s = (hipStream_t)stream;
-  fed::MassArgs ma{c->N, c->ne, c->d_incp, c->d_ince, c->d_mats, c->d_emat, c->d_ec0, c->d_V,
-                   T_lo, T_hi, c->d_M0, c->d_M1, c->d_Cmin, fc_min};
-  HIPCHK(fed::launch_mass(ma, s));
-  HIPCHK(hipMemsetAsync(c->d_lam, 0, sizeof(unsigned long long) * 2 * c->ninst, s));
-  fed::DtArgs da{c->ne, c->E, c->nrec, c->d_lamgeo, c->d_kscale, c->d_mats, c->d_emat, c->d_ec0,
-                 c->d_einst, c->d_recnode, c->d_ninst, c->d_b64[0], c->d_b64[2], c->d_Cmin,
-                 T_lo, T_hi, c->Tz, c->d_lam, c->d_lam + c->ninst, fk_max, fc_min};
-  HIPCHK(fed::launch_dt(da, s));
-  std::vector<unsigned long long> lam(2 * c->ninst);
-  HIPCHK(hipMemcpyAsync(lam.data(), c->d_lam, lam.size() * sizeof(unsigned long long),
-                        hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  std::vector<double> dtc(c->ninst);
-  for (int64_t i = 0; i < c->ninst; i++) {
-    double le, lb;
-    std::memcpy(&le, &lam[i], 8);
-    std::memcpy(&lb, &lam[c->ninst + i], 8);
-    dtc[i] = le + lb > 0 ? 2.0 / (le + lb) : INFINITY;
-  }
+  std::vector<double> dtc;
+  int rc = bound_dt(c, T_lo, T_hi, dtc, s);
+  if (rc) return rc;
   c->dt_crit = dtc;
   c->T_lo = T_lo;
   c->T_hi = T_hi;
-  c->fk_max = fk_max;
-  c->fc_min = fc_min;
+  c->fk_max = c->nkt ? table_extreme(c->h_ktab_T, c->h_ktab_f, T_lo, T_hi, true) : 1.0;
+  c->fc_min = c->nct ? table_extreme(c->h_ctab_T, c->h_ctab_f, T_lo, T_hi, false) : 1.0;
+  rc = derive_window(c, s);
+  if (rc) return rc;
+  // the new window starts clean
+  HIPCHK(fed::launch_health(c->d_health, 3, 0, s));
+  HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  HIPCHK(hipStreamSynchronize(s));
   for (int64_t i = 0; i < c->ninst; i++)
     if (c->dt_used[i] > c->dt_crit[i] && !c->allow_unstable)
       return fail(FED_E_UNSTABLE, "dt %.6g exceeds dt_crit %.6g on [%g, %g] (instance %lld)",

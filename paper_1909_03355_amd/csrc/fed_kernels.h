@@ -94,6 +94,22 @@ struct NodeArrArgs {
   void *rA, *rAT, *reA, *rTa, *rP;  // R[nrec]
 };
 
+// In-run health check (Sec. 3.4: the stability bound holds for temperatures
+// in [T_lo, T_hi]): the step kernels record the first step after which a
+// temperature left the window or was not finite, and at chosen steps the
+// energy balance of the explicit update.  One record per context, written by
+// the kernels and read by the host at synchronising calls.
+struct Health {
+  unsigned long long first_bad;  // smallest step count after which a temperature was
+                                 // outside the window or not finite; ~0 = none
+  long long base;                // step count at the start of the graph replay in flight
+  double energy_max;             // largest relative energy residual of the checks
+  long long energy_step;         // step count of that check (-1 = none)
+  long long checks;              // energy checks folded
+  unsigned int done;             // tiles that have written their partial sums (this check)
+  unsigned int pad_;
+};
+
 struct StepArgs {
   int prec, ne;
   int k;                      // steps this launch advances (1..tiling depth)
@@ -118,6 +134,16 @@ struct StepArgs {
   const void *ktab, *ctab;    // nullable R[2 n]: shared multiplier tables of D and c
   int nkt, nct;
   int op;                     // element operator: 0 folded 3x3, 1 uniform-gradient hexahedron
+  // health check (nullable hl: none).  The launch's steps are step0 + 1 ..
+  // step0 + k (plus hl->base when hbase != 0, in graph replays); energy != 0:
+  // the launch's last step is an energy check, each tile adding its partial
+  // sums to hpart[tile] and the last tile folding them in tile order
+  Health *hl;
+  double *hpart;              // [2 nt]
+  double win_lo, win_hi;
+  float win_lo_f, win_hi_f;   // the window rounded outward to FP32
+  long long step0;
+  int hbase, energy;
 };
 
 // One step of the discrete adjoint of the explicit update.
@@ -230,7 +256,8 @@ hipError_t launch_resident(const StepArgs &a, const ResArgs &r, hipStream_t s);
 hipError_t resident_prepare(const StepArgs &a, int *blocks_per_cu);
 hipError_t step_set_lds_limit(int prec, int ne, int tdk, int tdc, int gen, int op, int bytes);
 hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s);
-hipError_t adjres_prepare(int prec, int block, int lds, int *blocks_per_cu);
+// gen: the instance for property tables (else the linear laws only)
+hipError_t adjres_prepare(int prec, int gen, int block, int lds, int *blocks_per_cu);
 hipError_t launch_adjres(const AdjArgs &a, const AdjResArgs &r, hipStream_t s);
 hipError_t adjoint_set_lds_limit(int prec, int ne, int op, int bytes);
 // g_h[f] = -|f|/n_f * sum over the face's nodes of (S1 - Ta_f S0)
@@ -251,6 +278,10 @@ hipError_t launch_get_T(int prec, int64_t N, const int32_t *perm, const void *T,
                         const float *lo, double *Tuser, hipStream_t s);
 hipError_t launch_check(int prec, int64_t N, const void *T, const float *lo, double lo_b,
                         double hi_b, int *flag, hipStream_t s);
+// health record: op 0 reset (no bad step, no checks, base = 0), op 1 set the
+// graph replays' base step count to v, op 2 advance it by v, op 3 clear the
+// out-of-window record
+hipError_t launch_health(Health *h, int op, long long v, hipStream_t s);
 // gather/scatter of raw working arrays between caller and internal order
 // smallest / largest temperature as order keys (keys[0] must start at ~0,
 // keys[1] at 0); *nan |= 1 if a temperature is not finite

@@ -625,8 +625,8 @@ __device__ inline R node_sum(const R *v) {
 // evaluated at each node of the element from that node's temperature and the
 // nodal values are averaged for the element.  For the linear law s0 + s1 T
 // that average is s0 + s1 Tbar, which is how it is evaluated; the shared
-// multiplier table (n > 0) is evaluated at every node.  elem_d also returns
-// d s_e / d T_a times n_e (the law's slope at each node).
+// multiplier table (n > 0) is evaluated at every node.  slope(T_a) is
+// n_e d s_e / d T_a, the law's slope at node a.
 template <typename R>
 struct KLaw {
   R s0, s1;
@@ -636,25 +636,22 @@ struct KLaw {
   __device__ R elem(const R *T) const {
 #pragma clang fp contract(off)
     if (n) {
-      R f[NE], sl;
+      // summed node by node (one value live at a time)
+      R sl, f = table_eval(tab, n, T[0], sl);
 #pragma unroll
-      for (int a = 0; a < NE; a++) f[a] = table_eval(tab, n, T[a], sl);
-      return node_sum<R, NE>(f) * ((R)1 / (R)NE);
+      for (int a = 1; a < NE; a++) f = f + table_eval(tab, n, T[a], sl);
+      return f * ((R)1 / (R)NE);
     }
     return fma(s1, node_sum<R, NE>(T) * ((R)1 / (R)NE), s0);
   }
-  template <int NE>
-  __device__ R elem_d(const R *T, R ds[NE]) const {
-#pragma clang fp contract(off)
+  // the law's slope at one node temperature
+  __device__ R slope(R T) const {
     if (n) {
-      R f[NE];
-#pragma unroll
-      for (int a = 0; a < NE; a++) f[a] = table_eval(tab, n, T[a], ds[a]);
-      return node_sum<R, NE>(f) * ((R)1 / (R)NE);
+      R sl;
+      (void)table_eval(tab, n, T, sl);
+      return sl;
     }
-#pragma unroll
-    for (int a = 0; a < NE; a++) ds[a] = s1;
-    return fma(s1, node_sum<R, NE>(T) * ((R)1 / (R)NE), s0);
+    return s1;
   }
 };
 
@@ -927,6 +924,134 @@ __device__ inline R cap_den(R alpha, R beta, R T, const R *ctab, int nct) {
   return fma(beta, T, alpha);
 }
 
+// ---- in-run health check ----------------------------------------------------
+// (a temperature outside [win_lo, win_hi], the range the stability bound of
+// Sec. 3.4 was derived for widened by the caller's margin, or not finite)
+template <typename R>
+__device__ inline bool outside(R T, R lo, R hi) {
+  return !(T >= lo && T <= hi);
+}
+
+// the window in the working precision (kernel arguments: scalar registers)
+template <typename R>
+__device__ inline R win_lo(const StepArgs &a) {
+  if constexpr (sizeof(R) == 4) return a.win_lo_f;
+  else return a.win_lo;
+}
+template <typename R>
+__device__ inline R win_hi(const StepArgs &a) {
+  if constexpr (sizeof(R) == 4) return a.win_hi_f;
+  else return a.win_hi;
+}
+
+// the launch's step count before its first step (graph replays add the base
+// the replay started from)
+__device__ inline long long health_step0(const StepArgs &a) {
+  return a.step0 + (a.hbase ? __hip_atomic_load(&a.hl->base, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                            : 0LL);
+}
+
+// records that a temperature left the window after step count n
+__device__ inline void health_bad(const StepArgs &a, long long n) {
+  __hip_atomic_fetch_min(&a.hl->first_bad, (unsigned long long)n, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Energy balance of one owned node after its update (summed over all nodes it
+// is zero: the explicit update gives den dT = Q - F at every node that is not
+// Dirichlet, and the conductive loads F of every element sum to zero, so
+// sum_{not Dirichlet} (den dT - Q) - sum_{Dirichlet} F = -sum_k F_k = 0).  r
+// collects the terms, s their magnitudes and |F|.
+template <typename R, int MODE>
+__device__ inline void energy_terms(R den, R Q, R F, R hi0, float lo0, R hi1, float lo1,
+                                    double &r, double &s) {
+  const double f = (double)F;
+  if (!(den < (R)INFINITY)) {  // Dirichlet: den = +inf, T held
+    r -= f;
+    s += fabs(f);
+    return;
+  }
+  double dT = (double)hi1 - (double)hi0;
+  if (MODE == 1) dT += (double)lo1 - (double)lo0;
+  const double e = (double)den * dT, q = (double)Q;
+  r += e - q;
+  s += (fabs(e) + fabs(q)) + fabs(f);
+}
+
+// Sum of (r, s) over the block in a fixed order, valid in thread 0 (every
+// thread of the block calls it).
+__device__ inline void block_sum2(double &r, double &s, double *red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    r += __shfl_xor(r, o, 64);
+    s += __shfl_xor(s, o, 64);
+  }
+  const int w = threadIdx.x >> 6, nw = (int)(blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * w] = r;
+    red[2 * w + 1] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    r = 0.0;
+    s = 0.0;
+    for (int i = 0; i < nw; i++) {
+      r += red[2 * i];
+      s += red[2 * i + 1];
+    }
+  }
+}
+
+__device__ inline void st_f64(double *p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                     (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_f64(const double *p) {
+  return __longlong_as_double((long long)__hip_atomic_load(
+      reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Energy check at step count n: tile t adds its partial sums (r, s) (each
+// thread's share); the last tile to arrive folds every tile's sums in tile
+// order (deterministic for a given block size) and keeps the largest
+// relative residual |sum r| / sum s of the checks.  Every thread of a tile
+// block calls it.
+__device__ inline void health_energy(const StepArgs &a, int t, double r, double s, long long n) {
+  __shared__ double red[2 * 16];
+  __shared__ int last;
+  block_sum2(r, s, red);
+  if (threadIdx.x == 0) {
+    st_f64(a.hpart + 2 * t, r);
+    st_f64(a.hpart + 2 * t + 1, s);
+    __threadfence();
+    last = __hip_atomic_fetch_add(&a.hl->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+           (unsigned)(a.nt - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  r = 0.0;
+  s = 0.0;
+  for (int i = threadIdx.x; i < a.nt; i += blockDim.x) {
+    r += ld_f64(a.hpart + 2 * i);
+    s += ld_f64(a.hpart + 2 * i + 1);
+  }
+  block_sum2(r, s, red);
+  if (threadIdx.x == 0) {
+    Health *h = a.hl;
+    const double rho = s > 0.0 ? fabs(r) / s : fabs(r);
+    const double mx = ld_f64(&h->energy_max);
+    if (!isnan(mx) && !(rho <= mx)) {
+      st_f64(&h->energy_max, rho);
+      __hip_atomic_store(&h->energy_step, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __hip_atomic_fetch_add(&h->checks, 1LL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&h->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // per-node coefficients of the update
 template <typename R>
 struct NodeData {
@@ -1134,9 +1259,14 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
     elements_from_global<R, NE, TDK, GEN, EPT>(a, th, EPT * bs, nE1, Tl, slot, nU, nU1, pmask, kl);
   }
   __syncthreads();
+  // health: the first sub-step at which an owned node of the wave left the
+  // window (wave-uniform, a scalar register)
+  int bad = 0;
+  const R wlo = win_lo<R>(a), whi = win_hi<R>(a);
   for (int s = 1;; s++) {
     const int nUs = cum_n[k - s];
     const bool last = s == k;  // then nUs == nown
+    bool out = false;
     // NPT nodes per thread at a time: coefficient and record loads first
     constexpr int NPT = sizeof(R) == 4 ? 4 : 1;
     for (int base = 0; base < nUs; base += NPT * bs) {
@@ -1156,6 +1286,8 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
         const R Tn = node_update<R, MODE, TDC>(d[q], j, a.maxinc, nU, T, lo, slot, Tz,
                                                GEN ? (const R *)a.ctab : nullptr, GEN ? a.nct : 0,
                                                lo_new);
+        // owned nodes (the others are checked by their owners)
+        out = out || (j < nown && outside(Tn, wlo, whi));
         if (last) {
           Tout[th.nstart + j] = Tn;
           if (MODE == 1) a.loout[th.nstart + j] = lo_new;
@@ -1165,7 +1297,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
         }
       }
     }
-    if (last) break;
+    if (!bad && __ballot(out)) bad = s;
+    if (last) {
+      if (a.hl && bad && (tid & 63) == 0) health_bad(a, health_step0(a) + bad);
+      break;
+    }
     __syncthreads();
     const int nUn = cum_n[k - s - 1], nEn = cum_e[k - s - 1];
     elements_from_global<R, NE, TDK, GEN, EPT>(a, th, 0, nEn, Tl, slot, nU, nUn, pmask, kl);
@@ -1226,7 +1362,7 @@ __device__ inline float quotient<float>(float num, float den) {
 // Returns the new hi; lo_new receives the new lo of the compensated mode.
 template <typename R, int MODE, bool TDC>
 __device__ inline R advance(const Node1<R> &d, bool bnd, R T, R F, R Tz, const R *ctab, int nct,
-                           float &lo_new) {
+                           float &lo_new, R &Qo, R &deno) {
 #pragma clang fp contract(off)
   R Q = 0;
   if (bnd) {
@@ -1236,6 +1372,8 @@ __device__ inline R advance(const Node1<R> &d, bool bnd, R T, R F, R Tz, const R
   }
   R den = d.alpha;
   if (TDC) den = cap_den(d.alpha, d.beta, T, ctab, nct);
+  Qo = Q;
+  deno = den;
   const R dT = quotient<R>(Q - F, den);
   if (MODE == 1) {
     // compensated accumulation: T = hi + lo, Fast2Sum of hi and (dT + lo)
@@ -1257,16 +1395,22 @@ __device__ inline R slot_sum(const R *slot, int j, int nown, int maxinc) {
   return F;
 }
 
+// bad: the new temperature is outside the health window; r, s: the node's
+// energy terms (when the launch checks the energy balance)
 template <typename R, int MODE, bool TDC, bool GEN>
 __device__ inline void update1(const StepArgs &a, const TileHdr &th, int j, const Node1<R> &d,
-                               const R *Tl, const R *slot, R Tz) {
+                               const R *Tl, const R *slot, R Tz, bool &bad, double &r, double &s) {
   const int k = th.nstart + j;
   const R F = slot_sum(slot, j, th.nown, a.maxinc);
   float lo_new;
-  const R hi = advance<R, MODE, TDC>(d, j < th.nbnd, Tl[j], F, Tz, GEN ? (const R *)a.ctab : nullptr,
-                                     GEN ? a.nct : 0, lo_new);
+  R Q, den;
+  const R T0 = Tl[j];
+  const R hi = advance<R, MODE, TDC>(d, j < th.nbnd, T0, F, Tz, GEN ? (const R *)a.ctab : nullptr,
+                                     GEN ? a.nct : 0, lo_new, Q, den);
   ((R *)a.Tout)[k] = hi;
   if (MODE == 1) a.loout[k] = lo_new;
+  if (outside(hi, win_lo<R>(a), win_hi<R>(a))) bad = true;
+  if (a.energy) energy_terms<R, MODE>(den, Q, F, T0, d.lo, hi, lo_new, r, s);
 }
 
 template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN, int OP = 0>
@@ -1334,15 +1478,23 @@ __global__ __launch_bounds__(1024) void k_step1(StepArgs a) {
   __syncthreads();
   // ---- per node: ordered sum, surface loads, explicit update ----
   const R Tz = (R)a.Tz;
+  bool bad = false;
+  double er = 0.0, es = 0.0;
 #pragma unroll
   for (int q = 0; q < NPT; q++) {
     const int j = tid + q * bs;
-    if (j < nown) update1<R, MODE, TDC, GEN>(a, th, j, nd[q], Tl, slot, Tz);
+    if (j < nown) update1<R, MODE, TDC, GEN>(a, th, j, nd[q], Tl, slot, Tz, bad, er, es);
   }
   for (int j = tid + NPT * bs; j < nown; j += bs) {
     Node1<R> d;
     load_node1<R, MODE, TDC>(a, th, j, d);
-    update1<R, MODE, TDC, GEN>(a, th, j, d, Tl, slot, Tz);
+    update1<R, MODE, TDC, GEN>(a, th, j, d, Tl, slot, Tz, bad, er, es);
+  }
+  // ---- health: the window, and the energy balance at a check step ----
+  if (a.hl) {
+    const long long n = health_step0(a) + 1;
+    if (bad) health_bad(a, n);
+    if (a.energy) health_energy(a, t, er, es, n);
   }
 }
 
@@ -1516,14 +1668,13 @@ __device__ inline void adj_elem(const uint32_t *loc, const R *h, const KLaw<R> &
                                 bool owner, const R *Lmu, const R *LT, const R *Lw, R F[NE],
                                 R &se, R &muKT, R &gsum) {
 #pragma clang fp contract(off)
-  // s_e and n_e d s_e / d T_a from T^n, as in the forward load
+  // s_e from T^n, as in the forward load
   se = kle.s0;
-  R dse[NE];
   if (tdk) {
     R Te[NE];
 #pragma unroll
     for (int n = 0; n < NE; n++) Te[n] = LT[loc[n]];
-    se = kle.template elem_d<NE>(Te, dse);
+    se = kle.template elem<NE>(Te);
   }
   muKT = (R)0;
   if constexpr (OP == 0) {
@@ -1544,10 +1695,13 @@ __device__ inline void adj_elem(const uint32_t *loc, const R *h, const KLaw<R> &
     if (tdk || owner) muKT = AdjDot<R, NE, OP>::dot(Lmu, LT, loc, h);
     Op<R, NE, OP>::load(Lmu, loc, KLaw<R>{se, (R)0, nullptr, 0}, false, h, F);
   }
-  if (tdk) {
+  // n_e d s_e / d T_a is the law's slope at node a: s1 for the linear law (the
+  // same term at every node), the table's slope at T_a (taken here, not kept
+  // from above, so the slopes hold no registers through the element work)
+  const R spread = tdk && !kle.n ? kle.s1 * ((R)1 / (R)NE) * muKT : (R)0;
 #pragma unroll
-    for (int n = 0; n < NE; n++) F[n] = F[n] + dse[n] * ((R)1 / (R)NE) * muKT;
-  }
+  for (int n = 0; n < NE; n++)
+    F[n] = F[n] + (tdk && kle.n ? kle.slope(LT[loc[n]]) * ((R)1 / (R)NE) * muKT : spread);
   gsum = (R)0;
   if (owner) {
 #pragma unroll
@@ -1608,7 +1762,9 @@ __device__ inline R adj_dden(R alpha, R beta, R tn, const R *ctab, int nct) {
   return alpha * sl;
 }
 
-template <typename R, int NE, int MODE, int OP = 0>
+// GEN: the instance for property tables and per-element laws; the others
+// compile the shared linear laws only (no table code, fewer registers)
+template <typename R, int NE, int MODE, int OP = 0, bool GEN = true>
 __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   constexpr int HW = Op<R, NE, OP>::W;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1629,11 +1785,12 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   const R *beta = (const R *)a.beta;
   const R *Tn = (const R *)a.Tn, *Tn1 = (const R *)a.Tn1;
   const bool tdk = a.tdk != 0, tdc = a.tdc != 0;
-  const R *ctab = (const R *)a.ctab;
+  const R *ctab = GEN ? (const R *)a.ctab : nullptr;
+  const int nct = GEN ? a.nct : 0;
   for (int j = tid; j < ntouch; j += bs) {
     const int g = j < nown ? th.nstart + j : a.halo[th.hstart + j - nown];
     const R tn = Tn[g];
-    adj_stage<R>(lam[g], alpha[g], tdc ? beta[g] : (R)0, tn, Tn1[g], rdt[g], tdc, ctab, a.nct,
+    adj_stage<R>(lam[g], alpha[g], tdc ? beta[g] : (R)0, tn, Tn1[g], rdt[g], tdc, ctab, nct,
                  Lmu[j], Lw[j]);
     LT[j] = tn;
   }
@@ -1644,7 +1801,8 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
   const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
   const R *Hb = (const R *)a.H;
   const R *mV = (const R *)a.mV;
-  const KLaw<R> kl = KLaw<R>{(R)a.s0, (R)a.s1, (const R *)a.ktab, a.nkt};
+  const KLaw<R> kl = GEN ? KLaw<R>{(R)a.s0, (R)a.s1, (const R *)a.ktab, a.nkt}
+                         : KLaw<R>{(R)a.s0, (R)a.s1, nullptr, 0};
   const uint32_t pmask = (1u << a.pb) - 1u;
   for (int i = tid; i < nE; i += bs) {
     const int64_t e = (int64_t)th.estart + i;
@@ -1658,7 +1816,7 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
     for (int n = 0; n < NE; n++) loc[n] = v[n] >> a.pb;
     const bool owner = a.eowner[e] != 0;
     R F[NE], se, muKT, gsum;
-    adj_elem<R, NE, OP>(loc, h, elem_law<true>(a, kl, e), tdk, owner, Lmu, LT, Lw, F, se, muKT,
+    adj_elem<R, NE, OP>(loc, h, elem_law<GEN>(a, kl, e), tdk, owner, Lmu, LT, Lw, F, se, muKT,
                         gsum);
 #pragma unroll
     for (int n = 0; n < NE; n++)
@@ -1681,7 +1839,7 @@ __global__ __launch_bounds__(1024) void k_adjoint1(AdjArgs a) {
     const R mu = Lmu[j], tn = LT[j], tn1 = Tn1[k];
     const bool bnd = j < th.nbnd;
     const int r = th.bstart + j;
-    const R dden = tdc ? adj_dden<R>(alpha[k], beta[k], tn, ctab, a.nct) : (R)0;
+    const R dden = tdc ? adj_dden<R>(alpha[k], beta[k], tn, ctab, nct) : (R)0;
     const R d = adj_node<R>(F, mu, bnd, bnd ? rA[r] : (R)0, bnd ? reA[r] : (R)0, tn, tn1, Tz, tdc,
                             dden);
     if (bnd) {
@@ -1758,6 +1916,26 @@ __global__ void k_check(int64_t N, const R *T, const float *lo, double lo_b, dou
   double v = (double)T[k];
   if (MODE == 1) v += (double)lo[k];
   if (!(v >= lo_b && v <= hi_b)) atomicOr(flag, 1);  // also catches NaN
+}
+
+// health record: op 0 resets it, op 1 sets the graph replays' base step count
+// to v, op 2 advances it by v (the last node of a captured graph), op 3
+// clears the out-of-window record (a new window)
+__global__ void k_health(Health *h, int op, long long v) {
+  if (op == 3) {
+    h->first_bad = ~0ull;
+  } else if (op == 0) {
+    h->first_bad = ~0ull;
+    h->base = 0;
+    h->energy_max = 0.0;
+    h->energy_step = -1;
+    h->checks = 0;
+    h->done = 0;
+  } else if (op == 1) {
+    h->base = v;
+  } else {
+    h->base += v;
+  }
 }
 
 // Order-preserving unsigned key of a double (larger key, larger value).
@@ -2072,6 +2250,11 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   };
   // the elements with every node owned come first in the tile's list
   const int nint = r.split ? th.nint : 0;
+  // health: the first step at which a temperature of the wave's nodes left
+  // the window (wave-uniform, so it lives in a scalar register); the energy
+  // check runs in the one-step kernel
+  int bad = -1;
+  const R wlo = win_lo<R>(a), whi = win_hi<R>(a);
   // every load above completes here, once: otherwise the compiler waits for
   // them at their first use inside the loop, on every step, and such a wait
   // (vmcnt counts stores too) would also hold the interior elements until the
@@ -2145,6 +2328,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     // after the elements with every node owned, which read only owned T)
     unsigned long long *Xw = r.X[(s + 1) & 1];
     const unsigned tag = r.tag0 + (unsigned)s + 1u;
+    bool out = false;
 #pragma unroll
     for (int q = 0; q < NPT; q++) {
       const int j = tid + q * bs;
@@ -2164,13 +2348,16 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
           d.bP = Lbnd[4 * nbnd + j];
         }
         float lo_new;
+        R Q, den;
         hi[q] = advance<R, MODE, TDC>(d, bnd, hi[q], F, Tz, GEN ? (const R *)a.ctab : nullptr,
-                                      GEN ? a.nct : 0, lo_new);
+                                      GEN ? a.nct : 0, lo_new, Q, den);
+        out = out || outside(hi[q], wlo, whi);  // health: the window
         lo[q] = lo_new;
         if (ex[q]) Words<R>::put(Xw, th.nstart + j, tag, hi[q]);
         if (r.seg) ((R *)r.seg)[(int64_t)(s + 1) * r.segN + th.nstart + j] = hi[q];
       }
     }
+    if (bad < 0 && __ballot(out)) bad = s;
   }
   // ---- final state of the owned nodes ----
   R *Tf = (R *)r.Tfin;
@@ -2182,6 +2369,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       if (MODE == 1) r.lofin[th.nstart + j] = lo[q];
     }
   }
+  if (a.hl && bad >= 0 && (tid & 63) == 0) health_bad(a, health_step0(a) + bad + 1);
 }
 
 // Resident adjoint: one cooperative launch runs the adjoint steps n1-1 .. n0
@@ -2195,7 +2383,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
 // tagged exchange words (the tiles and their neighbour relation are the
 // forward's).  The arithmetic is that of k_adjoint1, so both give
 // bitwise-identical multipliers and derivatives.
-template <typename R, int MODE>
+template <typename R, int MODE, bool GEN>
 __global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
   constexpr int NE = 8;
   constexpr int EPT = ResCap<R, NE>::EPT, NPT = ResCap<R, NE>::NPT, HPT = ResCap<R, NE>::HPT;
@@ -2231,7 +2419,8 @@ __global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
   const int sstride = (1 << a.pb) + 1, nslot = ntouch * sstride;
   R *LrA = slot + nslot;
   R *LreA = LrA + nbnd;
-  const R *ctab = (const R *)a.ctab;
+  const R *ctab = GEN ? (const R *)a.ctab : nullptr;
+  const int nct = GEN ? a.nct : 0;
   using EntT = typename Ent<NE>::T;
   const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
   const R *Hb = (const R *)a.H;
@@ -2307,7 +2496,8 @@ __global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
     for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
   }
   __syncthreads();
-  const KLaw<R> kl = KLaw<R>{(R)a.s0, (R)a.s1, (const R *)a.ktab, a.nkt};
+  const KLaw<R> kl = GEN ? KLaw<R>{(R)a.s0, (R)a.s1, (const R *)a.ktab, a.nkt}
+                         : KLaw<R>{(R)a.s0, (R)a.s1, nullptr, 0};
   const R Tz = (R)a.Tz;
   const uint32_t pmask = (1u << a.pb) - 1u;
   R *LT = LTa, *LTp = LTb;  // T^n, T^{n+1}
@@ -2335,7 +2525,7 @@ __global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
     for (int q = 0; q < NPT; q++) {
       const int j = tid + q * bs;
       if (j < nown) {
-        adj_stage<R>(lam[q], Lal[j], tdc ? Lbe[j] : (R)0, tno[q], LTp[j], Lrdt[j], tdc, ctab, a.nct,
+        adj_stage<R>(lam[q], Lal[j], tdc ? Lbe[j] : (R)0, tno[q], LTp[j], Lrdt[j], tdc, ctab, nct,
                      Lmu[j], Lw[j]);
         LT[j] = tno[q];
       }
@@ -2344,7 +2534,7 @@ __global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
     for (int q = 0; q < HPT; q++) {
       const int j = nown + tid + q * bs;
       if (j < ntouch) {
-        adj_stage<R>(hv[q], Lal[j], tdc ? Lbe[j] : (R)0, tnh[q], LTp[j], Lrdt[j], tdc, ctab, a.nct,
+        adj_stage<R>(hv[q], Lal[j], tdc ? Lbe[j] : (R)0, tnh[q], LTp[j], Lrdt[j], tdc, ctab, nct,
                      Lmu[j], Lw[j]);
         LT[j] = tnh[q];
       }
@@ -2381,7 +2571,7 @@ __global__ __launch_bounds__(1024) void k_adjres(AdjArgs a, AdjResArgs r) {
         const R F = slot_sum(slot + j * sstride, 0, 1, a.maxinc);
         const R mu = Lmu[j], tn = LT[j], tn1 = LTp[j], al = Lal[j];
         const bool bnd = j < nbnd;
-        const R dden = tdc ? adj_dden<R>(al, Lbe[j], tn, ctab, a.nct) : (R)0;
+        const R dden = tdc ? adj_dden<R>(al, Lbe[j], tn, ctab, nct) : (R)0;
         const R d = adj_node<R>(F, mu, bnd, bnd ? LrA[j] : (R)0, bnd ? LreA[j] : (R)0, tn, tn1, Tz,
                                 tdc, dden);
         if (bnd) adj_bnd<R>(LS0[j], LS1[j], mu, tn);
@@ -2551,6 +2741,11 @@ hipError_t launch_check(int prec, int64_t N, const void *T, const float *lo, dou
   return hipGetLastError();
 }
 
+hipError_t launch_health(Health *h, int op, long long v, hipStream_t s) {
+  hipLaunchKernelGGL(k_health, dim3(1), dim3(1), 0, s, h, op, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_range(int prec, int64_t N, const void *T, const float *lo,
                         unsigned long long *keys, int *nan, hipStream_t s) {
   dim3 g(blocks_for(N, 256)), b(256);
@@ -2620,14 +2815,19 @@ hipError_t launch_resident(const StepArgs &a, const ResArgs &r, hipStream_t s) {
                                     (unsigned)a.lds, s);
 }
 
-const void *adjres_kernel(int prec) {
-  if (prec == 1) return (const void *)k_adjres<double, 0>;
-  if (prec == 0) return (const void *)k_adjres<float, 1>;
-  return (const void *)k_adjres<float, 0>;
+const void *adjres_kernel(int prec, bool gen) {
+  if (gen) {
+    if (prec == 1) return (const void *)k_adjres<double, 0, true>;
+    if (prec == 0) return (const void *)k_adjres<float, 1, true>;
+    return (const void *)k_adjres<float, 0, true>;
+  }
+  if (prec == 1) return (const void *)k_adjres<double, 0, false>;
+  if (prec == 0) return (const void *)k_adjres<float, 1, false>;
+  return (const void *)k_adjres<float, 0, false>;
 }
 
-hipError_t adjres_prepare(int prec, int block, int lds, int *blocks_per_cu) {
-  const void *f = adjres_kernel(prec);
+hipError_t adjres_prepare(int prec, int gen, int block, int lds, int *blocks_per_cu) {
+  const void *f = adjres_kernel(prec, gen != 0);
   hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds);
@@ -2637,49 +2837,49 @@ hipError_t launch_adjres(const AdjArgs &a, const AdjResArgs &r, hipStream_t s) {
   AdjArgs aa = a;
   AdjResArgs rr = r;
   void *args[] = {(void *)&aa, (void *)&rr};
-  return hipLaunchCooperativeKernel(adjres_kernel(a.prec), dim3(8 * a.nper), dim3(a.block), args,
-                                    (unsigned)a.lds, s);
+  return hipLaunchCooperativeKernel(adjres_kernel(a.prec, a.ktab || a.ctab || a.esk),
+                                    dim3(8 * a.nper), dim3(a.block), args, (unsigned)a.lds, s);
+}
+
+// the one-step adjoint instance of (precision, element, operator, laws)
+template <bool GEN>
+const void *adjoint_kernel_t(int prec, int ne, int op) {
+  if (ne == 8 && op == 1)
+    return prec == 1 ? (const void *)k_adjoint1<double, 8, 0, 1, GEN>
+                     : (prec == 0 ? (const void *)k_adjoint1<float, 8, 1, 1, GEN>
+                                  : (const void *)k_adjoint1<float, 8, 0, 1, GEN>);
+  if (ne == 8 && op == 2)
+    return prec == 1 ? (const void *)k_adjoint1<double, 8, 0, 2, GEN>
+                     : (prec == 0 ? (const void *)k_adjoint1<float, 8, 1, 2, GEN>
+                                  : (const void *)k_adjoint1<float, 8, 0, 2, GEN>);
+  if (prec == 1)
+    return ne == 8 ? (const void *)k_adjoint1<double, 8, 0, 0, GEN>
+                   : (const void *)k_adjoint1<double, 4, 0, 0, GEN>;
+  if (prec == 0)
+    return ne == 8 ? (const void *)k_adjoint1<float, 8, 1, 0, GEN>
+                   : (const void *)k_adjoint1<float, 4, 1, 0, GEN>;
+  return ne == 8 ? (const void *)k_adjoint1<float, 8, 0, 0, GEN>
+                 : (const void *)k_adjoint1<float, 4, 0, 0, GEN>;
+}
+
+const void *adjoint_kernel(int prec, int ne, int op, bool gen) {
+  return gen ? adjoint_kernel_t<true>(prec, ne, op) : adjoint_kernel_t<false>(prec, ne, op);
 }
 
 hipError_t launch_adjoint(const AdjArgs &a, hipStream_t s) {
-  dim3 g(8 * a.nper), b(a.block);
-  if (a.ne == 8 && a.op == 1) {
-    if (a.prec == 1) hipLaunchKernelGGL((k_adjoint1<double, 8, 0, 1>), g, b, a.lds, s, a);
-    else if (a.prec == 0) hipLaunchKernelGGL((k_adjoint1<float, 8, 1, 1>), g, b, a.lds, s, a);
-    else hipLaunchKernelGGL((k_adjoint1<float, 8, 0, 1>), g, b, a.lds, s, a);
-    return hipGetLastError();
-  }
-  if (a.ne == 8 && a.op == 2) {
-    if (a.prec == 1) hipLaunchKernelGGL((k_adjoint1<double, 8, 0, 2>), g, b, a.lds, s, a);
-    else if (a.prec == 0) hipLaunchKernelGGL((k_adjoint1<float, 8, 1, 2>), g, b, a.lds, s, a);
-    else hipLaunchKernelGGL((k_adjoint1<float, 8, 0, 2>), g, b, a.lds, s, a);
-    return hipGetLastError();
-  }
-  if (a.prec == 1) {
-    if (a.ne == 8) hipLaunchKernelGGL((k_adjoint1<double, 8, 0>), g, b, a.lds, s, a);
-    else hipLaunchKernelGGL((k_adjoint1<double, 4, 0>), g, b, a.lds, s, a);
-  } else if (a.prec == 0) {
-    if (a.ne == 8) hipLaunchKernelGGL((k_adjoint1<float, 8, 1>), g, b, a.lds, s, a);
-    else hipLaunchKernelGGL((k_adjoint1<float, 4, 1>), g, b, a.lds, s, a);
-  } else {
-    if (a.ne == 8) hipLaunchKernelGGL((k_adjoint1<float, 8, 0>), g, b, a.lds, s, a);
-    else hipLaunchKernelGGL((k_adjoint1<float, 4, 0>), g, b, a.lds, s, a);
-  }
-  return hipGetLastError();
+  AdjArgs aa = a;
+  void *args[] = {(void *)&aa};
+  return hipLaunchKernel(adjoint_kernel(a.prec, a.ne, a.op, a.ktab || a.ctab || a.esk),
+                         dim3(8 * a.nper), dim3(a.block), args, (size_t)a.lds, s);
 }
 
 hipError_t adjoint_set_lds_limit(int prec, int ne, int op, int bytes) {
-  const void *f;
-  if (ne == 8 && op == 1)
-    f = prec == 1 ? (const void *)k_adjoint1<double, 8, 0, 1>
-                  : (prec == 0 ? (const void *)k_adjoint1<float, 8, 1, 1> : (const void *)k_adjoint1<float, 8, 0, 1>);
-  else if (ne == 8 && op == 2)
-    f = prec == 1 ? (const void *)k_adjoint1<double, 8, 0, 2>
-                  : (prec == 0 ? (const void *)k_adjoint1<float, 8, 1, 2> : (const void *)k_adjoint1<float, 8, 0, 2>);
-  else if (prec == 1) f = ne == 8 ? (const void *)k_adjoint1<double, 8, 0> : (const void *)k_adjoint1<double, 4, 0>;
-  else if (prec == 0) f = ne == 8 ? (const void *)k_adjoint1<float, 8, 1> : (const void *)k_adjoint1<float, 4, 1>;
-  else f = ne == 8 ? (const void *)k_adjoint1<float, 8, 0> : (const void *)k_adjoint1<float, 4, 0>;
-  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  for (int g = 0; g < 2; g++) {
+    hipError_t e = hipFuncSetAttribute(adjoint_kernel(prec, ne, op, g != 0),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_face_grad(int64_t nf, int nfn, const int32_t *faces, const int32_t *perm,

@@ -69,10 +69,13 @@ def current_stream():
 
 class Simulation:
     def __init__(self, prob, prec="fp32c", tile_nodes=0, block_threads=0, fuse_steps=0,
-                 allow_unstable=False, stream=None, resident=False, allocator="torch"):
+                 allow_unstable=False, stream=None, resident=False, allocator="torch",
+                 check_margin=None, check_every=0, energy_tol=0.0):
         """allocator: "torch" takes the device memory from torch's caching
         allocator (the default when torch sees a GPU), "hip" lets the library
-        call hipMalloc."""
+        call hipMalloc.  check_margin, check_every, energy_tol: the in-run
+        health check (fed_options in include/fedfem.h); check_margin None: the
+        window the stability bound allows, a number: [T_lo - m, T_hi + m]."""
         lib = L.lib()
         self._ctx = None
         self.prec = prec
@@ -147,6 +150,10 @@ class Simulation:
         if self._hooks is not None:
             # the callbacks live as long as the context (self._hooks)
             opt.dev_alloc, opt.dev_free = self._hooks
+        opt.check_window = 0 if check_margin is None else 1
+        opt.check_margin = 0.0 if check_margin is None else float(check_margin)
+        opt.check_every = int(check_every)
+        opt.energy_tol = float(energy_tol)
         self.allocator = "torch" if self._hooks is not None else "hip"
         ctx = C.c_void_p()
         L.check(lib.fed_create(C.byref(mesh), C.byref(mats), C.byref(bcs), C.byref(opt),
@@ -198,6 +205,13 @@ class Simulation:
         L.check(L.lib().fed_get_temperature(self._c(), T.ctypes.data_as(C.c_void_p), 0,
                                             self.stream))
         return T
+
+    def health(self):
+        """The in-run health record (synchronises): steps, first_bad_step (-1
+        if none), the window, energy_residual, energy_step, energy_checks."""
+        h = L.fed_health()
+        L.check(L.lib().fed_health_get(self._c(), C.byref(h), self.stream))
+        return {k: getattr(h, k) for k, _ in L.fed_health._fields_}
 
     @property
     def device_bytes(self):

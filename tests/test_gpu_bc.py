@@ -31,6 +31,9 @@ def _oracle_schedule(p, schedule):
 
 def test_step_change_of_ambient_and_flux():
     p = P.cube_nonlinear_hex(8, 60)
+    # the tripled flux heats the patch past 1000 C: a range that holds the run
+    # (the stability bound, and so dt, follow it; the oracle reads the same)
+    p["T_hi"] = 2500.0
     Ta2 = p["face_Ta"] + 25.0                       # radiating faces keep a common Ta
     q2 = 3.0 * p["face_q"] + np.where(p["face_eps"] > 0, 2000.0, 0.0)
     ref = _oracle_schedule(p, [({}, 30), (dict(face_Ta=Ta2, face_q=q2), 30)])
