@@ -217,7 +217,9 @@ def cpu_info():
 
 def golden_error(name, sim_factory, steps):
     """err_max of a fresh run of the workload's full step count against the
-    oracle's stored temperatures at sampled nodes (tests/golden), or None."""
+    oracle's stored temperatures at sampled nodes (tests/golden), with the
+    health record of that run, or None.  sim_factory(check_every) makes the
+    simulation."""
     sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
     try:
         import make_golden as G
@@ -227,16 +229,19 @@ def golden_error(name, sim_factory, steps):
     if gsteps is None or not os.path.exists(G.path_of(name, gsteps)):
         return None
     head, ids, vals = G.read(name, gsteps)
-    with sim_factory() as sim:
+    # ten energy checks along the run (each in the one-step kernel)
+    with sim_factory(max(1, gsteps // 10)) as sim:
         sim.set_temperature()
         sim.step(gsteps, graph_steps=100)
         T = sim.temperature()
-        health = sim.health() if hasattr(sim, "health") else None
+        health = sim.health()
     err = float(np.max(np.abs(T[ids] - vals)) / float(head["max_abs"]))
     out = {"err_max": err, "steps": gsteps, "nodes": int(ids.size),
            "reference": f"tests/golden/{name}_{gsteps}.txt (oracle, sampled nodes)"}
-    if health is not None:
-        out["energy_residual"] = health["energy_residual"]
+    out["energy_residual"] = health["energy_residual"]
+    out["energy_checks"] = health["energy_checks"]
+    out["first_step_outside_window"] = health["first_bad_step"]
+    out["window"] = [health["window_lo"], health["window_hi"]]
     return out
 
 
@@ -344,7 +349,8 @@ def main():
         log(f"oracle {osteps} steps {tc:.2f} s; err_max {errs}")
     # error after the workload's full step count, against the stored oracle run
     for prec in res:
-        g = golden_error(args.workload, lambda: Simulation(prob, prec=prec, **kw), steps)
+        g = golden_error(args.workload,
+                         lambda ce: Simulation(prob, prec=prec, check_every=ce, **kw), steps)
         if g is not None:
             gerr[prec] = g
     if gerr:

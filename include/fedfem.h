@@ -139,13 +139,16 @@ typedef struct {
   int32_t fuse_steps;        /* K: steps one kernel launch advances (1..4), each tile carrying
                                 K element rings of halo; 0 = default (1).  Results do not
                                 depend on K. */
-  int32_t resident;          /* 1: resident stepping - one cooperative launch runs all the
-                                steps of a fed_step call, every tile's workgroup holding its
-                                elements and nodes in registers for the whole launch and
-                                exchanging only halo temperatures with its neighbours through
-                                memory.  Needs every tile resident at once (FED_E_MESH at
-                                fed_create if the mesh does not fit) and K = 1.  Results are
-                                bitwise identical to resident = 0 on the same tiles. */
+  int32_t resident;          /* 1: resident stepping - one launch runs all the steps of a
+                                fed_step call, every tile's workgroup holding its elements
+                                and nodes in registers for the whole launch and exchanging
+                                only halo temperatures with its neighbours through memory.
+                                Needs every tile resident at once (FED_E_MESH at fed_create
+                                if the mesh does not fit the GPU's resident workgroups) and
+                                K = 1.  The launch is an ordinary one: kernels of other
+                                streams that hold CUs for seconds make it report FED_E_HIP
+                                (its bounded halo waits give up) rather than hang.  Results
+                                are bitwise identical to resident = 0 on the same tiles. */
   int32_t hex_gradient;      /* hexahedra: 0 = gradient at the element centre (Eq. 17, the
                                 paper's one-point rule); 1 = uniform gradient (the mean of
                                 B over the element, W = V), which reproduces linear fields

@@ -29,11 +29,17 @@ class FEDFunction(torch.autograd.Function):
         out = torch.empty(sim.N, dtype=torch.float64, device=T0.device)
         sim.temperature(out=out)
         ctx.sim = sim
+        ctx.run = sim.run_id
         ctx.has = (log_k is not None, elem_c is not None, face_h is not None)
         return out
 
     @staticmethod
     def backward(ctx, gT):
+        if ctx.sim.run_id != ctx.run:
+            # the context's checkpoints and parameters belong to a later run
+            raise RuntimeError("FEDFunction.backward: the simulation has started another run "
+                               "since this output was computed; use one Simulation per "
+                               "differentiated run")
         g = ctx.sim.backward(gT.contiguous())
         hk, hc, hh = ctx.has
         return (g["logk"] if hk else None, g["c"] if hc else None, g["h"] if hh else None,

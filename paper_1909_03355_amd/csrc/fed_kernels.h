@@ -200,7 +200,7 @@ hipError_t launch_expand_sk(int prec, int64_t Eexp, const int32_t *eorig, const 
 // rows [from, to) of H0 take the per-element conductivity factor
 hipError_t launch_expand_H(int prec, int W, int from, int to, int64_t Eexp, int64_t E, const int32_t *eorig,
                            const double *H0, const double *kscale, void *H, hipStream_t s);
-// Resident stepping: one cooperative launch advances nsteps steps.  Every tile
+// Resident stepping: one launch advances nsteps steps.  Every tile
 // keeps its element operators and node coefficients in registers for the whole
 // launch.  The temperatures of exported nodes (those in another tile's halo)
 // are passed through two exchange buffers of tagged words (FP32: 64 bits, the

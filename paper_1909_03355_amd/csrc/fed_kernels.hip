@@ -1989,7 +1989,7 @@ __global__ void k_permute(int eb, int64_t N, const int32_t *perm, const unsigned
 }
 
 // ---------------------------------------------------------------------------
-// Resident stepping.  One cooperative launch advances r.nsteps steps, with
+// Resident stepping.  One launch advances r.nsteps steps, with
 // every tile's workgroup resident for the whole launch.  A tile keeps its
 // elements' entries and operators and its nodes' coefficients and state in
 // registers, so a step reads from memory only the halo temperatures and
@@ -2372,7 +2372,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   if (a.hl && bad >= 0 && (tid & 63) == 0) health_bad(a, health_step0(a) + bad + 1);
 }
 
-// Resident adjoint: one cooperative launch runs the adjoint steps n1-1 .. n0
+// Resident adjoint: one launch runs the adjoint steps n1-1 .. n0
 // of a checkpoint segment on the tiles of the resident forward kernel.  A tile
 // keeps its elements (entries, operator) and its owned nodes' lambda in
 // registers, the FP64 derivative sums of the elements it owns in registers
@@ -2807,12 +2807,20 @@ hipError_t resident_prepare(const StepArgs &a, int *blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, a.block, a.lds);
 }
 
+// Resident launches are ordinary launches: the grid fits the workgroups the
+// GPU holds at once (checked when the context is made, with the occupancy of
+// resident_prepare), so on a GPU that runs nothing else every tile is resident
+// from the start.  A cooperative launch guarantees the same but costs about
+// 14 us more per launch (it waits for the device); if another stream's
+// kernels hold CUs, tiles not yet resident start once those finish, and the
+// bounded halo waits (seconds) end a launch that cannot proceed with an
+// error instead of a hang.
 hipError_t launch_resident(const StepArgs &a, const ResArgs &r, hipStream_t s) {
   StepArgs aa = a;
   ResArgs rr = r;
   void *args[] = {(void *)&aa, (void *)&rr};
-  return hipLaunchCooperativeKernel(resident_kernel(a), dim3(8 * a.nper), dim3(a.block), args,
-                                    (unsigned)a.lds, s);
+  return hipLaunchKernel(resident_kernel(a), dim3(8 * a.nper), dim3(a.block), args,
+                         (size_t)a.lds, s);
 }
 
 const void *adjres_kernel(int prec, bool gen) {
@@ -2837,8 +2845,9 @@ hipError_t launch_adjres(const AdjArgs &a, const AdjResArgs &r, hipStream_t s) {
   AdjArgs aa = a;
   AdjResArgs rr = r;
   void *args[] = {(void *)&aa, (void *)&rr};
-  return hipLaunchCooperativeKernel(adjres_kernel(a.prec, a.ktab || a.ctab || a.esk),
-                                    dim3(8 * a.nper), dim3(a.block), args, (unsigned)a.lds, s);
+  // an ordinary launch, as launch_resident
+  return hipLaunchKernel(adjres_kernel(a.prec, a.ktab || a.ctab || a.esk), dim3(8 * a.nper),
+                         dim3(a.block), args, (size_t)a.lds, s);
 }
 
 // the one-step adjoint instance of (precision, element, operator, laws)

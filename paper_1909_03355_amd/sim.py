@@ -78,6 +78,7 @@ class Simulation:
         window the stability bound allows, a number: [T_lo - m, T_hi + m]."""
         lib = L.lib()
         self._ctx = None
+        self.run_id = 0    # counts set_temperature / set_state / set_params calls
         self.prec = prec
         self.prob = prob
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
@@ -177,6 +178,7 @@ class Simulation:
         """Initialisation (Sec. 3.5 (ii)): T0 (caller order, FP64 numpy array or
         CUDA tensor; default the problem's T0) with the Dirichlet values applied."""
         T = self.prob["T0"] if T is None else T
+        self.run_id += 1   # a new run: steps, checkpoints and states start over
         if hasattr(T, "is_cuda") and T.is_cuda:
             import torch
             assert T.dtype == torch.float64 and T.is_contiguous() and T.numel() == self.N
@@ -235,6 +237,7 @@ class Simulation:
         return hi, lo, st.value
 
     def set_state(self, hi, lo, step):
+        self.run_id += 1
         dt = np.float64 if self.prec == "fp64" else np.float32
         hi = np.ascontiguousarray(hi, dtype=dt)
         lo = np.ascontiguousarray(lo, dtype=np.float32)
@@ -262,6 +265,7 @@ class Simulation:
     def set_params(self, kscale=None, elem_c=None, face_h=None):
         """Replace per-element conductivity factors, per-element heat capacities
         and per-face convection coefficients; re-derives the precomputed arrays."""
+        self.run_id += 1   # the parameters of the adjoint change
         args = [self._arg(a) for a in (kscale, elem_c, face_h)]
         dev = {d for _, d, _ in args if d is not None}
         if len(dev) > 1:
