@@ -72,10 +72,10 @@ WORKLOADS = {
                      dict(resident=True), "steps"),
     "meanhex_hex64": ("cube_nonlinear_hex_mean", 2000, 100,
                       "nonlinear_hex64 on a distorted mesh (interior nodes moved up to 0.25 h) "
-                      "with the uniform-gradient hexahedron", dict(), "steps"),
+                      "with the uniform-gradient hexahedron", dict(resident=True), "steps"),
     "meanhg_hex64": ("cube_nonlinear_hex_mean_hg", 2000, 100,
                      "meanhex_hex64 with hourglass control (eps 0.3, 40 values per element)",
-                     dict(), "steps"),
+                     dict(resident=True), "steps"),
     "nladjoint_hex64": ("nonlinear_adjoint_hex", 2000, 100,
                         "nonlinear_hex64 (D(T), c(T), radiation) as the forward model of a sensor "
                         "loss; forward + adjoint with checkpoints every 100 steps",

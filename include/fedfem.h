@@ -75,7 +75,7 @@ typedef struct {
  * diagonals.  The factor of D is evaluated at each node of the element and the
  * nodal values averaged (for this linear law: its value at the element's mean
  * nodal temperature); c is evaluated at the node (Sec. 4.2.2).  Materials may differ in every field (different s0, s1
- * cost 2 values per element and step, and rule out resident stepping). */
+ * cost 2 values per element and step). */
 typedef struct {
   double rho, c0, c1;
   double k[6];
@@ -153,8 +153,9 @@ typedef struct {
                                 paper's one-point rule); 1 = uniform gradient (the mean of
                                 B over the element, W = V), which reproduces linear fields
                                 on distorted hexahedra (the patch test of Sec. 4.1); 27
-                                values per element instead of 6, one step per launch
-                                (fuse_steps <= 1, resident = 0).  Ignored for tetrahedra. */
+                                values per element instead of 6 (resident stepping reads
+                                them from memory every step); fuse_steps <= 1.  Ignored
+                                for tetrahedra. */
   double hourglass;          /* eps >= 0 (0 = off): hourglass control of the uniform-
                                 gradient hexahedron (not in the paper; the scalar-field form
                                 of Flanagan and Belytschko's orthogonal hourglass control).

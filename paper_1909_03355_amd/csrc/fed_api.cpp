@@ -408,9 +408,9 @@ int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, cons
   if (o->resident != 0 && o->resident != 1) return fail(FED_E_ARG, "resident must be 0 or 1");
   if (o->resident && o->fuse_steps > 1) return fail(FED_E_ARG, "resident stepping needs fuse_steps <= 1");
   if (o->hex_gradient != 0 && o->hex_gradient != 1) return fail(FED_E_ARG, "hex_gradient must be 0 or 1");
-  if (o->hex_gradient == 1 && m->elem == FED_HEX8 && (o->fuse_steps > 1 || o->resident))
-    return fail(FED_E_ARG, "the uniform-gradient hexahedron runs one step per launch "
-                           "(fuse_steps <= 1, resident = 0)");
+  if (o->hex_gradient == 1 && m->elem == FED_HEX8 && o->fuse_steps > 1)
+    return fail(FED_E_ARG, "the uniform-gradient hexahedron runs one step per launch or "
+                           "resident (fuse_steps <= 1)");
   if (!(o->hourglass >= 0) || !std::isfinite(o->hourglass))
     return fail(FED_E_ARG, "hourglass must be a finite number >= 0");
   if (!(o->check_margin >= 0) || !std::isfinite(o->check_margin))
@@ -577,13 +577,13 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   HIPCHK(P.alloc((void **)&c->d_rerr, sizeof(int)));
   HIPCHK(hipMemset(c->d_rerr, 0, sizeof(int)));
   // LDS of the resident kernel: T of the touched nodes, the slots of the
-  // touched nodes (hexahedra: 2^pb + 1 each) or of the owned nodes
-  // (tetrahedra: maxinc each) and the 5 boundary coefficients of the owned
-  // boundary nodes
+  // touched nodes (hexahedra with the folded operator: 2^pb + 1 each) or of
+  // the owned nodes (the others: maxinc each) and the 5 boundary coefficients
+  // of the owned boundary nodes
   int64_t lds = 0;
   for (const fed::TileHdr &th : T.tiles) {
-    const int64_t ns = c->ne == FED_HEX8 ? (int64_t)th.cum_n[1] * ((1 << T.pb) + 1)
-                                         : (int64_t)T.maxinc * th.nown;
+    const int64_t ns = c->ne == FED_HEX8 && c->op == 0 ? (int64_t)th.cum_n[1] * ((1 << T.pb) + 1)
+                                                       : (int64_t)T.maxinc * th.nown;
     lds = std::max<int64_t>(lds, (int64_t)c->rb * (th.cum_n[1] + ns + 5LL * th.nbnd) + 16);
   }
   if (lds > c->max_lds - kStaticLds)
@@ -609,7 +609,8 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   // the node-major slots of the touched nodes, hA and sigma eps A of the
   // owned boundary nodes; offered where it fits, else fed_backward runs one
   // adjoint step per launch
-  if (c->ne == FED_HEX8 && c->op == 0) {
+  // (per-element laws run the one-step adjoint, which reads them)
+  if (c->ne == FED_HEX8 && c->op == 0 && !c->d_esk) {
     int64_t alds = 0;
     for (const fed::TileHdr &th : T.tiles)
       alds = std::max<int64_t>(alds, 16LL * th.nbnd + (c->prec == FED_FP64 ? 24LL * th.cum_e[0] : 0) +
@@ -680,8 +681,6 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
     c->h_ctab_f.assign(mt->ctab_f, mt->ctab_f + c->nct);
     c->fc_min = table_extreme(c->h_ctab_T, c->h_ctab_f, o->T_lo, o->T_hi, false);
   }
-  if (mixed_k && o->resident)
-    return fail(FED_E_ARG, "resident stepping needs materials that share s0 and s1");
   c->resident = o->resident == 1;
   c->op = (ne == FED_HEX8 && o->hex_gradient == 1) ? (o->hourglass > 0 ? 2 : 1) : 0;
   c->hw = c->op == 2 ? 40 : c->op ? 27 : 6;

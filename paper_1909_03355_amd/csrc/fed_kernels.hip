@@ -2137,9 +2137,15 @@ __device__ inline void wait_halo(const unsigned long long *X, const int *hid, in
   }
 }
 
-template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN>
+// OP: the element operator (0 the folded 3x3, kept in registers for the whole
+// launch; 1 and 2 the uniform-gradient hexahedron without and with hourglass
+// control, 27 and 40 values an element, too many for registers: each step
+// reads them again from memory, where the launch's repeated reads of the
+// same data are served by the caches, and keeps only the packed entries)
+template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN, int OP = 0>
 __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   constexpr int EPT = ResCap<R, NE>::EPT, NPT = ResCap<R, NE>::NPT, HPT = ResCap<R, NE>::HPT;
+  constexpr int HW = Op<R, NE, OP>::W;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int t = (b & 7) * a.nper + (b >> 3);
@@ -2153,23 +2159,27 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
   const R *Hb = (const R *)a.H;
   EntT ew[EPT];
-  R eh[EPT][6];
+  R eh[EPT][OP ? 1 : 6];
 #pragma unroll
   for (int q = 0; q < EPT; q++) {
     const int i = tid + q * bs;
     if (i < nE) {
       const int64_t e = (int64_t)th.estart + i;
       ew[q] = ent[e];
+      if constexpr (OP == 0) {
 #pragma unroll
-      for (int c = 0; c < 6; c++) eh[q][c] = Hb[(int64_t)c * a.Eexp + e];
+        for (int c = 0; c < 6; c++) eh[q][c] = Hb[(int64_t)c * a.Eexp + e];
+      }
     }
   }
-  // hexahedra use node-major slots (below).  FP32 hexahedra keep precomputed
-  // LDS addresses instead of the packed entries, the node temperatures' and
-  // the slots' (16 registers an element), so the element phase spends no
-  // instructions on addressing
-  constexpr bool NM = NE == 8;
-  constexpr bool PRE = NM && sizeof(R) == 4;
+  // hexahedra with the folded operator use node-major slots (below); the
+  // uniform-gradient hexahedron, whose tiles on distorted meshes touch more
+  // halo nodes, keeps slots for the owned nodes only.  FP32 hexahedra with the
+  // folded operator keep precomputed LDS addresses instead of the packed
+  // entries, the node temperatures' and the slots' (16 registers an element),
+  // so the element phase spends no instructions on addressing
+  constexpr bool NM = NE == 8 && OP == 0;
+  constexpr bool PRE = NM && sizeof(R) == 4 && OP == 0;
   const int nslot = NM ? ntouch * ((1 << a.pb) + 1) : a.maxinc * nown;
   R *Tl = reinterpret_cast<R *>(smem_raw);
   R *slot = Tl + ntouch;
@@ -2217,8 +2227,9 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     const int j = tid + q * bs;
     hid[q] = j < nhalo ? a.halo[th.hstart + j] : 0;
   }
-  // hexahedra: node-major slots of every touched node (element phase without
-  // tests); tetrahedra (24 slots a node): position-major, owned nodes only
+  // hexahedra with the folded operator: node-major slots of every touched
+  // node (element phase without tests); the others (tetrahedra: 24 slots a
+  // node): position-major, owned nodes only
   const int nbnd = th.nbnd;
   for (int j = tid; j < nbnd; j += bs) {
     const int rr = th.bstart + j;
@@ -2235,17 +2246,34 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   const uint32_t pmask = (1u << a.pb) - 1u;
   int prow = r.pts_row;
   // element loads into the node-local slots
+  // (materials with different k(T) laws: the element's own (s0, s1), read
+  // when the element runs, as in the one-step kernel)
   auto element = [&](int q) {
-    if constexpr (PRE) {
+    const int64_t e = (int64_t)th.estart + tid + q * bs;
+    const KLaw<R> kle = elem_law<GEN>(a, kl, e);
+    if constexpr (OP != 0) {
+      // the operator from memory (SoA, coalesced), then the element's load.
+      // The offset is made opaque on every step, so the compiler keeps these
+      // loads in the step instead of hoisting HW values a element out of the
+      // loop into registers (and scratch)
+      uint32_t off = (uint32_t)(tid + q * bs);
+      asm volatile("" : "+v"(off));
+      const R *hp = Hb + th.estart + off;
+      R h[HW];
+#pragma unroll
+      for (int c = 0; c < HW; c++) h[c] = hp[(int64_t)c * a.Eexp];
+      keep_packed(ew[q]);
+      element_to_slots<R, NE, TDK, OP, NM>(ew[q], h, Tl, slot, nown, nown, a.pb, pmask, kle);
+    } else if constexpr (PRE) {
       R T[8], F[8];
 #pragma unroll
       for (int n = 0; n < 8; n++) T[n] = lds_ld<R>(ta[q][n]);
-      Elem<R, 8>::load_vals(T, kl, TDK, eh[q], F);
+      Elem<R, 8>::load_vals(T, kle, TDK, eh[q], F);
 #pragma unroll
       for (int n = 0; n < 8; n++) lds_st<R>(sa[q][n], F[n]);
     } else {
       keep_packed(ew[q]);
-      element_to_slots<R, NE, TDK, 0, NM>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, kl);
+      element_to_slots<R, NE, TDK, 0, NM>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, kle);
     }
   };
   // the elements with every node owned come first in the tile's list
@@ -2769,14 +2797,23 @@ hipError_t launch_permute(int elem_bytes, int64_t N, const int32_t *perm, const 
 
 namespace fed {
 
-template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN>
+template <typename R, int NE, int MODE, bool TDK, bool TDC, bool GEN, int OP = 0>
 const void *resident_fn() {
-  return (const void *)k_resident<R, NE, MODE, TDK, TDC, GEN>;
+  return (const void *)k_resident<R, NE, MODE, TDK, TDC, GEN, OP>;
 }
 
-// tables run the general instance (per-element laws are not offered resident)
+// tables and per-element laws run the general instance, and so does the
+// uniform-gradient hexahedron (op 1, 2)
 template <typename R, int NE, int MODE>
-const void *resident_tt(int tdk, int tdc, bool gen) {
+const void *resident_tt(int tdk, int tdc, bool gen, int op) {
+  // (the linear laws' instance with both laws on: a law with zero slope gives
+  // the same bits, fma(0, T, s0) = s0)
+  if (NE == 8 && op == 1)
+    return gen ? resident_fn<R, 8, MODE, true, true, true, 1>()
+               : resident_fn<R, 8, MODE, true, true, false, 1>();
+  if (NE == 8 && op == 2)
+    return gen ? resident_fn<R, 8, MODE, true, true, true, 2>()
+               : resident_fn<R, 8, MODE, true, true, false, 2>();
   if (gen) return resident_fn<R, NE, MODE, true, true, true>();
   if (tdk)
     return tdc ? resident_fn<R, NE, MODE, true, true, false>() : resident_fn<R, NE, MODE, true, false, false>();
@@ -2784,12 +2821,15 @@ const void *resident_tt(int tdk, int tdc, bool gen) {
 }
 
 const void *resident_kernel(const StepArgs &a) {
-  const bool g = a.ktab || a.ctab;
+  const bool g = a.ktab || a.ctab || a.esk;
   if (a.prec == 1)
-    return a.ne == 8 ? resident_tt<double, 8, 0>(a.tdk, a.tdc, g) : resident_tt<double, 4, 0>(a.tdk, a.tdc, g);
+    return a.ne == 8 ? resident_tt<double, 8, 0>(a.tdk, a.tdc, g, a.op)
+                     : resident_tt<double, 4, 0>(a.tdk, a.tdc, g, 0);
   if (a.prec == 0)
-    return a.ne == 8 ? resident_tt<float, 8, 1>(a.tdk, a.tdc, g) : resident_tt<float, 4, 1>(a.tdk, a.tdc, g);
-  return a.ne == 8 ? resident_tt<float, 8, 0>(a.tdk, a.tdc, g) : resident_tt<float, 4, 0>(a.tdk, a.tdc, g);
+    return a.ne == 8 ? resident_tt<float, 8, 1>(a.tdk, a.tdc, g, a.op)
+                     : resident_tt<float, 4, 1>(a.tdk, a.tdc, g, 0);
+  return a.ne == 8 ? resident_tt<float, 8, 0>(a.tdk, a.tdc, g, a.op)
+                   : resident_tt<float, 4, 0>(a.tdk, a.tdc, g, 0);
 }
 
 ResCaps resident_caps(int prec, int ne) {

@@ -97,11 +97,40 @@ struct Builder {
     return ntouch <= touch_limit && lds <= in.lds_budget;
   }
 
-  // recursive coordinate bisection of ids[b, e) into leaves (DFS order)
-  bool rcb(std::vector<int32_t> &ids, size_t b0, size_t e0,
-           std::vector<std::pair<size_t, size_t>> &leaves) {
-    std::vector<std::pair<size_t, size_t>> stack{{b0, e0}};
+  // Smoothed coordinates (each node moved to the mean centroid of its
+  // elements, a few times): on a distorted mesh they take the jitter out of
+  // the layers of nodes, so the bisection cuts follow mesh layers and the
+  // tiles keep compact boundaries (few halo nodes).  The tiling tries the
+  // nodes' own coordinates and these, and keeps the tiles with fewer halo
+  // nodes; no result depends on the tiling.
+  std::vector<double> sc[3];
+  void smooth_coordinates(int iterations) {
+    const int64_t N = in.N, E = in.E;
+    const int ne = in.ne;
     const double *X[3] = {in.x, in.y, in.z};
+    for (int d = 0; d < 3; d++) sc[d].assign(X[d], X[d] + N);
+    std::vector<double> cen((size_t)E), acc((size_t)N);
+    for (int it = 0; it < iterations; it++)
+      for (int d = 0; d < 3; d++) {
+        for (int64_t e = 0; e < E; e++) {
+          double c = 0;
+          for (int a = 0; a < ne; a++) c += sc[d][node(e, a)];
+          cen[e] = c / ne;
+        }
+        for (int64_t k = 0; k < N; k++) {
+          double c = 0;
+          for (int64_t p = cptr[k]; p < cptr[k + 1]; p++) c += cen[celem[p]];
+          acc[k] = cptr[k + 1] > cptr[k] ? c / (double)(cptr[k + 1] - cptr[k]) : sc[d][k];
+        }
+        sc[d].swap(acc);
+      }
+  }
+
+  // recursive coordinate bisection of ids[b, e) into leaves (DFS order), by
+  // the coordinates X
+  bool rcb(std::vector<int32_t> &ids, size_t b0, size_t e0,
+           std::vector<std::pair<size_t, size_t>> &leaves, const double *const X[3]) {
+    std::vector<std::pair<size_t, size_t>> stack{{b0, e0}};
     while (!stack.empty()) {
       auto [b, e] = stack.back();
       stack.pop_back();
@@ -133,6 +162,28 @@ struct Builder {
     return true;
   }
 
+  // halo nodes of a tiling, summed over the tiles: the (tile, node) pairs of
+  // nodes another tile owns that share an element with a node of the tile
+  int64_t halo_count(const std::vector<int32_t> &ids,
+                     const std::vector<std::pair<size_t, size_t>> &leaves) {
+    const int64_t N = in.N;
+    std::vector<int32_t> tile_of(N, -1), seen;
+    for (size_t t = 0; t < leaves.size(); t++)
+      for (size_t i = leaves[t].first; i < leaves[t].second; i++) tile_of[ids[i]] = (int32_t)t;
+    int64_t h = 0;
+    for (int64_t k = 0; k < N; k++) {
+      seen.clear();
+      for (int64_t p = cptr[k]; p < cptr[k + 1]; p++)
+        for (int a = 0; a < in.ne; a++) {
+          const int32_t tb = tile_of[node(celem[p], a)];
+          if (tb != tile_of[k]) seen.push_back(tb);
+        }
+      std::sort(seen.begin(), seen.end());
+      h += std::unique(seen.begin(), seen.end()) - seen.begin();
+    }
+    return h;
+  }
+
   std::string run() {
     const int64_t N = in.N, E = in.E;
     const int ne = in.ne;
@@ -150,11 +201,31 @@ struct Builder {
         if (in.node_instance[ids[i]] != in.node_instance[ids[i - 1]]) gstart.push_back(i);
     }
     gstart.push_back(N);
+    // bisect by the nodes' coordinates and by the smoothed ones; keep the
+    // tiling with fewer halo nodes (the first on a tie)
     std::vector<std::pair<size_t, size_t>> leaves;
-    for (size_t g = 0; g + 1 < gstart.size(); g++)
-      if (!rcb(ids, gstart[g], gstart[g + 1], leaves))
-        return "a single node touches more nodes or LDS than one tile can hold "
-               "(node incidence too high)";
+    int64_t best_halo = -1;
+    const std::vector<int32_t> ids0 = ids;
+    for (int pass = 0; pass < 2; pass++) {
+      const double *X[3] = {in.x, in.y, in.z};
+      if (pass == 1) {
+        smooth_coordinates(5);
+        for (int d = 0; d < 3; d++) X[d] = sc[d].data();
+      }
+      std::vector<int32_t> idp = ids0;
+      std::vector<std::pair<size_t, size_t>> lp;
+      for (size_t g = 0; g + 1 < gstart.size(); g++)
+        if (!rcb(idp, gstart[g], gstart[g + 1], lp, X))
+          return "a single node touches more nodes or LDS than one tile can hold "
+                 "(node incidence too high)";
+      const int64_t h = halo_count(idp, lp);
+      if (best_halo < 0 || h < best_halo) {
+        best_halo = h;
+        ids.swap(idp);
+        leaves.swap(lp);
+      }
+    }
+    for (int d = 0; d < 3; d++) std::vector<double>().swap(sc[d]);
     // internal order: tile by tile; inside a tile the boundary-record nodes
     // first, then by the sorted list of other tiles that read the node (nodes
     // no other tile reads last), then caller id, so the nodes a tile exports,

@@ -55,6 +55,8 @@ def test_distorted_mesh_matches_oracle():
         print(f"mean-gradient hex {prec}: err_max {err:.2e}", flush=True)
         assert err <= TOL[prec]
         assert np.array_equal(_run(p, prec, 100, tile_nodes=50, block_threads=128), T)
+        # resident stepping (operators read from memory every step): same bits
+        assert np.array_equal(_run(p, prec, 100, resident=True), T)
 
 
 def test_patch_test_on_gpu():
@@ -86,16 +88,21 @@ def test_mean_gradient_adjoint_matches_oracle():
     ref = o.adjoint(hist, lam)
     rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
     for prec in ("fp64", "fp32c"):
-        with _sim(p, prec) as s:
-            s.checkpoint_every(16)
-            s.set_temperature()
-            s.step(nsteps)
-            g = s.backward(lam)
+        gs = []
+        for kw in (dict(), dict(resident=True)):
+            with _sim(p, prec, **kw) as s:
+                s.checkpoint_every(16)
+                s.set_temperature()
+                s.step(nsteps)
+                gs.append(s.backward(lam))
+        g = gs[0]
         errs = {"logk": rel(g["logk"], ref["g_logk"]), "c": rel(g["c"], ref["g_c"]),
                 "h": rel(g["h"], ref["g_h"]), "T0": rel(g["T0"], ref["lam0"])}
         print("mean-gradient adjoint", prec, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
         for k, v in errs.items():
             assert v <= GTOL[prec], (prec, k, v)
+        for k in g:   # the resident recompute gives the same derivatives
+            assert np.array_equal(gs[1][k], g[k]), k
 
 
 def test_mean_equals_centre_on_box():
@@ -124,6 +131,7 @@ def test_hourglass_control_matches_oracle():
         print(f"hourglass-controlled hex {prec}: err_max {err:.2e}", flush=True)
         assert err <= TOL[prec]
         assert np.array_equal(_run(p, prec, 100, tile_nodes=50, block_threads=128), T)
+        assert np.array_equal(_run(p, prec, 100, resident=True), T)
 
 
 def test_hourglass_mode_decays_on_gpu():

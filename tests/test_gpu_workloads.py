@@ -105,29 +105,32 @@ def test_tables_hex64_full_size():
 
 def test_meanhex_hex64_full_size():
     """The uniform-gradient hexahedron on the distorted 64^3 mesh, 100 steps,
-    in the launch shape bench.py times, against the oracle."""
+    in the launch shape bench.py times (resident), against the oracle, and
+    bitwise equal to one step per launch."""
     p = P.cube_nonlinear_hex_mean(64, 100)
     ref = Oracle(p).run(100)
     for prec in ("fp64", "fp32c"):
-        T, dtc, _ = _run(p, prec, 100)
+        T, dtc, _ = _run(p, prec, 100, resident=True)
         err = oracle.err_max(T, ref)
         print(f"meanhex_hex64 {prec}: err_max {err:.2e}", flush=True)
         assert err <= TOL[prec]
+        assert np.array_equal(T, _run(p, prec, 100)[0])
 
 
 def test_meanhg_hex64_full_size():
     """Hourglass control on the distorted 64^3 mesh, 100 steps, in the launch
-    shape bench.py times: the critical step and the temperatures against the
-    oracle."""
+    shape bench.py times (resident): the critical step and the temperatures
+    against the oracle, bitwise equal to one step per launch."""
     p = P.cube_nonlinear_hex_mean_hg(64, 100)
     o = Oracle(p)
     ref = o.run(100)
     for prec in ("fp64", "fp32c"):
-        T, dtc, _ = _run(p, prec, 100)
+        T, dtc, _ = _run(p, prec, 100, resident=True)
         assert abs(dtc[0] / o.dt_crit - 1) < 1e-12
         err = oracle.err_max(T, ref)
         print(f"meanhg_hex64 {prec}: err_max {err:.2e}", flush=True)
         assert err <= TOL[prec]
+        assert np.array_equal(T, _run(p, prec, 100)[0])
 
 
 def test_nonlinear_adjoint_hex64():

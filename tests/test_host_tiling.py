@@ -92,8 +92,11 @@ def test_validation_rejects_bad_inputs():
     mats = [dict(p["materials"][0], c1=0.5)]
     _expect(dict(p, materials=mats, c_table=ok_tab), L.FED_E_ARG)
     _expect(dict(p, c_table=(ok_tab[0], np.array([1.0, -1.0]))), L.FED_E_ARG)
-    # the uniform-gradient hexahedron runs one step per launch
+    # the uniform-gradient hexahedron takes no temporal blocking
     _expect(dict(p, hex_gradient="mean"), L.FED_E_ARG, fuse_steps=2)
-    _expect(dict(p, hex_gradient="mean"), L.FED_E_ARG, resident=True)
+    # health-check and allocator options
+    _expect(p, L.FED_E_ARG, check_margin=-1.0)
+    _expect(p, L.FED_E_ARG, energy_tol=-1.0)
+    _expect(p, L.FED_E_ARG, check_every=-2)
     _expect(dict(p, hourglass=0.5), L.FED_E_ARG)                      # needs the mean gradient
     _expect(dict(p, hex_gradient="mean", hourglass=-1.0), L.FED_E_ARG)
