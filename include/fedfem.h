@@ -183,10 +183,13 @@ typedef struct {
   void (*dev_free)(void *ptr, void *alloc_ctx);
   void *alloc_ctx;
   /* In-run health check.  The stability bound (Sec. 3.4, Eq. 29) is derived
-   * for temperatures in [T_lo, T_hi]: every step checks every new temperature
-   * against a window (a value outside it or not finite latches the first such
-   * step, reported by the next fed_get_temperature as FED_E_UNSTABLE and by
-   * fed_health_get).  check_window 0: the window is [T_lo - m, T_hi + m] with
+   * for temperatures in [T_lo, T_hi]: every step's new temperatures are
+   * checked against a window (a value outside it or not finite latches the
+   * first such step, reported by the next fed_get_temperature as
+   * FED_E_UNSTABLE and by fed_health_get; resident launches compare the
+   * extremes of every step with the window every 32 steps and at their end,
+   * and report the step of the first check that finds one, at most 31 steps
+   * late).  check_window 0: the window is [T_lo - m, T_hi + m] with
    * m the largest margin for which the time step in use stays within the
    * bound over the window (the step takes a safety factor below the bound, so
    * it stays provably stable somewhat beyond the range; m = 0 if the step
@@ -286,7 +289,9 @@ int fed_get_temperature(fed_ctx *ctx, double *T, int32_t on_device, void *stream
 typedef struct {
   int64_t steps;              /* steps taken */
   int64_t first_bad_step;     /* first step after which a temperature was outside the
-                                 window or not finite; -1: none (fed_set_range clears it) */
+                                 window or not finite (resident launches: the first of
+                                 their checks, every 32 steps, that found one); -1: none
+                                 (fed_set_range clears it) */
   double window_lo, window_hi;  /* the window in use (see fed_options) */
   double energy_residual;     /* largest relative energy residual of the checks (0: none) */
   int64_t energy_step;        /* the step of that check; -1: none */

@@ -2006,6 +2006,12 @@ __global__ void k_permute(int eb, int64_t N, const int32_t *perm, const unsigned
 // loads, the ordered nodal sums and the update are those of k_step1 on the
 // same tiles, so both give bitwise-identical temperatures.
 
+// Resident stepping compares the running extremes of every step's
+// temperatures with the health window every kResCheck steps (a ballot a step
+// measured ~0.14 us on a ~2.3 us step); the first step outside is then
+// reported at the check that finds it, at most kResCheck - 1 steps late.
+constexpr int kResCheck = 32;
+
 // register capacity per thread: elements, owned nodes, halo ids
 template <typename R, int NE>
 struct ResCap {
@@ -2278,11 +2284,14 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   };
   // the elements with every node owned come first in the tile's list
   const int nint = r.split ? th.nint : 0;
-  // health: the first step at which a temperature of the wave's nodes left
-  // the window (wave-uniform, so it lives in a scalar register); the energy
-  // check runs in the one-step kernel
+  // health: the step count of the first check that found a temperature of
+  // the wave's nodes outside the window (wave-uniform, so it lives in a
+  // scalar register), and the extremes since the last check (FP32, compared
+  // with the window rounded outward); the energy check runs in the one-step
+  // kernel
   int bad = -1;
-  const R wlo = win_lo<R>(a), whi = win_hi<R>(a);
+  float tmn = INFINITY, tmx = -INFINITY;
+  const float wlo = a.win_lo_f, whi = a.win_hi_f;
   // every load above completes here, once: otherwise the compiler waits for
   // them at their first use inside the loop, on every step, and such a wait
   // (vmcnt counts stores too) would also hold the interior elements until the
@@ -2356,7 +2365,6 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     // after the elements with every node owned, which read only owned T)
     unsigned long long *Xw = r.X[(s + 1) & 1];
     const unsigned tag = r.tag0 + (unsigned)s + 1u;
-    bool out = false;
 #pragma unroll
     for (int q = 0; q < NPT; q++) {
       const int j = tid + q * bs;
@@ -2379,13 +2387,29 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
         R Q, den;
         hi[q] = advance<R, MODE, TDC>(d, bnd, hi[q], F, Tz, GEN ? (const R *)a.ctab : nullptr,
                                       GEN ? a.nct : 0, lo_new, Q, den);
-        out = out || outside(hi[q], wlo, whi);  // health: the window
         lo[q] = lo_new;
         if (ex[q]) Words<R>::put(Xw, th.nstart + j, tag, hi[q]);
         if (r.seg) ((R *)r.seg)[(int64_t)(s + 1) * r.segN + th.nstart + j] = hi[q];
       }
     }
-    if (bad < 0 && __ballot(out)) bad = s;
+    // ---- health: running extremes of the owned temperatures (after the
+    // exports, off the neighbours' critical path), compared with the window
+    // every kResCheck steps and at the launch's last step ----
+#pragma unroll
+    for (int q = 0; q < NPT; q++)
+      if (tid + q * bs < nown) {
+        tmn = fminf(tmn, (float)hi[q]);
+        tmx = fmaxf(tmx, (float)hi[q]);
+      }
+    if ((s + 1) % kResCheck == 0 || s + 1 == r.nsteps) {
+      bool out = tmn < wlo || tmx > whi;
+#pragma unroll
+      for (int q = 0; q < NPT; q++)
+        if (tid + q * bs < nown) out = out || !(hi[q] == hi[q]);  // not a number
+      if (bad < 0 && __ballot(out)) bad = s + 1;
+      tmn = INFINITY;
+      tmx = -INFINITY;
+    }
   }
   // ---- final state of the owned nodes ----
   R *Tf = (R *)r.Tfin;
@@ -2397,7 +2421,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       if (MODE == 1) r.lofin[th.nstart + j] = lo[q];
     }
   }
-  if (a.hl && bad >= 0 && (tid & 63) == 0) health_bad(a, health_step0(a) + bad + 1);
+  if (a.hl && bad >= 0 && (tid & 63) == 0) health_bad(a, health_step0(a) + bad);
 }
 
 // Resident adjoint: one launch runs the adjoint steps n1-1 .. n0
