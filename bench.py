@@ -34,19 +34,27 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
 # sources that decide a kernel's memory traffic: the kernels, the tiler, the launches
 TRAFFIC_SRC = [os.path.join(ROOT, "paper_1909_03355_amd", "csrc", f)
-               for f in ("fed_kernels.hip", "fed_tiling.cpp", "fed_api.cpp")]
-# Memory traffic of the dominant kernel in the default launch shape, from
-# rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
-# scaled by what the counter reads for a copy kernel of known size
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0): bytes per launch for a one-step kernel;
-# for resident stepping (one launch for all steps) bytes once per launch plus
-# bytes per step, from runs of two step counts.  Valid only for the sources
-# (TRAFFIC_SRC, concatenated) with this SHA-1; any other source reports null.
-#   workload -> (sha1, kernel, bytes per launch or once, bytes per step)
+               for f in ("fed_kernels.hip", "fed_kernels.h", "fed_tiling.cpp")]
+# Memory traffic of the dominant kernel, from rocprofv3 counter runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+# counter reads for a copy kernel of known size (FETCH_SIZE x 2.0, WRITE_SIZE
+# x 1.0): bytes per launch for a one-step kernel; for resident stepping (one
+# launch for all steps) bytes once per launch plus bytes per step, from two
+# launches of different step counts.  Valid only for the launch shape the
+# counters were taken in (tiles, block threads, steps per launch, resident) and
+# for the kernel sources and the tiler (TRAFFIC_SRC, concatenated) with this
+# SHA-1; anything else reports null.
+#   workload -> (sha1, kernel, shape, bytes per launch or once, bytes per step)
 TRAFFIC = {
-    "nonlinear_hex64": ("de64b5db9606d8bc557316424e90b8ec4b678c82", "k_resident", 20824839.1, 2357571.5),
-    "aniso_tet128": ("de64b5db9606d8bc557316424e90b8ec4b678c82", "k_step1", 620856944.0, 0.0),
-    "batched_hex256": ("de64b5db9606d8bc557316424e90b8ec4b678c82", "k_step1", 463512144.0, 0.0),
+    "nonlinear_hex64": ("eb7a33b0c51774ee139abedddb8f6b0c19b185e7", "k_resident", (256, 1024, 1, 1), 20617891.6, 2357694.4),
+    "aniso_tet128": ("eb7a33b0c51774ee139abedddb8f6b0c19b185e7", "k_step1", (4194, 512, 1, 0), 620535749.2, 0.0),
+    "batched_hex256": ("eb7a33b0c51774ee139abedddb8f6b0c19b185e7", "k_step1", (6437, 512, 1, 0), 463370996.1, 0.0),
+    "tables_hex64": ("eb7a33b0c51774ee139abedddb8f6b0c19b185e7", "k_resident", (256, 1024, 1, 1), 26198902.4, 2429218.1),
+    "meanhex_hex64": ("eb7a33b0c51774ee139abedddb8f6b0c19b185e7", "k_resident", (256, 1024, 1, 1), 24771953.5, 28528908.2),
+    "meanhg_hex64": ("eb7a33b0c51774ee139abedddb8f6b0c19b185e7", "k_resident", (256, 1024, 1, 1), 10546735.8, 59066432.8),
+    "moving_source_hex64": ("eb7a33b0c51774ee139abedddb8f6b0c19b185e7", "k_resident", (256, 1024, 1, 1), 22490476.6, 2364486.2),
+    "paper_standin_ti": ("eb7a33b0c51774ee139abedddb8f6b0c19b185e7", "k_resident", (250, 1024, 1, 1), 2943701.4, 201273.4),
+    "paper_standin_td": ("eb7a33b0c51774ee139abedddb8f6b0c19b185e7", "k_resident", (250, 1024, 1, 1), 2950028.5, 201206.7),
 }
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
 
@@ -119,6 +127,8 @@ def parse():
                     help="steps of the CPU oracle sample (timed baseline and error reference)")
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-golden", action="store_true",
+                    help="skip the full-horizon error run against the stored oracle temperatures")
     ap.add_argument("--no-autotune", action="store_true",
                     help="workloads timed with the autotuner's shape: use the fixed one")
     return ap.parse_args()
@@ -348,7 +358,7 @@ def main():
                 errs[prec] = oracle.err_max(sim.temperature(), ref)
         log(f"oracle {osteps} steps {tc:.2f} s; err_max {errs}")
     # error after the workload's full step count, against the stored oracle run
-    for prec in res:
+    for prec in ([] if args.no_golden else res):
         g = golden_error(args.workload,
                          lambda ce: Simulation(prob, prec=prec, check_every=ce, **kw), steps)
         if g is not None:
@@ -358,8 +368,6 @@ def main():
 
     import hashlib
     src_sha = hashlib.sha1(b"".join(open(f, "rb").read() for f in TRAFFIC_SRC)).hexdigest()
-    default_shape = not (args.tile_nodes or args.block or args.fuse or args.autotune
-                         or args.resident != "default") and tuned is None
     r32 = res["fp32c"]
     t = r32["t"]
     info = r32["info"]
@@ -374,6 +382,7 @@ def main():
         alg = info["algorithmic_bytes_per_launch"] + steps * (info["exchange_bytes_per_step"]
                                                               + sched_b)
         moved = info["moved_bytes_per_launch"] + steps * (info["exchange_bytes_per_step"]
+                                                          + info["reread_bytes_per_step"]
                                                           + sched_b)
         kernel = "k_resident"
     else:
@@ -384,8 +393,9 @@ def main():
     achieved = alg / (t / launches) / 1e9
     traffic = None
     tr = TRAFFIC.get(args.workload)
-    if tr and default_shape and tr[0] == src_sha and tr[1] == kernel:
-        traffic = tr[2] + (steps * tr[3] if resident else 0.0)
+    shape_now = (info["n_tiles"], info["block_threads"], K, int(resident))
+    if tr and tr[0] == src_sha and tr[1] == kernel and tuple(tr[2]) == shape_now:
+        traffic = tr[3] + (steps * tr[4] if resident else 0.0)
     cfg = {"workload": f"{args.workload}: {desc} ({E} elements, {N} nodes)",
            "elements": E, "nodes": N, "precision": "fp32c",
            "graph_steps": args.graph_steps,

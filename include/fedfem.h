@@ -233,6 +233,10 @@ typedef struct {
   int32_t reserved_;
   int64_t device_bytes;                /* device memory the context holds now (from the
                                           dev_alloc hook or hipMalloc) */
+  double reread_bytes_per_step;        /* resident stepping: bytes one step reads again
+                                          beyond the exchange (the operators of the
+                                          uniform-gradient hexahedron, too large to stay
+                                          on chip, re-read every step); 0 else */
 } fed_info;
 
 /*

@@ -84,7 +84,7 @@ class fed_info(C.Structure):
                 ("moved_bytes_per_launch", C.c_double),
                 ("exchange_bytes_per_step", C.c_double),
                 ("resident_adjoint", C.c_int32), ("reserved_", C.c_int32),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("reread_bytes_per_step", C.c_double)]
 
 
 # name -> (restype, argtypes) of every symbol the header declares

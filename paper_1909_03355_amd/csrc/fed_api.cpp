@@ -130,6 +130,8 @@ struct fed_ctx {
   unsigned xtag = 1;
   int *d_rerr = nullptr;
   int res_lds = 0;
+  bool res_oplds = false;  // resident uniform-gradient hexahedron: columns in LDS
+  bool res_nv = false;     // resident table laws: the table's values at the nodes in LDS
   // bounded halo waits of resident launches; tag_skew != 0 only in tests of
   // the failure path (fed_test_waits)
   int spin_limit = 1 << 22;
@@ -578,13 +580,37 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   HIPCHK(hipMemset(c->d_rerr, 0, sizeof(int)));
   // LDS of the resident kernel: T of the touched nodes, the slots of the
   // touched nodes (hexahedra with the folded operator: 2^pb + 1 each) or of
-  // the owned nodes (the others: maxinc each) and the 5 boundary coefficients
-  // of the owned boundary nodes
-  int64_t lds = 0;
-  for (const fed::TileHdr &th : T.tiles) {
-    const int64_t ns = c->ne == FED_HEX8 && c->op == 0 ? (int64_t)th.cum_n[1] * ((1 << T.pb) + 1)
-                                                       : (int64_t)T.maxinc * th.nown;
-    lds = std::max<int64_t>(lds, (int64_t)c->rb * (th.cum_n[1] + ns + 5LL * th.nbnd) + 16);
+  // the owned nodes (the others: maxinc each), the 5 boundary coefficients
+  // of the owned boundary nodes and, with a conductivity table, its value at
+  // every touched node (else the elements evaluate it at their nodes)
+  // (the uniform-gradient hexahedron adds its tile's mean-gradient columns,
+  // kOpLds values an element, where every tile has room for them)
+  auto need = [&](bool nv, bool opc) {
+    int64_t m = 0;
+    for (const fed::TileHdr &th : T.tiles) {
+      const int64_t ns = c->ne == FED_HEX8 && c->op == 0
+                             ? (int64_t)th.cum_n[1] * ((1 << T.pb) + 1)
+                             : (int64_t)T.maxinc * th.nown;
+      m = std::max<int64_t>(m, (int64_t)c->rb * (th.cum_n[1] + ns + 5LL * th.nbnd +
+                                                  (nv ? th.cum_n[1] : 0) +
+                                                  (opc ? (int64_t)fed::kOpLds * th.cum_e[0] : 0)) +
+                                   16);
+    }
+    return m;
+  };
+  const int64_t lds_limit = c->max_lds - kStaticLds;
+  const bool want_nv = c->nkt > 0, want_op = c->op != 0;
+  c->res_nv = c->res_oplds = false;
+  int64_t lds = need(false, false);
+  for (int k = 0; k < 4; k++) {
+    // preference: both, the table values only, the operator columns only
+    const bool nv = want_nv && k < 2, opc = want_op && (k == 0 || k == 2);
+    if ((nv || opc) && need(nv, opc) <= lds_limit) {
+      c->res_nv = nv;
+      c->res_oplds = opc;
+      lds = need(nv, opc);
+      break;
+    }
   }
   if (lds > c->max_lds - kStaticLds)
     return fail(FED_E_MESH, "resident stepping: a tile needs %lld bytes of LDS (the GPU has %d, "
@@ -737,6 +763,8 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   ti.real_bytes = c->rb;
   // staged per updated node: alpha, beta, record id, and lo for FP32C
   ti.upd_bytes = 2 * c->rb + 4 + (c->prec == FED_FP32C ? 4 : 0);
+  // a conductivity table's value at every touched node, staged with its T
+  ti.touch_bytes = c->nkt > 0 ? c->rb : 0;
   // resident stepping: one workgroup per CU for every 1024 threads a CU holds,
   // tiles as large as the node count over that many workgroups; only T of the
   // touched nodes and the slots live in LDS
@@ -1086,6 +1114,8 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   }
   moved += 5.0 * rb * nrec;
   I.moved_bytes_per_launch = moved;
+  // resident operators that do not stay on chip: every tile's copies, every step
+  I.reread_bytes_per_step = c->resident && c->op ? (double)c->hw * rb * c->Eexp : 0.0;
   *out = c.release();
   return FED_OK;
 }
@@ -1186,6 +1216,8 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
                        c->d_T[fin], c->d_lo[fin], nullptr, 0};
         r.split = c->res_split;
         r.tag_skew = c->tag_skew;
+        r.oplds = c->res_oplds ? 1 : 0;
+      r.nvals = c->res_nv ? 1 : 0;
         if (c->keep_states && c->ckpt_every > 0) {
           // fed_step breaks launches at checkpoints: this one stays inside segment g
           const int64_t g = st / c->ckpt_every, i0 = st % c->ckpt_every;
@@ -1807,6 +1839,8 @@ int backward_run(fed_ctx *c, const fed::AdjWork &w, const double *dL_dT, double 
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
                      seg(k), w.seglo[k & 1], segb, N};
       r.split = c->res_split;
+      r.oplds = c->res_oplds ? 1 : 0;
+      r.nvals = c->res_nv ? 1 : 0;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
         r.pts_nrec = c->nrec;

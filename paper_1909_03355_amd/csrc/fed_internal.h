@@ -43,6 +43,7 @@ struct TilingInput {
   int lds_budget = 64 * 1024;              // bytes of LDS one workgroup may use
   int real_bytes = 4;                      // sizeof(working real)
   int upd_bytes = 0;                       // LDS bytes per updated node besides its slots
+  int touch_bytes = 0;                     // LDS bytes per touched node besides its T
 };
 
 struct Tiling {

@@ -632,6 +632,35 @@ struct KLaw {
   R s0, s1;
   const R *tab;
   int n;
+  // table laws in the forward kernels: the table's value at every touched node
+  // of the tile, evaluated once per node and step where its temperature is
+  // staged (LDS, indexed like the temperatures); null: evaluated per element
+  R *nv = nullptr;
+  // the element mean of its nodes' table values V (the same sums as elem)
+  template <int NE>
+  __device__ R mean(const R *V) const {
+#pragma clang fp contract(off)
+    R f = V[0];
+#pragma unroll
+    for (int a = 1; a < NE; a++) f = f + V[a];
+    return f * ((R)1 / (R)NE);
+  }
+  // s_e of an element whose nodes sit at local indices loc
+  template <int NE>
+  __device__ R elem_at(const R *T, const uint32_t *loc) const {
+    if (n && nv) {
+      R V[NE];
+#pragma unroll
+      for (int a = 0; a < NE; a++) V[a] = nv[loc[a]];
+      return mean<NE>(V);
+    }
+    return elem<NE>(T);
+  }
+  // the table's value at one node, staged into nv[j]
+  __device__ void stage(int j, R T) const {
+    R sl;
+    nv[j] = table_eval(tab, n, T, sl);
+  }
   template <int NE>
   __device__ R elem(const R *T) const {
 #pragma clang fp contract(off)
@@ -667,9 +696,16 @@ struct Elem<R, 8> {
     R T[8];
 #pragma unroll
     for (int n = 0; n < 8; n++) T[n] = Tl[loc[n]];
-    load_vals(T, kl, tdk, h, F);
+    const bool staged = kl.n && kl.nv;
+    R V[8];
+    if (staged)
+#pragma unroll
+      for (int n = 0; n < 8; n++) V[n] = kl.nv[loc[n]];
+    load_vals(T, V, staged, kl, tdk, h, F);
   }
-  __device__ static void load_vals(const R *T, const KLaw<R> &kl, bool tdk, const R h[6], R F[8]) {
+  // V: the nodes' staged table values when staged
+  __device__ static void load_vals(const R *T, const R *V, bool staged, const KLaw<R> &kl,
+                                   bool tdk, const R h[6], R F[8]) {
     // rounding fixed by the source in every kernel that inlines this (no
     // FMA contraction; the FMAs are written out), so all step kernels agree
     // bit for bit
@@ -679,7 +715,7 @@ struct Elem<R, 8> {
     R uy = ((T3 - T0) + (T2 - T1)) + ((T7 - T4) + (T6 - T5));
     R uz = ((T4 - T0) + (T5 - T1)) + ((T6 - T2) + (T7 - T3));
     R s = kl.s0;
-    if (tdk) s = kl.template elem<8>(T);
+    if (tdk) s = staged ? kl.template mean<8>(V) : kl.template elem<8>(T);
     apply(s, h, ux, uy, uz, F);
   }
   // F from the gradient sums u and the factor s
@@ -708,7 +744,7 @@ struct Elem<R, 4> {
     const R T[4] = {Tl[loc[0]], Tl[loc[1]], Tl[loc[2]], Tl[loc[3]]};
     R d1 = T[1] - T[0], d2 = T[2] - T[0], d3 = T[3] - T[0];
     R s = kl.s0;
-    if (tdk) s = kl.template elem<4>(T);
+    if (tdk) s = kl.template elem_at<4>(T, loc);
     apply(s, h, d1, d2, d3, F);
   }
   __device__ static void apply(R s, const R h[6], R d1, R d2, R d3, R F[4]) {
@@ -742,7 +778,7 @@ struct ElemMean {
       gz += hb[3 * n + 2] * d;
     }
     R s = kl.s0;
-    if (tdk) s = kl.template elem<8>(T);
+    if (tdk) s = kl.template elem_at<8>(T, loc);
     const R *vd = hb + 21;
     const R qx = s * (vd[0] * gx + vd[3] * gy + vd[5] * gz);
     const R qy = s * (vd[3] * gx + vd[1] * gy + vd[4] * gz);
@@ -794,7 +830,7 @@ struct ElemMeanHg {
       gz += hb[3 * n + 2] * d[n];
     }
     R s = kl.s0;
-    if (tdk) s = kl.template elem<8>(T);
+    if (tdk) s = kl.template elem_at<8>(T, loc);
     const R *vd = hb + 21;
     const R qx = s * (vd[0] * gx + vd[3] * gy + vd[5] * gz);
     const R qy = s * (vd[3] * gx + vd[1] * gy + vd[4] * gz);
@@ -1202,6 +1238,10 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
   R *slot = reinterpret_cast<R *>(Llo + (MODE == 1 ? nU : 0));
   if (sizeof(R) == 8)
     slot = reinterpret_cast<R *>((reinterpret_cast<uintptr_t>(slot) + 7) & ~uintptr_t(7));
+  // table laws: the table's value at every touched node after the slots
+  KLaw<R> kl = step_law<R, GEN>(a);
+  const bool tabs = GEN && a.nkt > 0;
+  if (tabs) kl.nv = slot + a.maxinc * nU;
   const R *Tin = (const R *)a.Tin;
   const R *alpha = (const R *)a.alpha, *beta = (const R *)a.beta;
   // SPT nodes per thread at a time: all halo ids, then all values
@@ -1230,7 +1270,10 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
     for (int q = 0; q < SPT; q++) {
       const int j = base + tid + q * bs;
-      if (j < nT) Tl[j] = tv[q];
+      if (j < nT) {
+        Tl[j] = tv[q];
+        if (tabs) kl.stage(j, tv[q]);
+      }
       if (j < nU) {
         La[j] = av[q];
         if (TDC) Lb[j] = bv[q];
@@ -1242,7 +1285,6 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
   const int nslot = a.maxinc * nU;
   for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
   __syncthreads();
-  const KLaw<R> kl = step_law<R, GEN>(a);
   const R Tz = (R)a.Tz;
   const uint32_t pmask = (1u << a.pb) - 1u;
   R *Tout = (R *)a.Tout;
@@ -1293,6 +1335,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
           if (MODE == 1) a.loout[th.nstart + j] = lo_new;
         } else {
           Tl[j] = Tn;
+          if (tabs) kl.stage(j, Tn);
           if (MODE == 1) Llo[j] = lo_new;
         }
       }
@@ -1451,16 +1494,27 @@ __global__ __launch_bounds__(1024) void k_step1(StepArgs a) {
     if (j < nown) load_node1<R, MODE, TDC>(a, th, j, nd[q]);
   }
   // ---- stage T of owned and first-ring halo nodes; clear the slots ----
+  // (table laws: the table's value at every touched node after the slots)
   R *Tl = reinterpret_cast<R *>(smem_raw);
   R *slot = Tl + ntouch;
-  const R *Tin = (const R *)a.Tin;
-  for (int j = tid; j < nown; j += bs) Tl[j] = Tin[th.nstart + j];
-  for (int j = tid; j < nhalo; j += bs) Tl[nown + j] = Tin[a.halo[th.hstart + j]];
   const int nslot = a.maxinc * nown;
+  KLaw<R> kl = step_law<R, GEN>(a);
+  const bool tabs = GEN && a.nkt > 0;
+  if (tabs) kl.nv = slot + nslot;
+  const R *Tin = (const R *)a.Tin;
+  for (int j = tid; j < nown; j += bs) {
+    const R v = Tin[th.nstart + j];
+    Tl[j] = v;
+    if (tabs) kl.stage(j, v);
+  }
+  for (int j = tid; j < nhalo; j += bs) {
+    const R v = Tin[a.halo[th.hstart + j]];
+    Tl[nown + j] = v;
+    if (tabs) kl.stage(nown + j, v);
+  }
   for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
   __syncthreads();
   // ---- element loads into the node-local slots ----
-  const KLaw<R> kl = step_law<R, GEN>(a);
   const uint32_t pmask = (1u << a.pb) - 1u;
 #pragma unroll
   for (int q = 0; q < EPT; q++)
@@ -2181,15 +2235,31 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   // hexahedra with the folded operator use node-major slots (below); the
   // uniform-gradient hexahedron, whose tiles on distorted meshes touch more
   // halo nodes, keeps slots for the owned nodes only.  FP32 hexahedra with the
-  // folded operator keep precomputed LDS addresses instead of the packed
-  // entries, the node temperatures' and the slots' (16 registers an element),
-  // so the element phase spends no instructions on addressing
+  // folded operator and the shared linear laws keep precomputed LDS addresses
+  // instead of the packed entries, the node temperatures' and the slots' (16
+  // registers an element), so the element phase spends no instructions on
+  // addressing (tables and per-element laws need those registers)
   constexpr bool NM = NE == 8 && OP == 0;
-  constexpr bool PRE = NM && sizeof(R) == 4 && OP == 0;
+  constexpr bool PRE = NM && sizeof(R) == 4 && OP == 0 && !GEN;
   const int nslot = NM ? ntouch * ((1 << a.pb) + 1) : a.maxinc * nown;
   R *Tl = reinterpret_cast<R *>(smem_raw);
   R *slot = Tl + ntouch;
   R *Lbnd = slot + nslot;  // [5][nbnd]: hA, hA Ta, sigma eps A, radiation Ta, power
+  // uniform-gradient hexahedron: the mean-gradient columns of the tile's
+  // elements, element-major with an odd stride (kOpLds words: the lanes of a
+  // wave read distinct banks), loaded once; the rest of the operator is read
+  // from memory every step
+  // table laws: the table's value at every touched node, staged with T
+  const bool tabs = GEN && a.nkt > 0 && r.nvals;
+  R *NV = Lbnd + 5 * th.nbnd;
+  R *opl = NV + (tabs ? ntouch : 0);
+  if constexpr (OP != 0) {
+    if (r.oplds)
+      for (int k = tid; k < kOpLds * nE; k += bs) {
+        const int c = k / nE, i = k - c * nE;
+        opl[i * kOpLds + c] = Hb[(int64_t)c * a.Eexp + th.estart + i];
+      }
+  }
   uint32_t ta[PRE ? EPT : 1][8], sa[PRE ? EPT : 1][8];
   if constexpr (PRE) {
     const uint32_t tb = lds_addr(Tl), sb = lds_addr(slot);
@@ -2247,7 +2317,9 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   }
   // slots past a node's incidence are never written and stay zero
   for (int j = tid; j < nslot; j += bs) slot[j] = (R)0;
-  const KLaw<R> kl = step_law<R, GEN>(a);
+  KLaw<R> kl = step_law<R, GEN>(a);
+  if (tabs) kl.nv = NV;
+  const uint32_t dnv = (uint32_t)((NV - Tl) * (int)sizeof(R));  // byte offset T -> table value
   const R Tz = (R)a.Tz;
   const uint32_t pmask = (1u << a.pb) - 1u;
   int prow = r.pts_row;
@@ -2266,15 +2338,26 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       asm volatile("" : "+v"(off));
       const R *hp = Hb + th.estart + off;
       R h[HW];
+      if (r.oplds) {
+        const R *lp = opl + off * kOpLds;
 #pragma unroll
-      for (int c = 0; c < HW; c++) h[c] = hp[(int64_t)c * a.Eexp];
+        for (int c = 0; c < kOpLds; c++) h[c] = lp[c];
+#pragma unroll
+        for (int c = kOpLds; c < HW; c++) h[c] = hp[(int64_t)c * a.Eexp];
+      } else {
+#pragma unroll
+        for (int c = 0; c < HW; c++) h[c] = hp[(int64_t)c * a.Eexp];
+      }
       keep_packed(ew[q]);
       element_to_slots<R, NE, TDK, OP, NM>(ew[q], h, Tl, slot, nown, nown, a.pb, pmask, kle);
     } else if constexpr (PRE) {
-      R T[8], F[8];
+      R T[8], V[8], F[8];
 #pragma unroll
       for (int n = 0; n < 8; n++) T[n] = lds_ld<R>(ta[q][n]);
-      Elem<R, 8>::load_vals(T, kle, TDK, eh[q], F);
+      if (tabs)
+#pragma unroll
+        for (int n = 0; n < 8; n++) V[n] = lds_ld<R>(ta[q][n] + dnv);
+      Elem<R, 8>::load_vals(T, V, tabs, kle, TDK, eh[q], F);
 #pragma unroll
       for (int n = 0; n < 8; n++) lds_st<R>(sa[q][n], F[n]);
     } else {
@@ -2302,7 +2385,10 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
 #pragma unroll
     for (int q = 0; q < NPT; q++) {
       const int j = tid + q * bs;
-      if (j < nown) Tl[j] = hi[q];
+      if (j < nown) {
+        Tl[j] = hi[q];
+        if (tabs) kl.stage(j, hi[q]);
+      }
     }
     // ---- elements with every node owned need no halo value: they run while
     // the neighbours' exports of the previous step arrive (the barrier orders
@@ -2342,7 +2428,10 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
 #pragma unroll
     for (int q = 0; q < HPT; q++) {
       const int j = tid + q * bs;
-      if (j < nhalo) Tl[nown + j] = hv[q];
+      if (j < nhalo) {
+        Tl[nown + j] = hv[q];
+        if (tabs) kl.stage(nown + j, hv[q]);
+      }
     }
     if (r.pts) {
 #pragma unroll

@@ -92,7 +92,7 @@ struct Builder {
       if (l < in.depth) nupd += (int64_t)lev[l].size();
       ntouch += (int64_t)lev[l].size();
     }
-    int64_t lds = (int64_t)in.real_bytes * ntouch +
+    int64_t lds = ((int64_t)in.real_bytes + in.touch_bytes) * ntouch +
                   ((int64_t)in.upd_bytes + (int64_t)in.real_bytes * out.maxinc) * nupd + 8;
     return ntouch <= touch_limit && lds <= in.lds_budget;
   }
@@ -366,7 +366,7 @@ struct Builder {
       int32_t ntouch = th.cum_n[K], nupd = th.cum_n[K - 1];
       out.ntouch_max = std::max(out.ntouch_max, ntouch);
       out.nown_max = std::max(out.nown_max, th.nown);
-      lds_max = std::max<int64_t>(lds_max, (int64_t)in.real_bytes * ntouch +
+      lds_max = std::max<int64_t>(lds_max, ((int64_t)in.real_bytes + in.touch_bytes) * ntouch +
                                                ((int64_t)in.upd_bytes + (int64_t)in.real_bytes *
                                                 out.maxinc) * nupd + 8);
       if (ntouch > touch_limit) return "internal: tile exceeds the local index range";
