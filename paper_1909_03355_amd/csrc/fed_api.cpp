@@ -130,7 +130,6 @@ struct fed_ctx {
   unsigned xtag = 1;
   int *d_rerr = nullptr;
   int res_lds = 0;
-  bool res_oplds = false;  // resident uniform-gradient hexahedron: columns in LDS
   bool res_nv = false;     // resident table laws: the table's values at the nodes in LDS
   // bounded halo waits of resident launches; tag_skew != 0 only in tests of
   // the failure path (fed_test_waits)
@@ -579,39 +578,23 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   HIPCHK(P.alloc((void **)&c->d_rerr, sizeof(int)));
   HIPCHK(hipMemset(c->d_rerr, 0, sizeof(int)));
   // LDS of the resident kernel: T of the touched nodes, the slots of the
-  // touched nodes (hexahedra with the folded operator: 2^pb + 1 each) or of
-  // the owned nodes (the others: maxinc each), the 5 boundary coefficients
-  // of the owned boundary nodes and, with a conductivity table, its value at
-  // every touched node (else the elements evaluate it at their nodes)
-  // (the uniform-gradient hexahedron adds its tile's mean-gradient columns,
-  // kOpLds values an element, where every tile has room for them)
-  auto need = [&](bool nv, bool opc) {
+  // touched nodes (hexahedra except the FP64 uniform-gradient one: 2^pb + 1
+  // each) or of the owned nodes (the others: maxinc each), the 5 boundary
+  // coefficients of the owned boundary nodes and, with a conductivity table
+  // where every tile has room for it, the table's value at every touched node
+  // (else the elements evaluate it at their nodes)
+  const bool nm = c->ne == FED_HEX8 && (c->op == 0 || c->rb == 4);
+  auto need = [&](bool nv) {
     int64_t m = 0;
     for (const fed::TileHdr &th : T.tiles) {
-      const int64_t ns = c->ne == FED_HEX8 && c->op == 0
-                             ? (int64_t)th.cum_n[1] * ((1 << T.pb) + 1)
-                             : (int64_t)T.maxinc * th.nown;
-      m = std::max<int64_t>(m, (int64_t)c->rb * (th.cum_n[1] + ns + 5LL * th.nbnd +
-                                                  (nv ? th.cum_n[1] : 0) +
-                                                  (opc ? (int64_t)fed::kOpLds * th.cum_e[0] : 0)) +
-                                   16);
+      const int64_t ns = nm ? (int64_t)th.cum_n[1] * ((1 << T.pb) + 1) : (int64_t)T.maxinc * th.nown;
+      m = std::max<int64_t>(
+          m, (int64_t)c->rb * (th.cum_n[1] + ns + 5LL * th.nbnd + (nv ? th.cum_n[1] : 0)) + 16);
     }
     return m;
   };
-  const int64_t lds_limit = c->max_lds - kStaticLds;
-  const bool want_nv = c->nkt > 0, want_op = c->op != 0;
-  c->res_nv = c->res_oplds = false;
-  int64_t lds = need(false, false);
-  for (int k = 0; k < 4; k++) {
-    // preference: both, the table values only, the operator columns only
-    const bool nv = want_nv && k < 2, opc = want_op && (k == 0 || k == 2);
-    if ((nv || opc) && need(nv, opc) <= lds_limit) {
-      c->res_nv = nv;
-      c->res_oplds = opc;
-      lds = need(nv, opc);
-      break;
-    }
-  }
+  c->res_nv = c->nkt > 0 && need(true) <= c->max_lds - kStaticLds;
+  const int64_t lds = need(c->res_nv);
   if (lds > c->max_lds - kStaticLds)
     return fail(FED_E_MESH, "resident stepping: a tile needs %lld bytes of LDS (the GPU has %d, "
                 "%d of them taken by the health check)",
@@ -1216,7 +1199,6 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
                        c->d_T[fin], c->d_lo[fin], nullptr, 0};
         r.split = c->res_split;
         r.tag_skew = c->tag_skew;
-        r.oplds = c->res_oplds ? 1 : 0;
       r.nvals = c->res_nv ? 1 : 0;
         if (c->keep_states && c->ckpt_every > 0) {
           // fed_step breaks launches at checkpoints: this one stays inside segment g
@@ -1839,7 +1821,6 @@ int backward_run(fed_ctx *c, const fed::AdjWork &w, const double *dL_dT, double 
       fed::ResArgs r{k, 1 << 22, c->xtag, c->d_exported, {c->d_X[0], c->d_X[1]}, c->d_rerr,
                      seg(k), w.seglo[k & 1], segb, N};
       r.split = c->res_split;
-      r.oplds = c->res_oplds ? 1 : 0;
       r.nvals = c->res_nv ? 1 : 0;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;

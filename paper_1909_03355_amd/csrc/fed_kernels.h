@@ -228,18 +228,11 @@ struct ResArgs {
   int split;
   unsigned tag_skew;          // added to the tag a wait looks for: 0, or (tests of the
                               // failure path) a value no word carries
-  // uniform-gradient hexahedron: 1 if the mean-gradient columns (the first
-  // kOpLds operator values of each element) are copied to LDS once per launch
-  // and read there every step, 0 if every step reads them from memory
-  int oplds;
   // table laws: 1 if each step stages the conductivity table's value at every
   // touched node in LDS (the elements average those), 0 if the elements
   // evaluate the table at their nodes
   int nvals;
 };
-// operator values of the uniform-gradient hexahedron a resident tile may keep
-// in LDS: the seven mean-gradient columns b_0..b_6
-constexpr int kOpLds = 21;
 
 // Resident adjoint of one checkpoint segment (hexahedra, folded operator):
 // nsteps adjoint steps over the stored states T^{n0 + i} at seg + i * segN,

@@ -2232,34 +2232,22 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       }
     }
   }
-  // hexahedra with the folded operator use node-major slots (below); the
-  // uniform-gradient hexahedron, whose tiles on distorted meshes touch more
-  // halo nodes, keeps slots for the owned nodes only.  FP32 hexahedra with the
-  // folded operator and the shared linear laws keep precomputed LDS addresses
+  // hexahedra use node-major slots (below), except the FP64 uniform-gradient
+  // hexahedron, whose tiles on distorted meshes touch more halo nodes than
+  // such slots leave LDS for: it keeps slots for the owned nodes only.  FP32
+  // hexahedra with the folded operator and the shared linear laws keep precomputed LDS addresses
   // instead of the packed entries, the node temperatures' and the slots' (16
   // registers an element), so the element phase spends no instructions on
   // addressing (tables and per-element laws need those registers)
-  constexpr bool NM = NE == 8 && OP == 0;
+  constexpr bool NM = NE == 8 && (OP == 0 || sizeof(R) == 4);
   constexpr bool PRE = NM && sizeof(R) == 4 && OP == 0 && !GEN;
   const int nslot = NM ? ntouch * ((1 << a.pb) + 1) : a.maxinc * nown;
   R *Tl = reinterpret_cast<R *>(smem_raw);
   R *slot = Tl + ntouch;
   R *Lbnd = slot + nslot;  // [5][nbnd]: hA, hA Ta, sigma eps A, radiation Ta, power
-  // uniform-gradient hexahedron: the mean-gradient columns of the tile's
-  // elements, element-major with an odd stride (kOpLds words: the lanes of a
-  // wave read distinct banks), loaded once; the rest of the operator is read
-  // from memory every step
   // table laws: the table's value at every touched node, staged with T
   const bool tabs = GEN && a.nkt > 0 && r.nvals;
   R *NV = Lbnd + 5 * th.nbnd;
-  R *opl = NV + (tabs ? ntouch : 0);
-  if constexpr (OP != 0) {
-    if (r.oplds)
-      for (int k = tid; k < kOpLds * nE; k += bs) {
-        const int c = k / nE, i = k - c * nE;
-        opl[i * kOpLds + c] = Hb[(int64_t)c * a.Eexp + th.estart + i];
-      }
-  }
   uint32_t ta[PRE ? EPT : 1][8], sa[PRE ? EPT : 1][8];
   if constexpr (PRE) {
     const uint32_t tb = lds_addr(Tl), sb = lds_addr(slot);
@@ -2303,9 +2291,9 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     const int j = tid + q * bs;
     hid[q] = j < nhalo ? a.halo[th.hstart + j] : 0;
   }
-  // hexahedra with the folded operator: node-major slots of every touched
-  // node (element phase without tests); the others (tetrahedra: 24 slots a
-  // node): position-major, owned nodes only
+  // hexahedra (not the FP64 uniform-gradient one): node-major slots of every
+  // touched node (element phase without tests); the others (tetrahedra: 24
+  // slots a node): position-major, owned nodes only
   const int nbnd = th.nbnd;
   for (int j = tid; j < nbnd; j += bs) {
     const int rr = th.bstart + j;
@@ -2338,16 +2326,8 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       asm volatile("" : "+v"(off));
       const R *hp = Hb + th.estart + off;
       R h[HW];
-      if (r.oplds) {
-        const R *lp = opl + off * kOpLds;
 #pragma unroll
-        for (int c = 0; c < kOpLds; c++) h[c] = lp[c];
-#pragma unroll
-        for (int c = kOpLds; c < HW; c++) h[c] = hp[(int64_t)c * a.Eexp];
-      } else {
-#pragma unroll
-        for (int c = 0; c < HW; c++) h[c] = hp[(int64_t)c * a.Eexp];
-      }
+      for (int c = 0; c < HW; c++) h[c] = hp[(int64_t)c * a.Eexp];
       keep_packed(ew[q]);
       element_to_slots<R, NE, TDK, OP, NM>(ew[q], h, Tl, slot, nown, nown, a.pb, pmask, kle);
     } else if constexpr (PRE) {
