@@ -578,12 +578,13 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   HIPCHK(P.alloc((void **)&c->d_rerr, sizeof(int)));
   HIPCHK(hipMemset(c->d_rerr, 0, sizeof(int)));
   // LDS of the resident kernel: T of the touched nodes, the slots of the
-  // touched nodes (hexahedra except the FP64 uniform-gradient one: 2^pb + 1
-  // each) or of the owned nodes (the others: maxinc each), the 5 boundary
-  // coefficients of the owned boundary nodes and, with a conductivity table
-  // where every tile has room for it, the table's value at every touched node
-  // (else the elements evaluate it at their nodes)
-  const bool nm = c->ne == FED_HEX8 && (c->op == 0 || c->rb == 4);
+  // touched nodes (hexahedra, in FP64 except the uniform-gradient one and the
+  // general laws: 2^pb + 1 each) or of the owned nodes (the others: maxinc
+  // each), the 5 boundary coefficients of the owned boundary nodes and, with a
+  // conductivity table where every tile has room for it, the table's value at
+  // every touched node (else the elements evaluate it at their nodes)
+  const bool gen = c->d_ktab || c->d_ctab || c->d_esk;  // the kernel's general-law instance
+  const bool nm = c->ne == FED_HEX8 && (c->op == 0 || c->rb == 4) && !(gen && c->rb == 8);
   auto need = [&](bool nv) {
     int64_t m = 0;
     for (const fed::TileHdr &th : T.tiles) {

@@ -769,24 +769,26 @@ struct ElemMean {
     R T[8];
 #pragma unroll
     for (int n = 0; n < 8; n++) T[n] = Tl[loc[n]];
-    R gx = 0, gy = 0, gz = 0;
+    // (the FMAs written out, as in Elem<R, 8>, so every kernel rounds alike)
+    R d = T[0] - T[7];
+    R gx = hb[0] * d, gy = hb[1] * d, gz = hb[2] * d;
 #pragma unroll
-    for (int n = 0; n < 7; n++) {
-      const R d = T[n] - T[7];
-      gx += hb[3 * n] * d;
-      gy += hb[3 * n + 1] * d;
-      gz += hb[3 * n + 2] * d;
+    for (int n = 1; n < 7; n++) {
+      d = T[n] - T[7];
+      gx = fma(hb[3 * n], d, gx);
+      gy = fma(hb[3 * n + 1], d, gy);
+      gz = fma(hb[3 * n + 2], d, gz);
     }
     R s = kl.s0;
     if (tdk) s = kl.template elem_at<8>(T, loc);
     const R *vd = hb + 21;
-    const R qx = s * (vd[0] * gx + vd[3] * gy + vd[5] * gz);
-    const R qy = s * (vd[3] * gx + vd[1] * gy + vd[4] * gz);
-    const R qz = s * (vd[5] * gx + vd[4] * gy + vd[2] * gz);
+    const R qx = s * fma(vd[5], gz, fma(vd[3], gy, vd[0] * gx));
+    const R qy = s * fma(vd[4], gz, fma(vd[1], gy, vd[3] * gx));
+    const R qz = s * fma(vd[2], gz, fma(vd[4], gy, vd[5] * gx));
     R sum = 0;
 #pragma unroll
     for (int n = 0; n < 7; n++) {
-      F[n] = (hb[3 * n] * qx + hb[3 * n + 1] * qy) + hb[3 * n + 2] * qz;
+      F[n] = fma(hb[3 * n + 2], qz, fma(hb[3 * n + 1], qy, hb[3 * n] * qx));
       sum += F[n];
     }
     F[7] = -sum;
@@ -812,7 +814,7 @@ struct ElemMeanHg {
 #pragma unroll
       for (int n = 0; n < 7; n++) ht = hg_sign(al, n) > 0 ? ht + d[n] : ht - d[n];
       const R *hx = hb + 28 + 3 * al;
-      c[al] = (ht - ((hx[0] * gx + hx[1] * gy) + hx[2] * gz)) * (R)0.125;
+      c[al] = (ht - fma(hx[2], gz, fma(hx[1], gy, hx[0] * gx))) * (R)0.125;
     }
   }
   __device__ static void load(const R *Tl, const uint32_t *loc, const KLaw<R> &kl, bool tdk,
@@ -821,28 +823,29 @@ struct ElemMeanHg {
     R T[8], d[7];
 #pragma unroll
     for (int n = 0; n < 8; n++) T[n] = Tl[loc[n]];
-    R gx = 0, gy = 0, gz = 0;
+    d[0] = T[0] - T[7];
+    R gx = hb[0] * d[0], gy = hb[1] * d[0], gz = hb[2] * d[0];
 #pragma unroll
-    for (int n = 0; n < 7; n++) {
+    for (int n = 1; n < 7; n++) {
       d[n] = T[n] - T[7];
-      gx += hb[3 * n] * d[n];
-      gy += hb[3 * n + 1] * d[n];
-      gz += hb[3 * n + 2] * d[n];
+      gx = fma(hb[3 * n], d[n], gx);
+      gy = fma(hb[3 * n + 1], d[n], gy);
+      gz = fma(hb[3 * n + 2], d[n], gz);
     }
     R s = kl.s0;
     if (tdk) s = kl.template elem_at<8>(T, loc);
     const R *vd = hb + 21;
-    const R qx = s * (vd[0] * gx + vd[3] * gy + vd[5] * gz);
-    const R qy = s * (vd[3] * gx + vd[1] * gy + vd[4] * gz);
-    const R qz = s * (vd[5] * gx + vd[4] * gy + vd[2] * gz);
+    const R qx = s * fma(vd[5], gz, fma(vd[3], gy, vd[0] * gx));
+    const R qy = s * fma(vd[4], gz, fma(vd[1], gy, vd[3] * gx));
+    const R qz = s * fma(vd[2], gz, fma(vd[4], gy, vd[5] * gx));
     R c[4];
     amps(d, gx, gy, gz, hb, c);
-    R w0 = 0, w1 = 0, w2 = 0;
+    R w0 = c[0] * hb[28], w1 = c[0] * hb[29], w2 = c[0] * hb[30];
 #pragma unroll
-    for (int al = 0; al < 4; al++) {
-      w0 += c[al] * hb[28 + 3 * al];
-      w1 += c[al] * hb[29 + 3 * al];
-      w2 += c[al] * hb[30 + 3 * al];
+    for (int al = 1; al < 4; al++) {
+      w0 = fma(c[al], hb[28 + 3 * al], w0);
+      w1 = fma(c[al], hb[29 + 3 * al], w1);
+      w2 = fma(c[al], hb[30 + 3 * al], w2);
     }
     const R sk = s * hb[27] * (R)0.125;
     R sum = 0;
@@ -851,8 +854,8 @@ struct ElemMeanHg {
       R hc = 0;
 #pragma unroll
       for (int al = 0; al < 4; al++) hc = hg_sign(al, n) > 0 ? hc + c[al] : hc - c[al];
-      const R wb = (w0 * hb[3 * n] + w1 * hb[3 * n + 1]) + w2 * hb[3 * n + 2];
-      F[n] = ((hb[3 * n] * qx + hb[3 * n + 1] * qy) + hb[3 * n + 2] * qz) + sk * (hc - wb);
+      const R wb = fma(w2, hb[3 * n + 2], fma(w1, hb[3 * n + 1], w0 * hb[3 * n]));
+      F[n] = fma(sk, hc - wb, fma(hb[3 * n + 2], qz, fma(hb[3 * n + 1], qy, hb[3 * n] * qx)));
       sum += F[n];
     }
     F[7] = -sum;
@@ -2232,14 +2235,15 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       }
     }
   }
-  // hexahedra use node-major slots (below), except the FP64 uniform-gradient
+  // hexahedra use node-major slots (below), except in FP64 the uniform-gradient
   // hexahedron, whose tiles on distorted meshes touch more halo nodes than
-  // such slots leave LDS for: it keeps slots for the owned nodes only.  FP32
+  // such slots leave LDS for, and the general laws, whose table values need
+  // the room: they keep slots for the owned nodes only.  FP32
   // hexahedra with the folded operator and the shared linear laws keep precomputed LDS addresses
   // instead of the packed entries, the node temperatures' and the slots' (16
   // registers an element), so the element phase spends no instructions on
   // addressing (tables and per-element laws need those registers)
-  constexpr bool NM = NE == 8 && (OP == 0 || sizeof(R) == 4);
+  constexpr bool NM = NE == 8 && (OP == 0 || sizeof(R) == 4) && !(GEN && sizeof(R) == 8);
   constexpr bool PRE = NM && sizeof(R) == 4 && OP == 0 && !GEN;
   const int nslot = NM ? ntouch * ((1 << a.pb) + 1) : a.maxinc * nown;
   R *Tl = reinterpret_cast<R *>(smem_raw);
@@ -2291,9 +2295,9 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     const int j = tid + q * bs;
     hid[q] = j < nhalo ? a.halo[th.hstart + j] : 0;
   }
-  // hexahedra (not the FP64 uniform-gradient one): node-major slots of every
-  // touched node (element phase without tests); the others (tetrahedra: 24
-  // slots a node): position-major, owned nodes only
+  // hexahedra (in FP64 not the uniform-gradient one, nor the general laws):
+  // node-major slots of every touched node (element phase without tests); the
+  // others (tetrahedra: 24 slots a node): position-major, owned nodes only
   const int nbnd = th.nbnd;
   for (int j = tid; j < nbnd; j += bs) {
     const int rr = th.bstart + j;
