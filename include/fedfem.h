@@ -235,8 +235,8 @@ typedef struct {
                                           dev_alloc hook or hipMalloc) */
   double reread_bytes_per_step;        /* resident stepping: bytes one step reads again
                                           beyond the exchange (the operators of the
-                                          uniform-gradient hexahedron, too large to stay
-                                          on chip, re-read every step); 0 else */
+                                          uniform-gradient hexahedron that do not stay on
+                                          chip, re-read every step); 0 else */
 } fed_info;
 
 /*

@@ -131,6 +131,8 @@ struct fed_ctx {
   int *d_rerr = nullptr;
   int res_lds = 0;
   bool res_nv = false;     // resident table laws: the table's values at the nodes in LDS
+  bool res_oph = false;    // resident uniform-gradient hexahedron: halo elements' operators in LDS
+  int64_t res_oph_elems = 0;  // (expanded) elements whose operators stay in LDS
   // bounded halo waits of resident launches; tag_skew != 0 only in tests of
   // the failure path (fed_test_waits)
   int spin_limit = 1 << 22;
@@ -578,24 +580,38 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   HIPCHK(P.alloc((void **)&c->d_rerr, sizeof(int)));
   HIPCHK(hipMemset(c->d_rerr, 0, sizeof(int)));
   // LDS of the resident kernel: T of the touched nodes, the slots of the
-  // touched nodes (hexahedra, in FP64 except the uniform-gradient one and the
-  // general laws: 2^pb + 1 each) or of the owned nodes (the others: maxinc
+  // touched nodes (hexahedra, except the FP32 uniform-gradient instance that
+  // keeps halo elements' operators, and in FP64 the uniform-gradient one and
+  // the general laws: 2^pb + 1 each) or of the owned nodes (the others: maxinc
   // each), the 5 boundary coefficients of the owned boundary nodes and, with a
   // conductivity table where every tile has room for it, the table's value at
   // every touched node (else the elements evaluate it at their nodes)
+  // (the FP32 uniform-gradient hexahedron without hourglass control and with
+  // the shared laws adds, where every tile has room for them, the operators
+  // of its elements that touch the halo)
   const bool gen = c->d_ktab || c->d_ctab || c->d_esk;  // the kernel's general-law instance
-  const bool nm = c->ne == FED_HEX8 && (c->op == 0 || c->rb == 4) && !(gen && c->rb == 8);
-  auto need = [&](bool nv) {
+  const bool oph_inst = c->op == 1 && !gen && c->rb == 4;  // the kernel's OPH instances
+  const bool nm = c->ne == FED_HEX8 && (c->op == 0 || (c->rb == 4 && !oph_inst)) &&
+                  !(gen && c->rb == 8);
+  auto need = [&](bool nv, bool oph) {
     int64_t m = 0;
     for (const fed::TileHdr &th : T.tiles) {
       const int64_t ns = nm ? (int64_t)th.cum_n[1] * ((1 << T.pb) + 1) : (int64_t)T.maxinc * th.nown;
-      m = std::max<int64_t>(
-          m, (int64_t)c->rb * (th.cum_n[1] + ns + 5LL * th.nbnd + (nv ? th.cum_n[1] : 0)) + 16);
+      const int64_t nh = th.cum_e[0] - (c->res_split ? th.nint : 0);  // elements after the wait
+      m = std::max<int64_t>(m, (int64_t)c->rb * (th.cum_n[1] + ns + 5LL * th.nbnd +
+                                                  (nv ? th.cum_n[1] : 0) +
+                                                  (oph ? (int64_t)(c->hw | 1) * nh : 0)) +
+                                   16);
     }
     return m;
   };
-  c->res_nv = c->nkt > 0 && need(true) <= c->max_lds - kStaticLds;
-  const int64_t lds = need(c->res_nv);
+  const int64_t lds_limit = c->max_lds - kStaticLds;
+  c->res_nv = c->nkt > 0 && need(true, false) <= lds_limit;
+  c->res_oph = oph_inst && need(c->res_nv, true) <= lds_limit;
+  const int64_t lds = need(c->res_nv, c->res_oph);
+  c->res_oph_elems = 0;
+  if (c->res_oph)
+    for (const fed::TileHdr &th : T.tiles) c->res_oph_elems += th.cum_e[0] - (c->res_split ? th.nint : 0);
   if (lds > c->max_lds - kStaticLds)
     return fail(FED_E_MESH, "resident stepping: a tile needs %lld bytes of LDS (the GPU has %d, "
                 "%d of them taken by the health check)",
@@ -1098,8 +1114,10 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
   }
   moved += 5.0 * rb * nrec;
   I.moved_bytes_per_launch = moved;
-  // resident operators that do not stay on chip: every tile's copies, every step
-  I.reread_bytes_per_step = c->resident && c->op ? (double)c->hw * rb * c->Eexp : 0.0;
+  // resident operators that do not stay on chip (the elements that run before
+  // the halo wait, or all): every tile's copies, every step
+  I.reread_bytes_per_step =
+      c->resident && c->op ? (double)c->hw * rb * (double)(c->Eexp - c->res_oph_elems) : 0.0;
   *out = c.release();
   return FED_OK;
 }
@@ -1201,6 +1219,7 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
         r.split = c->res_split;
         r.tag_skew = c->tag_skew;
       r.nvals = c->res_nv ? 1 : 0;
+      r.ophalo = c->res_oph ? 1 : 0;
         if (c->keep_states && c->ckpt_every > 0) {
           // fed_step breaks launches at checkpoints: this one stays inside segment g
           const int64_t g = st / c->ckpt_every, i0 = st % c->ckpt_every;
@@ -1823,6 +1842,7 @@ int backward_run(fed_ctx *c, const fed::AdjWork &w, const double *dL_dT, double 
                      seg(k), w.seglo[k & 1], segb, N};
       r.split = c->res_split;
       r.nvals = c->res_nv ? 1 : 0;
+      r.ophalo = c->res_oph ? 1 : 0;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
         r.pts_nrec = c->nrec;

@@ -232,6 +232,9 @@ struct ResArgs {
   // touched node in LDS (the elements average those), 0 if the elements
   // evaluate the table at their nodes
   int nvals;
+  // uniform-gradient hexahedron: 1 if the operators of the elements that
+  // touch the halo are copied to LDS at the launch's start
+  int ophalo;
 };
 
 // Resident adjoint of one checkpoint segment (hexahedra, folded operator):

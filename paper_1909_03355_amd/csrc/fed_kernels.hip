@@ -2235,15 +2235,22 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       }
     }
   }
-  // hexahedra use node-major slots (below), except in FP64 the uniform-gradient
-  // hexahedron, whose tiles on distorted meshes touch more halo nodes than
-  // such slots leave LDS for, and the general laws, whose table values need
-  // the room: they keep slots for the owned nodes only.  FP32
-  // hexahedra with the folded operator and the shared linear laws keep precomputed LDS addresses
-  // instead of the packed entries, the node temperatures' and the slots' (16
-  // registers an element), so the element phase spends no instructions on
-  // addressing (tables and per-element laws need those registers)
-  constexpr bool NM = NE == 8 && (OP == 0 || sizeof(R) == 4) && !(GEN && sizeof(R) == 8);
+  // OPH: the FP32 uniform-gradient hexahedron without hourglass control, with
+  // the shared laws, keeps the operators of the elements that touch the halo
+  // in LDS (below); the other instances keep one code path, which their
+  // registers need.
+  // Hexahedra use node-major slots (below), except where the LDS is wanted
+  // for more: the OPH operators, the FP64 uniform-gradient hexahedron (whose
+  // tiles on distorted meshes touch more halo nodes than such slots leave LDS
+  // for) and the FP64 general laws (their table values); they keep slots for
+  // the owned nodes only.  FP32 hexahedra with the folded operator and the
+  // shared linear laws keep precomputed LDS addresses instead of the packed
+  // entries, the node temperatures' and the slots' (16 registers an element),
+  // so the element phase spends no instructions on addressing (tables and
+  // per-element laws need those registers)
+  constexpr bool OPH = OP == 1 && !GEN && sizeof(R) == 4;
+  constexpr bool NM =
+      NE == 8 && (OP == 0 || (sizeof(R) == 4 && !OPH)) && !(GEN && sizeof(R) == 8);
   constexpr bool PRE = NM && sizeof(R) == 4 && OP == 0 && !GEN;
   const int nslot = NM ? ntouch * ((1 << a.pb) + 1) : a.maxinc * nown;
   R *Tl = reinterpret_cast<R *>(smem_raw);
@@ -2252,6 +2259,23 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   // table laws: the table's value at every touched node, staged with T
   const bool tabs = GEN && a.nkt > 0 && r.nvals;
   R *NV = Lbnd + 5 * th.nbnd;
+  // the elements with every node owned come first in the tile's list
+  const int nint = r.split ? th.nint : 0;
+  // OPH: the operators of the elements that touch the halo, copied to LDS
+  // once (element-major, an odd stride: the lanes of a wave read distinct
+  // banks), so the elements that run after the halo wait read no memory; the
+  // others read theirs from memory while the halo arrives
+  constexpr int HWS = HW | 1;
+  R *oph = NV + (tabs ? ntouch : 0);
+  if constexpr (OPH) {
+    if (r.ophalo) {
+      const int nh = nE - nint;
+      for (int k = tid; k < HW * nh; k += bs) {
+        const int c = k / nh, m = k - c * nh;
+        oph[m * HWS + c] = Hb[(int64_t)c * a.Eexp + th.estart + nint + m];
+      }
+    }
+  }
   uint32_t ta[PRE ? EPT : 1][8], sa[PRE ? EPT : 1][8];
   if constexpr (PRE) {
     const uint32_t tb = lds_addr(Tl), sb = lds_addr(slot);
@@ -2318,20 +2342,33 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   // element loads into the node-local slots
   // (materials with different k(T) laws: the element's own (s0, s1), read
   // when the element runs, as in the one-step kernel)
-  auto element = [&](int q) {
+  // the operator of element slot q from memory (SoA, coalesced).  The offset
+  // is made opaque on every call, so the compiler keeps these loads where
+  // they are written instead of hoisting HW values an element out of the
+  // step loop into registers (and scratch)
+  auto load_op = [&](int q, R *h) {
+    uint32_t off = (uint32_t)(tid + q * bs);
+    asm volatile("" : "+v"(off));
+    const R *hp = Hb + th.estart + off;
+#pragma unroll
+    for (int c = 0; c < HW; c++) h[c] = hp[(int64_t)c * a.Eexp];
+  };
+  // (halo: the element runs after the halo wait)
+  auto element = [&](int q, bool halo) {
     const int64_t e = (int64_t)th.estart + tid + q * bs;
     const KLaw<R> kle = elem_law<GEN>(a, kl, e);
     if constexpr (OP != 0) {
-      // the operator from memory (SoA, coalesced), then the element's load.
-      // The offset is made opaque on every step, so the compiler keeps these
-      // loads in the step instead of hoisting HW values a element out of the
-      // loop into registers (and scratch)
+      // the operator from registers, LDS or memory, then the element's load
       uint32_t off = (uint32_t)(tid + q * bs);
       asm volatile("" : "+v"(off));
-      const R *hp = Hb + th.estart + off;
       R h[HW];
+      if (OPH && halo && r.ophalo) {
+        const R *lp = oph + (off - (uint32_t)nint) * HWS;
 #pragma unroll
-      for (int c = 0; c < HW; c++) h[c] = hp[(int64_t)c * a.Eexp];
+        for (int c = 0; c < HW; c++) h[c] = lp[c];
+      } else {
+        load_op(q, h);
+      }
       keep_packed(ew[q]);
       element_to_slots<R, NE, TDK, OP, NM>(ew[q], h, Tl, slot, nown, nown, a.pb, pmask, kle);
     } else if constexpr (PRE) {
@@ -2349,8 +2386,6 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       element_to_slots<R, NE, TDK, 0, NM>(ew[q], eh[q], Tl, slot, nown, nown, a.pb, pmask, kle);
     }
   };
-  // the elements with every node owned come first in the tile's list
-  const int nint = r.split ? th.nint : 0;
   // health: the step count of the first check that found a temperature of
   // the wave's nodes outside the window (wave-uniform, so it lives in a
   // scalar register), and the extremes since the last check (FP32, compared
@@ -2381,7 +2416,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < EPT; q++)
-        if (tid + q * bs < nint) element(q);
+        if (tid + q * bs < nint) element(q, false);
     }
     // ---- halo from the state or the exchange, once the previous step's
     // export stores have completed (polling while they drain is slower;
@@ -2429,7 +2464,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
 #pragma unroll
     for (int q = 0; q < EPT; q++) {
       const int i = tid + q * bs;
-      if (i >= nint && i < nE) element(q);
+      if (i >= nint && i < nE) element(q, true);
     }
     __syncthreads();
     // ---- per node: ordered sum, surface loads, explicit update, export ----
