@@ -347,8 +347,8 @@ int validate(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc, cons
     const int32_t n = w ? mt->n_ctab : mt->n_ktab;
     const double *tT = w ? mt->ctab_T : mt->ktab_T, *tf = w ? mt->ctab_f : mt->ktab_f;
     if (n == 0) continue;
-    if (n < 2 || n > 16 || !tT || !tf)
-      return fail(FED_E_ARG, "%s table: need 2..16 points", w ? "c" : "k");
+    if (n < 2 || n > fed::kMaxTablePoints || !tT || !tf)
+      return fail(FED_E_ARG, "%s table: need 2..%d points", w ? "c" : "k", fed::kMaxTablePoints);
     for (int i = 0; i < n; i++)
       if (!finite(tT[i]) || !(tf[i] > 0) || !finite(tf[i]) || (i && !(tT[i] > tT[i - 1])))
         return fail(FED_E_ARG, "%s table: T must increase strictly and f be positive and finite",

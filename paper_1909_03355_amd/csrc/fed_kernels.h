@@ -206,6 +206,9 @@ hipError_t launch_expand_H(int prec, int W, int from, int to, int64_t Eexp, int6
 // are passed through two exchange buffers of tagged words (FP32: 64 bits, the
 // step number and the value; FP64: 16 bytes, step, value, step), so a reader
 // polls the data itself until it carries the step it needs.
+// largest number of breakpoints of a property table
+constexpr int kMaxTablePoints = 16;
+
 struct ResArgs {
   int nsteps;
   int spin_limit;             // polls of a halo word before the wait gives up
