@@ -46,15 +46,15 @@ TRAFFIC_SRC = [os.path.join(ROOT, "paper_1909_03355_amd", "csrc", f)
 # SHA-1; anything else reports null.
 #   workload -> (sha1, kernel, shape, bytes per launch or once, bytes per step)
 TRAFFIC = {
-    "nonlinear_hex64": ("4eb14d888b638b9f035a2161002a17cccf33041b", "k_resident", (256, 1024, 1, 1), 20516101.8, 2362566.3),
-    "aniso_tet128": ("4eb14d888b638b9f035a2161002a17cccf33041b", "k_step1", (4194, 512, 1, 0), 620604992.5, 0.0),
-    "batched_hex256": ("4eb14d888b638b9f035a2161002a17cccf33041b", "k_step1", (6437, 512, 1, 0), 463401794.0, 0.0),
-    "tables_hex64": ("4eb14d888b638b9f035a2161002a17cccf33041b", "k_resident", (256, 1024, 1, 1), 20509079.2, 2399753.0),
-    "meanhex_hex64": ("4eb14d888b638b9f035a2161002a17cccf33041b", "k_resident", (256, 1024, 1, 1), 23518523.1, 28100634.8),
-    "meanhg_hex64": ("4eb14d888b638b9f035a2161002a17cccf33041b", "k_resident", (256, 1024, 1, 1), 10040492.5, 59101662.6),
-    "moving_source_hex64": ("4eb14d888b638b9f035a2161002a17cccf33041b", "k_resident", (256, 1024, 1, 1), 22445799.0, 2367225.7),
-    "paper_standin_ti": ("4eb14d888b638b9f035a2161002a17cccf33041b", "k_resident", (250, 1024, 1, 1), 2930533.9, 202059.8),
-    "paper_standin_td": ("4eb14d888b638b9f035a2161002a17cccf33041b", "k_resident", (250, 1024, 1, 1), 2974561.3, 201528.7),
+    "nonlinear_hex64": ("4de496a391821fd0eb72e5ea626e70fd4b6659ec", "k_resident", (256, 1024, 1, 1), 20624603.9, 2357877.1),
+    "aniso_tet128": ("4de496a391821fd0eb72e5ea626e70fd4b6659ec", "k_step1", (4194, 512, 1, 0), 620544661.6, 0.0),
+    "batched_hex256": ("4de496a391821fd0eb72e5ea626e70fd4b6659ec", "k_step1", (6437, 512, 1, 0), 463393666.4, 0.0),
+    "tables_hex64": ("4de496a391821fd0eb72e5ea626e70fd4b6659ec", "k_resident", (256, 1024, 1, 1), 20403242.9, 2401953.8),
+    "meanhex_hex64": ("4de496a391821fd0eb72e5ea626e70fd4b6659ec", "k_resident", (256, 1024, 1, 1), 49267351.2, 5366890.4),
+    "meanhg_hex64": ("4de496a391821fd0eb72e5ea626e70fd4b6659ec", "k_resident", (256, 1024, 1, 1), 10521187.6, 59088731.0),
+    "moving_source_hex64": ("4de496a391821fd0eb72e5ea626e70fd4b6659ec", "k_resident", (256, 1024, 1, 1), 22422906.8, 2365752.9),
+    "paper_standin_ti": ("4de496a391821fd0eb72e5ea626e70fd4b6659ec", "k_resident", (250, 1024, 1, 1), 2940329.7, 201851.6),
+    "paper_standin_td": ("4de496a391821fd0eb72e5ea626e70fd4b6659ec", "k_resident", (250, 1024, 1, 1), 2979732.6, 202332.5),
 }
 METRIC = "element-updates/s & HBM GB/s, FP32-compensated vs FP64 on GPU at stated error"
 
