@@ -2340,9 +2340,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     const int j = tid + q * bs;
     hid[q] = j < nhalo ? a.halo[th.hstart + j] : 0;
   }
-  // hexahedra (in FP64 not the uniform-gradient one, nor the general laws):
-  // node-major slots of every touched node (element phase without tests); the
-  // others (tetrahedra: 24 slots a node): position-major, owned nodes only
+  // the boundary records of the owned nodes into LDS (slots: NM above)
   const int nbnd = th.nbnd;
   for (int j = tid; j < nbnd; j += bs) {
     const int rr = th.bstart + j;

@@ -106,7 +106,10 @@ def test_tables_hex64_full_size():
 def test_meanhex_hex64_full_size():
     """The uniform-gradient hexahedron on the distorted 64^3 mesh, 100 steps,
     in the launch shape bench.py times (resident), against the oracle, and
-    bitwise equal to one step per launch."""
+    bitwise equal to one step per launch.  In FP32 this launch keeps the
+    operators of the elements that run after the halo wait in LDS, so it
+    re-reads less than every operator each step; FP64 re-reads them all."""
+    from paper_1909_03355_amd import Simulation
     p = P.cube_nonlinear_hex_mean(64, 100)
     ref = Oracle(p).run(100)
     for prec in ("fp64", "fp32c"):
@@ -115,6 +118,15 @@ def test_meanhex_hex64_full_size():
         print(f"meanhex_hex64 {prec}: err_max {err:.2e}", flush=True)
         assert err <= TOL[prec]
         assert np.array_equal(T, _run(p, prec, 100)[0])
+        with Simulation(p, prec=prec, resident=True) as s:
+            i = s.info
+        full = 27 * (8 if prec == "fp64" else 4) * i["n_elems_expanded"]
+        print(f"meanhex_hex64 {prec}: re-read {i['reread_bytes_per_step'] / 1e6:.2f} of "
+              f"{full / 1e6:.2f} MB a step", flush=True)
+        if prec == "fp32c":
+            assert 0 < i["reread_bytes_per_step"] < 0.8 * full
+        else:
+            assert i["reread_bytes_per_step"] == full
 
 
 def test_meanhg_hex64_full_size():
