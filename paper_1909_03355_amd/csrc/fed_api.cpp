@@ -133,6 +133,9 @@ struct fed_ctx {
   bool res_nv = false;     // resident table laws: the table's values at the nodes in LDS
   bool res_oph = false;    // resident uniform-gradient hexahedron: halo elements' operators in LDS
   int64_t res_oph_elems = 0;  // (expanded) elements whose operators stay in LDS
+  int16_t *d_sigma = nullptr;  // resident LDS positions of the touched nodes (or null)
+  uint16_t *d_ent_sigma = nullptr;  // the packed entries with those positions
+  int res_sstride = 0;
   // bounded halo waits of resident launches; tag_skew != 0 only in tests of
   // the failure path (fed_test_waits)
   int spin_limit = 1 << 22;
@@ -572,6 +575,42 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   }
   DevPool &P = c->pool;
   HIPCHK(upload(P, &c->d_exported, exported.data(), exported.size()));
+  // FP32 hexahedra with the folded operator and the shared laws: each tile's
+  // touched nodes take LDS positions in caller order, so the temperatures
+  // and slots a wave's elements touch are mostly consecutive words (the
+  // tile's own order groups its nodes by the tiles that read them)
+  c->res_sstride = 0;
+  if (c->ne == FED_HEX8 && c->op == 0 && c->rb == 4 && !(c->d_ktab || c->d_ctab || c->d_esk)) {
+    int32_t smax = 1;
+    for (const fed::TileHdr &th : T.tiles) smax = std::max(smax, th.cum_n[1]);
+    std::vector<int16_t> sigma((size_t)T.nt * smax, 0);
+    std::vector<std::pair<int32_t, int32_t>> key;
+    for (int32_t t = 0; t < T.nt; t++) {
+      const fed::TileHdr &th = T.tiles[t];
+      const int32_t nt = th.cum_n[1];
+      key.clear();
+      for (int32_t l = 0; l < nt; l++) {
+        const int32_t ki = l < th.nown ? th.nstart + l : T.halo[th.hstart + l - th.nown];
+        key.emplace_back(T.iperm[ki], l);
+      }
+      std::sort(key.begin(), key.end());
+      for (int32_t r = 0; r < nt; r++) sigma[(size_t)t * smax + key[r].second] = (int16_t)r;
+    }
+    // the packed entries with the positions in place of the local indices
+    std::vector<uint16_t> ents(T.ent);
+    const uint32_t pm = (1u << T.pb) - 1u;
+    for (int32_t t = 0; t < T.nt; t++) {
+      const fed::TileHdr &th = T.tiles[t];
+      const int16_t *sg = sigma.data() + (size_t)t * smax;
+      for (int64_t i = (int64_t)th.estart * c->ne; i < (int64_t)(th.estart + th.ecount) * c->ne; i++) {
+        const uint32_t w = ents[i];
+        ents[i] = (uint16_t)(((uint32_t)sg[w >> T.pb] << T.pb) | (w & pm));
+      }
+    }
+    HIPCHK(upload(P, &c->d_sigma, sigma.data(), sigma.size()));
+    HIPCHK(upload(P, &c->d_ent_sigma, ents.data(), ents.size()));
+    c->res_sstride = smax;
+  }
   const int words = c->prec == FED_FP64 ? 2 : 1;
   for (int i = 0; i < 2; i++) {
     HIPCHK(P.alloc((void **)&c->d_X[i], sizeof(unsigned long long) * words * N));
@@ -1220,6 +1259,9 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
         r.tag_skew = c->tag_skew;
       r.nvals = c->res_nv ? 1 : 0;
       r.ophalo = c->res_oph ? 1 : 0;
+      r.sigma = c->d_sigma;
+      r.sstride = c->res_sstride;
+      r.ent_sigma = c->d_ent_sigma;
         if (c->keep_states && c->ckpt_every > 0) {
           // fed_step breaks launches at checkpoints: this one stays inside segment g
           const int64_t g = st / c->ckpt_every, i0 = st % c->ckpt_every;
@@ -1843,6 +1885,9 @@ int backward_run(fed_ctx *c, const fed::AdjWork &w, const double *dL_dT, double 
       r.split = c->res_split;
       r.nvals = c->res_nv ? 1 : 0;
       r.ophalo = c->res_oph ? 1 : 0;
+      r.sigma = c->d_sigma;
+      r.sstride = c->res_sstride;
+      r.ent_sigma = c->d_ent_sigma;
       if (c->ps_rows > 0) {
         r.pts = c->d_psP;
         r.pts_nrec = c->nrec;

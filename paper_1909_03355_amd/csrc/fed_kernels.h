@@ -238,6 +238,14 @@ struct ResArgs {
   // uniform-gradient hexahedron: 1 if the operators of the elements that
   // touch the halo are copied to LDS at the launch's start
   int ophalo;
+  // nullable (FP32 hexahedra with the folded operator and the shared laws):
+  // per tile, the LDS position of each touched node's temperature and slots,
+  // at [tile * sstride + local index]: the tile's touched nodes in caller
+  // order, so a wave's elements gather and scatter mostly consecutive LDS
+  // words; null: the local index itself
+  const int16_t *sigma;
+  int sstride;
+  const void *ent_sigma;  // with sigma: the packed entries with those positions
 };
 
 // Resident adjoint of one checkpoint segment (hexahedra, folded operator):

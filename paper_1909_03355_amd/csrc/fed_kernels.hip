@@ -2240,7 +2240,10 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   const int tid = threadIdx.x, bs = blockDim.x;
   const int nown = th.nown, ntouch = nown + nhalo;
   using EntT = typename Ent<NE>::T;
-  const EntT *ent = reinterpret_cast<const EntT *>(a.ent);
+  // (PRE with LDS positions: the entries that carry them)
+  constexpr bool PRE0 = NE == 8 && sizeof(R) == 4 && OP == 0 && !GEN;
+  const EntT *ent =
+      reinterpret_cast<const EntT *>(PRE0 && r.sigma ? r.ent_sigma : a.ent);
   const R *Hb = (const R *)a.H;
   EntT ew[EPT];
   R eh[EPT][OP ? 1 : 6];
@@ -2297,6 +2300,12 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       }
     }
   }
+  // PRE: a touched node's temperature and slots sit at LDS position sig(local
+  // index) (r.sigma: the tile's touched nodes in caller order; the elements'
+  // packed entries, r.ent_sigma, carry those positions already), the others
+  // at the local index itself
+  const int16_t *sg = PRE && r.sigma ? r.sigma + (int64_t)t * r.sstride : nullptr;
+  auto sig = [&](int l) -> int { return PRE && sg ? (int)sg[l] : l; };
   uint32_t ta[PRE ? EPT : 1][8], sa[PRE ? EPT : 1][8];
   if constexpr (PRE) {
     const uint32_t tb = lds_addr(Tl), sb = lds_addr(slot);
@@ -2340,6 +2349,12 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     const int j = tid + q * bs;
     hid[q] = j < nhalo ? a.halo[th.hstart + j] : 0;
   }
+  // LDS positions of this thread's owned and halo nodes
+  int jpos[NPT], hpos[HPT];
+#pragma unroll
+  for (int q = 0; q < NPT; q++) jpos[q] = tid + q * bs < nown ? sig(tid + q * bs) : 0;
+#pragma unroll
+  for (int q = 0; q < HPT; q++) hpos[q] = tid + q * bs < nhalo ? sig(nown + tid + q * bs) : 0;
   // the boundary records of the owned nodes into LDS (slots: NM above)
   const int nbnd = th.nbnd;
   for (int j = tid; j < nbnd; j += bs) {
@@ -2424,7 +2439,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     for (int q = 0; q < NPT; q++) {
       const int j = tid + q * bs;
       if (j < nown) {
-        Tl[j] = hi[q];
+        Tl[jpos[q]] = hi[q];
         if (tabs) kl.stage(j, hi[q]);
       }
     }
@@ -2467,7 +2482,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     for (int q = 0; q < HPT; q++) {
       const int j = tid + q * bs;
       if (j < nhalo) {
-        Tl[nown + j] = hv[q];
+        Tl[hpos[q]] = hv[q];
         if (tabs) kl.stage(nown + j, hv[q]);
       }
     }
@@ -2496,7 +2511,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     for (int q = 0; q < NPT; q++) {
       const int j = tid + q * bs;
       if (j < nown) {
-        const R F = NM ? slot_sum(slot + j * ((1 << a.pb) + 1), 0, 1, a.maxinc)
+        const R F = NM ? slot_sum(slot + jpos[q] * ((1 << a.pb) + 1), 0, 1, a.maxinc)
                        : slot_sum(slot, j, nown, a.maxinc);
         Node1<R> d;
         d.alpha = al[q];
