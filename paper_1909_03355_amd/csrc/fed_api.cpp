@@ -1152,6 +1152,9 @@ int fed_create(const fed_mesh *m, const fed_materials *mt, const fed_bcs *bc,
     moved += (rb + lo_b) * th.nown;                              // writes
   }
   moved += 5.0 * rb * nrec;
+  // resident LDS positions of the touched nodes (2 B each)
+  if (c->res_sstride > 0)
+    for (const fed::TileHdr &th : T.tiles) moved += 2.0 * th.cum_n[1];
   I.moved_bytes_per_launch = moved;
   // resident operators that do not stay on chip (the elements that run before
   // the halo wait, or all): every tile's copies, every step

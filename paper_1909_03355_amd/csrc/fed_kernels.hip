@@ -2300,12 +2300,10 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       }
     }
   }
-  // PRE: a touched node's temperature and slots sit at LDS position sig(local
-  // index) (r.sigma: the tile's touched nodes in caller order; the elements'
-  // packed entries, r.ent_sigma, carry those positions already), the others
-  // at the local index itself
-  const int16_t *sg = PRE && r.sigma ? r.sigma + (int64_t)t * r.sstride : nullptr;
-  auto sig = [&](int l) -> int { return PRE && sg ? (int)sg[l] : l; };
+  // PRE: a touched node's temperature and slots sit at LDS position
+  // r.sigma[local index] (the tile's touched nodes in caller order; the
+  // elements' packed entries, r.ent_sigma, carry those positions already), or
+  // at the local index itself when r.sigma is null
   uint32_t ta[PRE ? EPT : 1][8], sa[PRE ? EPT : 1][8];
   if constexpr (PRE) {
     const uint32_t tb = lds_addr(Tl), sb = lds_addr(slot);
@@ -2349,12 +2347,22 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     const int j = tid + q * bs;
     hid[q] = j < nhalo ? a.halo[th.hstart + j] : 0;
   }
-  // LDS positions of this thread's owned and halo nodes
-  int jpos[NPT], hpos[HPT];
+  // PRE: LDS positions of this thread's owned and halo nodes, kept in
+  // registers (the other instances use the local index itself)
+  int jpos[PRE ? NPT : 1], hpos[PRE ? HPT : 1];
+  if constexpr (PRE) {
+    const int16_t *sg = r.sigma ? r.sigma + (int64_t)t * r.sstride : nullptr;
 #pragma unroll
-  for (int q = 0; q < NPT; q++) jpos[q] = tid + q * bs < nown ? sig(tid + q * bs) : 0;
+    for (int q = 0; q < NPT; q++) {
+      const int l = tid + q * bs;
+      jpos[q] = l < nown ? (sg ? (int)sg[l] : l) : 0;
+    }
 #pragma unroll
-  for (int q = 0; q < HPT; q++) hpos[q] = tid + q * bs < nhalo ? sig(nown + tid + q * bs) : 0;
+    for (int q = 0; q < HPT; q++) {
+      const int l = nown + tid + q * bs;
+      hpos[q] = tid + q * bs < nhalo ? (sg ? (int)sg[l] : l) : 0;
+    }
+  }
   // the boundary records of the owned nodes into LDS (slots: NM above)
   const int nbnd = th.nbnd;
   for (int j = tid; j < nbnd; j += bs) {
@@ -2439,7 +2447,8 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     for (int q = 0; q < NPT; q++) {
       const int j = tid + q * bs;
       if (j < nown) {
-        Tl[jpos[q]] = hi[q];
+        if constexpr (PRE) Tl[jpos[q]] = hi[q];
+        else Tl[j] = hi[q];
         if (tabs) kl.stage(j, hi[q]);
       }
     }
@@ -2482,7 +2491,8 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     for (int q = 0; q < HPT; q++) {
       const int j = tid + q * bs;
       if (j < nhalo) {
-        Tl[hpos[q]] = hv[q];
+        if constexpr (PRE) Tl[hpos[q]] = hv[q];
+        else Tl[nown + j] = hv[q];
         if (tabs) kl.stage(nown + j, hv[q]);
       }
     }
@@ -2511,7 +2521,7 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
     for (int q = 0; q < NPT; q++) {
       const int j = tid + q * bs;
       if (j < nown) {
-        const R F = NM ? slot_sum(slot + jpos[q] * ((1 << a.pb) + 1), 0, 1, a.maxinc)
+        const R F = NM ? slot_sum(slot + (PRE ? jpos[q] : j) * ((1 << a.pb) + 1), 0, 1, a.maxinc)
                        : slot_sum(slot, j, nown, a.maxinc);
         Node1<R> d;
         d.alpha = al[q];

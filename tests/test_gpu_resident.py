@@ -1,8 +1,9 @@
-"""Resident stepping (one cooperative launch for all the steps of a call, each
-tile's elements and nodes held in registers, halo temperatures exchanged
-through memory with per-tile step flags) against the one-step-per-launch
-kernel (bitwise: same element loads, same ordered nodal sums, same update)
-and the FP64 oracle (err_max <= 1e-12 FP64, <= 1e-5 compensated FP32)."""
+"""Resident stepping (one launch for all the steps of a call, each tile's
+elements and nodes held in registers, halo temperatures exchanged through
+step-tagged words in memory; FP32 hexahedral tiles place their nodes in LDS
+in caller order) against the one-step-per-launch kernel (bitwise: same
+element loads, same ordered nodal sums, same update) and the FP64 oracle
+(err_max <= 1e-12 FP64, <= 1e-5 compensated FP32)."""
 from __future__ import annotations
 
 import numpy as np
