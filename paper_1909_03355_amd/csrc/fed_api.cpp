@@ -1260,11 +1260,11 @@ int run_steps(fed_ctx *c, int64_t nsteps, hipStream_t s) {
                        c->d_T[fin], c->d_lo[fin], nullptr, 0};
         r.split = c->res_split;
         r.tag_skew = c->tag_skew;
-      r.nvals = c->res_nv ? 1 : 0;
-      r.ophalo = c->res_oph ? 1 : 0;
-      r.sigma = c->d_sigma;
-      r.sstride = c->res_sstride;
-      r.ent_sigma = c->d_ent_sigma;
+        r.nvals = c->res_nv ? 1 : 0;
+        r.ophalo = c->res_oph ? 1 : 0;
+        r.sigma = c->d_sigma;
+        r.sstride = c->res_sstride;
+        r.ent_sigma = c->d_ent_sigma;
         if (c->keep_states && c->ckpt_every > 0) {
           // fed_step breaks launches at checkpoints: this one stays inside segment g
           const int64_t g = st / c->ckpt_every, i0 = st % c->ckpt_every;
