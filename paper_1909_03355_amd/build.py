@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfedfem.so")
 CALIB = os.path.join(HERE, "copy_calibrate")
-SOURCES = ["fed_api.cpp", "fed_kernels.hip", "fed_tiling.cpp"]
+SOURCES = ["fed_api.cpp", "fed_kernels.hip", "fed_tiling.cpp", "fed_lds_order.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -581,35 +581,14 @@ int setup_resident(fed_ctx *c, int n_cu, double *exch) {
   // tile's own order groups its nodes by the tiles that read them)
   c->res_sstride = 0;
   if (c->ne == FED_HEX8 && c->op == 0 && c->rb == 4 && !(c->d_ktab || c->d_ctab || c->d_esk)) {
-    int32_t smax = 1;
-    for (const fed::TileHdr &th : T.tiles) smax = std::max(smax, th.cum_n[1]);
-    std::vector<int16_t> sigma((size_t)T.nt * smax, 0);
-    std::vector<std::pair<int32_t, int32_t>> key;
-    for (int32_t t = 0; t < T.nt; t++) {
-      const fed::TileHdr &th = T.tiles[t];
-      const int32_t nt = th.cum_n[1];
-      key.clear();
-      for (int32_t l = 0; l < nt; l++) {
-        const int32_t ki = l < th.nown ? th.nstart + l : T.halo[th.hstart + l - th.nown];
-        key.emplace_back(T.iperm[ki], l);
-      }
-      std::sort(key.begin(), key.end());
-      for (int32_t r = 0; r < nt; r++) sigma[(size_t)t * smax + key[r].second] = (int16_t)r;
+    std::vector<int16_t> sigma;
+    std::vector<uint16_t> ents;
+    int32_t stride = 0;
+    if (fed::caller_order_positions(T, c->ne, sigma, stride, ents)) {
+      HIPCHK(upload(P, &c->d_sigma, sigma.data(), sigma.size()));
+      HIPCHK(upload(P, &c->d_ent_sigma, ents.data(), ents.size()));
+      c->res_sstride = stride;
     }
-    // the packed entries with the positions in place of the local indices
-    std::vector<uint16_t> ents(T.ent);
-    const uint32_t pm = (1u << T.pb) - 1u;
-    for (int32_t t = 0; t < T.nt; t++) {
-      const fed::TileHdr &th = T.tiles[t];
-      const int16_t *sg = sigma.data() + (size_t)t * smax;
-      for (int64_t i = (int64_t)th.estart * c->ne; i < (int64_t)(th.estart + th.ecount) * c->ne; i++) {
-        const uint32_t w = ents[i];
-        ents[i] = (uint16_t)(((uint32_t)sg[w >> T.pb] << T.pb) | (w & pm));
-      }
-    }
-    HIPCHK(upload(P, &c->d_sigma, sigma.data(), sigma.size()));
-    HIPCHK(upload(P, &c->d_ent_sigma, ents.data(), ents.size()));
-    c->res_sstride = smax;
   }
   const int words = c->prec == FED_FP64 ? 2 : 1;
   for (int i = 0; i < 2; i++) {

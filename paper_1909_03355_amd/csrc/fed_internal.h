@@ -71,4 +71,12 @@ struct Tiling {
 // Builds the tiling; returns an empty string on success, else the reason.
 std::string build_tiling(const TilingInput &in, Tiling &out);
 
+// Resident LDS placement (fed_lds_order.cpp): per tile, the position of each
+// touched node (local index l -> sigma[t * stride + l]), the tile's touched
+// nodes in caller order, and T.ent with those positions in place of the local
+// indices.  Positions are a permutation of the tile's touched nodes.  False
+// (and nothing to use) when a tile has more touched nodes than an int16 holds.
+bool caller_order_positions(const Tiling &T, int ne, std::vector<int16_t> &sigma, int32_t &stride,
+                            std::vector<uint16_t> &ent);
+
 }  // namespace fed

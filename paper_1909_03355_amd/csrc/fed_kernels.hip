@@ -2300,10 +2300,12 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
       }
     }
   }
-  // PRE: a touched node's temperature and slots sit at LDS position
-  // r.sigma[local index] (the tile's touched nodes in caller order; the
-  // elements' packed entries, r.ent_sigma, carry those positions already), or
-  // at the local index itself when r.sigma is null
+  // PRE: a touched node's temperature and slots sit at LDS position sig(local
+  // index) (r.sigma: the tile's touched nodes in caller order; the elements'
+  // packed entries, r.ent_sigma, carry those positions already), the others
+  // at the local index itself
+  const int16_t *sg = PRE && r.sigma ? r.sigma + (int64_t)t * r.sstride : nullptr;
+  auto sig = [&](int l) -> int { return PRE && sg ? (int)sg[l] : l; };
   uint32_t ta[PRE ? EPT : 1][8], sa[PRE ? EPT : 1][8];
   if constexpr (PRE) {
     const uint32_t tb = lds_addr(Tl), sb = lds_addr(slot);
@@ -2351,17 +2353,10 @@ __global__ __launch_bounds__(1024) void k_resident(StepArgs a, ResArgs r) {
   // registers (the other instances use the local index itself)
   int jpos[PRE ? NPT : 1], hpos[PRE ? HPT : 1];
   if constexpr (PRE) {
-    const int16_t *sg = r.sigma ? r.sigma + (int64_t)t * r.sstride : nullptr;
 #pragma unroll
-    for (int q = 0; q < NPT; q++) {
-      const int l = tid + q * bs;
-      jpos[q] = l < nown ? (sg ? (int)sg[l] : l) : 0;
-    }
+    for (int q = 0; q < NPT; q++) jpos[q] = tid + q * bs < nown ? sig(tid + q * bs) : 0;
 #pragma unroll
-    for (int q = 0; q < HPT; q++) {
-      const int l = nown + tid + q * bs;
-      hpos[q] = tid + q * bs < nhalo ? (sg ? (int)sg[l] : l) : 0;
-    }
+    for (int q = 0; q < HPT; q++) hpos[q] = tid + q * bs < nhalo ? sig(nown + tid + q * bs) : 0;
   }
   // the boundary records of the owned nodes into LDS (slots: NM above)
   const int nbnd = th.nbnd;

@@ -1,5 +1,5 @@
-"""Host-side checks (CPU only): the tiler's index structures under
-AddressSanitizer / UBSan, and that the C-ABI library loads and exports every
+"""Host-side checks (CPU only): the tiler's index structures and the resident
+LDS placement under AddressSanitizer / UBSan, and that the C-ABI library loads and exports every
 symbol the header declares and rejects bad inputs before touching a GPU."""
 from __future__ import annotations
 
@@ -17,7 +17,8 @@ BIN = os.path.join(ROOT, "tests", "_tiling_check")
 @pytest.fixture(scope="module")
 def checker():
     src = [os.path.join(ROOT, "tests", "tiling_check.cpp"),
-           os.path.join(ROOT, "paper_1909_03355_amd", "csrc", "fed_tiling.cpp")]
+           os.path.join(ROOT, "paper_1909_03355_amd", "csrc", "fed_tiling.cpp"),
+           os.path.join(ROOT, "paper_1909_03355_amd", "csrc", "fed_lds_order.cpp")]
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=all"] + src + ["-o", BIN]
     subprocess.run(cmd, check=True)

@@ -255,6 +255,36 @@ int main(int argc, char **argv) {
       if (!a.empty() && !b.empty()) REQUIRE(!(b < a));
     }
   }
+  // resident LDS placement: per tile a permutation of the touched nodes in
+  // caller order, and entries that carry it
+  {
+    std::vector<int16_t> sigma;
+    std::vector<uint16_t> ent2;
+    int32_t stride = 0;
+    REQUIRE(fed::caller_order_positions(T, ne, sigma, stride, ent2));
+    REQUIRE(ent2.size() == T.ent.size());
+    for (int t = 0; t < T.nt; t++) {
+      const fed::TileHdr &th = T.tiles[t];
+      const int nt = th.cum_n[T.depth];
+      REQUIRE(nt <= stride);
+      const int16_t *sg = sigma.data() + (size_t)t * stride;
+      std::vector<int> at(nt, -1);
+      for (int l = 0; l < nt; l++) {
+        REQUIRE(sg[l] >= 0 && sg[l] < nt);
+        REQUIRE(at[sg[l]] < 0);
+        at[sg[l]] = l;
+      }
+      auto caller = [&](int l) {
+        return T.iperm[l < th.nown ? th.nstart + l : T.halo[th.hstart + l - th.nown]];
+      };
+      for (int r = 1; r < nt; r++) REQUIRE(caller(at[r - 1]) < caller(at[r]));
+      for (int64_t i = (int64_t)th.estart * ne; i < (int64_t)(th.estart + th.ecount) * ne; i++) {
+        const uint32_t w = T.ent[i], w2 = ent2[i];
+        REQUIRE((w2 >> T.pb) == (uint32_t)sg[w >> T.pb]);
+        REQUIRE((w2 & ((1u << T.pb) - 1u)) == (w & ((1u << T.pb) - 1u)));
+      }
+    }
+  }
   std::printf("OK %d tiles, %zu expanded elements, maxinc %d, pb %d\n", T.nt, T.eorig.size(),
               T.maxinc, T.pb);
   return 0;
